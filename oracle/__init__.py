@@ -1,0 +1,191 @@
+"""CPU oracle of the forced lattice-Boltzmann step (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never does, and this
+package never imports the product package.
+
+The arithmetic lives in ``lbm_oracle.c`` (built by ``oracle/build.py`` into a
+double and a float library); this module only marshals NumPy arrays.  Array
+layout: populations ``f[i, n]`` with ``n = (z*ny + y)*nx + x`` (x fastest), the
+stored value being ``f-bar_i - w_i * shift``; velocity and acceleration fields
+``u[a, n]`` / ``g[a, n]`` with three component planes (z plane zero in 2-D).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+from . import lattice as lat
+
+_LIBS: dict = {}
+
+
+class _Lattice(C.Structure):
+    _fields_ = [("D", C.c_int32), ("Q", C.c_int32), ("NM", C.c_int32),
+                ("e", C.c_void_p), ("opp", C.c_void_p), ("mi", C.c_void_p),
+                ("w", C.c_void_p), ("H", C.c_void_p), ("Minv", C.c_void_p)]
+
+
+def _params_struct(real_t):
+    class _Params(C.Structure):
+        _fields_ = [("collision", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+                    ("nz", C.c_int32), ("wall", C.c_int32 * 3), ("store16", C.c_int32),
+                    ("shift", real_t), ("omega", real_t), ("hforce", real_t),
+                    ("q2", real_t), ("q3", real_t)]
+    return _Params
+
+
+_P64 = _params_struct(C.c_double)
+_P32 = _params_struct(C.c_float)
+
+
+def _lib(kind: str):
+    if kind not in _LIBS:
+        path = _build.lib_path(kind)
+        if not os.path.exists(path):
+            _build.build(force=False)
+        L = C.CDLL(path)
+        vp = C.c_void_p
+        real = C.c_double if kind == "f64" else C.c_float
+        L.oracle_step.argtypes = [vp, vp, vp, vp, vp, real]
+        L.oracle_run.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64]
+        L.oracle_init.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.oracle_moments.argtypes = [vp, vp, vp, vp, real, vp, vp]
+        L.oracle_collide_node.argtypes = [vp, vp, vp, vp, vp]
+        L.oracle_init_node.argtypes = [vp, vp, real, vp, vp, vp]
+        L.oracle_bgk_terms.argtypes = [vp, real, vp, vp, vp, vp]
+        L.oracle_round_half.argtypes = [C.c_float]
+        L.oracle_round_half.restype = C.c_float
+        _LIBS[kind] = L
+    return _LIBS[kind]
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def round_half(x: float) -> float:
+    """The oracle's own binary16 rounding (IEEE round to nearest even)."""
+    return float(_lib("f32").oracle_round_half(float(x)))
+
+
+class Oracle:
+    """Plain forced LB step on one periodic / walled box.
+
+    lattice: 'D2Q9' | 'D3Q19' | 'D3Q27'; collision: 'bgk' | 'smrt';
+    shape (nx, ny, nz) (nz = 1 in 2-D); walls: per-axis flags (halfway bounce-back
+    on both faces); tau: dict or tuple of tau-hat per Hermite order (tau2, tau3,
+    tau4) -- BGK uses tau2 only, SMRT requires tau4 == 1 (order 4 is trimmed);
+    shift: constant s removed from stored populations (f-bar_i - w_i s);
+    real: 'f64' (reference) or 'f32' (emulation); store16: round stores to binary16.
+    """
+
+    def __init__(self, lattice: str, collision: str, shape, walls=(0, 0, 0), tau=(0.8, 0.8, 1.0),
+                 shift: float = 0.0, real: str = "f64", store16: bool = False):
+        self.lattice = lattice
+        self.collision = collision.lower()
+        nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+        self.shape = (nx, ny, nz)
+        self.N = nx * ny * nz
+        self.real = real
+        self.dtype = np.float64 if real == "f64" else np.float32
+        self.L = lat.tables(lattice, self.dtype)
+        self.Q = self.L["Q"]
+        self.D = self.L["D"]
+        tau2, tau3, tau4 = tau
+        if min(tau2, tau3) <= 0.5:
+            raise ValueError("tau-hat must exceed 1/2")
+        if self.collision == "smrt" and tau4 != 1.0:
+            raise ValueError("SMRT trims order 4: tau4 must be 1")
+        self._lat = _Lattice(self.L["D"], self.L["Q"], self.L["NM"],
+                             self.L["e"].ctypes.data, self.L["opp"].ctypes.data,
+                             self.L["mi"].ctypes.data, self.L["w"].ctypes.data,
+                             self.L["H"].ctypes.data, self.L["Minv"].ctypes.data)
+        omega = 1.0 / tau2
+        vals = dict(shift=shift, omega=omega, hforce=1.0 - 0.5 * omega,
+                    q2=1.0 - 1.0 / tau2, q3=1.0 - 1.0 / tau3)
+        P = _P64 if real == "f64" else _P32
+        cast = float if real == "f64" else (lambda v: float(np.float32(v)))
+        self._p = P(1 if self.collision == "smrt" else 0, nx, ny, nz,
+                    (C.c_int32 * 3)(*[int(bool(w)) for w in walls]), int(bool(store16)),
+                    *[cast(vals[k]) for k in ("shift", "omega", "hforce", "q2", "q3")])
+        self._l = _lib(real)
+        self._lref = C.byref(self._lat)
+        self._pref = C.byref(self._p)
+
+    # ---- helpers ------------------------------------------------------------------
+    def _arr(self, a, rows):
+        a = np.ascontiguousarray(a, dtype=self.dtype)
+        return a.reshape(rows, self.N)
+
+    def field(self, g):
+        """Broadcast an acceleration (3,), (3, N) or None to a (3, N) array."""
+        if g is None:
+            return np.zeros((3, self.N), self.dtype)
+        g = np.asarray(g, dtype=np.float64)
+        if g.ndim == 1:
+            g = np.repeat(g[:, None], self.N, axis=1)
+        return self._arr(g, 3)
+
+    # ---- whole-lattice operations -------------------------------------------------
+    def init(self, rho, u, g):
+        rho = self._arr(np.broadcast_to(np.asarray(rho, np.float64), (self.N,)), 1)
+        u = self.field(u)
+        g = self.field(g)
+        f = np.empty((self.Q, self.N), self.dtype)
+        self._l.oracle_init(self._lref, self._pref, _ptr(rho), _ptr(u), _ptr(g), _ptr(f))
+        return f
+
+    def step(self, f, g, gscale: float = 1.0):
+        f = self._arr(f, self.Q)
+        g = self.field(g)
+        out = np.empty_like(f)
+        self._l.oracle_step(self._lref, self._pref, _ptr(f), _ptr(out), _ptr(g), gscale)
+        return out
+
+    def run(self, f, g, nsteps: int, gscale=None):
+        f = self._arr(f, self.Q).copy()
+        g = self.field(g)
+        tmp = np.empty_like(f)
+        gs = None
+        if gscale is not None:
+            gs = np.ascontiguousarray(gscale, dtype=self.dtype)
+            assert gs.shape == (nsteps,)
+        self._l.oracle_run(self._lref, self._pref, _ptr(f), _ptr(tmp), _ptr(g),
+                           None if gs is None else _ptr(gs), int(nsteps))
+        return f
+
+    def moments(self, f, g, gscale: float = 1.0):
+        f = self._arr(f, self.Q)
+        g = self.field(g)
+        rho = np.empty(self.N, self.dtype)
+        u = np.empty((3, self.N), self.dtype)
+        self._l.oracle_moments(self._lref, self._pref, _ptr(f), _ptr(g), gscale,
+                               _ptr(rho), _ptr(u))
+        return rho, u
+
+    # ---- single-node pieces (pins) --------------------------------------------------
+    def collide_node(self, f, g):
+        f = np.ascontiguousarray(f, self.dtype)
+        g = np.ascontiguousarray(np.resize(np.asarray(g, np.float64), 3), self.dtype)
+        out = np.empty(self.Q, self.dtype)
+        self._l.oracle_collide_node(self._lref, self._pref, _ptr(f), _ptr(g), _ptr(out))
+        return out
+
+    def init_node(self, rho, u, g):
+        u = np.ascontiguousarray(np.resize(np.asarray(u, np.float64), 3), self.dtype)
+        g = np.ascontiguousarray(np.resize(np.asarray(g, np.float64), 3), self.dtype)
+        out = np.empty(self.Q, self.dtype)
+        self._l.oracle_init_node(self._lref, self._pref, rho, _ptr(u), _ptr(g), _ptr(out))
+        return out
+
+    def bgk_terms(self, rho, u, g):
+        u = np.ascontiguousarray(np.resize(np.asarray(u, np.float64), 3), self.dtype)
+        g = np.ascontiguousarray(np.resize(np.asarray(g, np.float64), 3), self.dtype)
+        feq = np.empty(self.Q, self.dtype)
+        Fi = np.empty(self.Q, self.dtype)
+        self._l.oracle_bgk_terms(self._lref, rho, _ptr(u), _ptr(g), _ptr(feq), _ptr(Fi))
+        return feq, Fi

@@ -1,0 +1,41 @@
+"""Build the CPU oracle shared libraries (test infrastructure only).
+
+Two builds of lbm_oracle.c:
+  liboracle_f64.so  REAL = double  (the FP64 reference)
+  liboracle_f32.so  REAL = float   (emulation of the reduced-precision storage modes)
+
+Flags: -O2 -ffp-contract=off (no fused multiply-add, so every product and sum is
+rounded as written), no fast-math, OpenMP over the outermost lattice axis (each
+node's arithmetic is independent of the thread count).
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lbm_oracle.c")
+LIBS = {"f64": "liboracle_f64.so", "f32": "liboracle_f32.so"}
+
+
+def lib_path(kind: str) -> str:
+    return os.path.join(HERE, LIBS[kind])
+
+
+def build(force: bool = True) -> None:
+    for kind, real in (("f64", "double"), ("f32", "float")):
+        out = lib_path(kind)
+        if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+            continue
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", f"-DREAL={real}",
+               "-Wall", "-Wextra", "-Wno-unused-parameter",
+               SRC, "-o", out + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+
+
+if __name__ == "__main__":
+    build(force=True)
+    print("built", [lib_path(k) for k in LIBS], file=sys.stderr)

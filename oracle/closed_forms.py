@@ -1,0 +1,180 @@
+"""Closed-form and brute-force steady states used to pin the oracle (test infrastructure).
+
+None of this calls the oracle's step; the pins compare the oracle against these.
+
+Setting: D2Q9, flow invariant along x, acceleration g(y) along x, density 1 and
+u_y = 0 throughout (these hold exactly for such flows: every even-in-e_x source
+of the step has zero mass inside each e_y group, so the y-momentum and density
+never change).  What remains is linear and lives in the odd-in-e_x sector:
+per row y the three differences h_c(y) = f(1, c) - f(-1, c), c in {-1, 0, 1}, or
+equivalently the moments
+    X = sum f e_x = h_-1 + h_0 + h_1                 (x momentum j_x)
+    Y = sum f e_x e_y = h_1 - h_-1                   (shear stress moment)
+    Z = sum f e_x (3 e_y^2 - 1) = 2 h_1 + 2 h_-1 - h_0
+(Z/3 is the third-order Hermite moment H_xyy in lattice units).
+
+Collision in this sector (paper Sec. II.B and II.C):
+  * BGK with Guo force (eq:explict_eq, second-order force): the odd part of the
+    equilibrium is 3 w e_x u_x and of the force 3 w e_x g, so per group
+    h* = h - omega (h - 6 w_c u_x) + (1 - omega/2) 6 w_c g, u_x = X + g/2,
+    with w_0 = 1/9 and w_{+-1} = 1/36.
+  * SMRT: the first moment gains F (post-collision a^(1) = rho u + F/2 with
+    rho u = j + F/2), the second- and third-order central moments (here equal to
+    Y and Z/3 because u_y = 0 and the yy moment vanishes) relax with q_n = 1 - omega_n:
+    X' = X + g, Y' = q2 Y, Z' = q3 Z.
+Streaming moves group c by c rows; at a halfway bounce-back wall the leaving
+population returns in the opposite direction, so h_c at the boundary row takes
+-h*_(-c) of the same row.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def nu_of(tau2: float) -> float:
+    """Kinematic viscosity c_s^2 (tau-hat - 1/2) in lattice units."""
+    return (tau2 - 0.5) / 3.0
+
+
+# ---- closed forms ---------------------------------------------------------------------
+
+def poiseuille_profile(n: int, g: float, tau2: float, tau3: float) -> np.ndarray:
+    """Exact discrete steady u_x on rows y = 1..n between halfway walls.
+
+    Parabola with curvature -g/nu plus a constant slip u_s = g (16 L - 3) / (8 (tau2 - 1/2)),
+    L = (tau2 - 1/2)(tau3 - 1/2) (BGK: tau3 = tau2).
+    """
+    y = np.arange(1, n + 1, dtype=np.float64)
+    nu = nu_of(tau2)
+    lam = (tau2 - 0.5) * (tau3 - 0.5)
+    us = g * (16 * lam - 3) / (8 * (tau2 - 0.5))
+    return g / (2 * nu) * ((n / 2) ** 2 - (y - (n + 1) / 2) ** 2) + us
+
+
+def kolmogorov_amplitude(G: float, k: float, tau2: float, tau3: float) -> float:
+    """Exact discrete steady amplitude U of u_x = U sin(k y) for g_x = G sin(k y), SMRT.
+
+    With c = cos k, s = sin k, q_n = 1 - 1/tau_n:
+      R = c - s^2 q2 / (1 - c q2),  X = [R G + (2G/omega3)(1 - R q3)] / (1 - R),  U = X + G/2.
+    """
+    q2 = 1 - 1 / tau2
+    q3 = 1 - 1 / tau3
+    w3 = 1 / tau3
+    c = math.cos(k)
+    s = math.sin(k)
+    one_m_c = 2 * math.sin(k / 2) ** 2
+    den = (1 / tau2) + q2 * one_m_c  # 1 - c q2
+    R = c - s * s * q2 / den
+    one_m_R = one_m_c + s * s * q2 / den
+    X = (R * G + (2 * G / w3) * (1 - R * q3)) / one_m_R
+    return X + G / 2
+
+
+def kolmogorov_amplitude_bgk(G: float, k: float, tau: float) -> float:
+    """Same for BGK, derived from populations: U = G [4 tau + 1 + Z (1 - omega/2)] / (2 - omega Z),
+    Z = 2 (c - q) / (1 - 2 q c + q^2).  Equals the SMRT form at tau3 = tau2."""
+    w = 1 / tau
+    q = 1 - w
+    c = math.cos(k)
+    Z = 2 * (c - q) / (1 - 2 * q * c + q * q)
+    return G * (4 * tau + 1 + Z * (1 - w / 2)) / (2 - w * Z)
+
+
+def kolmogorov_amplitude_continuum(G: float, k: float, tau2: float) -> float:
+    return G / (nu_of(tau2) * k * k)
+
+
+# ---- brute force: dense steady solve of the odd sector --------------------------------
+
+def odd_sector_steady(g: np.ndarray, tau2: float, tau3: float, collision: str,
+                      walls: bool) -> np.ndarray:
+    """Steady u_x(y) of the odd sector by one dense linear solve.
+
+    g: acceleration per row (length n).  Unknowns: h_c(y) for c in (-1, 0, 1) after
+    streaming (pre-collision).  One step is an affine map h -> A h + b; the steady
+    state solves (I - A) h = b.
+    """
+    g = np.asarray(g, dtype=np.float64)
+    n = g.size
+    cs = (-1, 0, 1)
+    wc = {-1: 1 / 36, 0: 1 / 9, 1: 1 / 36}
+    nv = 3 * n
+
+    def idx(c, y):
+        return cs.index(c) * n + y
+
+    # collision: h* = C h + d, built row by row
+    Cm = np.zeros((nv, nv))
+    d = np.zeros(nv)
+    for y in range(n):
+        if collision == "bgk":
+            om = 1 / tau2
+            for c in cs:
+                r = idx(c, y)
+                Cm[r, r] += 1 - om
+                # + omega * 6 w_c u_x, u_x = X + g/2, X = sum_c' h_c'
+                for c2 in cs:
+                    Cm[r, idx(c2, y)] += om * 6 * wc[c]
+                d[r] += om * 6 * wc[c] * g[y] / 2 + (1 - om / 2) * 6 * wc[c] * g[y]
+        else:
+            q2 = 1 - 1 / tau2
+            q3 = 1 - 1 / tau3
+            # moments of h: X = h-1 + h0 + h1, Y = h1 - h-1, Z = 2h1 + 2h-1 - h0
+            T = np.array([[1, 1, 1], [-1, 0, 1], [2, -1, 2]], dtype=np.float64)
+            Ti = np.linalg.inv(T)
+            K = Ti @ np.diag([1.0, q2, q3]) @ T
+            off = Ti @ np.array([g[y], 0.0, 0.0])
+            rows = [idx(c, y) for c in cs]
+            for a, ra in enumerate(rows):
+                for b, rb in enumerate(rows):
+                    Cm[ra, rb] += K[a, b]
+                d[ra] += off[a]
+    # streaming with walls / periodic
+    S = np.zeros((nv, nv))
+    for c in cs:
+        for y in range(n):
+            src = y - c
+            if 0 <= src < n:
+                S[idx(c, y), idx(c, src)] = 1
+            elif not walls:
+                S[idx(c, y), idx(c, src % n)] = 1
+            else:
+                # population leaving row y toward the wall returns as -c: h_c(y) <- -h*_{-c}(y)
+                S[idx(c, y), idx(-c, y)] = -1
+    A = S @ Cm
+    b = S @ d
+    if walls:
+        h = np.linalg.solve(np.eye(nv) - A, b)
+    else:
+        # periodic: uniform x-momentum is a free (neutral) mode; fix it by the total
+        # momentum sum_y X = -sum_y g/2 of a flow whose mean physical velocity is zero.
+        con = np.zeros((1, nv))
+        con[0, :] = 1.0
+        M = np.vstack([np.eye(nv) - A, con])
+        r = np.concatenate([b, [-g.sum() / 2]])
+        h = np.linalg.lstsq(M, r, rcond=None)[0]
+    X = h[: n] + h[n: 2 * n] + h[2 * n:]
+    return X + g / 2
+
+
+def taylor_green_velocity(shape, u0: float, nu: float, t: float):
+    """2-D decaying Taylor-Green field of the paper's Sec. III.A (k1 = k2 = 2 pi / L):
+    u = -u0 [cos(k x) sin(k y), -sin(k x) cos(k y)] exp(-(k1^2 + k2^2) nu t)."""
+    nx, ny = shape
+    k1 = 2 * math.pi / nx
+    k2 = 2 * math.pi / ny
+    x = np.arange(nx)[None, :]
+    y = np.arange(ny)[:, None]
+    decay = math.exp(-(k1 * k1 + k2 * k2) * nu * t)
+    ux = -u0 * np.cos(k1 * x) * np.sin(k2 * y) * decay
+    uy = u0 * (k1 / k2) * np.sin(k1 * x) * np.cos(k2 * y) * decay
+    return ux, uy
+
+
+def e2_error(u, ua) -> float:
+    """Relative L2 velocity error of the paper's Sec. III.A."""
+    u = np.asarray(u, dtype=np.float64)
+    ua = np.asarray(ua, dtype=np.float64)
+    return math.sqrt(float(np.sum((u - ua) ** 2) / np.sum(ua ** 2)))

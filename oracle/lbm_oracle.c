@@ -1,0 +1,485 @@
+/*
+ * Plain CPU oracle of the forced lattice-Boltzmann time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link or call this
+ * file; only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark use it.  It shares no code, header or table generator with the HIP
+ * library: its lattice tables are produced by oracle/lattice.py in exact
+ * rational arithmetic and passed in already rounded.
+ *
+ * Built twice: with REAL = double (the reference, FP64) and with REAL = float
+ * (an emulation of the library's reduced-precision modes: FP32 arithmetic in
+ * the same order, stores rounded to binary32 or binary16).
+ *
+ * Paper: X. Li, W. Duan, X. Shan, "Second-order force scheme for lattice
+ * Boltzmann method" (arXiv 2212.07494).  Each function cites the passage it
+ * follows.  Lattice units, c_s^2 = 1/3; Hermite polynomials in lattice units
+ * (H_m(e) = c_s^|m| times the paper's tensor Hermite polynomial of e/c_s).
+ *
+ * State.  The oracle holds the paper's stored variable f-bar(x, t) (the
+ * pre-collision population after the change of variable eq:newf) and advances
+ * it with the explicit evolution eq:evolution: collide at x, then stream the
+ * post-collision value to x + e_i.  To allow reduced-precision storage the
+ * array holds deviations d_i = f-bar_i - w_i s from a constant shift s (s = 0
+ * gives the plain populations; the arithmetic below then is literally the
+ * paper's).
+ *
+ * Fixed operation order.  Every sum starts from -0.0 (the additive identity,
+ * so an empty sum is -0 and a one-term sum is that term exactly), adds its
+ * terms in the stated index order, and skips terms whose constant coefficient
+ * is exactly zero.  Products of velocity components are formed left to right
+ * over x, y, z.  Constants are exact rationals rounded once.  Compiled with
+ * -ffp-contract=off, no fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef REAL
+#define REAL double
+#endif
+typedef REAL real;
+
+#define MAXQ 27
+
+typedef struct {
+  int32_t D, Q, NM;
+  const int32_t *e;    /* Q x 3 velocity components */
+  const int32_t *opp;  /* Q: index of -e_i */
+  const int32_t *mi;   /* NM x 3 multi-indices, canonical order */
+  const real *w;       /* Q weights */
+  const real *H;       /* NM x Q: H_m(e_i) */
+  const real *Minv;    /* Q x NM: exact inverse of H */
+} oracle_lattice;
+
+typedef struct {
+  int32_t collision;   /* 0 = BGK, 1 = SMRT */
+  int32_t nx, ny, nz;
+  int32_t wall[3];     /* per axis: 1 = halfway bounce-back walls on both faces, 0 = periodic */
+  int32_t store16;     /* 1: round every stored value to binary16 (emulation only) */
+  real shift;          /* s: stored value is f-bar_i - w_i s */
+  real omega;          /* BGK: 1 / tau-hat */
+  real hforce;         /* BGK: 1 - omega / 2 */
+  real q2, q3;         /* SMRT: 1 - omega_n, omega_n = 1 / tau-hat_n */
+} oracle_params;
+
+/* ---- binary16 rounding (IEEE 754 round to nearest, ties to even) ------------------ */
+static float round_to_half(float x) {
+  union { float f; uint32_t u; } v = {x};
+  uint32_t sign = v.u & 0x80000000u;
+  uint32_t ax = v.u & 0x7fffffffu;
+  float a;
+  memcpy(&a, &ax, 4);
+  float r;
+  if (ax >= 0x7f800000u) {
+    r = a; /* inf / nan stay */
+  } else if (a >= 65520.0f) {
+    r = INFINITY; /* beyond the largest half after rounding */
+  } else if (a < 6.103515625e-05f) {
+    /* subnormal half: quantum 2^-24 */
+    float q = 5.9604644775390625e-08f;
+    float n = a / q; /* exact: power-of-two scaling */
+    float fl = floorf(n);
+    float rem = n - fl;
+    if (rem > 0.5f || (rem == 0.5f && fmodf(fl, 2.0f) != 0.0f)) fl += 1.0f;
+    r = fl * q;
+  } else {
+    int ex;
+    frexpf(a, &ex); /* a = m 2^ex, m in [0.5, 1) */
+    float q = ldexpf(1.0f, ex - 11); /* 10 fraction bits + hidden bit */
+    float n = a / q;
+    float fl = floorf(n);
+    float rem = n - fl;
+    if (rem > 0.5f || (rem == 0.5f && fmodf(fl, 2.0f) != 0.0f)) fl += 1.0f;
+    r = fl * q;
+  }
+  union { float f; uint32_t u; } o = {r};
+  o.u |= sign;
+  return o.f;
+}
+
+float oracle_round_half(float x) { return round_to_half(x); }
+
+static real store_value(const oracle_params *P, real x) {
+  if (P->store16) return (real)round_to_half((float)x);
+  return x;
+}
+
+/* ---- multi-index helpers --------------------------------------------------------- */
+static int mabs(const int32_t *m) { return m[0] + m[1] + m[2]; }
+
+static int find_index(const oracle_lattice *L, int a, int b, int c) {
+  for (int k = 0; k < L->NM; ++k) {
+    const int32_t *m = L->mi + 3 * k;
+    if (m[0] == a && m[1] == b && m[2] == c) return k;
+  }
+  return -1;
+}
+
+static int binom(int n, int k) { return (k == 0 || k == n) ? 1 : n; /* n <= 2 */ }
+
+/* u^m = prod_a u_a^{m_a}, multiplied left to right over x, y, z starting from 1. */
+static real upow(const int32_t *m, const real u[3]) {
+  real p = (real)1;
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < m[a]; ++k) p = p * u[a];
+  return p;
+}
+
+/* ---- macroscopic quantities (Sec. II.B, eq:half_F and the relations after it) ----- */
+/* rho-bar = rho; rho u-bar = rho u - F/2, so u = j/rho + g/2 with F = rho g. */
+typedef struct {
+  real drho, rho, j[3], u[3], F[3];
+} macro_t;
+
+static void macroscopic(const oracle_lattice *L, const oracle_params *P, const real *f,
+                        const real g[3], macro_t *M) {
+  real s = -0.0;
+  for (int i = 0; i < L->Q; ++i) s = s + f[i];
+  M->drho = s;
+  M->rho = P->shift + s;
+  for (int a = 0; a < 3; ++a) {
+    real ja = -0.0;
+    for (int i = 0; i < L->Q; ++i) {
+      int ea = L->e[3 * i + a];
+      if (ea != 0) ja = ja + (real)ea * f[i];
+    }
+    M->j[a] = ja;
+  }
+  for (int a = 0; a < 3; ++a) {
+    M->u[a] = M->j[a] / M->rho + (real)0.5 * g[a];
+    M->F[a] = M->rho * g[a];
+  }
+}
+
+/* ---- BGK (Sec. II.B, eq:explict_eq) ------------------------------------------------ */
+/* Second-order truncated equilibrium evaluated at e_i (expansion after
+ * eq:collision_BGK): w_i rho [1 + e.u/c_s^2 + ((e.u)^2 - c_s^2 u^2)/(2 c_s^4)], written
+ * as w_i (rho + rho P_i) with P_i = (3 e.u + 4.5 (e.u)^2) - 1.5 u.u; in deviation
+ * form the leading rho becomes drho (sum_i w_i s = s). */
+static real bgk_P(const oracle_lattice *L, int i, const real u[3], real *eu_out) {
+  real eu = -0.0;
+  for (int a = 0; a < 3; ++a) {
+    int ea = L->e[3 * i + a];
+    if (ea != 0) eu = eu + (real)ea * u[a];
+  }
+  real usq = -0.0;
+  for (int a = 0; a < L->D; ++a) usq = usq + u[a] * u[a];
+  *eu_out = eu;
+  return ((real)3 * eu + (real)4.5 * (eu * eu)) - (real)1.5 * usq;
+}
+
+/* Force term truncated to second order (the familiar form below eq:Fr, evaluated at
+ * e_i): F_i = w_i [ (e_i - u).F / c_s^2 + (e_i.F)(e_i.u) / c_s^4 ], F = rho g. */
+static real bgk_force(const oracle_lattice *L, int i, const real u[3], const real F[3],
+                      real eu) {
+  real eF = -0.0;
+  for (int a = 0; a < 3; ++a) {
+    int ea = L->e[3 * i + a];
+    if (ea != 0) eF = eF + (real)ea * F[a];
+  }
+  real uF = -0.0;
+  for (int a = 0; a < L->D; ++a) uF = uF + u[a] * F[a];
+  real G = (real)3 * (eF - uF) + (real)9 * (eF * eu);
+  return L->w[i] * G;
+}
+
+static void collide_bgk(const oracle_lattice *L, const oracle_params *P, const real *f,
+                        const real g[3], real *out) {
+  macro_t M;
+  macroscopic(L, P, f, g, &M);
+  for (int i = 0; i < L->Q; ++i) {
+    real eu;
+    real Pi = bgk_P(L, i, M.u, &eu);
+    real feq = L->w[i] * (M.drho + M.rho * Pi);
+    real Fi = bgk_force(L, i, M.u, M.F, eu);
+    out[i] = (f[i] - P->omega * (f[i] - feq)) + P->hforce * Fi;
+  }
+}
+
+/* ---- SMRT (Sec. II.C, eq:domg, eq:RHS, eq:bbd1 and the reconstruction after it) --- */
+/*
+ * Raw moments A_m = sum_i f_i H_m(e_i) (eq:dft).  Non-equilibrium raw moments
+ * N_m = A_m - rho u^m (isothermal equilibrium a_0 = rho u^n), with N_0 = 0 and
+ * N_{e_a} = -F_a/2 (the first-order relation rho u-bar = rho u - F/2).
+ * Central non-equilibrium moments by the Hermite shift to the frame moving with u:
+ *   D_m = sum_{l <= m} C(m,l) (-u)^l N_{m-l}.
+ * Relaxation (eq:RHS with d_0 = 0 for n >= 1 and d_F^(n) = 0 for n >= 2 when the
+ * non-equilibrium part of the force is neglected): P_m = (1 - omega_|m|) D_m for
+ * |m| = 2, 3; P_{e_a} = F_a/2; order 4 trimmed (P_m = 0).
+ * Back to raw moments: R_m = sum_{l <= m} C(m,l) u^l P_{m-l} for 1 <= |m| <= 4
+ * (this is eq:bbd1 written per multi-index), post-collision a*_m = rho u^m + R_m for
+ * |m| <= 4 and 0 above order 4; f* = Minv a* (reconstruction after eq:bbd1).
+ */
+/* Index bookkeeping of the two Hermite shifts, built once per call: for each m the
+ * sub-multi-indices l (canonical order, l != 0, l != m), the index of m - l and the
+ * integer coefficient (C(m,l) (-1)^|l| for the shift to the moving frame, C(m,l) back). */
+typedef struct {
+  int n[MAXQ];
+  int kl[MAXQ][MAXQ], km[MAXQ][MAXQ], cdown[MAXQ][MAXQ], cup[MAXQ][MAXQ];
+} smrt_plan;
+
+static void make_plan(const oracle_lattice *L, smrt_plan *S) {
+  for (int k = 0; k < L->NM; ++k) {
+    const int32_t *m = L->mi + 3 * k;
+    S->n[k] = 0;
+    for (int kl = 1; kl < L->NM; ++kl) {
+      const int32_t *l = L->mi + 3 * kl;
+      if (l[0] > m[0] || l[1] > m[1] || l[2] > m[2] || kl == k) continue;
+      int c = binom(m[0], l[0]) * binom(m[1], l[1]) * binom(m[2], l[2]);
+      int t = S->n[k]++;
+      S->kl[k][t] = kl;
+      S->km[k][t] = find_index(L, m[0] - l[0], m[1] - l[1], m[2] - l[2]);
+      S->cup[k][t] = c;
+      S->cdown[k][t] = (mabs(l) % 2) ? -c : c;
+    }
+  }
+}
+
+static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const smrt_plan *S,
+                         const real *f, const real g[3], real *out) {
+  macro_t M;
+  macroscopic(L, P, f, g, &M);
+  const int NM = L->NM;
+  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ], astar[MAXQ];
+  for (int k = 0; k < NM; ++k) {
+    U[k] = upow(L->mi + 3 * k, M.u);
+    E[k] = M.rho * U[k];
+  }
+  /* non-equilibrium raw moments */
+  for (int k = 0; k < NM; ++k) {
+    const int32_t *m = L->mi + 3 * k;
+    int n = mabs(m);
+    N[k] = 0;
+    if (n == 1) {
+      int a = m[0] ? 0 : (m[1] ? 1 : 2);
+      N[k] = (real)-0.5 * M.F[a];
+    } else if (n == 2 || n == 3) {
+      real A = -0.0;
+      for (int i = 0; i < L->Q; ++i) {
+        real h = L->H[k * L->Q + i];
+        if (h != 0) A = A + h * f[i];
+      }
+      N[k] = A - E[k];
+    }
+  }
+  /* shift to the moving frame, relax */
+  for (int k = 0; k < NM; ++k) {
+    const int32_t *m = L->mi + 3 * k;
+    int n = mabs(m);
+    Pc[k] = 0;
+    if (n == 1) {
+      int a = m[0] ? 0 : (m[1] ? 1 : 2);
+      Pc[k] = (real)0.5 * M.F[a];
+    } else if (n == 2 || n == 3) {
+      real D = N[k]; /* l = 0 term; l = m multiplies N_0 = 0 */
+      for (int t = 0; t < S->n[k]; ++t)
+        D = D + (real)S->cdown[k][t] * (U[S->kl[k][t]] * N[S->km[k][t]]);
+      Pc[k] = (n == 2 ? P->q2 : P->q3) * D;
+    }
+  }
+  /* back to raw moments, add the equilibrium */
+  for (int k = 0; k < NM; ++k) {
+    int n = mabs(L->mi + 3 * k);
+    if (n == 0) {
+      astar[k] = M.drho;
+      continue;
+    }
+    if (n > 4) {
+      astar[k] = 0;
+      continue;
+    }
+    real R = (n <= 3) ? Pc[k] : (real)-0.0; /* l = 0 term; P_m = 0 for |m| = 4 */
+    for (int t = 0; t < S->n[k]; ++t) {
+      int km = S->km[k][t];
+      if (mabs(L->mi + 3 * km) > 3) continue; /* P = 0 at order 4 */
+      R = R + (real)S->cup[k][t] * (U[S->kl[k][t]] * Pc[km]);
+    }
+    astar[k] = E[k] + R;
+  }
+  for (int i = 0; i < L->Q; ++i) {
+    real acc = -0.0;
+    for (int k = 0; k < NM; ++k) {
+      real c = L->Minv[i * NM + k];
+      if (c != 0 && mabs(L->mi + 3 * k) <= 4) acc = acc + c * astar[k];
+    }
+    out[i] = acc;
+  }
+}
+
+static void collide(const oracle_lattice *L, const oracle_params *P, const smrt_plan *S,
+                    const real *f, const real *g, real *out) {
+  if (P->collision == 0)
+    collide_bgk(L, P, f, g, out);
+  else
+    collide_smrt(L, P, S, f, g, out);
+}
+
+void oracle_collide_node(const oracle_lattice *L, const oracle_params *P, const real *f,
+                         const real *g, real *out) {
+  smrt_plan S;
+  make_plan(L, &S);
+  collide(L, P, &S, f, g, out);
+}
+
+/* ---- equilibrium minus half force: the initial stored state ------------------------- */
+/* eq:newf with Omega = 0 at t = 0: f-bar = f_eq - F_i / 2, so that rho-bar = rho and
+ * u = u-bar + F/(2 rho) return the prescribed (rho, u).  BGK uses its second-order
+ * equilibrium and force term; SMRT uses the equilibrium moments rho u^m and the raw
+ * force moments a_F,m = sum_a m_a u^{m - e_a} F_a (appendix, a_F^(1..4) at theta = 1),
+ * both up to order 4, reconstructed with Minv. */
+void oracle_init_node(const oracle_lattice *L, const oracle_params *P, real rho,
+                      const real *u, const real *g, real *out) {
+  real F[3];
+  for (int a = 0; a < 3; ++a) F[a] = rho * g[a];
+  real drho = rho - P->shift;
+  if (P->collision == 0) {
+    for (int i = 0; i < L->Q; ++i) {
+      real eu;
+      real Pi = bgk_P(L, i, u, &eu);
+      real feq = L->w[i] * (drho + rho * Pi);
+      real Fi = bgk_force(L, i, u, F, eu);
+      out[i] = feq - (real)0.5 * Fi;
+    }
+    return;
+  }
+  const int NM = L->NM;
+  real a[MAXQ];
+  for (int k = 0; k < NM; ++k) {
+    const int32_t *m = L->mi + 3 * k;
+    int n = mabs(m);
+    if (n == 0) {
+      a[k] = drho;
+      continue;
+    }
+    if (n > 4) {
+      a[k] = 0;
+      continue;
+    }
+    real aF = -0.0;
+    for (int al = 0; al < 3; ++al) {
+      if (m[al] == 0) continue;
+      int32_t r[3] = {m[0], m[1], m[2]};
+      r[al] -= 1;
+      aF = aF + (real)m[al] * (upow(r, u) * F[al]);
+    }
+    a[k] = rho * upow(m, u) - (real)0.5 * aF;
+  }
+  for (int i = 0; i < L->Q; ++i) {
+    real acc = -0.0;
+    for (int k = 0; k < NM; ++k) {
+      real c = L->Minv[i * NM + k];
+      if (c != 0 && mabs(L->mi + 3 * k) <= 4) acc = acc + c * a[k];
+    }
+    out[i] = acc;
+  }
+}
+
+/* ---- whole-lattice operations -------------------------------------------------------- */
+static int64_t node_count(const oracle_params *P) {
+  return (int64_t)P->nx * P->ny * P->nz;
+}
+
+/* Initial state from per-node rho (N) and u (3 x N, component planes) and g (3 x N). */
+void oracle_init(const oracle_lattice *L, const oracle_params *P, const real *rho,
+                 const real *u, const real *g, real *f) {
+  const int64_t N = node_count(P);
+#pragma omp parallel for schedule(static)
+  for (int64_t n = 0; n < N; ++n) {
+    real un[3] = {u[n], u[N + n], u[2 * N + n]};
+    real gn[3] = {g[n], g[N + n], g[2 * N + n]};
+    real out[MAXQ];
+    oracle_init_node(L, P, rho[n], un, gn, out);
+    for (int i = 0; i < L->Q; ++i) f[i * N + n] = store_value(P, out[i]);
+  }
+}
+
+/* One explicit step (eq:evolution): collide at every node, then stream the
+ * post-collision value to x + e_i (the streaming after the SMRT reconstruction).
+ * Periodic axes wrap; across a wall face the value returns to the same node in the
+ * opposite direction (halfway bounce-back, a stationary no-slip wall midway between
+ * the last fluid node and the next).  g is the acceleration field (3 x N) and gscale
+ * the time factor s(t) applied to it. */
+void oracle_step(const oracle_lattice *L, const oracle_params *P, const real *f,
+                 real *fnew, const real *g, real gscale) {
+  const int nx = P->nx, ny = P->ny, nz = P->nz;
+  const int64_t N = node_count(P);
+  const int dims[3] = {nx, ny, nz};
+  smrt_plan S;
+  make_plan(L, &S);
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < nz; ++z) {
+    for (int y = 0; y < ny; ++y) {
+      for (int x = 0; x < nx; ++x) {
+        const int64_t n = ((int64_t)z * ny + y) * nx + x;
+        real fi[MAXQ], out[MAXQ];
+        for (int i = 0; i < L->Q; ++i) fi[i] = f[i * N + n];
+        real gn[3];
+        for (int a = 0; a < 3; ++a) gn[a] = g[a * N + n] * gscale;
+        collide(L, P, &S, fi, gn, out);
+        const int c[3] = {x, y, z};
+        for (int i = 0; i < L->Q; ++i) {
+          int d[3];
+          int wall_hit = 0;
+          for (int a = 0; a < 3; ++a) {
+            d[a] = c[a] + L->e[3 * i + a];
+            if (d[a] < 0 || d[a] >= dims[a]) {
+              if (P->wall[a])
+                wall_hit = 1;
+              else
+                d[a] = (d[a] + dims[a]) % dims[a];
+            }
+          }
+          real v = store_value(P, out[i]);
+          if (wall_hit)
+            fnew[(int64_t)L->opp[i] * N + n] = v;
+          else
+            fnew[(int64_t)i * N + ((int64_t)d[2] * ny + d[1]) * nx + d[0]] = v;
+        }
+      }
+    }
+  }
+}
+
+void oracle_run(const oracle_lattice *L, const oracle_params *P, real *f, real *tmp,
+                const real *g, const real *gscale, int64_t nsteps) {
+  const int64_t N = node_count(P);
+  for (int64_t t = 0; t < nsteps; ++t) {
+    oracle_step(L, P, f, tmp, g, gscale ? gscale[t] : (real)1);
+    memcpy(f, tmp, sizeof(real) * (size_t)N * (size_t)L->Q);
+  }
+}
+
+/* Physical density and velocity of the stored state (eq:half_F: u = u-bar + F/(2 rho)). */
+void oracle_moments(const oracle_lattice *L, const oracle_params *P, const real *f,
+                    const real *g, real gscale, real *rho, real *u) {
+  const int64_t N = node_count(P);
+#pragma omp parallel for schedule(static)
+  for (int64_t n = 0; n < N; ++n) {
+    real fi[MAXQ];
+    for (int i = 0; i < L->Q; ++i) fi[i] = f[i * N + n];
+    real gn[3];
+    for (int a = 0; a < 3; ++a) gn[a] = g[a * N + n] * gscale;
+    macro_t M;
+    macroscopic(L, P, fi, gn, &M);
+    if (rho) rho[n] = M.rho;
+    if (u)
+      for (int a = 0; a < 3; ++a) u[a * N + n] = M.u[a];
+  }
+}
+
+/* The BGK pieces on their own, for the force-moment pins. */
+void oracle_bgk_terms(const oracle_lattice *L, real rho, const real *u, const real *g,
+                      real *feq, real *Fi) {
+  real F[3];
+  for (int a = 0; a < 3; ++a) F[a] = rho * g[a];
+  for (int i = 0; i < L->Q; ++i) {
+    real eu;
+    real Pi = bgk_P(L, i, u, &eu);
+    feq[i] = L->w[i] * (rho + rho * Pi);
+    Fi[i] = bgk_force(L, i, u, F, eu);
+  }
+}
+
+int oracle_real_size(void) { return (int)sizeof(real); }

@@ -1,0 +1,229 @@
+"""Pins of the oracle's per-node arithmetic against identities the paper states.
+
+* P-F1: the BGK force term has zero mass, first moment rho g and second moment
+  rho (g u + u g) (paper Sec. I and eq:af: a_F^(0) = 0, a_F^(1) = rho g; the
+  second-order truncation below eq:Fr).
+* P-M: the initial state returns the prescribed rho and u (eq:half_F).
+* SMRT post-collision moments equal eq:bbd1 evaluated literally in tensor form
+  (orders 0..4, theta = 1, order 4 by the recursion), a formulation independent of
+  the oracle's multi-index Hermite shifts.
+* BGK post-collision moments equal those of eq:explict_eq in moment form.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from oracle import lattice as lat
+
+CS2 = 1.0 / 3.0
+
+
+def _setup(L, seed):
+    rng = np.random.default_rng(seed)
+    D = lat.dim(L)
+    rho = 1.0 + 0.1 * rng.uniform(-1, 1)
+    u = np.zeros(3)
+    g = np.zeros(3)
+    u[:D] = rng.uniform(-0.08, 0.08, D)
+    g[:D] = rng.uniform(-1e-3, 1e-3, D)
+    return rho, u, g
+
+
+def _tol(terms):
+    return 16 * np.finfo(np.float64).eps * np.sum(np.abs(terms))
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("seed", range(5))
+def test_bgk_force_moments(L, seed):
+    rho, u, g = _setup(L, seed)
+    o = Oracle(L, "bgk", (2, 2, 2 if lat.dim(L) == 3 else 1))
+    feq, Fi = o.bgk_terms(rho, u, g)
+    e = o.L["e"].astype(np.float64)
+    assert abs(Fi.sum()) <= _tol(Fi)
+    m1 = (Fi[:, None] * e).sum(0)
+    for a in range(3):
+        assert abs(m1[a] - rho * g[a]) <= _tol(Fi * e[:, a]) + 1e-30
+    m2 = np.einsum("i,ia,ib->ab", Fi, e, e)
+    want = rho * (np.outer(g, u) + np.outer(u, g))
+    assert np.all(np.abs(m2 - want) <= _tol(Fi) + 1e-30)
+    # equilibrium: mass rho, momentum rho u, second moment rho (uu + c_s^2 I)
+    assert abs(feq.sum() - rho) <= _tol(feq)
+    assert np.allclose((feq[:, None] * e).sum(0), rho * u, rtol=0, atol=1e-15)
+    D = lat.dim(L)
+    want2 = rho * (np.outer(u, u) + CS2 * np.diag([1.0] * D + [0.0] * (3 - D)))
+    assert np.allclose(np.einsum("i,ia,ib->ab", feq, e, e), want2, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+@pytest.mark.parametrize("shift", [0.0, 1.0])
+def test_init_recovers_rho_u(L, coll, shift):
+    rng = np.random.default_rng(3)
+    D = lat.dim(L)
+    shape = (3, 4, 2 if D == 3 else 1)
+    N = int(np.prod(shape))
+    rho = 1.0 + 0.05 * rng.uniform(-1, 1, N)
+    u = np.zeros((3, N))
+    g = np.zeros((3, N))
+    u[:D] = rng.uniform(-0.05, 0.05, (D, N))
+    g[:D] = rng.uniform(-1e-3, 1e-3, (D, N))
+    o = Oracle(L, coll, shape, tau=(0.7, 0.9 if coll == "smrt" else 0.7, 1.0), shift=shift)
+    f = o.init(rho, u, g)
+    r2, u2 = o.moments(f, g)
+    assert np.max(np.abs(r2 - rho)) <= 8 * np.finfo(float).eps * 2
+    assert np.max(np.abs(u2 - u)) <= 1e-15
+
+
+# --- eq:bbd1 in tensor form ---------------------------------------------------------
+
+def _sym_outer(*parts):
+    """Sum over all distinct placements of index groups: sym product as written in the
+    paper (e.g. 3 u a2 -> u_a a_bc + u_b a_ac + u_c a_ab)."""
+    order = sum(p.ndim for p in parts)
+    out = np.zeros((3,) * order)
+    sizes = [p.ndim for p in parts]
+    seen = set()
+    for perm in itertools.permutations(range(order)):
+        # assign positions to parts in order; identical placements counted once
+        key = []
+        pos = 0
+        for s in sizes:
+            key.append(tuple(sorted(perm[pos:pos + s])))
+            pos += s
+        key = tuple(key)
+        if key in seen:
+            continue
+        seen.add(key)
+        letters = "abcdefgh"[:order]
+        subs = []
+        for grp in key:
+            subs.append("".join(letters[i] for i in grp))
+        out += np.einsum(",".join(subs) + "->" + letters, *parts)
+    return out
+
+
+def _lattice_hermite_tensors(e):
+    I = np.eye(3)
+    H2 = np.einsum("a,b->ab", e, e) - CS2 * I
+    H3 = np.einsum("a,b,c->abc", e, e, e) - CS2 * (
+        np.einsum("a,bc->abc", e, I) + np.einsum("b,ac->abc", e, I) + np.einsum("c,ab->abc", e, I))
+    return H2, H3
+
+
+def _component(T, m):
+    idx = (0,) * m[0] + (1,) * m[1] + (2,) * m[2]
+    return T[idx] if idx else T
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("seed", range(4))
+def test_smrt_matches_bbd1_tensor_form(L, seed):
+    rho0, u0, g = _setup(L, seed)
+    D = lat.dim(L)
+    o = Oracle(L, "smrt", (1, 1, 1), tau=(0.62, 0.83, 1.0))
+    E = o.L["e"].astype(np.float64)
+    # a pre-collision state: equilibrium plus a seeded non-equilibrium perturbation
+    f = o.init_node(rho0, u0, g)
+    rng = np.random.default_rng(100 + seed)
+    f = f * (1 + 0.02 * rng.uniform(-1, 1, f.size))
+    out = o.collide_node(f, g)
+    # macroscopic (eq:half_F)
+    rho = f.sum()
+    j = (f[:, None] * E).sum(0)
+    u = j / rho + g / 2
+    F = rho * g
+    w2, w3 = 1 / 0.62, 1 / 0.83
+    a2 = sum(fi * _lattice_hermite_tensors(e)[0] for fi, e in zip(f, E))
+    a3 = sum(fi * _lattice_hermite_tensors(e)[1] for fi, e in zip(f, E))
+    # non-equilibrium parts (a_0^(n) = rho u^n at theta = 1)
+    a2_1 = a2 - rho * _sym_outer(u, u) / 2  # sym_outer(u,u) = 2 uu
+    a3_1 = a3 - rho * np.einsum("a,b,c->abc", u, u, u)
+    a1_p = F / 2
+    aF2 = _sym_outer(F, u)             # 2 F u   (appendix a_F^(2))
+    aF3 = _sym_outer(F, np.einsum("a,b->ab", u, u))  # 3 F u u  (appendix a_F^(3))
+    a2_p = (1 - w2) * a2_1 + (1 - w2 / 2) * aF2
+    a3_p = ((1 - w3) * a3_1 + (w3 - w2) * _sym_outer(u, a2_1)
+            + (1 - w3 / 2) * aF3 + (w3 / 2 - w2 / 2) * _sym_outer(u, aF2))
+    uu = np.einsum("a,b->ab", u, u)
+    a4_p = (_sym_outer(u, a3_p) - _sym_outer(uu, a2_p)
+            + _sym_outer(np.einsum("a,b,c->abc", u, u, u), a1_p))
+    # post-collision lattice moments of the oracle's output
+    M = o.L["H"]
+    mom = M @ out
+    ms = [tuple(m) for m in o.L["mi"]]
+    for k, m in enumerate(ms):
+        n = sum(m)
+        if n == 0:
+            want = rho
+        elif n == 1:
+            want = _component(rho * u + a1_p, m)
+        elif n == 2:
+            want = _component(rho * uu + a2_p, m)
+        elif n == 3:
+            want = _component(rho * np.einsum("a,b,c->abc", u, u, u) + a3_p, m)
+        elif n == 4:
+            want = _component(rho * np.einsum("a,b,c,d->abcd", u, u, u, u) + a4_p, m)
+        else:
+            want = 0.0
+        assert abs(mom[k] - want) <= 1e-14 * max(1.0, abs(want)), (m, mom[k], want)
+    assert D in (2, 3)
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+def test_bgk_post_collision_moments(L):
+    """Moments of eq:explict_eq: mass kept, momentum j + F, second Hermite moment
+    (1 - omega)(a2 - rho uu) + rho uu + (1 - omega/2)(F u + u F)."""
+    rho0, u0, g = _setup(L, 7)
+    tau = 0.71
+    o = Oracle(L, "bgk", (1, 1, 1), tau=(tau, tau, 1.0))
+    E = o.L["e"].astype(np.float64)
+    f = o.init_node(rho0, u0, g)
+    f = f * (1 + 0.02 * np.random.default_rng(5).uniform(-1, 1, f.size))
+    out = o.collide_node(f, g)
+    rho = f.sum()
+    j = (f[:, None] * E).sum(0)
+    u = j / rho + g / 2
+    F = rho * g
+    om = 1 / tau
+    assert abs(out.sum() - rho) < 1e-15
+    assert np.allclose((out[:, None] * E).sum(0), j + F, rtol=0, atol=1e-16)
+    D = lat.dim(L)
+    I = np.diag([1.0] * D + [0.0] * (3 - D))
+    a2 = np.einsum("i,ia,ib->ab", f, E, E) - CS2 * rho * I
+    a2o = np.einsum("i,ia,ib->ab", out, E, E) - CS2 * rho * I
+    uu = np.outer(u, u)
+    want = (1 - om) * (a2 - rho * uu) + rho * uu + (1 - om / 2) * (np.outer(F, u) + np.outer(u, F))
+    assert np.allclose(a2o, want, rtol=0, atol=2e-15)
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+def test_smrt_equal_rates_one_is_half_force(L):
+    """SMRT with omega_2 = omega_3 = 1: every non-equilibrium moment is replaced by half
+    the raw force moment, a*^(n) = rho u^n + a_F^(n)/2 for n = 1..4 (appendix, theta = 1)."""
+    rho, u, g = _setup(L, 11)
+    o = Oracle(L, "smrt", (1, 1, 1), tau=(1.0, 1.0, 1.0))
+    f = o.init_node(rho, u, g)
+    f = f * (1 + 0.03 * np.random.default_rng(9).uniform(-1, 1, f.size))
+    out = o.collide_node(f, g)
+    E = o.L["e"].astype(np.float64)
+    r = f.sum()
+    uu = (f[:, None] * E).sum(0) / r + g / 2
+    F = r * g
+    mom = o.L["H"] @ out
+    for k, m in enumerate(o.L["mi"]):
+        m = tuple(m)
+        n = sum(m)
+        if n == 0 or n > 4:
+            continue
+        up = np.prod([uu[a] ** m[a] for a in range(3)])
+        aF = 0.0
+        for a in range(3):
+            if m[a]:
+                r_ = list(m)
+                r_[a] -= 1
+                aF += m[a] * np.prod([uu[b] ** r_[b] for b in range(3)]) * F[a]
+        assert math.isclose(mom[k], r * up + aF / 2, rel_tol=0, abs_tol=1e-15)

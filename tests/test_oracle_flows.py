@@ -1,0 +1,251 @@
+"""Whole-step pins of the oracle: exact invariants, closed-form and brute-force steady
+states, the paper's Taylor-Green convergence order, symmetry and Galilean checks."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from oracle import closed_forms as cf
+from oracle import lattice as lat
+from paper_2212_07494_amd import inputs
+
+
+# ---- P-U: uniform force in a periodic box ---------------------------------------------
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+def test_uniform_force_momentum_balance(L, coll):
+    """Periodic box, uniform g, any initial field: mass is conserved and the total
+    momentum J = sum rho u grows by exactly t M g (each step adds F = rho g per node,
+    the first moment of the force term; Sec. I and eq:af)."""
+    D = lat.dim(L)
+    shape = (5, 4, 3) if D == 3 else (6, 5, 1)
+    rho, u, _ = inputs.random_fields(shape, seed=4, dim=D)
+    g = np.array([2e-5, -1e-5, 3e-5 if D == 3 else 0.0])
+    o = Oracle(L, coll, shape, tau=(0.66, 0.9 if coll == "smrt" else 0.66, 1.0))
+    f = o.init(rho, u, g)
+    r0, u0 = o.moments(f, g)
+    M0 = r0.sum()
+    J0 = (r0 * u0).sum(1)
+    steps = 400
+    f = o.run(f, g, steps)
+    r1, u1 = o.moments(f, g)
+    assert abs(r1.sum() - M0) <= 1e-12 * M0
+    J1 = (r1 * u1).sum(1)
+    dJ = J1 - J0
+    assert np.allclose(dJ, steps * M0 * g, rtol=1e-9, atol=1e-16)
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+def test_uniform_state_accelerates_exactly(L, coll):
+    """A uniform state under uniform g stays uniform with u(t) = u0 + t g."""
+    D = lat.dim(L)
+    shape = (3, 3, 3) if D == 3 else (3, 3, 1)
+    N = int(np.prod(shape))
+    u0 = np.array([0.01, -0.02, 0.015 if D == 3 else 0.0])
+    g = np.array([1e-5, 2e-5, -1e-5 if D == 3 else 0.0])
+    o = Oracle(L, coll, shape, tau=(0.8, 0.7 if coll == "smrt" else 0.8, 1.0))
+    f = o.init(1.0, u0, g)
+    f = o.run(f, g, 50)
+    r, u = o.moments(f, g)
+    assert np.allclose(r, 1.0, rtol=0, atol=1e-14)
+    for a in range(3):
+        assert np.allclose(u[a], u0[a] + 50 * g[a], rtol=0, atol=1e-14)
+    assert np.ptp(u, axis=1).max() <= 1e-15
+    assert N > 1
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+def test_equilibrium_is_fixed_point_without_force(L, coll):
+    """Zero force: the equilibrium of a uniform moving state is a fixed point."""
+    D = lat.dim(L)
+    shape = (3, 2, 2) if D == 3 else (3, 2, 1)
+    u0 = np.array([0.03, -0.01, 0.02 if D == 3 else 0.0])
+    o = Oracle(L, coll, shape, tau=(0.57, 1.0, 1.0))
+    f0 = o.init(1.0, u0, None)
+    f1 = o.run(f0, None, 20)
+    assert np.max(np.abs(f1 - f0)) <= 1e-14 * np.max(np.abs(f0))  # 20 steps of round-off
+
+
+# ---- P-POIS / P-KOLM / P-BRUTE -----------------------------------------------------------
+
+@pytest.mark.parametrize("coll,tau2,tau3", [("bgk", 0.8, 0.8), ("smrt", 0.8, 1.0),
+                                            ("smrt", 0.6, 1.0), ("smrt", 0.9, 0.7)])
+def test_closed_forms_equal_brute_force(coll, tau2, tau3):
+    g = 1e-6
+    n = 32
+    bf = cf.odd_sector_steady(np.full(n, g), tau2, tau3, coll, walls=True)
+    assert np.max(np.abs(bf - cf.poiseuille_profile(n, g, tau2, tau3))) <= 1e-12 * bf.max()
+    L = 64
+    k = 2 * math.pi / L
+    G = 1e-7
+    y = np.arange(L)
+    bf = cf.odd_sector_steady(G * np.sin(k * y), tau2, tau3, coll, walls=False)
+    U = (cf.kolmogorov_amplitude(G, k, tau2, tau3) if coll == "smrt"
+         else cf.kolmogorov_amplitude_bgk(G, k, tau2))
+    assert np.max(np.abs(bf - U * np.sin(k * y))) <= 1e-11 * U
+    if coll == "bgk":
+        assert math.isclose(cf.kolmogorov_amplitude(G, k, tau2, tau2), U, rel_tol=1e-11)
+
+
+def test_closed_form_limits():
+    """Slip vanishes at Lambda = 3/16; Kolmogorov tends to G/(nu k^2) as k -> 0."""
+    t2 = 0.75
+    t3 = 0.5 + 3 / 16 / (t2 - 0.5)
+    prof = cf.poiseuille_profile(20, 1e-6, t2, t3)
+    nu = cf.nu_of(t2)
+    assert abs(prof[0] - 1e-6 / (2 * nu) * (100 - 90.25)) < 1e-18
+    G = 1e-8
+    for k in (2 * math.pi / 4096, 2 * math.pi / 16384):
+        r = cf.kolmogorov_amplitude(G, k, 0.6, 1.0) / cf.kolmogorov_amplitude_continuum(G, k, 0.6)
+        assert abs(r - 1) < 200 * k * k
+
+
+@pytest.mark.parametrize("coll,tau3", [("bgk", None), ("smrt", 1.0), ("smrt", 0.7)])
+def test_poiseuille_matches_closed_form(coll, tau3):
+    """Channel 4 (periodic x) x 32 (walls), tau-hat 0.8, g = 1e-6: at convergence the
+    profile equals the exact discrete parabola-plus-slip to 5e-11 relative.  (The odd
+    sector's slowest mode has decayed to ~1e-19 by 45,000 steps; what remains is FP64
+    round-off accumulated in slowly relaxing even modes, ~1e-16 per step.)"""
+    tau = 0.8
+    t3 = tau if tau3 is None else tau3
+    w = inputs.poiseuille_channel(nx=4, ny=32, tau=tau, collision=coll)
+    o = Oracle("D2Q9", coll, w.shape, walls=w.walls, tau=(tau, t3, 1.0))
+    f = o.init(w.rho, w.u, w.g)
+    f = o.run(f, w.g, 45_000)
+    _, u = o.moments(f, w.g)
+    ux = u[0].reshape(32, 4)
+    assert np.ptp(ux, axis=1).max() == 0.0
+    want = cf.poiseuille_profile(32, 1e-6, tau, t3)
+    assert np.max(np.abs(ux[:, 0] - want)) <= 5e-11 * want.max()
+    assert np.max(np.abs(u[1])) <= 5e-15  # round-off of sums of O(0.1) populations
+
+
+def test_poiseuille_config_transient():
+    """The 64 x 32 channel after 10,000 steps: the slowest mode (decay time
+    N^2/(pi^2 nu) ~ 1038 steps) leaves a relative transient of order e^-9.6 ~ 7e-5."""
+    w = inputs.poiseuille_channel()
+    o = Oracle("D2Q9", "bgk", w.shape, walls=w.walls, tau=w.tau)
+    f = o.run(o.init(w.rho, w.u, w.g), w.g, w.steps)
+    _, u = o.moments(f, w.g)
+    want = cf.poiseuille_profile(32, 1e-6, 0.8, 0.8)
+    err = np.max(np.abs(u[0].reshape(32, 64)[:, 0] - want)) / want.max()
+    assert 1e-5 < err < 2e-4
+
+
+@pytest.mark.parametrize("coll,tau2,tau3", [("smrt", 0.6, 1.0), ("bgk", 0.6, 0.6)])
+def test_kolmogorov_matches_discrete_closed_form(coll, tau2, tau3):
+    """Periodic shear flow g_x = G sin(ky), L = 64: converged amplitude equals the exact
+    discrete amplitude to 1e-10 relative (the continuum value differs by ~1e-3)."""
+    w = inputs.kolmogorov_box(L=64, tau2=tau2, tau3=tau3, noise=0.0, collision=coll)
+    nx = 2
+    shape = (nx, 64, 1)
+    gp = np.repeat(w.g[0].reshape(64, 64)[:, :1], nx, axis=1).ravel()
+    g = np.zeros((3, nx * 64))
+    g[0] = gp
+    u = np.zeros((3, nx * 64))
+    u[0] = np.repeat(w.u[0].reshape(64, 64)[:, :1], nx, axis=1).ravel()
+    o = Oracle("D2Q9", coll, shape, tau=w.tau)
+    f = o.run(o.init(1.0, u, g), g, 60_000)
+    _, uo = o.moments(f, g)
+    k = w.meta["k"]
+    G = w.meta["A"]
+    U = (cf.kolmogorov_amplitude(G, k, tau2, tau3) if coll == "smrt"
+         else cf.kolmogorov_amplitude_bgk(G, k, tau2))
+    y = np.arange(64)
+    assert np.max(np.abs(uo[0].reshape(64, nx)[:, 0] - U * np.sin(k * y))) <= 1e-10 * U
+
+
+# ---- P-TG: the paper's convergence claim ------------------------------------------------
+
+@pytest.mark.parametrize("coll", ["smrt", "bgk"])
+def test_taylor_green_second_order(coll):
+    """Sec. III.A: forced 2-D Taylor-Green, Re = 50, u0 = 0.005, E2 at t = ln2/(2 nu k^2)
+    for L = 16, 32, 64 falls by ~4 per doubling (observed order in [1.8, 2.2])."""
+    errs = []
+    for L in (16, 32, 64):
+        w = inputs.taylor_green_2d(L=L, collision=coll)
+        o = Oracle("D2Q9", coll, w.shape, tau=w.tau)
+        f = o.run(o.init(w.rho, w.u, w.g), w.g, w.steps)
+        _, u = o.moments(f, w.g)
+        ax, ay = cf.taylor_green_velocity((L, L), w.meta["u0"], w.meta["nu"], w.steps)
+        errs.append(cf.e2_error(np.concatenate([u[0], u[1]]),
+                                np.concatenate([ax.ravel(), ay.ravel()])))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.8 <= p <= 2.2 for p in orders), (errs, orders)
+
+
+# ---- P-SYM: rotation symmetry --------------------------------------------------------------
+
+def _rotate_xy(field3, shape):
+    """Rotate a (3, N) vector field by -90 degrees about z on an n x n x nz grid: the
+    value at old (x, y) moves to new (y, n-1-x) and (vx, vy) becomes (vy, -vx)."""
+    nx, ny, nz = shape
+    a = field3.reshape(3, nz, ny, nx)
+    rot = np.rot90(a, k=1, axes=(2, 3))  # rotate the (y, x) plane
+    out = np.empty_like(rot)
+    out[0] = rot[1]
+    out[1] = -rot[0]
+    out[2] = rot[2]
+    return out.reshape(3, -1)
+
+
+def _rotate_scalar(s, shape):
+    nx, ny, nz = shape
+    return np.rot90(s.reshape(nz, ny, nx), k=1, axes=(1, 2)).reshape(-1)
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+def test_rotation_symmetry(L, coll):
+    """Rotating the inputs by 90 degrees about z rotates the outputs (to round-off)."""
+    D = lat.dim(L)
+    shape = (6, 6, 3) if D == 3 else (6, 6, 1)
+    rho, u, g = inputs.random_fields(shape, seed=21, dim=D, g_amp=1e-3)
+    o = Oracle(L, coll, shape, tau=(0.62, 0.85 if coll == "smrt" else 0.62, 1.0))
+
+    def run(rho, u, g):
+        f = o.run(o.init(rho, u, g), g, 12)
+        return o.moments(f, g)
+
+    r1, u1 = run(rho, u, g)
+    r2, u2 = run(_rotate_scalar(rho, shape), _rotate_xy(u, shape), _rotate_xy(g, shape))
+    assert np.allclose(_rotate_scalar(r1, shape), r2, rtol=0, atol=1e-14)
+    assert np.allclose(_rotate_xy(u1, shape), u2, rtol=0, atol=1e-14)
+
+
+# ---- reduced-precision emulation ---------------------------------------------------------
+
+def test_half_rounding_pins():
+    """binary16 round-to-nearest-even at representative points (IEEE 754)."""
+    from oracle import round_half
+    assert round_half(1.0) == 1.0
+    assert round_half(1.0 + 2 ** -11) == 1.0            # tie -> even
+    assert round_half(1.0 + 3 * 2 ** -11) == 1.0 + 2 ** -9  # tie -> even (up)
+    assert round_half(1.0 + 2 ** -11 + 2 ** -20) == 1.0 + 2 ** -10
+    assert round_half(65504.0) == 65504.0
+    assert math.isinf(round_half(65520.0))
+    assert round_half(2 ** -24) == 2 ** -24              # smallest subnormal
+    assert round_half(2 ** -25) == 0.0                   # tie -> even (zero)
+    assert round_half(-3 * 2 ** -25) == -(2 ** -23)
+    rng = np.random.default_rng(0)
+    xs = (rng.standard_normal(2000) * 10.0 ** rng.integers(-6, 4, 2000)).astype(np.float32)
+    for x in xs:
+        assert round_half(float(x)) == float(np.float16(x))
+
+
+@pytest.mark.parametrize("store16", [False, True])
+def test_emulation_close_to_fp64(store16):
+    """The FP32-arithmetic oracle (shifted storage) stays close to the FP64 oracle."""
+    w = inputs.taylor_green_3d(n=16, u0=0.02, steps=40)
+    o64 = Oracle("D3Q19", "smrt", w.shape, tau=w.tau)
+    o32 = Oracle("D3Q19", "smrt", w.shape, tau=w.tau, shift=1.0, real="f32", store16=store16)
+    f64 = o64.run(o64.init(w.rho, w.u, w.g), w.g, w.steps)
+    f32 = o32.run(o32.init(w.rho, w.u, w.g), w.g, w.steps)
+    _, u64 = o64.moments(f64, w.g)
+    _, u32 = o32.moments(f32, w.g)
+    e2 = cf.e2_error(u32, u64)
+    assert e2 < (2e-2 if store16 else 1e-5), e2
