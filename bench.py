@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the fused forced lattice-Boltzmann step on one MI355X.
+
+Workload: D3Q19 SMRT with the second-order force, 256^3 periodic box, Taylor-Green
+initial field (u0 = 0.02) plus the steady body force g = 1e-6 (sin 2 pi z/256, 0, 0),
+tau-hat_2 = 0.56, higher orders 1; populations stored as binary32 deviations from
+w_i rho0 (FP32-shifted), binary32 arithmetic.  Inputs are synthetic and seeded and
+sit in HBM before the timed region starts.
+
+Prints one JSON line: MLUPS (whole job), the roofline of the step kernel against the
+vendor HBM peak and against a measured stream copy, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X vendor peak
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2212_07494_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_hash: str, storage: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"step_d3q19_smrt_{storage}_256_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def copy_roofline(torch, L, stream, nbytes=2 << 30, reps=10):
+    """Best read+write bandwidth of the library's stream-copy probe over block sizes."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    best = 0.0
+    for block in (256, 512, 1024):
+        with torch.cuda.stream(stream):
+            L.lbm_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, 2, block, stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            L.lbm_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, reps, block, stream)
+            e1.record(stream)
+        e1.synchronize()
+        gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        best = max(best, gbps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
+def cpu_baseline(w, steps: int):
+    """The FP64 oracle as it stands, on the host cores, over `steps` steps of the
+    same 256^3 workload."""
+    from oracle import Oracle
+    o = Oracle(w.lattice, w.collision, w.shape, walls=w.walls, tau=w.tau)
+    f = o.init(w.rho, w.u, w.g)
+    t0 = time.perf_counter()
+    f = o.run(f, w.g, steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, {steps} steps of the full {w.shape[0]}^3 D3Q19 SMRT workload "
+                      f"({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32s", choices=["f64", "f32", "f32s", "f16s"])
+    ap.add_argument("--n", type=int, default=256, help="box edge (the workload is 256)")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-copy", action="store_true", help="skip the stream-copy roofline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU step "
+              "(--gpus 1); multi-GPU runs are not supported.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2212_07494_amd import inputs
+    from paper_2212_07494_amd import lbm as L
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    L.load()
+    w = inputs.taylor_green_3d(n=args.n)
+    stream = torch.cuda.Stream()
+    Q = L.QOF[w.lattice]
+    S = L.STORAGE_BYTES[args.storage]
+    lat = L.Lattice(w.lattice, w.collision, args.storage, w.shape, w.walls, w.tau, rho=w.rho,
+                    u=w.u, g_profile=w.g_profile, stream=stream)
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    mlups = w.N * args.steps / (ms * 1e-3) / 1e6
+    bytes_launch = 2 * Q * S * w.N
+    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    m = lat.monitors()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+    copy_gbps = None if args.no_copy else copy_roofline(torch, L, stream)
+    khash = kernel_source_hash()
+    traffic = measured_traffic(khash, args.storage) if args.n == 256 else None
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": bytes_launch,
+            "measured_copy_GBps": None if copy_gbps is None else round(copy_gbps, 1),
+            "frac_of_copy": None if copy_gbps is None else round(achieved / copy_gbps, 4)}
+    dtype = {"f64": "f64", "f32": "f32", "f32s": "f32", "f16s": "f32"}[args.storage]
+    rec = {
+        "metric": "MLUPS (D3Q19 SMRT+force 256^3)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 SMRT + second-order force, {args.n}^3 periodic, "
+                               "Taylor-Green u0=0.02 + g=1e-6 sin(2 pi z/L) x, tau2=0.56, "
+                               "tau3=tau4=1",
+                   "storage": {"f64": "FP64", "f32": "FP32", "f32s": "FP32-shifted",
+                               "f16s": "FP16-shifted"}[args.storage],
+                   "nodes": w.N, "parallelism": "single GPU"},
+        "roofline": roof,
+        "monitors": {"step": m.step, "mass": m.mass, "umax": m.umax, "nonfinite": m.nonfinite},
+        "kernel_source_hash": khash,
+    }
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

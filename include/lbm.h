@@ -1,0 +1,180 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) forced lattice-Boltzmann library.
+ *
+ * The library advances the discrete-velocity Boltzmann equation with a body force,
+ * d f_i/dt + e_i . grad f_i = Omega_i + F_i (Li, Duan & Shan, arXiv 2212.07494,
+ * Sec. II.A, eq:dv), discretised in space and time by the second-order (trapezoidal)
+ * rule of Sec. II.B: the stored variable is f-bar_i = f_i - Omega_i/2 - F_i/2
+ * (eq:newf) and one step is f-bar_i(x + e_i, t+1) = f-bar_i + Omega_i + F_i
+ * (eq:evolution), implemented as one fused pull-streaming + collision kernel.
+ *
+ *   collision  BGK   : eq:explict_eq with the second-order truncated equilibrium and
+ *                      the second-order (Guo-form) force term (Sec. II.B).
+ *              SMRT  : relaxation of central Hermite moments per order (eq:domg,
+ *                      eq:RHS), force entering through the first central moment only,
+ *                      back-transform of eq:bbd1 to order 4, reconstruction with the
+ *                      lattice's exact inverse Hermite transform (Sec. II.C).
+ *   lattice    D2Q9, D3Q19, D3Q27 (lattice units, c_s^2 = 1/3).
+ *   force      g(x, t) = g(x) s(t): an acceleration; the force density is rho g.
+ *   walls      halfway bounce-back (stationary no-slip wall midway between the last
+ *              fluid node and the next) on both faces of an axis, or periodic.
+ *
+ * Conventions for every entry point
+ *   - Returns LBM_OK (0) or a negative lbm_status; never aborts or throws.  After a
+ *     failure lbm_last_error() returns a thread-local message.
+ *   - Node index n = (z * ny + y) * nx + x (x fastest); N = nx * ny * nz (nz = 1 in 2-D).
+ *   - Host arrays passed in are read during the call only; the caller keeps them.
+ *     Output arrays are caller-allocated host memory.
+ *   - All device work is enqueued on the HIP stream given at init, in call order.
+ *     Calls that return host data (lbm_moments, lbm_get_populations, lbm_monitors)
+ *     synchronise that stream; lbm_step and lbm_set_populations do not.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Population order (shared with any external consumer of lbm_get_populations):
+ *   i = 0 rest, then pairs (e, -e):
+ *   D2Q9 : (1,0) (-1,0) (0,1) (0,-1) (1,1) (-1,-1) (1,-1) (-1,1)
+ *   D3Q19: +-x, +-y, +-z, +-(1,1,0), +-(1,-1,0), +-(1,0,1), +-(1,0,-1), +-(0,1,1), +-(0,1,-1)
+ *   D3Q27: D3Q19 then +-(1,1,1), +-(1,1,-1), +-(1,-1,1), +-(1,-1,-1)
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument or parameter combination */
+  LBM_ENOMEM = -2,     /* device or host allocation failed */
+  LBM_EDEVICE = -3,    /* a HIP call failed; message in lbm_last_error() */
+  LBM_ENONFINITE = -4, /* the monitors saw a NaN or Inf; the state is kept for inspection */
+  LBM_ESTATE = -5      /* NULL or wrong-kind context */
+} lbm_status;
+
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_lattice;
+typedef enum { LBM_BGK = 0, LBM_SMRT = 1 } lbm_collision;
+
+/* Storage of the populations in HBM and the arithmetic of the step.
+ *   LBM_F64          binary64 values of f-bar_i, binary64 arithmetic (reference mode).
+ *   LBM_F32          binary32 values of f-bar_i, binary32 arithmetic.
+ *   LBM_F32_SHIFTED  binary32 deviations f-bar_i - w_i rho0, binary32 arithmetic.
+ *   LBM_F16_SHIFTED  binary16 deviations f-bar_i - w_i rho0, binary32 arithmetic.
+ * Stores round to nearest-even.  Bytes per node and step: 2 Q sizeof(storage). */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32_SHIFTED = 2, LBM_F16_SHIFTED = 3 } lbm_storage;
+
+typedef enum { LBM_PERIODIC = 0, LBM_WALLS = 1 } lbm_bc;
+
+/* Acceleration field g(x):
+ *   LBM_G_UNIFORM  g_uniform[3] everywhere.
+ *   LBM_G_PROFILE  g depends on one coordinate: g_axis in {0,1,2}; g_data holds
+ *                  3 x n_axis doubles, component-major (gx[0..n), gy[0..n), gz[0..n)).
+ *   LBM_G_FIELD    g_data holds 3 x N doubles, component planes (gx[N], gy[N], gz[N]).
+ * 2-D lattices ignore the z component. */
+typedef enum { LBM_G_UNIFORM = 0, LBM_G_PROFILE = 1, LBM_G_FIELD = 2 } lbm_force_kind;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc returns
+ * device memory of at least `bytes` bytes aligned to 256 bytes, or NULL. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *user;
+} lbm_allocator;
+
+typedef struct {
+  int32_t lattice;     /* lbm_lattice */
+  int32_t collision;   /* lbm_collision */
+  int32_t storage;     /* lbm_storage */
+  int32_t nx, ny, nz;  /* nz must be 1 for D2Q9 */
+  int32_t bc[3];       /* lbm_bc per axis (both faces of the axis) */
+  /* tau-hat per Hermite order n (tau-hat = tau + 1/2 of Sec. II.B, omega_n = 1/tau-hat_n,
+   * viscosity (tau[2] - 1/2)/3).  BGK uses tau[2] only.  SMRT relaxes order 2 with
+   * tau[2] and order 3 with tau[3]; order 4 is trimmed, which is tau[4] == 1 (required).
+   * tau[0], tau[1] are ignored (mass and momentum are conserved).  Each used value > 1/2. */
+  double tau[5];
+  double rho0;         /* reference density: the shift of *_SHIFTED storage; default rho */
+  int32_t g_kind;      /* lbm_force_kind */
+  int32_t g_axis;      /* for LBM_G_PROFILE */
+  double g_uniform[3]; /* for LBM_G_UNIFORM */
+  const double *g_data;         /* host array, copied at init (see lbm_force_kind) */
+  int32_t monitor_every;        /* K >= 1: lbm_step updates the monitors every K steps; 0 = never */
+  const lbm_allocator *allocator; /* NULL: hipMalloc / hipFree */
+} lbm_params;
+
+/* Monitor record (binary64, summed on the device in a fixed order).
+ *   mass = sum rho, mom = sum rho u (physical u of eq:half_F), umax = max |u|,
+ *   resid = sqrt(sum |u(t) - u(t-1)|^2 / sum |u(t)|^2) over the nodes,
+ *   nonfinite = number of nodes whose rho or u is NaN or Inf.
+ * step is the time t the fields belong to (-1: never computed). */
+typedef struct {
+  int64_t step;
+  double mass, mom[3], umax, resid;
+  int64_t nonfinite;
+} lbm_monitors;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
+
+/* Create a lattice of the given parameters and set its state to the force-corrected
+ * equilibrium f-bar_i = f_eq_i(rho, u) - F_i(rho, u, g(x, 0))/2 (eq:newf with Omega = 0),
+ * whose density and physical velocity are exactly rho and u.
+ *   rho_init : N doubles, or NULL for rho0 everywhere.
+ *   u_init   : D x N doubles (component planes, D = 2 or 3), or NULL for rest.
+ *   hip_stream: a hipStream_t (NULL = the default stream).
+ * Errors: LBM_EINVAL (tau <= 1/2, SMRT with tau[4] != 1, nz != 1 on D2Q9, unknown
+ * enum, non-positive size, node count >= 2^31, missing g_data, rho0 <= 0),
+ * LBM_ENOMEM, LBM_EDEVICE.  On error *out is NULL. */
+int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init,
+             void *hip_stream, lbm_ctx **out);
+
+/* Advance n >= 0 steps.  g_scale: NULL (s(t) = 1) or n host doubles, the factor s(t)
+ * of g(x) for each step.  Enqueues work only (no synchronisation).  If monitor_every
+ * is K > 0 the monitors are refreshed after every step whose time is a multiple of K. */
+int lbm_step(lbm_ctx *c, int64_t n, const double *g_scale);
+
+/* Density and physical velocity u = j/rho + g s/2 (eq:half_F) of the current state,
+ * evaluated with acceleration g(x) * g_scale.  rho: N doubles or NULL; u: D x N doubles
+ * (component planes) or NULL.  Synchronises the stream. */
+int lbm_moments(lbm_ctx *c, double g_scale, double *rho, double *u);
+
+/* Refresh and return the monitor record of the current state (force scale of the last
+ * step, 1 before any step); resid compares with the state one step earlier when that
+ * was recorded, else 0.  Returns LBM_ENONFINITE if any node is not finite.
+ * Synchronises the stream. */
+int lbm_monitors_get(lbm_ctx *c, lbm_monitors *mon);
+
+/* Pre-collision populations f-bar_i(x, t) of the current state, values as stored
+ * (f-bar_i - w_i rho0 for *_SHIFTED storage) converted exactly to binary64.
+ *   nodes: nnodes node indices, or NULL for all N nodes in order (then nnodes == N).
+ *   out  : Q x nnodes doubles, population-major.  Synchronises the stream. */
+int lbm_get_populations(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double *out);
+
+/* Replace the state by the given pre-collision populations (Q x N doubles, as stored,
+ * population-major), rounded to the storage type (nearest-even). */
+int lbm_set_populations(lbm_ctx *c, const double *f);
+
+/* Simulation time t (number of steps taken since init or the last set_populations). */
+int lbm_time(const lbm_ctx *c, int64_t *t);
+
+/* Bytes of device memory the context holds. */
+int lbm_device_bytes(const lbm_ctx *c, size_t *bytes);
+
+int lbm_free(lbm_ctx *c);
+
+/* Stream-copy probe: dst[i] = src[i] for `bytes` bytes (multiple of 16) of device
+ * memory, enqueued `reps` times on hip_stream with the block size `block` (64..1024,
+ * multiple of 64; 0 = 256).  The measured read + write bandwidth of this copy is the
+ * practical HBM roofline the step is compared against. */
+int lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t reps, int32_t block,
+                   void *hip_stream);
+
+const char *lbm_strerror(int status);
+const char *lbm_last_error(void);
+int lbm_version(void); /* 100 * major + minor */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,269 @@
+// Kernels of the forced lattice-Boltzmann library (gfx950).
+//
+// Memory layout in HBM: structure of arrays, one plane of N values per population
+// (population-major, node index n = (z ny + y) nx + x, x fastest).  Two such buffers
+// alternate between steps.  The buffer a step writes holds, at slot (i, x), the
+// post-collision population f*_i(x, t); the next step pulls slot (i, x - e_i) into node
+// x (or, when x - e_i lies beyond a wall, slot (opp(i), x): halfway bounce-back).
+// Reads of each population plane are therefore row-contiguous with a one-element
+// x offset, writes are aligned and contiguous: every wavefront moves 64 consecutive
+// values per plane in each direction.
+//
+// A thread owns one node.  Blocks tile (x, y) rows with blockDim = (bx, by), one z
+// slice per blockIdx.z.  Each node is read and written once per step and no value is
+// reused by another block, so the block order carries no cache locality to exploit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm_node.h"
+
+namespace lbm {
+
+enum { GK_PROFILE = 0, GK_FIELD = 1 };
+
+struct Geom {
+  int nx, ny, nz, N;
+  int wall[3];
+};
+
+template <class T>
+struct ForceRef {
+  const T *tab;  // profile: 3 x n (component-major); field: 3 planes of N
+  int axis;      // profile: 0, 1, 2, or -1 (uniform, n = 1)
+  int n;
+  T scale;       // s(t)
+};
+
+template <class S, class T>
+__device__ __forceinline__ T load_as(const S *p) {
+  return T(*p);
+}
+template <class S, class T>
+__device__ __forceinline__ S store_as(T v) {
+  return S(v);
+}
+
+// Slot that node (x, y, z) pulls population i from: (i, x - e_i) with periodic wrap,
+// or (opp(i), x) when x - e_i crosses a wall face.
+template <class L, int i>
+__device__ __forceinline__ int64_t pull_slot(int x, int y, int z, const Geom &G,
+                                             int node) {
+  constexpr int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
+  int xs = x - ex, ys = y - ey, zs = z - ez;
+  bool bounce = false;
+  if constexpr (ex != 0) {
+    const bool o = (xs < 0) | (xs >= G.nx);
+    bounce |= o & (G.wall[0] != 0);
+    xs = (xs < 0) ? xs + G.nx : ((xs >= G.nx) ? xs - G.nx : xs);
+  }
+  if constexpr (ey != 0) {
+    const bool o = (ys < 0) | (ys >= G.ny);
+    bounce |= o & (G.wall[1] != 0);
+    ys = (ys < 0) ? ys + G.ny : ((ys >= G.ny) ? ys - G.ny : ys);
+  }
+  if constexpr (ez != 0) {
+    const bool o = (zs < 0) | (zs >= G.nz);
+    bounce |= o & (G.wall[2] != 0);
+    zs = (zs < 0) ? zs + G.nz : ((zs >= G.nz) ? zs - G.nz : zs);
+  }
+  const int src = (zs * G.ny + ys) * G.nx + xs;
+  return bounce ? (int64_t)L::OPP[i] * G.N + node : (int64_t)i * G.N + src;
+}
+
+template <class T, int GK>
+__device__ __forceinline__ void load_force(const ForceRef<T> &F, int x, int y, int z, int node,
+                                           int N, int D, T (&g)[3]) {
+  if constexpr (GK == GK_FIELD) {
+    for (int a = 0; a < 3; ++a) g[a] = (a < D) ? F.tab[(int64_t)a * N + node] * F.scale : T(0);
+  } else {
+    const int c = F.axis == 0 ? x : (F.axis == 1 ? y : (F.axis == 2 ? z : 0));
+    for (int a = 0; a < 3; ++a) g[a] = (a < D) ? F.tab[a * F.n + c] * F.scale : T(0);
+  }
+}
+
+template <class T>
+struct StepArgs {
+  const void *fin;
+  void *fout;
+  Geom geo;
+  ForceRef<T> force;
+  T shift;
+  T c0, c1;  // BGK: omega, 1 - omega/2;  SMRT: q2, q3
+};
+
+template <class L, int COLL, class S, class T, int GK>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.geo.nx || y >= a.geo.ny) return;
+  const int node = (z * a.geo.ny + y) * a.geo.nx + x;
+  const S *__restrict__ fin = static_cast<const S *>(a.fin);
+  S *__restrict__ fout = static_cast<S *>(a.fout);
+  T d[L::Q];
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    d[i] = load_as<S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, node));
+  });
+  T g[3];
+  load_force<T, GK>(a.force, x, y, z, node, a.geo.N, L::D, g);
+  if constexpr (COLL == 0) {
+    collide_bgk<L>(d, a.shift, g, BGKCoef<T>{a.c0, a.c1});
+  } else {
+    collide_smrt<L>(d, a.shift, g, SMRTCoef<T>{a.c0, a.c1});
+  }
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    fout[(int64_t)i * a.geo.N + node] = store_as<S, T>(d[i]);
+  });
+}
+
+// Initial state: compute f-bar(x, 0) at every node and place each population in the
+// slot the first step will pull it from.
+template <class L, int COLL, class S, class T, int GK>
+__global__ void __launch_bounds__(256) init_kernel(StepArgs<T> a, const double *rho,
+                                                   const double *u, int has_rho, int has_u,
+                                                   T rho0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.geo.nx || y >= a.geo.ny) return;
+  const int node = (z * a.geo.ny + y) * a.geo.nx + x;
+  const int N = a.geo.N;
+  T r = has_rho ? T(rho[node]) : rho0;
+  T uu[3];
+  for (int c = 0; c < 3; ++c) uu[c] = (has_u && c < L::D) ? T(u[(int64_t)c * N + node]) : T(0);
+  T g[3];
+  load_force<T, GK>(a.force, x, y, z, node, N, L::D, g);
+  T out[L::Q];
+  init_node<L, T, COLL>(r, uu, g, a.shift, out);
+  S *__restrict__ f = static_cast<S *>(a.fout);
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    f[pull_slot<L, i>(x, y, z, a.geo, node)] = store_as<S, T>(out[i]);
+  });
+}
+
+// Pre-collision populations at selected nodes (or all nodes), as stored, in binary64.
+template <class L, class S>
+__global__ void __launch_bounds__(256) gather_kernel(const S *__restrict__ f, Geom geo,
+                                                     const int64_t *nodes, int64_t nn,
+                                                     double *__restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nn) return;
+  const int node = nodes ? (int)nodes[j] : (int)j;
+  const int x = node % geo.nx;
+  const int y = (node / geo.nx) % geo.ny;
+  const int z = node / (geo.nx * geo.ny);
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    out[(int64_t)i * nn + j] = double(f[pull_slot<L, i>(x, y, z, geo, node)]);
+  });
+}
+
+template <class L, class S>
+__global__ void __launch_bounds__(256) scatter_kernel(S *__restrict__ f, Geom geo,
+                                                      const double *__restrict__ in) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= geo.N) return;
+  const int n = (int)node;
+  const int x = n % geo.nx;
+  const int y = (n / geo.nx) % geo.ny;
+  const int z = n / (geo.nx * geo.ny);
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const double v = in[(int64_t)i * geo.N + n];
+    if constexpr (std::is_same<S, double>::value)
+      f[pull_slot<L, i>(x, y, z, geo, n)] = v;
+    else
+      f[pull_slot<L, i>(x, y, z, geo, n)] = S(float(v));
+  });
+}
+
+// ---- monitors -------------------------------------------------------------------------
+// Slots of a block partial (binary64): mass, mom x/y/z, sum |du|^2, sum |u|^2, max |u|,
+// non-finite count.
+enum { MON_MASS = 0, MON_MX, MON_MY, MON_MZ, MON_DU2, MON_U2, MON_UMAX, MON_BAD, MON_SLOTS };
+enum { MOM_WRITE = 1, MOM_RECORD = 2, MOM_COMPARE = 4 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Density and physical velocity of the current state (pulled), optionally written out
+// (binary64), recorded into uprev, and reduced into per-block monitor partials.
+template <class L, class S, class T, int GK>
+__global__ void __launch_bounds__(256) moments_kernel(StepArgs<T> a, double *rho_out,
+                                                      double *u_out, T *uprev, int mode,
+                                                      double *partials) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  const bool live = (x < a.geo.nx) && (y < a.geo.ny);
+  double v[MON_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (live) {
+    const int node = (z * a.geo.ny + y) * a.geo.nx + x;
+    const int N = a.geo.N;
+    const S *__restrict__ fin = static_cast<const S *>(a.fin);
+    T d[L::Q];
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      d[i] = load_as<S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, node));
+    });
+    T g[3];
+    load_force<T, GK>(a.force, x, y, z, node, N, L::D, g);
+    const Macro<T> M = macroscopic<L>(d, a.shift, g);
+    if (mode & MOM_WRITE) {
+      if (rho_out) rho_out[node] = double(M.rho);
+      if (u_out)
+        for (int c = 0; c < L::D; ++c) u_out[(int64_t)c * N + node] = double(M.u[c]);
+    }
+    const double r = double(M.rho);
+    double u2 = 0, du2 = 0;
+    for (int c = 0; c < L::D; ++c) {
+      const double uc = double(M.u[c]);
+      u2 += uc * uc;
+      v[MON_MX + c] = r * uc;
+      if (mode & MOM_COMPARE) {
+        const double dd = uc - double(uprev[(int64_t)c * N + node]);
+        du2 += dd * dd;
+      }
+      if (mode & (MOM_RECORD | MOM_COMPARE)) uprev[(int64_t)c * N + node] = M.u[c];
+    }
+    v[MON_MASS] = r;
+    v[MON_DU2] = du2;
+    v[MON_U2] = u2;
+    v[MON_UMAX] = sqrt(u2);
+    const bool bad = !isfinite(r) || !isfinite(u2);
+    v[MON_BAD] = bad ? 1.0 : 0.0;
+    if (bad) v[MON_UMAX] = 0;
+  }
+  if (!partials) return;
+  __shared__ double red[4][MON_SLOTS];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int s = 0; s < MON_SLOTS; ++s) {
+    const double t = (s == MON_UMAX) ? wave_max(v[s]) : wave_sum(v[s]);
+    if (lane == 0) red[wave][s] = t;
+  }
+  __syncthreads();
+  if (tid < MON_SLOTS) {
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+    double acc = red[0][tid];
+    for (int w = 1; w < nw; ++w) acc = (tid == MON_UMAX) ? fmax(acc, red[w][tid]) : acc + red[w][tid];
+    const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    partials[b * MON_SLOTS + tid] = acc;
+  }
+}
+
+}  // namespace lbm

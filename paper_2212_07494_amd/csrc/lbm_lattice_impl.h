@@ -1,0 +1,142 @@
+// Launchers of one lattice's kernels; included once per lattice unit with LBM_LAT set
+// to the lattice struct (D2Q9, D3Q19, D3Q27) and LBM_OPS to the exported table name.
+#pragma once
+
+#include "lbm_internal.h"
+#include "lbm_kernels.h"
+
+namespace lbm {
+namespace impl {
+
+template <class T>
+inline StepArgs<T> make_args(const LaunchDesc &d) {
+  StepArgs<T> a;
+  a.fin = d.fin;
+  a.fout = d.fout;
+  a.geo.nx = d.geo.nx;
+  a.geo.ny = d.geo.ny;
+  a.geo.nz = d.geo.nz;
+  a.geo.N = d.geo.N;
+  for (int c = 0; c < 3; ++c) a.geo.wall[c] = d.geo.wall[c];
+  a.force.tab = static_cast<const T *>(d.gtab);
+  a.force.axis = d.g_axis;
+  a.force.n = d.g_n;
+  a.force.scale = T(d.gscale);
+  a.shift = T(d.shift);
+  a.c0 = T(d.c0);
+  a.c1 = T(d.c1);
+  return a;
+}
+
+inline Geom geom_of(const LaunchDesc &d) {
+  Geom g;
+  g.nx = d.geo.nx;
+  g.ny = d.geo.ny;
+  g.nz = d.geo.nz;
+  g.N = d.geo.N;
+  for (int c = 0; c < 3; ++c) g.wall[c] = d.geo.wall[c];
+  return g;
+}
+
+// storage mode -> (storage type S, arithmetic type T)
+template <class F>
+inline hipError_t with_types(int storage, F &&f) {
+  switch (storage) {
+    case 0: return f((double *)nullptr, (double *)nullptr);
+    case 1:
+    case 2: return f((float *)nullptr, (float *)nullptr);
+    case 3: return f((_Float16 *)nullptr, (float *)nullptr);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class L>
+struct Ops {
+  template <int COLL, class S, class T, int GK>
+  static hipError_t step_t(const LaunchDesc &d, hipStream_t s) {
+    hipLaunchKernelGGL((step_kernel<L, COLL, S, T, GK>), grid_of(d), dim3(d.bx, d.by), 0, s,
+                       make_args<T>(d));
+    return hipGetLastError();
+  }
+  static hipError_t step(const LaunchDesc &d, hipStream_t s) {
+    return with_types(d.storage, [&](auto *sp, auto *tp) -> hipError_t {
+      using S = std::remove_pointer_t<decltype(sp)>;
+      using T = std::remove_pointer_t<decltype(tp)>;
+      if (d.coll == 0)
+        return d.gk ? step_t<0, S, T, GK_FIELD>(d, s) : step_t<0, S, T, GK_PROFILE>(d, s);
+      return d.gk ? step_t<1, S, T, GK_FIELD>(d, s) : step_t<1, S, T, GK_PROFILE>(d, s);
+    });
+  }
+  template <int COLL, class S, class T, int GK>
+  static hipError_t init_t(const LaunchDesc &d, const double *rho, const double *u,
+                           double rho0, hipStream_t s) {
+    hipLaunchKernelGGL((init_kernel<L, COLL, S, T, GK>), grid_of(d), dim3(d.bx, d.by), 0, s,
+                       make_args<T>(d), rho, u, rho != nullptr, u != nullptr, T(rho0));
+    return hipGetLastError();
+  }
+  static hipError_t init(const LaunchDesc &d, const double *rho, const double *u, double rho0,
+                         hipStream_t s) {
+    return with_types(d.storage, [&](auto *sp, auto *tp) -> hipError_t {
+      using S = std::remove_pointer_t<decltype(sp)>;
+      using T = std::remove_pointer_t<decltype(tp)>;
+      if (d.coll == 0)
+        return d.gk ? init_t<0, S, T, GK_FIELD>(d, rho, u, rho0, s)
+                    : init_t<0, S, T, GK_PROFILE>(d, rho, u, rho0, s);
+      return d.gk ? init_t<1, S, T, GK_FIELD>(d, rho, u, rho0, s)
+                  : init_t<1, S, T, GK_PROFILE>(d, rho, u, rho0, s);
+    });
+  }
+  static hipError_t gather(const LaunchDesc &d, const int64_t *nodes, int64_t nn, double *out,
+                           hipStream_t s) {
+    if (nn <= 0) return hipSuccess;
+    return with_types(d.storage, [&](auto *sp, auto *) -> hipError_t {
+      using S = std::remove_pointer_t<decltype(sp)>;
+      const unsigned blocks = (unsigned)((nn + 255) / 256);
+      hipLaunchKernelGGL((gather_kernel<L, S>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<const S *>(d.fin), geom_of(d), nodes, nn, out);
+      return hipGetLastError();
+    });
+  }
+  static hipError_t scatter(const LaunchDesc &d, const double *in, hipStream_t s) {
+    return with_types(d.storage, [&](auto *sp, auto *) -> hipError_t {
+      using S = std::remove_pointer_t<decltype(sp)>;
+      const unsigned blocks = (unsigned)((d.geo.N + 255) / 256);
+      hipLaunchKernelGGL((scatter_kernel<L, S>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<S *>(d.fout), geom_of(d), in);
+      return hipGetLastError();
+    });
+  }
+  template <class S, class T, int GK>
+  static hipError_t moments_t(const LaunchDesc &d, double *rho, double *u, void *uprev, int mode,
+                              double *partials, hipStream_t s) {
+    hipLaunchKernelGGL((moments_kernel<L, S, T, GK>), grid_of(d), dim3(d.bx, d.by), 0, s,
+                       make_args<T>(d), rho, u, static_cast<T *>(uprev), mode, partials);
+    return hipGetLastError();
+  }
+  static hipError_t moments(const LaunchDesc &d, double *rho, double *u, void *uprev, int mode,
+                            double *partials, hipStream_t s) {
+    return with_types(d.storage, [&](auto *sp, auto *tp) -> hipError_t {
+      using S = std::remove_pointer_t<decltype(sp)>;
+      using T = std::remove_pointer_t<decltype(tp)>;
+      return d.gk ? moments_t<S, T, GK_FIELD>(d, rho, u, uprev, mode, partials, s)
+                  : moments_t<S, T, GK_PROFILE>(d, rho, u, uprev, mode, partials, s);
+    });
+  }
+};
+
+}  // namespace impl
+
+// Host function returning the launcher table (a host-only definition, so the device
+// compilation pass never references host launchers).
+const LatticeOps &LBM_OPS() {
+  static const LatticeOps ops = {LBM_LAT::D,
+                                 LBM_LAT::Q,
+                                 &impl::Ops<LBM_LAT>::step,
+                                 &impl::Ops<LBM_LAT>::init,
+                                 &impl::Ops<LBM_LAT>::gather,
+                                 &impl::Ops<LBM_LAT>::scatter,
+                                 &impl::Ops<LBM_LAT>::moments};
+  return ops;
+}
+
+}  // namespace lbm

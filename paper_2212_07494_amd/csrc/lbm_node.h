@@ -1,0 +1,326 @@
+// Per-node arithmetic of the forced lattice-Boltzmann step (device code, gfx950).
+//
+// Li, Duan & Shan, "Second-order force scheme for lattice Boltzmann method"
+// (arXiv 2212.07494).  Lattice units, c_s^2 = 1/3, Hermite polynomials written in
+// lattice units (H_m(e) = prod_a h_{m_a}(e_a), h_0 = 1, h_1 = e, h_2 = e^2 - 1/3).
+//
+// Everything here is templated on the lattice L (constants from lbm_tables.h) and the
+// arithmetic type T (double or float), and every loop runs over compile-time indices
+// (static_for), so the coefficient tables fold into immediates and zero coefficients
+// disappear.  The operation order is fixed and identical in both precisions:
+//   * each sum starts from -0.0 (the additive identity) and adds its non-zero terms
+//     in index order;
+//   * products of velocity components are formed left to right over x, y, z;
+//   * constants are exact rationals rounded once; no fused multiply-add (the
+//     library is compiled with -ffp-contract=off).
+// With T = double this reproduces an FP64 implementation written in that order
+// bit for bit.
+//
+// Populations are handled as deviations d_i = f-bar_i - w_i s from a constant shift
+// s (s = 0 for plain storage): the mass moment carries d-rho = sum_i d_i and
+// rho = s + d-rho, every other moment of d equals that of f-bar (sum_i w_i H_m = 0
+// for m != 0), and the reconstruction's rest coefficient multiplies d-rho, so the
+// same code serves plain and shifted storage and keeps full relative precision of
+// the small deviations in binary32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "lbm_tables.h"
+
+namespace lbm {
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  [&]<int... I>(std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+  }(std::make_integer_sequence<int, N>{});
+}
+
+// Constant tables in the arithmetic precision.
+template <class L, class T>
+struct Tab;
+template <class L>
+struct Tab<L, double> {
+  static constexpr double w(int i) { return L::W[i]; }
+  static constexpr double h(int k, int i) { return L::H[k][i]; }
+  static constexpr double minv(int i, int k) { return L::MINV[i][k]; }
+};
+template <class L>
+struct Tab<L, float> {
+  static constexpr float w(int i) { return L::Wf[i]; }
+  static constexpr float h(int k, int i) { return L::Hf[k][i]; }
+  static constexpr float minv(int i, int k) { return L::MINVf[i][k]; }
+};
+
+template <class T>
+struct Macro {
+  T drho, rho;
+  T u[3], F[3];
+};
+
+// Density, physical velocity and force density (Sec. II.B, eq:half_F and after):
+// rho-bar = rho, rho u-bar = rho u - F/2 with F = rho g, so u = j/rho + g/2.
+template <class L, class T>
+__device__ __forceinline__ Macro<T> macroscopic(const T (&d)[L::Q], T shift, const T (&g)[3]) {
+  Macro<T> M;
+  T s = T(-0.0);
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    s = s + d[i];
+  });
+  M.drho = s;
+  M.rho = shift + s;
+  static_for<L::D>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    T j = T(-0.0);
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int ea = L::E[i][a];
+      if constexpr (ea == 1) j = j + d[i];
+      if constexpr (ea == -1) j = j + (-d[i]);
+    });
+    M.u[a] = j / M.rho + T(0.5) * g[a];
+    M.F[a] = M.rho * g[a];
+  });
+  if constexpr (L::D == 2) {
+    M.u[2] = T(0);
+    M.F[2] = T(0);
+  }
+  return M;
+}
+
+// u^m = prod_a u_a^{m_a}, left to right over x, y, z starting from 1.
+template <class L, int K, class T>
+__device__ __forceinline__ T upow(const T (&u)[3]) {
+  T p = T(1);
+  static_for<3>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    static_for<L::MI[K][a]>([&](auto) { p = p * u[a]; });
+  });
+  return p;
+}
+
+template <class T>
+struct BGKCoef {
+  T omega, hforce;  // 1/tau-hat, 1 - omega/2
+};
+template <class T>
+struct SMRTCoef {
+  T q2, q3;  // 1 - omega_n for orders 2 and 3
+};
+
+// BGK with the second-order force term (Sec. II.B, eq:explict_eq):
+//   f*_i = f_i - omega (f_i - f_eq_i) + (1 - omega/2) F_i
+//   f_eq_i = w_i (rho + rho P_i),  P_i = (3 e.u + 4.5 (e.u)^2) - 1.5 u.u
+//   F_i   = w_i (3 (e.F - u.F) + 9 (e.F)(e.u))
+// (the truncated Hermite equilibrium and the second-order force, c_s^2 = 1/3).  In
+// deviation form the leading rho of f_eq becomes d-rho.
+template <class L, class T>
+__device__ __forceinline__ void collide_bgk(T (&d)[L::Q], T shift, const T (&g)[3],
+                                            const BGKCoef<T> &c) {
+  const Macro<T> M = macroscopic<L>(d, shift, g);
+  T usq = T(-0.0), uF = T(-0.0);
+  static_for<L::D>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    usq = usq + M.u[a] * M.u[a];
+  });
+  static_for<L::D>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    uF = uF + M.u[a] * M.F[a];
+  });
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    T eu = T(-0.0), eF = T(-0.0);
+    static_for<3>([&](auto A) {
+      constexpr int a = decltype(A)::value;
+      constexpr int ea = L::E[i][a];
+      if constexpr (ea == 1) {
+        eu = eu + M.u[a];
+        eF = eF + M.F[a];
+      }
+      if constexpr (ea == -1) {
+        eu = eu + (-M.u[a]);
+        eF = eF + (-M.F[a]);
+      }
+    });
+    constexpr T wi = Tab<L, T>::w(i);
+    const T P = (T(3) * eu + T(4.5) * (eu * eu)) - T(1.5) * usq;
+    const T feq = wi * (M.drho + M.rho * P);
+    const T G = T(3) * (eF - uF) + T(9) * (eF * eu);
+    const T Fi = wi * G;
+    d[i] = (d[i] - c.omega * (d[i] - feq)) + c.hforce * Fi;
+  });
+}
+
+// Reconstruction f_i = sum_k MINV[i][k] a_k over the moments of order <= 4
+// (reconstruction after eq:bbd1; orders 5 and 6 of D3Q27 are zero).
+template <class L, class T>
+__device__ __forceinline__ void reconstruct(const T (&a)[L::NM], T (&out)[L::Q]) {
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    T acc = T(-0.0);
+    static_for<L::NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr T c = Tab<L, T>::minv(i, k);
+      if constexpr (c != T(0) && L::ORD[k] <= 4) acc = acc + c * a[k];
+    });
+    out[i] = acc;
+  });
+}
+
+// SMRT with the force in the first central moment (Sec. II.C, eq:domg, eq:RHS, eq:bbd1):
+//   A_m = sum_i d_i H_m(e_i)                         (orders 2, 3; eq:dft)
+//   N_m = A_m - rho u^m,  N_{e_a} = -F_a/2             (non-equilibrium raw moments)
+//   D_m = sum_{l <= m} C(m,l) (-u)^l N_{m-l}           (shift to the frame moving with u)
+//   P_m = (1 - omega_|m|) D_m (|m| = 2, 3), P_{e_a} = F_a/2, order 4 trimmed
+//   R_m = sum_{l <= m} C(m,l) u^l P_{m-l}              (back to raw moments, |m| <= 4)
+//   a*_m = rho u^m + R_m (|m| <= 4), a*_0 = d-rho;  f* = MINV a*
+template <class L, class T>
+__device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)[3],
+                                             const SMRTCoef<T> &c) {
+  constexpr int NM = L::NM;
+  const Macro<T> M = macroscopic<L>(d, shift, g);
+  T U[NM], E[NM], N[NM], P[NM], A[NM];
+  static_for<NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    U[k] = upow<L, k>(M.u);
+    E[k] = M.rho * U[k];
+  });
+  static_for<NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int n = L::ORD[k];
+    if constexpr (n == 1) {
+      constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
+      N[k] = T(-0.5) * M.F[a];
+    } else if constexpr (n == 2 || n == 3) {
+      T acc = T(-0.0);
+      static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr T h = Tab<L, T>::h(k, i);
+        if constexpr (h != T(0)) acc = acc + h * d[i];
+      });
+      N[k] = acc - E[k];
+    } else {
+      N[k] = T(0);
+    }
+  });
+  static_for<NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int n = L::ORD[k];
+    if constexpr (n == 1) {
+      constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
+      P[k] = T(0.5) * M.F[a];
+    } else if constexpr (n == 2 || n == 3) {
+      T Dm = N[k];
+      static_for<L::NT[k]>([&](auto Tt) {
+        constexpr int t = decltype(Tt)::value;
+        constexpr int kl = L::TL[k][t], km = L::TM[k][t];
+        Dm = Dm + T(L::CDN[k][t]) * (U[kl] * N[km]);
+      });
+      P[k] = (n == 2 ? c.q2 : c.q3) * Dm;
+    } else {
+      P[k] = T(0);
+    }
+  });
+  static_for<NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int n = L::ORD[k];
+    if constexpr (n == 0) {
+      A[k] = M.drho;
+    } else if constexpr (n > 4) {
+      A[k] = T(0);
+    } else {
+      T R = (n <= 3) ? P[k] : T(-0.0);
+      static_for<L::NT[k]>([&](auto Tt) {
+        constexpr int t = decltype(Tt)::value;
+        constexpr int kl = L::TL[k][t], km = L::TM[k][t];
+        if constexpr (L::ORD[km] <= 3) R = R + T(L::CUP[k][t]) * (U[kl] * P[km]);
+      });
+      A[k] = E[k] + R;
+    }
+  });
+  reconstruct<L>(A, d);
+}
+
+// Initial stored state f-bar = f_eq - F_i/2 (eq:newf with Omega = 0): density and
+// physical velocity are then exactly rho and u.  BGK: its second-order equilibrium
+// and force term.  SMRT: equilibrium moments rho u^m and raw force moments
+// a_F,m = sum_a m_a u^{m-e_a} F_a (the appendix's a_F^(1..4) at theta = 1), |m| <= 4.
+template <class L, class T, int COLL>
+__device__ __forceinline__ void init_node(T rho, const T (&u)[3], const T (&g)[3], T shift,
+                                          T (&out)[L::Q]) {
+  T F[3];
+  static_for<3>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    F[a] = rho * g[a];
+  });
+  const T drho = rho - shift;
+  if constexpr (COLL == 0) {
+    T usq = T(-0.0), uF = T(-0.0);
+    static_for<L::D>([&](auto A) {
+      constexpr int a = decltype(A)::value;
+      usq = usq + u[a] * u[a];
+    });
+    static_for<L::D>([&](auto A) {
+      constexpr int a = decltype(A)::value;
+      uF = uF + u[a] * F[a];
+    });
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      T eu = T(-0.0), eF = T(-0.0);
+      static_for<3>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        constexpr int ea = L::E[i][a];
+        if constexpr (ea == 1) {
+          eu = eu + u[a];
+          eF = eF + F[a];
+        }
+        if constexpr (ea == -1) {
+          eu = eu + (-u[a]);
+          eF = eF + (-F[a]);
+        }
+      });
+      constexpr T wi = Tab<L, T>::w(i);
+      const T P = (T(3) * eu + T(4.5) * (eu * eu)) - T(1.5) * usq;
+      const T feq = wi * (drho + rho * P);
+      const T G = T(3) * (eF - uF) + T(9) * (eF * eu);
+      out[i] = feq - T(0.5) * (wi * G);
+    });
+  } else {
+    constexpr int NM = L::NM;
+    T a[NM];
+    static_for<NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr int n = L::ORD[k];
+      if constexpr (n == 0) {
+        a[k] = drho;
+      } else if constexpr (n > 4) {
+        a[k] = T(0);
+      } else {
+        T aF = T(-0.0);
+        static_for<3>([&](auto A) {
+          constexpr int al = decltype(A)::value;
+          constexpr int ma = L::MI[k][al];
+          if constexpr (ma > 0) {
+            // u^{m - e_al}
+            T p = T(1);
+            static_for<3>([&](auto B) {
+              constexpr int b = decltype(B)::value;
+              constexpr int mb = L::MI[k][b] - (b == al ? 1 : 0);
+              static_for<mb>([&](auto) { p = p * u[b]; });
+            });
+            aF = aF + T(ma) * (p * F[al]);
+          }
+        });
+        a[k] = rho * upow<L, k>(u) - T(0.5) * aF;
+      }
+    });
+    reconstruct<L>(a, out);
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,503 @@
+// C-ABI runtime of the forced lattice-Boltzmann library: parameter validation, device
+// memory, dispatch to the per-lattice kernels, monitors and data transfer.
+// The declarations and their contracts are in include/lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(LBM_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                              \
+  } while (0)
+
+constexpr uint32_t kMagic = 0x4c424d31u;  // "LBM1"
+
+size_t storage_bytes(int s) { return s == LBM_F64 ? 8 : (s == LBM_F16_SHIFTED ? 2 : 4); }
+size_t arith_bytes(int s) { return s == LBM_F64 ? 8 : 4; }
+bool shifted(int s) { return s == LBM_F32_SHIFTED || s == LBM_F16_SHIFTED; }
+
+const lbm::LatticeOps &ops_for(int lattice) {
+  switch (lattice) {
+    case LBM_D2Q9: return lbm::ops_d2q9();
+    case LBM_D3Q19: return lbm::ops_d3q19();
+    default: return lbm::ops_d3q27();
+  }
+}
+
+// Block shape: 64-wide rows (one wavefront per row segment), up to 256 threads.
+void block_shape(int nx, int &bx, int &by) {
+  bx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
+  by = 256 / bx;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  uint32_t magic = kMagic;
+  lbm_params p{};
+  const lbm::LatticeOps *ops = nullptr;
+  int D = 0, Q = 0;
+  int64_t N = 0;
+  hipStream_t stream = nullptr;
+  lbm_allocator alloc{};
+  bool own_alloc = true;
+  void *buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  void *gtab = nullptr;
+  int g_n = 1, g_axis = -1, gk = 0;
+  void *uprev = nullptr;
+  int64_t uprev_time = -2;
+  double *partials = nullptr;
+  int64_t nblocks = 0;
+  double *mon_dev = nullptr;
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  size_t bytes = 0;
+  int64_t t = 0;
+  double last_scale = 1.0;
+  double c0 = 0, c1 = 0, shift = 0;
+  int bx = 64, by = 4;
+  lbm_monitors mon{};
+
+  int dalloc(void **ptr, size_t n) {
+    *ptr = nullptr;
+    if (n == 0) n = 256;
+    if (alloc.alloc) {
+      *ptr = alloc.alloc(n, alloc.user);
+      if (!*ptr) return fail(LBM_ENOMEM, "allocator returned NULL for %zu bytes", n);
+    } else {
+      hipError_t e = hipMalloc(ptr, n);
+      if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "hipMalloc(%zu): %s", n,
+                    hipGetErrorString(e));
+      }
+    }
+    bytes += n;
+    return LBM_OK;
+  }
+  void dfree(void *ptr) {
+    if (!ptr) return;
+    if (alloc.free)
+      alloc.free(ptr, alloc.user);
+    else if (!alloc.alloc)
+      (void)hipFree(ptr);
+  }
+  int need_scratch(size_t n) {
+    if (n <= scratch_bytes) return LBM_OK;
+    // the stream may still use the old scratch
+    HIP_TRY(hipStreamSynchronize(stream));
+    dfree(scratch);
+    bytes -= scratch_bytes;
+    scratch = nullptr;
+    scratch_bytes = 0;
+    int rc = dalloc(&scratch, n);
+    if (rc) return rc;
+    scratch_bytes = n;
+    return LBM_OK;
+  }
+  lbm::LaunchDesc desc(double gscale) const {
+    lbm::LaunchDesc d{};
+    d.coll = p.collision;
+    d.storage = p.storage;
+    d.gk = gk;
+    d.fin = buf[cur];
+    d.fout = buf[cur ^ 1];
+    d.geo.nx = p.nx;
+    d.geo.ny = p.ny;
+    d.geo.nz = p.nz;
+    d.geo.N = (int)N;
+    for (int a = 0; a < 3; ++a) d.geo.wall[a] = p.bc[a] == LBM_WALLS;
+    d.gtab = gtab;
+    d.g_axis = g_axis;
+    d.g_n = g_n;
+    d.gscale = gscale;
+    d.shift = shift;
+    d.c0 = c0;
+    d.c1 = c1;
+    d.bx = bx;
+    d.by = by;
+    return d;
+  }
+};
+
+namespace {
+
+bool valid(const lbm_ctx *c) { return c && c->magic == kMagic; }
+
+int validate(const lbm_params *p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->lattice < LBM_D2Q9 || p->lattice > LBM_D3Q27)
+    return fail(LBM_EINVAL, "unknown lattice %d", p->lattice);
+  if (p->collision != LBM_BGK && p->collision != LBM_SMRT)
+    return fail(LBM_EINVAL, "unknown collision %d", p->collision);
+  if (p->storage < LBM_F64 || p->storage > LBM_F16_SHIFTED)
+    return fail(LBM_EINVAL, "unknown storage %d", p->storage);
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0)
+    return fail(LBM_EINVAL, "sizes must be positive (%d, %d, %d)", p->nx, p->ny, p->nz);
+  if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+  if (p->ny > 65535 || p->nz > 65535) return fail(LBM_EINVAL, "ny and nz must be <= 65535");
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  if (N >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "node count %lld >= 2^31", (long long)N);
+  for (int a = 0; a < 3; ++a)
+    if (p->bc[a] != LBM_PERIODIC && p->bc[a] != LBM_WALLS)
+      return fail(LBM_EINVAL, "unknown boundary kind %d on axis %d", p->bc[a], a);
+  if (!(p->tau[2] > 0.5) || !std::isfinite(p->tau[2]))
+    return fail(LBM_EINVAL, "tau[2] = %g must exceed 1/2", p->tau[2]);
+  if (p->collision == LBM_SMRT) {
+    if (!(p->tau[3] > 0.5) || !std::isfinite(p->tau[3]))
+      return fail(LBM_EINVAL, "tau[3] = %g must exceed 1/2", p->tau[3]);
+    if (p->tau[4] != 1.0)
+      return fail(LBM_EINVAL, "SMRT trims order 4: tau[4] must be 1 (got %g)", p->tau[4]);
+  }
+  if (!(p->rho0 > 0) || !std::isfinite(p->rho0))
+    return fail(LBM_EINVAL, "rho0 = %g must be positive", p->rho0);
+  if (p->g_kind < LBM_G_UNIFORM || p->g_kind > LBM_G_FIELD)
+    return fail(LBM_EINVAL, "unknown force kind %d", p->g_kind);
+  if (p->g_kind == LBM_G_PROFILE && (p->g_axis < 0 || p->g_axis > 2))
+    return fail(LBM_EINVAL, "profile axis %d", p->g_axis);
+  if (p->g_kind != LBM_G_UNIFORM && !p->g_data)
+    return fail(LBM_EINVAL, "g_data is NULL for a profile or field force");
+  if (p->monitor_every < 0) return fail(LBM_EINVAL, "monitor_every must be >= 0");
+  if (p->allocator && (!p->allocator->alloc || !p->allocator->free))
+    return fail(LBM_EINVAL, "allocator needs both alloc and free");
+  return LBM_OK;
+}
+
+template <class T>
+void convert(const double *src, size_t n, std::vector<unsigned char> &out) {
+  out.resize(n * sizeof(T));
+  T *o = reinterpret_cast<T *>(out.data());
+  for (size_t i = 0; i < n; ++i) o[i] = static_cast<T>(src[i]);
+}
+
+void release(lbm_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  c->dfree(c->buf[0]);
+  c->dfree(c->buf[1]);
+  c->dfree(c->gtab);
+  c->dfree(c->uprev);
+  c->dfree(c->partials);
+  c->dfree(c->mon_dev);
+  c->dfree(c->scratch);
+  c->magic = 0;
+  delete c;
+}
+
+}  // namespace
+
+// Monitor finalisation and the stream-copy probe (lbm_aux.hip).
+namespace lbm {
+hipError_t finalize_monitors(const double *partials, int64_t nb, double *out, hipStream_t s);
+hipError_t copy_probe(const void *src, void *dst, size_t bytes, int reps, int block,
+                      hipStream_t s);
+}  // namespace lbm
+
+namespace {
+
+int refresh_monitors(lbm_ctx *c, int mode) {
+  lbm::LaunchDesc d = c->desc(c->last_scale);
+  HIP_TRY(c->ops->moments(d, nullptr, nullptr, c->uprev, mode, c->partials, c->stream));
+  HIP_TRY(lbm::finalize_monitors(c->partials, c->nblocks, c->mon_dev, c->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_version(void) { return 100; }
+
+const char *lbm_strerror(int status) {
+  switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory";
+    case LBM_EDEVICE: return "device error";
+    case LBM_ENONFINITE: return "non-finite value in the state";
+    case LBM_ESTATE: return "invalid context";
+    default: return "unknown status";
+  }
+}
+
+const char *lbm_last_error(void) { return g_last_error.c_str(); }
+
+int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, void *hip_stream,
+             lbm_ctx **out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_ENOMEM, "host allocation of the context failed");
+  c->p = *p;
+  c->p.g_data = nullptr;
+  if (p->allocator) c->alloc = *p->allocator;
+  c->ops = &ops_for(p->lattice);
+  c->D = c->ops->D;
+  c->Q = c->ops->Q;
+  c->N = (int64_t)p->nx * p->ny * p->nz;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->shift = shifted(p->storage) ? p->rho0 : 0.0;
+  if (p->collision == LBM_BGK) {
+    const double om = 1.0 / p->tau[2];
+    c->c0 = om;
+    c->c1 = 1.0 - 0.5 * om;
+  } else {
+    c->c0 = 1.0 - 1.0 / p->tau[2];
+    c->c1 = 1.0 - 1.0 / p->tau[3];
+  }
+  block_shape(p->nx, c->bx, c->by);
+  const dim3 grid((p->nx + c->bx - 1) / c->bx, (p->ny + c->by - 1) / c->by, p->nz);
+  c->nblocks = (int64_t)grid.x * grid.y * grid.z;
+
+  const size_t pop_bytes = (size_t)c->Q * (size_t)c->N * storage_bytes(p->storage);
+  const size_t ab = arith_bytes(p->storage);
+  // force table, in the arithmetic type
+  std::vector<double> gh;
+  if (p->g_kind == LBM_G_UNIFORM) {
+    c->g_axis = -1;
+    c->g_n = 1;
+    gh.assign(p->g_uniform, p->g_uniform + 3);
+  } else if (p->g_kind == LBM_G_PROFILE) {
+    c->g_axis = p->g_axis;
+    c->g_n = p->g_axis == 0 ? p->nx : (p->g_axis == 1 ? p->ny : p->nz);
+    gh.assign(p->g_data, p->g_data + 3 * (size_t)c->g_n);
+  } else {
+    c->gk = 1;
+    c->g_axis = -1;
+    c->g_n = (int)c->N;
+    gh.assign(p->g_data, p->g_data + 3 * (size_t)c->N);
+  }
+  for (double v : gh)
+    if (!std::isfinite(v)) {
+      delete c;
+      return fail(LBM_EINVAL, "non-finite acceleration value");
+    }
+  std::vector<unsigned char> gconv;
+  if (ab == 8)
+    convert<double>(gh.data(), gh.size(), gconv);
+  else
+    convert<float>(gh.data(), gh.size(), gconv);
+
+  if ((rc = c->dalloc(&c->buf[0], pop_bytes)) || (rc = c->dalloc(&c->buf[1], pop_bytes)) ||
+      (rc = c->dalloc(&c->gtab, gconv.size())) ||
+      (rc = c->dalloc(&c->uprev, 3 * (size_t)c->N * ab)) ||
+      (rc = c->dalloc((void **)&c->partials, (size_t)c->nblocks * 8 * sizeof(double))) ||
+      (rc = c->dalloc((void **)&c->mon_dev, 8 * sizeof(double)))) {
+    std::string msg = g_last_error;
+    release(c);
+    return fail(rc, "%s", msg.c_str());
+  }
+  auto bail = [&](int code) {
+    std::string msg = g_last_error;
+    release(c);
+    return fail(code, "%s", msg.c_str());
+  };
+  if (hipMemcpyAsync(c->gtab, gconv.data(), gconv.size(), hipMemcpyHostToDevice, c->stream) !=
+      hipSuccess)
+    return bail(fail(LBM_EDEVICE, "uploading the force table failed"));
+  // upload initial fields
+  const size_t fld = (size_t)c->N * sizeof(double);
+  if ((rho_init || u_init) && (rc = c->need_scratch(fld * (1 + c->D)))) return bail(rc);
+  double *rho_d = nullptr, *u_d = nullptr;
+  if (rho_init) {
+    for (int64_t n = 0; n < c->N; ++n)
+      if (!(rho_init[n] > 0) || !std::isfinite(rho_init[n]))
+        return bail(fail(LBM_EINVAL, "rho_init[%lld] = %g is not a positive finite density",
+                         (long long)n, rho_init[n]));
+    rho_d = static_cast<double *>(c->scratch);
+    if (hipMemcpyAsync(rho_d, rho_init, fld, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return bail(fail(LBM_EDEVICE, "uploading rho_init failed"));
+  }
+  if (u_init) {
+    for (int64_t n = 0; n < (int64_t)c->D * c->N; ++n)
+      if (!std::isfinite(u_init[n])) return bail(fail(LBM_EINVAL, "non-finite u_init value"));
+    u_d = reinterpret_cast<double *>(static_cast<char *>(c->scratch) + fld);
+    if (hipMemcpyAsync(u_d, u_init, fld * c->D, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return bail(fail(LBM_EDEVICE, "uploading u_init failed"));
+  }
+  lbm::LaunchDesc d = c->desc(1.0);
+  d.fout = c->buf[0];
+  if (c->ops->init(d, rho_d, u_d, p->rho0, c->stream) != hipSuccess)
+    return bail(fail(LBM_EDEVICE, "init kernel launch failed"));
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(fail(LBM_EDEVICE, "init failed: %s", hipGetErrorString(hipGetLastError())));
+  c->cur = 0;
+  c->t = 0;
+  c->mon.step = -1;
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t n, const double *g_scale) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (n < 0) return fail(LBM_EINVAL, "negative step count");
+  const int K = c->p.monitor_every;
+  for (int64_t s = 0; s < n; ++s) {
+    const double sc = g_scale ? g_scale[s] : 1.0;
+    if (!std::isfinite(sc)) return fail(LBM_EINVAL, "g_scale[%lld] is not finite", (long long)s);
+    lbm::LaunchDesc d = c->desc(sc);
+    HIP_TRY(c->ops->step(d, c->stream));
+    c->cur ^= 1;
+    c->t += 1;
+    c->last_scale = sc;
+    if (K > 0) {
+      if ((c->t + 1) % K == 0) {
+        int rc = refresh_monitors(c, 2 /* record */);
+        if (rc) return rc;
+        c->uprev_time = c->t;
+      } else if (c->t % K == 0) {
+        const int mode = (c->uprev_time == c->t - 1) ? 4 : 2;
+        int rc = refresh_monitors(c, mode);
+        if (rc) return rc;
+        c->uprev_time = c->t;
+        c->mon.step = c->t;
+      }
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_monitors_get(lbm_ctx *c, lbm_monitors *mon) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!mon) return fail(LBM_EINVAL, "mon is NULL");
+  const int mode = (c->uprev_time == c->t - 1) ? 4 : 2;
+  int rc = refresh_monitors(c, mode);
+  if (rc) return rc;
+  c->uprev_time = c->t;
+  double h[8];
+  HIP_TRY(hipMemcpyAsync(h, c->mon_dev, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  lbm_monitors m{};
+  m.step = c->t;
+  m.mass = h[0];
+  m.mom[0] = h[1];
+  m.mom[1] = h[2];
+  m.mom[2] = h[3];
+  m.resid = (mode == 4 && h[5] > 0) ? std::sqrt(h[4] / h[5]) : 0.0;
+  m.umax = h[6];
+  m.nonfinite = (int64_t)h[7];
+  c->mon = m;
+  *mon = m;
+  if (m.nonfinite) return fail(LBM_ENONFINITE, "%lld nodes are not finite", (long long)m.nonfinite);
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx *c, double g_scale, double *rho, double *u) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!std::isfinite(g_scale)) return fail(LBM_EINVAL, "g_scale is not finite");
+  const size_t fld = (size_t)c->N * sizeof(double);
+  int rc = c->need_scratch(fld * (1 + c->D));
+  if (rc) return rc;
+  double *rho_d = static_cast<double *>(c->scratch);
+  double *u_d = reinterpret_cast<double *>(static_cast<char *>(c->scratch) + fld);
+  lbm::LaunchDesc d = c->desc(g_scale);
+  HIP_TRY(c->ops->moments(d, rho_d, u_d, nullptr, 1, nullptr, c->stream));
+  if (rho) HIP_TRY(hipMemcpyAsync(rho, rho_d, fld, hipMemcpyDeviceToHost, c->stream));
+  if (u) HIP_TRY(hipMemcpyAsync(u, u_d, fld * c->D, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double *out) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  if (!nodes && nnodes != c->N) return fail(LBM_EINVAL, "nodes NULL requires nnodes == N");
+  if (nnodes < 0) return fail(LBM_EINVAL, "negative node count");
+  if (nnodes == 0) return LBM_OK;
+  if (nodes)
+    for (int64_t j = 0; j < nnodes; ++j)
+      if (nodes[j] < 0 || nodes[j] >= c->N)
+        return fail(LBM_EINVAL, "node index %lld out of range", (long long)nodes[j]);
+  const size_t outb = (size_t)c->Q * nnodes * sizeof(double);
+  const size_t idxb = nodes ? (size_t)nnodes * sizeof(int64_t) : 0;
+  int rc = c->need_scratch(outb + idxb);
+  if (rc) return rc;
+  double *out_d = static_cast<double *>(c->scratch);
+  int64_t *idx_d = nodes ? reinterpret_cast<int64_t *>(static_cast<char *>(c->scratch) + outb)
+                         : nullptr;
+  if (nodes) HIP_TRY(hipMemcpyAsync(idx_d, nodes, idxb, hipMemcpyHostToDevice, c->stream));
+  lbm::LaunchDesc d = c->desc(1.0);
+  HIP_TRY(c->ops->gather(d, idx_d, nnodes, out_d, c->stream));
+  HIP_TRY(hipMemcpyAsync(out, out_d, outb, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx *c, const double *f) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!f) return fail(LBM_EINVAL, "f is NULL");
+  const size_t inb = (size_t)c->Q * c->N * sizeof(double);
+  int rc = c->need_scratch(inb);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(c->scratch, f, inb, hipMemcpyHostToDevice, c->stream));
+  lbm::LaunchDesc d = c->desc(1.0);
+  d.fout = c->buf[c->cur];
+  HIP_TRY(c->ops->scatter(d, static_cast<const double *>(c->scratch), c->stream));
+  // the host array may be released once this returns
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->t = 0;
+  c->uprev_time = -2;
+  return LBM_OK;
+}
+
+int lbm_time(const lbm_ctx *c, int64_t *t) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!t) return fail(LBM_EINVAL, "t is NULL");
+  *t = c->t;
+  return LBM_OK;
+}
+
+int lbm_device_bytes(const lbm_ctx *c, size_t *bytes) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  *bytes = c->bytes;
+  return LBM_OK;
+}
+
+int lbm_free(lbm_ctx *c) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  release(c);
+  return LBM_OK;
+}
+
+int lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t reps, int32_t block,
+                   void *hip_stream) {
+  if (!src || !dst) return fail(LBM_EINVAL, "NULL buffer");
+  if (bytes % 16) return fail(LBM_EINVAL, "bytes must be a multiple of 16");
+  if (reps < 0) return fail(LBM_EINVAL, "negative repetition count");
+  if (block == 0) block = 256;
+  if (block < 64 || block > 1024 || block % 64) return fail(LBM_EINVAL, "block %d", block);
+  HIP_TRY(lbm::copy_probe(src, dst, bytes, reps, block, static_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,303 @@
+"""ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function keeps the C name.  All lattice work runs in the HIP library
+``liblbm.so`` next to this file; if that library is missing, loading fails with an
+error (there is no fallback).  Build it with ``python -m paper_2212_07494_amd.build``.
+
+Arrays: NumPy float64, node index n = (z*ny + y)*nx + x (x fastest); vector fields
+are (D, N) component planes; populations are (Q, N).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
+COLLISIONS = {"bgk": 0, "smrt": 1}
+STORAGES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3}
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f32s": 4, "f16s": 2}
+QOF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+G_UNIFORM, G_PROFILE, G_FIELD = 0, 1, 2
+PERIODIC, WALLS = 0, 1
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"lbm status {status}: {message}")
+        self.status = status
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class lbm_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+class lbm_params(C.Structure):
+    _fields_ = [("lattice", C.c_int32), ("collision", C.c_int32), ("storage", C.c_int32),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("bc", C.c_int32 * 3), ("tau", C.c_double * 5), ("rho0", C.c_double),
+                ("g_kind", C.c_int32), ("g_axis", C.c_int32), ("g_uniform", C.c_double * 3),
+                ("g_data", C.c_void_p), ("monitor_every", C.c_int32),
+                ("allocator", C.POINTER(lbm_allocator))]
+
+
+class lbm_monitors(C.Structure):
+    _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("mom", C.c_double * 3),
+                ("umax", C.c_double), ("resid", C.c_double), ("nonfinite", C.c_int64)]
+
+    def as_dict(self):
+        return dict(step=self.step, mass=self.mass, mom=list(self.mom), umax=self.umax,
+                    resid=self.resid, nonfinite=self.nonfinite)
+
+
+EXPORTS = {
+    "lbm_init": ([C.POINTER(lbm_params), C.c_void_p, C.c_void_p, C.c_void_p,
+                  C.POINTER(C.c_void_p)], C.c_int),
+    "lbm_step": ([C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+    "lbm_moments": ([C.c_void_p, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_monitors_get": ([C.c_void_p, C.POINTER(lbm_monitors)], C.c_int),
+    "lbm_get_populations": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_set_populations": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_time": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
+    "lbm_device_bytes": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
+    "lbm_free": ([C.c_void_p], C.c_int),
+    "lbm_copy_probe": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_int32, C.c_void_p],
+                       C.c_int),
+    "lbm_strerror": ([C.c_int], C.c_char_p),
+    "lbm_last_error": ([], C.c_char_p),
+    "lbm_version": ([], C.c_int),
+}
+
+_lib = None
+
+
+def load():
+    """Load liblbm.so (raises OSError if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"{LIB_PATH} is not built; run python -m paper_2212_07494_amd.build")
+        lib = C.CDLL(LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != LBM_OK:
+        msg = load().lbm_last_error().decode(errors="replace")
+        raise LBMError(rc, msg)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)  # torch.cuda.Stream
+
+
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator (uint8 tensors kept
+    alive until the library frees them)."""
+
+    def __init__(self, device="cuda"):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+
+        def _alloc(nbytes, user):
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+            p = t.data_ptr()
+            self.live[p] = t
+            return p
+
+        def _free(ptr, user):
+            self.live.pop(ptr, None)
+
+        self._a = ALLOC_FN(_alloc)
+        self._f = FREE_FN(_free)
+        self.struct = lbm_allocator(self._a, self._f, None)
+
+
+# ---- C-ABI functions ------------------------------------------------------------------
+
+def make_params(lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1), bc=(0, 0, 0),
+                tau=(0.8, 0.8, 1.0), rho0=1.0, g=None, g_profile=None, g_field=None,
+                monitor_every=0, allocator=None):
+    """Fill an lbm_params.  g: uniform (3,) acceleration; g_profile: (axis, (3, n) table);
+    g_field: (3, N) array.  Returned together with the arrays it points to (keep both)."""
+    nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+    p = lbm_params()
+    p.lattice = LATTICES[lattice]
+    p.collision = COLLISIONS[collision]
+    p.storage = STORAGES[storage]
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.bc = (C.c_int32 * 3)(*[int(b) for b in bc])
+    tau2, tau3, tau4 = tau
+    p.tau = (C.c_double * 5)(0.0, 0.0, tau2, tau3, tau4)
+    p.rho0 = rho0
+    keep = []
+    if g_field is not None:
+        arr = np.ascontiguousarray(g_field, dtype=np.float64)
+        p.g_kind, p.g_data = G_FIELD, arr.ctypes.data
+        keep.append(arr)
+    elif g_profile is not None:
+        axis, table = g_profile
+        arr = np.ascontiguousarray(table, dtype=np.float64)
+        p.g_kind, p.g_axis, p.g_data = G_PROFILE, int(axis), arr.ctypes.data
+        keep.append(arr)
+    else:
+        gv = [0.0, 0.0, 0.0] if g is None else [float(v) for v in g]
+        p.g_kind = G_UNIFORM
+        p.g_uniform = (C.c_double * 3)(*gv)
+    p.monitor_every = monitor_every
+    if allocator is not None:
+        p.allocator = C.pointer(allocator.struct)
+        keep.append(allocator)
+    return p, keep
+
+
+def lbm_init(params: lbm_params, rho_init=None, u_init=None, stream=None) -> C.c_void_p:
+    lib = load()
+    out = C.c_void_p()
+    r = None if rho_init is None else np.ascontiguousarray(rho_init, dtype=np.float64)
+    u = None if u_init is None else np.ascontiguousarray(u_init, dtype=np.float64)
+    _check(lib.lbm_init(C.byref(params), _ptr(r), _ptr(u), _stream_handle(stream), C.byref(out)))
+    return out
+
+
+def lbm_step(ctx, n: int, g_scale=None):
+    gs = None if g_scale is None else np.ascontiguousarray(g_scale, dtype=np.float64)
+    if gs is not None and gs.size < n:
+        raise ValueError("g_scale needs n entries")
+    _check(load().lbm_step(ctx, int(n), _ptr(gs)))
+
+
+def lbm_moments(ctx, N: int, D: int, g_scale: float = 1.0):
+    rho = np.empty(N)
+    u = np.empty((D, N))
+    _check(load().lbm_moments(ctx, float(g_scale), _ptr(rho), _ptr(u)))
+    return rho, u
+
+
+def lbm_monitors_get(ctx) -> lbm_monitors:
+    m = lbm_monitors()
+    rc = load().lbm_monitors_get(ctx, C.byref(m))
+    if rc not in (LBM_OK, LBM_ENONFINITE):
+        _check(rc)
+    return m
+
+
+def lbm_get_populations(ctx, Q: int, N: int, nodes=None):
+    if nodes is None:
+        out = np.empty((Q, N))
+        _check(load().lbm_get_populations(ctx, N, None, _ptr(out)))
+        return out
+    idx = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.empty((Q, idx.size))
+    _check(load().lbm_get_populations(ctx, idx.size, _ptr(idx), _ptr(out)))
+    return out
+
+
+def lbm_set_populations(ctx, f):
+    arr = np.ascontiguousarray(f, dtype=np.float64)
+    _check(load().lbm_set_populations(ctx, _ptr(arr)))
+
+
+def lbm_time(ctx) -> int:
+    t = C.c_int64()
+    _check(load().lbm_time(ctx, C.byref(t)))
+    return t.value
+
+
+def lbm_device_bytes(ctx) -> int:
+    b = C.c_size_t()
+    _check(load().lbm_device_bytes(ctx, C.byref(b)))
+    return b.value
+
+
+def lbm_free(ctx):
+    _check(load().lbm_free(ctx))
+
+
+def lbm_copy_probe(src_ptr: int, dst_ptr: int, nbytes: int, reps: int = 1, block: int = 256,
+                   stream=None):
+    _check(load().lbm_copy_probe(C.c_void_p(src_ptr), C.c_void_p(dst_ptr), int(nbytes), int(reps),
+                                 int(block), _stream_handle(stream)))
+
+
+# ---- convenience object -----------------------------------------------------------------
+
+class Lattice:
+    """Owns one lbm context (created by lbm_init, released by close())."""
+
+    def __init__(self, lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1),
+                 walls=(0, 0, 0), tau=(0.8, 0.8, 1.0), rho0=1.0, rho=None, u=None, g=None,
+                 g_profile=None, g_field=None, monitor_every=0, stream=None, allocator=None):
+        self.lattice = lattice
+        self.Q = QOF[lattice]
+        self.D = 2 if lattice == "D2Q9" else 3
+        nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+        self.shape = (nx, ny, nz)
+        self.N = nx * ny * nz
+        self.storage = storage
+        self._params, self._keep = make_params(lattice, collision, storage, self.shape, walls, tau,
+                                               rho0, g, g_profile, g_field, monitor_every,
+                                               allocator)
+        if u is not None:
+            u = np.asarray(u, dtype=np.float64)[: self.D]
+        self.ctx = lbm_init(self._params, rho, u, stream)
+
+    def step(self, n=1, g_scale=None):
+        lbm_step(self.ctx, n, g_scale)
+
+    def moments(self, g_scale=1.0):
+        return lbm_moments(self.ctx, self.N, self.D, g_scale)
+
+    def monitors(self):
+        return lbm_monitors_get(self.ctx)
+
+    def populations(self, nodes=None):
+        return lbm_get_populations(self.ctx, self.Q, self.N, nodes)
+
+    def set_populations(self, f):
+        lbm_set_populations(self.ctx, f)
+
+    @property
+    def time(self):
+        return lbm_time(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            lbm_free(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,105 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared entry point,
+and rejects invalid parameters before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    names = _declared("lbm.h")
+    assert "lbm_init" in names and "lbm_step" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    # the binding covers the same names
+    assert set(names) <= set(lbm.EXPORTS)
+
+
+def test_version_and_strerror():
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    assert lib.lbm_version() == 100
+    assert lib.lbm_strerror(-1) == b"invalid argument"
+
+
+@pytest.mark.parametrize("change,fragment", [
+    (dict(tau=(0.5, 0.8, 1.0)), "tau[2]"),
+    (dict(collision="smrt", tau=(0.8, 0.8, 0.9)), "tau[4]"),
+    (dict(collision="smrt", tau=(0.8, 0.4, 1.0)), "tau[3]"),
+    (dict(shape=(8, 8, 2)), "nz == 1"),
+    (dict(shape=(0, 8, 1)), "positive"),
+    (dict(rho0=0.0), "rho0"),
+    (dict(lattice="D3Q19", shape=(2048, 2048, 1024)), "2^31"),
+])
+def test_invalid_parameters_rejected(change, fragment):
+    from paper_2212_07494_amd import lbm
+    kw = dict(lattice="D2Q9", collision="bgk", storage="f64", shape=(8, 8, 1),
+              tau=(0.8, 0.8, 1.0), rho0=1.0)
+    kw.update(change)
+    p, keep = lbm.make_params(**kw)
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.lbm_init(p)
+    assert ei.value.status == lbm.LBM_EINVAL
+    assert fragment in str(ei.value)
+
+
+def test_unknown_enums_and_null_arguments():
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    p, keep = lbm.make_params()
+    p.storage = 9
+    out = C.c_void_p()
+    assert lib.lbm_init(C.byref(p), None, None, None, C.byref(out)) == lbm.LBM_EINVAL
+    assert out.value is None
+    assert lib.lbm_init(None, None, None, None, C.byref(out)) == lbm.LBM_EINVAL
+    p, keep = lbm.make_params()
+    p.g_kind = lbm.G_FIELD  # field without data
+    assert lib.lbm_init(C.byref(p), None, None, None, C.byref(out)) == lbm.LBM_EINVAL
+    # calls on a NULL context report a state error
+    assert lib.lbm_step(None, 1, None) == lbm.LBM_ESTATE
+    assert lib.lbm_free(None) == lbm.LBM_ESTATE
+    assert lib.lbm_copy_probe(None, None, 16, 1, 256, None) == lbm.LBM_EINVAL
+
+
+def test_generated_tables_are_current():
+    """lbm_tables.h is what gen_tables.py produces (the build regenerates it)."""
+    import importlib.util
+    path = os.path.join(ROOT, "paper_2212_07494_amd", "csrc", "gen_tables.py")
+    spec = importlib.util.spec_from_file_location("gen_tables", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    tmp = os.path.join(ROOT, "_build", "lbm_tables_check.h")
+    os.makedirs(os.path.dirname(tmp), exist_ok=True)
+    mod.generate(tmp)
+    cur = os.path.join(ROOT, "paper_2212_07494_amd", "csrc", "lbm_tables.h")
+    assert open(tmp).read() == open(cur).read()
+
+
+def test_library_constants_equal_oracle_rationals():
+    """The library's independently derived tables equal the oracle's exact rationals."""
+    import importlib.util
+    from oracle import lattice as olat
+    path = os.path.join(ROOT, "paper_2212_07494_amd", "csrc", "gen_tables.py")
+    spec = importlib.util.spec_from_file_location("gen_tables", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    for name in olat.LATTICES:
+        vel, w, ms = mod.lattice(name)
+        _, minv = mod.reconstruction(vel, w, ms)
+        assert vel == olat.velocities(name)
+        assert w == olat.weights(name)
+        assert ms == olat.index_set(name)
+        assert [list(r) for r in olat.reconstruction(name)] == minv
+        assert np.all(np.isfinite(np.array([[float(x) for x in r] for r in minv])))
