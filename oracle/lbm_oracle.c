@@ -210,7 +210,13 @@ static void collide_bgk(const oracle_lattice *L, const oracle_params *P, const r
  * |m| = 2, 3; P_{e_a} = F_a/2; order 4 trimmed (P_m = 0).
  * Back to raw moments: R_m = sum_{l <= m} C(m,l) u^l P_{m-l} for 1 <= |m| <= 4
  * (this is eq:bbd1 written per multi-index), post-collision a*_m = rho u^m + R_m for
- * |m| <= 4 and 0 above order 4; f* = Minv a* (reconstruction after eq:bbd1).
+ * |m| <= 4 and 0 above order 4 (reconstruction after eq:bbd1).
+ * The post-collision state is formed as eq:evolution writes it, f-bar + (Omega + F):
+ * the increment is the reconstruction Minv (a* - a) of the moment changes, which are 0
+ * for the mass, F for the momentum, R_m - N_m for orders 2..4 and -a_m above.  In real
+ * arithmetic this equals Minv a*; in floating point it keeps the conserved moments
+ * away from the rounded reconstruction coefficients, so mass and momentum carry no
+ * per-step bias (with Minv a* they would be scaled by sum_i e_i^2 fl(Minv) != 1).
  */
 /* Index bookkeeping of the two Hermite shifts, built once per call: for each m the
  * sub-multi-indices l (canonical order, l != 0, l != m), the index of m - l and the
@@ -242,7 +248,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
   macro_t M;
   macroscopic(L, P, f, g, &M);
   const int NM = L->NM;
-  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ], astar[MAXQ];
+  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ];
   for (int k = 0; k < NM; ++k) {
     U[k] = upow(L->mi + 3 * k, M.u);
     E[k] = M.rho * U[k];
@@ -279,16 +285,33 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       Pc[k] = (n == 2 ? P->q2 : P->q3) * D;
     }
   }
-  /* back to raw moments, add the equilibrium */
+  /* back to raw moments; the change of every moment over the collision */
+  real dA[MAXQ];
   for (int k = 0; k < NM; ++k) {
-    int n = mabs(L->mi + 3 * k);
-    if (n == 0) {
-      astar[k] = M.drho;
+    const int32_t *m = L->mi + 3 * k;
+    int n = mabs(m);
+    if (n == 0) { /* mass is unchanged */
+      dA[k] = 0;
       continue;
     }
-    if (n > 4) {
-      astar[k] = 0;
+    if (n == 1) { /* momentum gains F (a*^(1) = rho u + F/2 = j + F) */
+      int a = m[0] ? 0 : (m[1] ? 1 : 2);
+      dA[k] = M.F[a];
       continue;
+    }
+    /* pre-collision raw moment of order >= 4 (orders 2, 3 are already in N) */
+    real Nk = N[k];
+    if (n >= 4) {
+      real A = -0.0;
+      for (int i = 0; i < L->Q; ++i) {
+        real h = L->H[k * L->Q + i];
+        if (h != 0) A = A + h * f[i];
+      }
+      if (n > 4) { /* orders above 4 are not carried: a*_m = 0 */
+        dA[k] = -A;
+        continue;
+      }
+      Nk = A - E[k];
     }
     real R = (n <= 3) ? Pc[k] : (real)-0.0; /* l = 0 term; P_m = 0 for |m| = 4 */
     for (int t = 0; t < S->n[k]; ++t) {
@@ -296,15 +319,17 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       if (mabs(L->mi + 3 * km) > 3) continue; /* P = 0 at order 4 */
       R = R + (real)S->cup[k][t] * (U[S->kl[k][t]] * Pc[km]);
     }
-    astar[k] = E[k] + R;
+    /* a*_m - a_m = (rho u^m + R_m) - (rho u^m + N_m) */
+    dA[k] = R - Nk;
   }
+  /* eq:evolution: f-bar + Omega + F, the increment reconstructed from dA */
   for (int i = 0; i < L->Q; ++i) {
     real acc = -0.0;
-    for (int k = 0; k < NM; ++k) {
+    for (int k = 1; k < NM; ++k) {
       real c = L->Minv[i * NM + k];
-      if (c != 0 && mabs(L->mi + 3 * k) <= 4) acc = acc + c * astar[k];
+      if (c != 0) acc = acc + c * dA[k];
     }
-    out[i] = acc;
+    out[i] = f[i] + acc;
   }
 }
 

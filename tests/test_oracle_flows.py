@@ -107,9 +107,10 @@ def test_closed_form_limits():
 @pytest.mark.parametrize("coll,tau3", [("bgk", None), ("smrt", 1.0), ("smrt", 0.7)])
 def test_poiseuille_matches_closed_form(coll, tau3):
     """Channel 4 (periodic x) x 32 (walls), tau-hat 0.8, g = 1e-6: at convergence the
-    profile equals the exact discrete parabola-plus-slip to 5e-11 relative.  (The odd
-    sector's slowest mode has decayed to ~1e-19 by 45,000 steps; what remains is FP64
-    round-off accumulated in slowly relaxing even modes, ~1e-16 per step.)"""
+    profile equals the exact discrete parabola-plus-slip to 1e-12 relative for SMRT
+    (the odd sector's slowest mode has decayed to ~1e-19 by 45,000 steps).  BGK's
+    population-form update (eq:explict_eq) takes the equilibrium's momentum through
+    the rounded weights, which leaves a round-off drift of a few 1e-12 here."""
     tau = 0.8
     t3 = tau if tau3 is None else tau3
     w = inputs.poiseuille_channel(nx=4, ny=32, tau=tau, collision=coll)
@@ -120,7 +121,8 @@ def test_poiseuille_matches_closed_form(coll, tau3):
     ux = u[0].reshape(32, 4)
     assert np.ptp(ux, axis=1).max() == 0.0
     want = cf.poiseuille_profile(32, 1e-6, tau, t3)
-    assert np.max(np.abs(ux[:, 0] - want)) <= 5e-11 * want.max()
+    tol = 5e-12 if coll == "bgk" else 1e-12
+    assert np.max(np.abs(ux[:, 0] - want)) <= tol * want.max()
     assert np.max(np.abs(u[1])) <= 5e-15  # round-off of sums of O(0.1) populations
 
 
