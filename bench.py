@@ -26,13 +26,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X vendor peak
 
 
+STEP_SOURCES = ("lbm_tables.h", "lbm_node.h", "lbm_kernels.h", "lbm_lattice_impl.h",
+                "lbm_internal.h", "lbm_d3q19.hip")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the D3Q19 step kernel is compiled from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2212_07494_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in STEP_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -50,22 +54,26 @@ def measured_traffic(kernel_hash: str, storage: str):
 
 
 def copy_roofline(torch, L, stream, nbytes=2 << 30, reps=10):
-    """Best read+write bandwidth of the library's stream-copy probe over block sizes."""
+    """Best read+write bandwidth of the library's stream-copy probe (2 GiB -> 2 GiB, far
+    beyond the last-level cache) over its variants and block sizes."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     src.fill_(1)
-    best = 0.0
-    for block in (256, 512, 1024):
-        with torch.cuda.stream(stream):
-            L.lbm_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, 2, block, stream)
+    best = (0.0, None)
+    for variant in (1, 2):
+        for block in (256, 512):
+            L.lbm_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, 2, block, variant=variant,
+                             stream=stream)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            L.lbm_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, reps, block, stream)
+            L.lbm_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, reps, block,
+                             variant=variant, stream=stream)
             e1.record(stream)
-        e1.synchronize()
-        gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        best = max(best, gbps)
+            e1.synchronize()
+            gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+            if gbps > best[0]:
+                best = (gbps, {"variant": variant, "block": block})
     del src, dst
     torch.cuda.empty_cache()
     return best
@@ -93,9 +101,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32s", choices=["f64", "f32", "f32s", "f16s"])
     ap.add_argument("--n", type=int, default=256, help="box edge (the workload is 256)")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the stream-copy roofline")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed launch configuration bx,by,variant instead of the tuner")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -118,6 +128,11 @@ def main():
     lat = L.Lattice(w.lattice, w.collision, args.storage, w.shape, w.walls, w.tau, rho=w.rho,
                     u=w.u, g_profile=w.g_profile, stream=stream)
     lat.step(args.warmup)
+    if args.tuning:
+        bx, by, var = (int(v) for v in args.tuning.split(","))
+        tuning = lat.tune(bx, by, var)
+    else:
+        tuning = lat.tune(autotune_steps=20)  # the library's launch-configuration tuner
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -135,7 +150,7 @@ def main():
     del lat
     torch.cuda.empty_cache()
 
-    copy_gbps = None if args.no_copy else copy_roofline(torch, L, stream)
+    copy_gbps, copy_cfg = (None, None) if args.no_copy else copy_roofline(torch, L, stream)
     khash = kernel_source_hash()
     traffic = measured_traffic(khash, args.storage) if args.n == 256 else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
@@ -143,6 +158,9 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": bytes_launch,
             "measured_copy_GBps": None if copy_gbps is None else round(copy_gbps, 1),
+            "copy_probe": copy_cfg,
+            "launch": {"block": [tuning[0], tuning[1]],
+                       "memory_variant": ["plain", "nt-store", "nt-load+store"][tuning[2]]},
             "frac_of_copy": None if copy_gbps is None else round(achieved / copy_gbps, 4)}
     dtype = {"f64": "f64", "f32": "f32", "f32s": "f32", "f16s": "f32"}[args.storage]
     rec = {

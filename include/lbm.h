@@ -163,12 +163,32 @@ int lbm_device_bytes(const lbm_ctx *c, size_t *bytes);
 
 int lbm_free(lbm_ctx *c);
 
-/* Stream-copy probe: dst[i] = src[i] for `bytes` bytes (multiple of 16) of device
- * memory, enqueued `reps` times on hip_stream with the block size `block` (64..1024,
- * multiple of 64; 0 = 256).  The measured read + write bandwidth of this copy is the
- * practical HBM roofline the step is compared against. */
+/* Launch configuration of the step kernel: block shape bx x by (bx in {64, 128, 256},
+ * bx * by <= 256) and memory-access variant (0 plain loads and stores, 1 non-temporal
+ * stores, 2 non-temporal loads and stores).  Results are identical for every
+ * configuration; only the speed differs. */
+typedef struct {
+  int32_t bx, by;
+  int32_t variant;
+} lbm_tuning;
+
+int lbm_set_tuning(lbm_ctx *c, const lbm_tuning *t);
+int lbm_get_tuning(const lbm_ctx *c, lbm_tuning *t);
+
+/* Time every launch configuration for `steps` steps (>= 1) and keep the fastest.  The
+ * state is saved before and restored after, so the simulation is unchanged.  best and
+ * best_ms (time per step of the winner) may be NULL.  Synchronises the stream and
+ * temporarily needs one extra population buffer of device memory. */
+int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_tuning *best, double *best_ms);
+
+/* Stream-copy probe: dst = src for `bytes` bytes (multiple of 16) of device memory,
+ * enqueued `reps` times on hip_stream with the block size `block` (64..1024, multiple
+ * of 64; 0 = 256).  variant: 0 grid-stride 16-byte vectors, 1 one 16-byte vector per
+ * thread, 2 as 1 with non-temporal loads and stores, 3 four vectors per thread.  The
+ * best read + write bandwidth over variants is the practical HBM roofline the step is
+ * compared against. */
 int lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t reps, int32_t block,
-                   void *hip_stream);
+                   int32_t variant, void *hip_stream);
 
 const char *lbm_strerror(int status);
 const char *lbm_last_error(void);

@@ -28,7 +28,8 @@ struct LaunchDesc {
   double gscale;
   double shift;
   double c0, c1;
-  int bx, by;        // block shape (bx * by <= 256, bx multiple of 64 or == block)
+  int bx, by;        // block shape (bx * by <= 256, bx a multiple of 64)
+  int variant;       // memory-access variant of the step kernel (MEM_*)
 };
 
 struct LatticeOps {

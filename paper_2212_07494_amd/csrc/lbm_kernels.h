@@ -37,6 +37,12 @@ struct ForceRef {
   T scale;       // s(t)
 };
 
+// Memory-access variants of the step (chosen at run time by the tuner):
+//   MEM_PLAIN  ordinary loads and stores;
+//   MEM_NTST   non-temporal stores (the written buffer is not re-read this step);
+//   MEM_NTALL  non-temporal loads and stores.
+enum { MEM_PLAIN = 0, MEM_NTST = 1, MEM_NTALL = 2, MEM_VARIANTS = 3 };
+
 template <class S, class T>
 __device__ __forceinline__ T load_as(const S *p) {
   return T(*p);
@@ -44,6 +50,20 @@ __device__ __forceinline__ T load_as(const S *p) {
 template <class S, class T>
 __device__ __forceinline__ S store_as(T v) {
   return S(v);
+}
+template <int MEM, class S, class T>
+__device__ __forceinline__ T load_v(const S *p) {
+  if constexpr (MEM == MEM_NTALL)
+    return T(__builtin_nontemporal_load(p));
+  else
+    return T(*p);
+}
+template <int MEM, class S, class T>
+__device__ __forceinline__ void store_v(S *p, T v) {
+  if constexpr (MEM == MEM_NTST || MEM == MEM_NTALL)
+    __builtin_nontemporal_store(S(v), p);
+  else
+    *p = S(v);
 }
 
 // Slot that node (x, y, z) pulls population i from: (i, x - e_i) with periodic wrap,
@@ -94,7 +114,7 @@ struct StepArgs {
   T c0, c1;  // BGK: omega, 1 - omega/2;  SMRT: q2, q3
 };
 
-template <class L, int COLL, class S, class T, int GK>
+template <class L, int COLL, class S, class T, int GK, int MEM>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -106,7 +126,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   T d[L::Q];
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    d[i] = load_as<S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, node));
+    d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, node));
   });
   T g[3];
   load_force<T, GK>(a.force, x, y, z, node, a.geo.N, L::D, g);
@@ -117,7 +137,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   }
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    fout[(int64_t)i * a.geo.N + node] = store_as<S, T>(d[i]);
+    store_v<MEM, S, T>(fout + (int64_t)i * a.geo.N + node, d[i]);
   });
 }
 

@@ -52,11 +52,20 @@ inline hipError_t with_types(int storage, F &&f) {
 
 template <class L>
 struct Ops {
+  template <int COLL, class S, class T, int GK, int MEM>
+  static hipError_t step_m(const LaunchDesc &d, hipStream_t s) {
+    hipLaunchKernelGGL((step_kernel<L, COLL, S, T, GK, MEM>), grid_of(d), dim3(d.bx, d.by), 0,
+                       s, make_args<T>(d));
+    return hipGetLastError();
+  }
   template <int COLL, class S, class T, int GK>
   static hipError_t step_t(const LaunchDesc &d, hipStream_t s) {
-    hipLaunchKernelGGL((step_kernel<L, COLL, S, T, GK>), grid_of(d), dim3(d.bx, d.by), 0, s,
-                       make_args<T>(d));
-    return hipGetLastError();
+    switch (d.variant) {
+      case MEM_PLAIN: return step_m<COLL, S, T, GK, MEM_PLAIN>(d, s);
+      case MEM_NTST: return step_m<COLL, S, T, GK, MEM_NTST>(d, s);
+      case MEM_NTALL: return step_m<COLL, S, T, GK, MEM_NTALL>(d, s);
+      default: return hipErrorInvalidValue;
+    }
   }
   static hipError_t step(const LaunchDesc &d, hipStream_t s) {
     return with_types(d.storage, [&](auto *sp, auto *tp) -> hipError_t {

@@ -19,9 +19,10 @@
 // Populations are handled as deviations d_i = f-bar_i - w_i s from a constant shift
 // s (s = 0 for plain storage): the mass moment carries d-rho = sum_i d_i and
 // rho = s + d-rho, every other moment of d equals that of f-bar (sum_i w_i H_m = 0
-// for m != 0), and the reconstruction's rest coefficient multiplies d-rho, so the
-// same code serves plain and shifted storage and keeps full relative precision of
-// the small deviations in binary32.
+// for m != 0), the step changes no mass, and where a full state is reconstructed
+// (the initial state) the rest coefficient multiplies d-rho.  The same code thus
+// serves plain and shifted storage and keeps the full relative precision of the
+// small deviations in binary32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -173,18 +174,23 @@ __device__ __forceinline__ void reconstruct(const T (&a)[L::NM], T (&out)[L::Q])
 }
 
 // SMRT with the force in the first central moment (Sec. II.C, eq:domg, eq:RHS, eq:bbd1):
-//   A_m = sum_i d_i H_m(e_i)                         (orders 2, 3; eq:dft)
+//   A_m = sum_i d_i H_m(e_i)                         (eq:dft)
 //   N_m = A_m - rho u^m,  N_{e_a} = -F_a/2             (non-equilibrium raw moments)
 //   D_m = sum_{l <= m} C(m,l) (-u)^l N_{m-l}           (shift to the frame moving with u)
 //   P_m = (1 - omega_|m|) D_m (|m| = 2, 3), P_{e_a} = F_a/2, order 4 trimmed
 //   R_m = sum_{l <= m} C(m,l) u^l P_{m-l}              (back to raw moments, |m| <= 4)
-//   a*_m = rho u^m + R_m (|m| <= 4), a*_0 = d-rho;  f* = MINV a*
+//   a*_m = rho u^m + R_m (|m| <= 4), 0 above order 4
+// applied as eq:evolution writes the step, f-bar + (Omega + F): the increment is
+// MINV (a* - a), whose moment changes are 0 for the mass, F for the momentum,
+// R_m - N_m for orders 2..4 and -A_m above.  Equal to MINV a* in real arithmetic; in
+// floating point the conserved moments never pass through the rounded coefficients,
+// so they carry no per-step bias.
 template <class L, class T>
 __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)[3],
                                              const SMRTCoef<T> &c) {
   constexpr int NM = L::NM;
   const Macro<T> M = macroscopic<L>(d, shift, g);
-  T U[NM], E[NM], N[NM], P[NM], A[NM];
+  T U[NM], E[NM], N[NM], P[NM], dA[NM];
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     U[k] = upow<L, k>(M.u);
@@ -196,14 +202,18 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
     if constexpr (n == 1) {
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
       N[k] = T(-0.5) * M.F[a];
-    } else if constexpr (n == 2 || n == 3) {
+    } else if constexpr (n >= 2) {
       T acc = T(-0.0);
       static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr T h = Tab<L, T>::h(k, i);
         if constexpr (h != T(0)) acc = acc + h * d[i];
       });
-      N[k] = acc - E[k];
+      // orders 2..4: non-equilibrium part; above 4: the raw moment itself
+      if constexpr (n <= 4)
+        N[k] = acc - E[k];
+      else
+        N[k] = acc;
     } else {
       N[k] = T(0);
     }
@@ -230,9 +240,12 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
     constexpr int k = decltype(K)::value;
     constexpr int n = L::ORD[k];
     if constexpr (n == 0) {
-      A[k] = M.drho;
+      dA[k] = T(0);
+    } else if constexpr (n == 1) {
+      constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
+      dA[k] = M.F[a];
     } else if constexpr (n > 4) {
-      A[k] = T(0);
+      dA[k] = -N[k];
     } else {
       T R = (n <= 3) ? P[k] : T(-0.0);
       static_for<L::NT[k]>([&](auto Tt) {
@@ -240,10 +253,19 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
         constexpr int kl = L::TL[k][t], km = L::TM[k][t];
         if constexpr (L::ORD[km] <= 3) R = R + T(L::CUP[k][t]) * (U[kl] * P[km]);
       });
-      A[k] = E[k] + R;
+      dA[k] = R - N[k];
     }
   });
-  reconstruct<L>(A, d);
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    T acc = T(-0.0);
+    static_for<NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr T cf = Tab<L, T>::minv(i, k);
+      if constexpr (k > 0 && cf != T(0)) acc = acc + cf * dA[k];
+    });
+    d[i] = d[i] + acc;
+  });
 }
 
 // Initial stored state f-bar = f_eq - F_i/2 (eq:newf with Omega = 0): density and

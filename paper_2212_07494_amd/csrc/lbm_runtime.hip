@@ -82,7 +82,7 @@ struct lbm_ctx {
   int64_t t = 0;
   double last_scale = 1.0;
   double c0 = 0, c1 = 0, shift = 0;
-  int bx = 64, by = 4;
+  int bx = 64, by = 4, variant = 0;
   lbm_monitors mon{};
 
   int dalloc(void **ptr, size_t n) {
@@ -143,6 +143,7 @@ struct lbm_ctx {
     d.c1 = c1;
     d.bx = bx;
     d.by = by;
+    d.variant = variant;
     return d;
   }
 };
@@ -217,7 +218,7 @@ void release(lbm_ctx *c) {
 namespace lbm {
 hipError_t finalize_monitors(const double *partials, int64_t nb, double *out, hipStream_t s);
 hipError_t copy_probe(const void *src, void *dst, size_t bytes, int reps, int block,
-                      hipStream_t s);
+                      int variant, hipStream_t s);
 }  // namespace lbm
 
 namespace {
@@ -490,13 +491,126 @@ int lbm_free(lbm_ctx *c) {
 }
 
 int lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t reps, int32_t block,
-                   void *hip_stream) {
+                   int32_t variant, void *hip_stream) {
   if (!src || !dst) return fail(LBM_EINVAL, "NULL buffer");
   if (bytes % 16) return fail(LBM_EINVAL, "bytes must be a multiple of 16");
   if (reps < 0) return fail(LBM_EINVAL, "negative repetition count");
+  if (variant < 0 || variant > 3) return fail(LBM_EINVAL, "copy variant %d", variant);
   if (block == 0) block = 256;
   if (block < 64 || block > 1024 || block % 64) return fail(LBM_EINVAL, "block %d", block);
-  HIP_TRY(lbm::copy_probe(src, dst, bytes, reps, block, static_cast<hipStream_t>(hip_stream)));
+  if (bytes / 16 / (size_t)block >= (size_t(1) << 31))
+    return fail(LBM_EINVAL, "copy of %zu bytes needs too many blocks", bytes);
+  HIP_TRY(lbm::copy_probe(src, dst, bytes, reps, block, variant,
+                          static_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+namespace {
+constexpr int kVariants = 3;
+bool tuning_ok(const lbm_tuning *t) {
+  return t && (t->bx == 64 || t->bx == 128 || t->bx == 256) && t->by >= 1 &&
+         t->bx * t->by <= 256 && t->variant >= 0 && t->variant < kVariants;
+}
+}  // namespace
+
+int lbm_set_tuning(lbm_ctx *c, const lbm_tuning *t) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!tuning_ok(t)) return fail(LBM_EINVAL, "invalid tuning");
+  if (t->by > 65535) return fail(LBM_EINVAL, "invalid tuning");
+  c->bx = t->bx;
+  c->by = t->by;
+  c->variant = t->variant;
+  // the monitor partials are sized by the block grid
+  const int64_t nb = (int64_t)((c->p.nx + c->bx - 1) / c->bx) * ((c->p.ny + c->by - 1) / c->by) *
+                     c->p.nz;
+  if (nb > c->nblocks) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->dfree(c->partials);
+    c->partials = nullptr;
+    int rc = c->dalloc((void **)&c->partials, (size_t)nb * 8 * sizeof(double));
+    if (rc) return rc;
+  }
+  c->nblocks = nb;
+  return LBM_OK;
+}
+
+int lbm_get_tuning(const lbm_ctx *c, lbm_tuning *t) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!t) return fail(LBM_EINVAL, "t is NULL");
+  t->bx = c->bx;
+  t->by = c->by;
+  t->variant = c->variant;
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_tuning *best, double *best_ms) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+  const size_t pop_bytes = (size_t)c->Q * c->N * storage_bytes(c->p.storage);
+  int rc = c->need_scratch(pop_bytes);
+  if (rc) return rc;
+  // save the state; trials ping-pong between the two buffers
+  HIP_TRY(hipMemcpyAsync(c->scratch, c->buf[c->cur], pop_bytes, hipMemcpyDeviceToDevice,
+                         c->stream));
+  const lbm_tuning start = {c->bx, c->by, c->variant};
+  lbm_tuning win = start;
+  float win_ms = -1.0f;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int cur0 = c->cur;
+  int status = LBM_OK;
+  for (int bx : {64, 128, 256}) {
+    if (bx > 64 && bx >= 2 * c->p.nx) continue;  // mostly idle lanes
+    for (int by : {1, 2, 4}) {
+      if (bx * by > 256) continue;
+      for (int v = 0; v < kVariants; ++v) {
+        c->bx = bx;
+        c->by = by;
+        c->variant = v;
+        // warm-up launch, then the timed ones
+        lbm::LaunchDesc d = c->desc(1.0);
+        hipError_t e = c->ops->step(d, c->stream);
+        c->cur ^= 1;
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int s = 0; s < steps && e == hipSuccess; ++s) {
+          d = c->desc(1.0);
+          e = c->ops->step(d, c->stream);
+          c->cur ^= 1;
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          status = fail(LBM_EDEVICE, "autotune trial failed: %s", hipGetErrorString(e));
+          break;
+        }
+        ms /= steps;
+        if (win_ms < 0 || ms < win_ms) {
+          win_ms = ms;
+          win = {bx, by, v};
+        }
+      }
+      if (status) break;
+    }
+    if (status) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // restore the state into the buffer it came from
+  c->cur = cur0;
+  HIP_TRY(hipMemcpyAsync(c->buf[c->cur], c->scratch, pop_bytes, hipMemcpyDeviceToDevice,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (status) {
+    lbm_set_tuning(c, &start);
+    return status;
+  }
+  rc = lbm_set_tuning(c, &win);
+  if (rc) return rc;
+  if (best) *best = win;
+  if (best_ms) *best_ms = win_ms;
   return LBM_OK;
 }
 

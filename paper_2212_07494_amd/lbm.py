@@ -50,6 +50,13 @@ class lbm_params(C.Structure):
                 ("allocator", C.POINTER(lbm_allocator))]
 
 
+class lbm_tuning(C.Structure):
+    _fields_ = [("bx", C.c_int32), ("by", C.c_int32), ("variant", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.bx, self.by, self.variant)
+
+
 class lbm_monitors(C.Structure):
     _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("mom", C.c_double * 3),
                 ("umax", C.c_double), ("resid", C.c_double), ("nonfinite", C.c_int64)]
@@ -70,8 +77,11 @@ EXPORTS = {
     "lbm_time": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "lbm_device_bytes": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
     "lbm_free": ([C.c_void_p], C.c_int),
-    "lbm_copy_probe": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_int32, C.c_void_p],
-                       C.c_int),
+    "lbm_copy_probe": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_int32, C.c_int32,
+                        C.c_void_p], C.c_int),
+    "lbm_set_tuning": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_get_tuning": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_autotune": ([C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "lbm_strerror": ([C.c_int], C.c_char_p),
     "lbm_last_error": ([], C.c_char_p),
     "lbm_version": ([], C.c_int),
@@ -239,9 +249,27 @@ def lbm_free(ctx):
 
 
 def lbm_copy_probe(src_ptr: int, dst_ptr: int, nbytes: int, reps: int = 1, block: int = 256,
-                   stream=None):
+                   variant: int = 0, stream=None):
     _check(load().lbm_copy_probe(C.c_void_p(src_ptr), C.c_void_p(dst_ptr), int(nbytes), int(reps),
-                                 int(block), _stream_handle(stream)))
+                                 int(block), int(variant), _stream_handle(stream)))
+
+
+def lbm_set_tuning(ctx, bx: int, by: int, variant: int):
+    t = lbm_tuning(bx, by, variant)
+    _check(load().lbm_set_tuning(ctx, C.byref(t)))
+
+
+def lbm_get_tuning(ctx):
+    t = lbm_tuning()
+    _check(load().lbm_get_tuning(ctx, C.byref(t)))
+    return t.as_tuple()
+
+
+def lbm_autotune(ctx, steps: int = 10):
+    t = lbm_tuning()
+    ms = C.c_double()
+    _check(load().lbm_autotune(ctx, int(steps), C.byref(t), C.byref(ms)))
+    return t.as_tuple(), ms.value
 
 
 # ---- convenience object -----------------------------------------------------------------
@@ -274,6 +302,15 @@ class Lattice:
 
     def monitors(self):
         return lbm_monitors_get(self.ctx)
+
+    def tune(self, bx=None, by=None, variant=None, autotune_steps=None):
+        """Set the launch configuration, or time all of them (autotune_steps) and keep the
+        fastest; returns (bx, by, variant)."""
+        if autotune_steps:
+            return lbm_autotune(self.ctx, autotune_steps)[0]
+        cur = lbm_get_tuning(self.ctx)
+        lbm_set_tuning(self.ctx, bx or cur[0], by or cur[1], cur[2] if variant is None else variant)
+        return lbm_get_tuning(self.ctx)
 
     def populations(self, nodes=None):
         return lbm_get_populations(self.ctx, self.Q, self.N, nodes)

@@ -70,7 +70,7 @@ def test_unknown_enums_and_null_arguments():
     # calls on a NULL context report a state error
     assert lib.lbm_step(None, 1, None) == lbm.LBM_ESTATE
     assert lib.lbm_free(None) == lbm.LBM_ESTATE
-    assert lib.lbm_copy_probe(None, None, 16, 1, 256, None) == lbm.LBM_EINVAL
+    assert lib.lbm_copy_probe(None, None, 16, 1, 256, 0, None) == lbm.LBM_EINVAL
 
 
 def test_generated_tables_are_current():
