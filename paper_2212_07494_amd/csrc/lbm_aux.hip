@@ -3,6 +3,8 @@
 
 #include <cstdint>
 
+#include "lbm_internal.h"
+
 namespace lbm {
 namespace {
 
@@ -68,7 +70,69 @@ __global__ void copy_four(const float4 *__restrict__ src, float4 *__restrict__ d
   }
 }
 
+// Per-domain convergence decision after a compare pass (one thread per domain).
+__global__ void decide_kernel(const int *__restrict__ tile_begin, const int *__restrict__ tile_end,
+                              const double *__restrict__ partials, DomState *__restrict__ st,
+                              int *__restrict__ active, int *__restrict__ n_active, int ndom,
+                              double tol, int stall_checks, int steps) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= ndom || !active[d]) return;
+  double du2 = 0.0, u2 = 0.0, bad = 0.0;
+  for (int t = tile_begin[d]; t < tile_end[d]; ++t) {
+    du2 += partials[(int64_t)t * 3 + 0];
+    u2 += partials[(int64_t)t * 3 + 1];
+    bad += partials[(int64_t)t * 3 + 2];
+  }
+  DomState s = st[d];
+  s.steps += steps;
+  const double r = u2 > 0.0 ? sqrt(du2 / u2) : (du2 > 0.0 ? INFINITY : 0.0);
+  s.resid = r;
+  int stop = 0;
+  if (bad > 0.0 || !isfinite(r)) {
+    s.status = 3;
+    stop = 1;
+  } else if (r < tol) {
+    s.status = 1;
+    stop = 1;
+  } else {
+    if (r < 0.99 * s.best) {
+      s.best = r;
+      s.stall = 0;
+    } else if (++s.stall >= stall_checks) {
+      s.status = 2;
+      stop = 1;
+    }
+  }
+  st[d] = s;
+  if (stop) {
+    active[d] = 0;
+    atomicSub(n_active, 1);
+  }
+}
+
+// Steps taken by eager advances of the active domains.
+__global__ void add_steps_kernel(const int *__restrict__ active, DomState *__restrict__ st,
+                                 int ndom, int64_t n) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d < ndom && active[d]) st[d].steps += n;
+}
+
 }  // namespace
+
+hipError_t decide_domains(const int *tile_begin, const int *tile_end, const double *partials,
+                          void *state, int *active, int *n_active, int ndom, double tol,
+                          int stall_checks, int steps, hipStream_t s) {
+  hipLaunchKernelGGL(decide_kernel, dim3((ndom + 255) / 256), dim3(256), 0, s, tile_begin,
+                     tile_end, partials, static_cast<DomState *>(state), active, n_active, ndom,
+                     tol, stall_checks, steps);
+  return hipGetLastError();
+}
+
+hipError_t add_domain_steps(const int *active, void *state, int ndom, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(add_steps_kernel, dim3((ndom + 255) / 256), dim3(256), 0, s, active,
+                     static_cast<DomState *>(state), ndom, n);
+  return hipGetLastError();
+}
 
 hipError_t finalize_monitors(const double *partials, int64_t nb, double *out, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, nb, out);

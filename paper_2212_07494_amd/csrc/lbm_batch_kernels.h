@@ -1,0 +1,137 @@
+// Kernels of the batched engine: many independent domains, one persistent launch per
+// step.
+//
+// Layout: the domains' population planes are packed one domain after another in each
+// of the two population buffers (domain d occupies Q planes of N_d values starting at
+// element base_d); velocities recorded for the residual are packed the same way (D
+// planes per domain); force tables / fields are packed into one table buffer.
+//
+// Work decomposition: a flattened table of tiles, each tile = one 256-thread workgroup
+// of one domain (tbx x tby nodes of one z slice, tbx = 64, 128 or 256).  A fixed grid of
+// workgroups (a few per compute unit) walks the table with a stride of the grid size,
+// so domains of any size share the machine evenly; tiles of inactive (converged)
+// domains are skipped after reading one flag.
+#pragma once
+
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+struct BatchDom {
+  int64_t base;   // population offset (elements) of plane 0
+  int64_t ubase;  // offset of the recorded-velocity planes
+  int64_t goff;   // offset of the force table / field in the table buffer
+  int nx, ny, nz, N;
+  int wall[3];
+  int gaxis;      // 0, 1, 2: profile along that axis; -1: uniform (3 values); 3: full field
+  int gn;         // profile length
+  int tbx_log2;   // tile width 2^tbx_log2; tile height 256 >> tbx_log2
+  int tile_begin, tile_end;
+  double c0, c1;  // collision coefficients (see StepArgs)
+};
+
+struct BatchTile {
+  int dom, x0, y0, z;
+};
+
+template <class T>
+__device__ __forceinline__ void batch_force(const T *__restrict__ gbuf, const BatchDom &dm, int x,
+                                            int y, int z, int node, int D, T (&g)[3]) {
+  const T *tab = gbuf + dm.goff;
+  if (dm.gaxis == 3) {
+    for (int a = 0; a < 3; ++a) g[a] = (a < D) ? tab[(int64_t)a * dm.N + node] : T(0);
+  } else {
+    const int c = dm.gaxis == 0 ? x : (dm.gaxis == 1 ? y : (dm.gaxis == 2 ? z : 0));
+    for (int a = 0; a < 3; ++a) g[a] = (a < D) ? tab[a * dm.gn + c] : T(0);
+  }
+}
+
+__device__ __forceinline__ Geom batch_geom(const BatchDom &dm) {
+  Geom geo;
+  geo.nx = dm.nx;
+  geo.ny = dm.ny;
+  geo.nz = dm.nz;
+  geo.N = dm.N;
+  for (int a = 0; a < 3; ++a) geo.wall[a] = dm.wall[a];
+  return geo;
+}
+
+template <class L, int COLL, class S, class T, int MEM>
+__global__ void __launch_bounds__(256)
+    batch_step_kernel(const S *__restrict__ fin, S *__restrict__ fout, const T *__restrict__ gbuf,
+                      const BatchDom *__restrict__ doms, const BatchTile *__restrict__ tiles,
+                      const int *__restrict__ active, int ntiles, T shift) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tile = tiles[t];
+    if (!active[tile.dom]) continue;
+    const BatchDom dm = doms[tile.dom];
+    const int x = tile.x0 + (threadIdx.x & ((1 << dm.tbx_log2) - 1));
+    const int y = tile.y0 + (threadIdx.x >> dm.tbx_log2);
+    const int z = tile.z;
+    if (x >= dm.nx || y >= dm.ny) continue;
+    const Geom geo = batch_geom(dm);
+    const int node = (z * dm.ny + y) * dm.nx + x;
+    T g[3];
+    batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);
+    step_node<L, COLL, S, T, MEM>(fin + dm.base, fout + dm.base, geo, x, y, z, node, g, shift,
+                                  T(dm.c0), T(dm.c1));
+  }
+}
+
+// Residual monitor over the tiles of active domains: physical u(t) of the current state
+// (pulled), compared with the recorded u (mode 4) and/or recorded (modes 2 and 4).
+// Writes per tile: sum |u - u_rec|^2, sum |u|^2, non-finite count.
+template <class L, class S, class T>
+__global__ void __launch_bounds__(256)
+    batch_monitor_kernel(const S *__restrict__ f, const T *__restrict__ gbuf,
+                         const BatchDom *__restrict__ doms, const BatchTile *__restrict__ tiles,
+                         const int *__restrict__ active, int ntiles, T shift,
+                         T *__restrict__ urec, int mode, double *__restrict__ partials) {
+  __shared__ double red[4][3];
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tile = tiles[t];
+    if (!active[tile.dom]) continue;
+    const BatchDom dm = doms[tile.dom];
+    const int x = tile.x0 + (threadIdx.x & ((1 << dm.tbx_log2) - 1));
+    const int y = tile.y0 + (threadIdx.x >> dm.tbx_log2);
+    const int z = tile.z;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (x < dm.nx && y < dm.ny) {
+      const Geom geo = batch_geom(dm);
+      const int node = (z * dm.ny + y) * dm.nx + x;
+      T d[L::Q];
+      const S *fd = f + dm.base;
+      static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        d[i] = T(fd[pull_slot<L, i>(x, y, z, geo, node)]);
+      });
+      T g[3];
+      batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);
+      const Macro<T> M = macroscopic<L>(d, shift, g);
+      T *ur = urec + dm.ubase;
+      for (int c = 0; c < L::D; ++c) {
+        const double uc = double(M.u[c]);
+        v[1] += uc * uc;
+        if (mode & MOM_COMPARE) {
+          const double dd = uc - double(ur[(int64_t)c * dm.N + node]);
+          v[0] += dd * dd;
+        }
+        ur[(int64_t)c * dm.N + node] = M.u[c];
+      }
+      v[2] = (isfinite(v[1]) && isfinite(double(M.rho))) ? 0.0 : 1.0;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int s = 0; s < 3; ++s) {
+      const double r = wave_sum(v[s]);
+      if (lane == 0) red[wave][s] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const int s = threadIdx.x;
+      partials[(int64_t)t * 3 + s] = ((red[0][s] + red[1][s]) + red[2][s]) + red[3][s];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace lbm

@@ -32,6 +32,23 @@ struct LaunchDesc {
   int variant;       // memory-access variant of the step kernel (MEM_*)
 };
 
+// One launch of the batched engine's persistent kernels.
+struct BatchLaunch {
+  int coll, storage, variant;
+  const void *fin;
+  void *fout;
+  const void *gbuf;
+  const void *doms;   // device BatchDom[ndom]
+  const void *tiles;  // device BatchTile[ntiles]
+  const int *active;
+  int ntiles;
+  int grid;           // persistent workgroups
+  double shift;
+  void *urec;         // monitor: recorded velocities
+  int mode;           // monitor: 2 record, 4 compare + record
+  double *partials;   // monitor: 3 per tile
+};
+
 struct LatticeOps {
   int D, Q;
   hipError_t (*step)(const LaunchDesc &, hipStream_t);
@@ -42,11 +59,30 @@ struct LatticeOps {
   hipError_t (*scatter)(const LaunchDesc &, const double *in, hipStream_t);
   hipError_t (*moments)(const LaunchDesc &, double *rho, double *u, void *uprev, int mode,
                         double *partials, hipStream_t);
+  hipError_t (*batch_step)(const BatchLaunch &, hipStream_t);
+  hipError_t (*batch_monitor)(const BatchLaunch &, hipStream_t);
 };
+
+// Per-domain convergence state of the batched engine (device array, one per domain).
+struct DomState {
+  int64_t steps;
+  double resid, best;
+  int status, stall;
+};
+
+// lbm_aux.hip
+hipError_t decide_domains(const int *tile_begin, const int *tile_end, const double *partials,
+                          void *state, int *active, int *n_active, int ndom, double tol,
+                          int stall_checks, int steps, hipStream_t s);
+hipError_t add_domain_steps(const int *active, void *state, int ndom, int64_t n, hipStream_t s);
 
 const LatticeOps &ops_d2q9();
 const LatticeOps &ops_d3q19();
 const LatticeOps &ops_d3q27();
+
+// Error reporting shared by the runtime units (lbm_runtime.hip): records the message
+// for lbm_last_error() and returns status.
+int set_error(int status, const char *fmt, ...);
 
 inline dim3 grid_of(const LaunchDesc &d) {
   return dim3((d.geo.nx + d.bx - 1) / d.bx, (d.geo.ny + d.by - 1) / d.by, d.geo.nz);

@@ -114,6 +114,28 @@ struct StepArgs {
   T c0, c1;  // BGK: omega, 1 - omega/2;  SMRT: q2, q3
 };
 
+// One node of the fused step: pull the populations (periodic wrap or halfway
+// bounce-back), collide with the force, store at the node's own slots.
+template <class L, int COLL, class S, class T, int MEM>
+__device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restrict__ fout,
+                                          const Geom &geo, int x, int y, int z, int node,
+                                          const T (&g)[3], T shift, T c0, T c1) {
+  T d[L::Q];
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, geo, node));
+  });
+  if constexpr (COLL == 0) {
+    collide_bgk<L>(d, shift, g, BGKCoef<T>{c0, c1});
+  } else {
+    collide_smrt<L>(d, shift, g, SMRTCoef<T>{c0, c1});
+  }
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    store_v<MEM, S, T>(fout + (int64_t)i * geo.N + node, d[i]);
+  });
+}
+
 template <class L, int COLL, class S, class T, int GK, int MEM>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -121,24 +143,10 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   const int z = blockIdx.z;
   if (x >= a.geo.nx || y >= a.geo.ny) return;
   const int node = (z * a.geo.ny + y) * a.geo.nx + x;
-  const S *__restrict__ fin = static_cast<const S *>(a.fin);
-  S *__restrict__ fout = static_cast<S *>(a.fout);
-  T d[L::Q];
-  static_for<L::Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, node));
-  });
   T g[3];
   load_force<T, GK>(a.force, x, y, z, node, a.geo.N, L::D, g);
-  if constexpr (COLL == 0) {
-    collide_bgk<L>(d, a.shift, g, BGKCoef<T>{a.c0, a.c1});
-  } else {
-    collide_smrt<L>(d, a.shift, g, SMRTCoef<T>{a.c0, a.c1});
-  }
-  static_for<L::Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    store_v<MEM, S, T>(fout + (int64_t)i * a.geo.N + node, d[i]);
-  });
+  step_node<L, COLL, S, T, MEM>(static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.geo,
+                                x, y, z, node, g, a.shift, a.c0, a.c1);
 }
 
 // Initial state: compute f-bar(x, 0) at every node and place each population in the

@@ -2,6 +2,7 @@
 // to the lattice struct (D2Q9, D3Q19, D3Q27) and LBM_OPS to the exported table name.
 #pragma once
 
+#include "lbm_batch_kernels.h"
 #include "lbm_internal.h"
 #include "lbm_kernels.h"
 
@@ -131,6 +132,41 @@ struct Ops {
                   : moments_t<S, T, GK_PROFILE>(d, rho, u, uprev, mode, partials, s);
     });
   }
+  template <int COLL, class S, class T, int MEM>
+  static hipError_t batch_step_t(const BatchLaunch &b, hipStream_t s) {
+    hipLaunchKernelGGL((batch_step_kernel<L, COLL, S, T, MEM>), dim3(b.grid), dim3(256), 0, s,
+                       static_cast<const S *>(b.fin), static_cast<S *>(b.fout),
+                       static_cast<const T *>(b.gbuf), static_cast<const BatchDom *>(b.doms),
+                       static_cast<const BatchTile *>(b.tiles), b.active, b.ntiles, T(b.shift));
+    return hipGetLastError();
+  }
+  static hipError_t batch_step(const BatchLaunch &b, hipStream_t s) {
+    return with_types(b.storage, [&](auto *sp, auto *tp) -> hipError_t {
+      using S = std::remove_pointer_t<decltype(sp)>;
+      using T = std::remove_pointer_t<decltype(tp)>;
+      switch (b.variant + 3 * b.coll) {
+        case 0: return batch_step_t<0, S, T, MEM_PLAIN>(b, s);
+        case 1: return batch_step_t<0, S, T, MEM_NTST>(b, s);
+        case 2: return batch_step_t<0, S, T, MEM_NTALL>(b, s);
+        case 3: return batch_step_t<1, S, T, MEM_PLAIN>(b, s);
+        case 4: return batch_step_t<1, S, T, MEM_NTST>(b, s);
+        case 5: return batch_step_t<1, S, T, MEM_NTALL>(b, s);
+        default: return hipErrorInvalidValue;
+      }
+    });
+  }
+  static hipError_t batch_monitor(const BatchLaunch &b, hipStream_t s) {
+    return with_types(b.storage, [&](auto *sp, auto *tp) -> hipError_t {
+      using S = std::remove_pointer_t<decltype(sp)>;
+      using T = std::remove_pointer_t<decltype(tp)>;
+      hipLaunchKernelGGL((batch_monitor_kernel<L, S, T>), dim3(b.grid), dim3(256), 0, s,
+                         static_cast<const S *>(b.fin), static_cast<const T *>(b.gbuf),
+                         static_cast<const BatchDom *>(b.doms),
+                         static_cast<const BatchTile *>(b.tiles), b.active, b.ntiles, T(b.shift),
+                         static_cast<T *>(b.urec), b.mode, b.partials);
+      return hipGetLastError();
+    });
+  }
 };
 
 }  // namespace impl
@@ -144,7 +180,9 @@ const LatticeOps &LBM_OPS() {
                                  &impl::Ops<LBM_LAT>::init,
                                  &impl::Ops<LBM_LAT>::gather,
                                  &impl::Ops<LBM_LAT>::scatter,
-                                 &impl::Ops<LBM_LAT>::moments};
+                                 &impl::Ops<LBM_LAT>::moments,
+                                 &impl::Ops<LBM_LAT>::batch_step,
+                                 &impl::Ops<LBM_LAT>::batch_monitor};
   return ops;
 }
 

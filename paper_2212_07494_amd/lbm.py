@@ -338,3 +338,166 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+
+# ---- batched engine (include/lbm_batch.h) ------------------------------------------------
+
+class lbm_domain(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc", C.c_int32 * 3),
+                ("tau", C.c_double * 5), ("g_kind", C.c_int32), ("g_axis", C.c_int32),
+                ("g_uniform", C.c_double * 3), ("g_data", C.c_void_p), ("rho_init", C.c_void_p),
+                ("u_init", C.c_void_p)]
+
+
+class lbm_batch_tuning(C.Structure):
+    _fields_ = [("tile_bx", C.c_int32), ("blocks_per_cu", C.c_int32), ("variant", C.c_int32)]
+
+    def as_tuple(self):
+        return (self.tile_bx, self.blocks_per_cu, self.variant)
+
+
+DOM_RUNNING, DOM_CONVERGED, DOM_FLOOR, DOM_NONFINITE = 0, 1, 2, 3
+
+EXPORTS_BATCH = {
+    "lbm_batch_init": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                        C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "lbm_batch_advance": ([C.c_void_p, C.c_int64], C.c_int),
+    "lbm_batch_run": ([C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
+                       C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_batch_moments": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_batch_get_populations": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "lbm_batch_set_populations": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "lbm_batch_set_tuning": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_batch_get_tuning": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_batch_autotune": ([C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "lbm_batch_info": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                        C.POINTER(C.c_size_t)], C.c_int),
+    "lbm_batch_free": ([C.c_void_p], C.c_int),
+}
+EXPORTS.update(EXPORTS_BATCH)
+
+
+def make_domain(shape, walls=(0, 0, 0), tau=(0.8, 0.8, 1.0), g=None, g_profile=None,
+                g_field=None, rho=None, u=None):
+    """Fill an lbm_domain; returns (struct, arrays it points to)."""
+    nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+    d = lbm_domain()
+    d.nx, d.ny, d.nz = nx, ny, nz
+    d.bc = (C.c_int32 * 3)(*[int(w) for w in walls])
+    d.tau = (C.c_double * 5)(0.0, 0.0, *tau)
+    keep = []
+    if g_field is not None:
+        arr = np.ascontiguousarray(g_field, dtype=np.float64)
+        d.g_kind, d.g_data = G_FIELD, arr.ctypes.data
+        keep.append(arr)
+    elif g_profile is not None:
+        axis, table = g_profile
+        arr = np.ascontiguousarray(table, dtype=np.float64)
+        d.g_kind, d.g_axis, d.g_data = G_PROFILE, int(axis), arr.ctypes.data
+        keep.append(arr)
+    else:
+        d.g_kind = G_UNIFORM
+        d.g_uniform = (C.c_double * 3)(*([0.0] * 3 if g is None else [float(v) for v in g]))
+    for name, val in (("rho_init", rho), ("u_init", u)):
+        if val is not None:
+            arr = np.ascontiguousarray(val, dtype=np.float64)
+            setattr(d, name, arr.ctypes.data)
+            keep.append(arr)
+    return d, keep
+
+
+class Batch:
+    """Owns one lbm_batch context: many domains stepped by one persistent launch."""
+
+    def __init__(self, domains, lattice="D2Q9", collision="smrt", storage="f32s", rho0=1.0,
+                 stream=None):
+        """domains: list of dicts with keys shape, walls, tau, and g / g_profile / g_field,
+        optionally rho, u."""
+        lib = load()
+        self.lattice = lattice
+        self.Q = QOF[lattice]
+        self.D = 2 if lattice == "D2Q9" else 3
+        self.shapes = []
+        structs, self._keep = [], []
+        for dd in domains:
+            s, keep = make_domain(**dd)
+            structs.append(s)
+            self._keep.extend(keep)
+            self.shapes.append((s.nx, s.ny, s.nz))
+        arr = (lbm_domain * len(structs))(*structs)
+        out = C.c_void_p()
+        _check(lib.lbm_batch_init(C.cast(arr, C.c_void_p), len(structs), LATTICES[lattice],
+                                  COLLISIONS[collision], STORAGES[storage], rho0,
+                                  _stream_handle(stream), C.byref(out)))
+        self.ctx = out
+        self.ndom = len(structs)
+
+    def advance(self, n):
+        _check(load().lbm_batch_advance(self.ctx, int(n)))
+
+    def run(self, max_steps, tol, check_every=200, stall_checks=10):
+        steps = np.zeros(self.ndom, np.int64)
+        resid = np.zeros(self.ndom)
+        status = np.zeros(self.ndom, np.int32)
+        _check(load().lbm_batch_run(self.ctx, int(max_steps), float(tol), int(check_every),
+                                    int(stall_checks), _ptr(steps), _ptr(resid), _ptr(status)))
+        return steps, resid, status
+
+    def N(self, d):
+        nx, ny, nz = self.shapes[d]
+        return nx * ny * nz
+
+    def moments(self, d):
+        rho = np.empty(self.N(d))
+        u = np.empty((self.D, self.N(d)))
+        _check(load().lbm_batch_moments(self.ctx, int(d), _ptr(rho), _ptr(u)))
+        return rho, u
+
+    def populations(self, d):
+        f = np.empty((self.Q, self.N(d)))
+        _check(load().lbm_batch_get_populations(self.ctx, int(d), _ptr(f)))
+        return f
+
+    def set_populations(self, d, f):
+        arr = np.ascontiguousarray(f, dtype=np.float64)
+        _check(load().lbm_batch_set_populations(self.ctx, int(d), _ptr(arr)))
+
+    def tune(self, tile_bx=None, blocks_per_cu=None, variant=None, autotune_steps=None):
+        lib = load()
+        if autotune_steps:
+            t = lbm_batch_tuning()
+            ms = C.c_double()
+            _check(lib.lbm_batch_autotune(self.ctx, int(autotune_steps), C.byref(t), C.byref(ms)))
+            return t.as_tuple(), ms.value
+        t = lbm_batch_tuning()
+        _check(lib.lbm_batch_get_tuning(self.ctx, C.byref(t)))
+        if tile_bx is not None:
+            t.tile_bx = tile_bx
+        if blocks_per_cu is not None:
+            t.blocks_per_cu = blocks_per_cu
+        if variant is not None:
+            t.variant = variant
+        _check(lib.lbm_batch_set_tuning(self.ctx, C.byref(t)))
+        return t.as_tuple(), None
+
+    def info(self):
+        n, t, b = C.c_int64(), C.c_int64(), C.c_size_t()
+        _check(load().lbm_batch_info(self.ctx, C.byref(n), C.byref(t), C.byref(b)))
+        return dict(nodes=n.value, tiles=t.value, bytes=b.value)
+
+    def close(self):
+        if self.ctx:
+            _check(load().lbm_batch_free(self.ctx))
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,11 +16,12 @@ def _declared(header):
     return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
 
 
-def test_library_exports_every_declared_symbol():
+@pytest.mark.parametrize("header", ["lbm.h", "lbm_batch.h"])
+def test_library_exports_every_declared_symbol(header):
     from paper_2212_07494_amd import lbm
     lib = lbm.load()
-    names = _declared("lbm.h")
-    assert "lbm_init" in names and "lbm_step" in names
+    names = _declared(header)
+    assert len(names) >= 8
     for n in names:
         assert hasattr(lib, n), n
     # the binding covers the same names
@@ -71,6 +72,21 @@ def test_unknown_enums_and_null_arguments():
     assert lib.lbm_step(None, 1, None) == lbm.LBM_ESTATE
     assert lib.lbm_free(None) == lbm.LBM_ESTATE
     assert lib.lbm_copy_probe(None, None, 16, 1, 256, 0, None) == lbm.LBM_EINVAL
+
+
+def test_batch_rejects_invalid_domains():
+    from paper_2212_07494_amd import lbm
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.Batch([dict(shape=(8, 8, 1)), dict(shape=(8, 8, 1), tau=(0.4, 0.8, 1.0))],
+                  lattice="D2Q9", collision="bgk", storage="f32s")
+    assert ei.value.status == lbm.LBM_EINVAL and "domain 1" in str(ei.value)
+    with pytest.raises(lbm.LBMError):
+        lbm.Batch([dict(shape=(8, 8, 1), tau=(0.8, 0.8, 0.5))], collision="smrt")
+    with pytest.raises(lbm.LBMError):
+        lbm.Batch([dict(shape=(8, 8, 2))], lattice="D2Q9")
+    lib = lbm.load()
+    assert lib.lbm_batch_advance(None, 1) == lbm.LBM_ESTATE
+    assert lib.lbm_batch_free(None) == lbm.LBM_ESTATE
 
 
 def test_generated_tables_are_current():
