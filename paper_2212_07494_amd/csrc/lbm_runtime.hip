@@ -246,6 +246,26 @@ int refresh_monitors(lbm_ctx *c, int mode) {
 
 }  // namespace
 
+namespace {
+
+// Network output (point-major rows: D velocity channels / U, then (rho - rho0) / U^2) or
+// plain planes (rho, then D velocity planes) -> binary64 planes for the init kernel.
+__global__ void fields_to_planes_kernel(const float *in, int point_major, int64_t N, int D,
+                                        double U, double rho0, double *rho, double *u) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  if (point_major) {
+    const float *row = in + n * (D + 1);
+    rho[n] = rho0 + U * U * (double)row[D];
+    for (int c = 0; c < D; ++c) u[c * N + n] = U * (double)row[c];
+  } else {
+    rho[n] = (double)in[n];
+    for (int c = 0; c < D; ++c) u[c * N + n] = (double)in[N + c * N + n];
+  }
+}
+
+}  // namespace
+
 extern "C" {
 
 int lbm_version(void) { return 100; }
@@ -481,6 +501,29 @@ int lbm_set_populations(lbm_ctx *c, const double *f) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->t = 0;
   c->uprev_time = -2;
+  return LBM_OK;
+}
+
+int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t point_major, double U) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!fields_dev) return fail(LBM_EINVAL, "fields_dev is NULL");
+  if (point_major && !(std::isfinite(U) && U > 0)) return fail(LBM_EINVAL, "U must be positive");
+  const size_t fld = (size_t)c->N * sizeof(double);
+  int rc = c->need_scratch(fld * (1 + c->D));
+  if (rc) return rc;
+  double *rho_d = static_cast<double *>(c->scratch);
+  double *u_d = reinterpret_cast<double *>(static_cast<char *>(c->scratch) + fld);
+  hipLaunchKernelGGL(fields_to_planes_kernel, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0,
+                     c->stream, fields_dev, point_major ? 1 : 0, c->N, c->D, U, c->p.rho0, rho_d,
+                     u_d);
+  HIP_TRY(hipGetLastError());
+  c->cur = 0;
+  lbm::LaunchDesc d = c->desc(1.0);
+  d.fout = c->buf[0];
+  HIP_TRY(c->ops->init(d, rho_d, u_d, c->p.rho0, c->stream));
+  c->t = 0;
+  c->uprev_time = -2;
+  c->mon.step = -1;
   return LBM_OK;
 }
 

@@ -207,3 +207,34 @@ def batch_domains(n=512, seed=7494, h_range=(16, 128), l_range=(64, 256),
             continue
         out.append(dict(kind=kind, nx=Lx, ny=H, tau2=tau2, g=amp, peak=peak))
     return out
+
+
+def mlp_init_params(widths, seed: int) -> np.ndarray:
+    """Seeded initial network parameters (flat, W_0, b_0, W_1, b_1, ...; W row-major
+    out x in): weights uniform in +-sqrt(6 / (in + out)), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(len(widths) - 1):
+        k, n = widths[l], widths[l + 1]
+        bound = math.sqrt(6.0 / (k + n))
+        parts.append(rng.uniform(-bound, bound, n * k))
+        parts.append(np.zeros(n))
+    return np.concatenate(parts)
+
+
+def warmstart_problem(seed: int, box: int = 128, tau_range=(0.55, 1.2), kmax=4,
+                      amp_range=(1e-7, 1e-5), umax=0.05, remax=0.5, nmodes=4):
+    """One seeded warm-start problem on a periodic box^3: tau2 uniform in tau_range and
+    nmodes Fourier forcing modes (fourier_modes), redrawn until the summed Stokes
+    amplitude U = sum_j amp_j / (nu K_j^2) (K_j = 2 pi |k_j| / box) is at most umax and
+    the Reynolds number U / (nu K_min) at most remax.  Returns dict(tau2, modes, U)."""
+    rng = np.random.default_rng(seed)
+    while True:
+        tau2 = float(rng.uniform(*tau_range))
+        modes = fourier_modes(seed=int(rng.integers(0, 2 ** 31)), nmodes=nmodes, kmax=kmax,
+                              amp_range=amp_range)
+        nu = (tau2 - 0.5) / 3
+        Ks = [2 * math.pi * float(np.linalg.norm(m["k"])) / box for m in modes]
+        U = sum(m["amp"] / (nu * K * K) for m, K in zip(modes, Ks))
+        if U <= umax and U / (nu * min(Ks)) <= remax:
+            return dict(tau2=tau2, modes=modes, U=U)

@@ -501,3 +501,132 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---- warm-start network (include/lbm_nn.h) -----------------------------------------------
+
+class lbm_ws_problem(C.Structure):
+    _fields_ = [("tau2", C.c_double), ("nmodes", C.c_int32), ("k", (C.c_double * 3) * 8),
+                ("p", (C.c_double * 3) * 8), ("amp", C.c_double * 8), ("phase", C.c_double * 8)]
+
+
+WS_FEATURES = 34
+
+EXPORTS_NN = {
+    "lbm_mlp_create": ([C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)],
+                       C.c_int),
+    "lbm_mlp_num_params": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
+    "lbm_mlp_set_params": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
+    "lbm_mlp_get_params": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
+    "lbm_mlp_get_grads": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
+    "lbm_mlp_forward": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+    "lbm_mlp_loss_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)],
+                              C.c_int),
+    "lbm_mlp_backward": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_mlp_zero_grads": ([C.c_void_p], C.c_int),
+    "lbm_mlp_adam": ([C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64],
+                     C.c_int),
+    "lbm_mlp_free": ([C.c_void_p], C.c_int),
+    "lbm_ws_features": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double),
+                         C.c_void_p], C.c_int),
+    "lbm_upsample_periodic": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                               C.c_void_p], C.c_int),
+    "lbm_reset_fields": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double], C.c_int),
+}
+EXPORTS.update(EXPORTS_NN)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or an int)."""
+    return C.c_void_p(t if isinstance(t, int) else t.data_ptr())
+
+
+class MLP:
+    """Owns one lbm_mlp: BF16 per-point network with FP32 master weights.  Device arrays
+    are torch float32 CUDA tensors (row-major, one row per point)."""
+
+    def __init__(self, widths, max_rows, stream=None):
+        lib = load()
+        self.widths = list(widths)
+        arr = (C.c_int32 * len(widths))(*widths)
+        out = C.c_void_p()
+        _check(lib.lbm_mlp_create(C.cast(arr, C.c_void_p), len(widths) - 1, int(max_rows),
+                                  _stream_handle(stream), C.byref(out)))
+        self.ctx = out
+        n = C.c_int64()
+        _check(lib.lbm_mlp_num_params(self.ctx, C.byref(n)))
+        self.nparams = n.value
+
+    def set_params(self, p):
+        arr = np.ascontiguousarray(p, dtype=np.float32)
+        _check(load().lbm_mlp_set_params(self.ctx, _ptr(arr), arr.size))
+
+    def params(self):
+        out = np.empty(self.nparams, np.float32)
+        _check(load().lbm_mlp_get_params(self.ctx, _ptr(out), out.size))
+        return out
+
+    def grads(self):
+        out = np.empty(self.nparams, np.float32)
+        _check(load().lbm_mlp_get_grads(self.ctx, _ptr(out), out.size))
+        return out
+
+    def forward(self, x, y):
+        _check(load().lbm_mlp_forward(self.ctx, _dptr(x), int(x.shape[0]), _dptr(y)))
+
+    def zero_grads(self):
+        _check(load().lbm_mlp_zero_grads(self.ctx))
+
+    def loss_backward(self, target, weight=None):
+        w = None if weight is None else np.ascontiguousarray(weight, np.float32)
+        loss = C.c_double()
+        _check(load().lbm_mlp_loss_backward(self.ctx, _dptr(target), _ptr(w), C.byref(loss)))
+        return loss.value
+
+    def backward(self, dy):
+        _check(load().lbm_mlp_backward(self.ctx, _dptr(dy)))
+
+    def adam(self, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+        _check(load().lbm_mlp_adam(self.ctx, lr, b1, b2, eps, int(t)))
+
+    def close(self):
+        if self.ctx:
+            _check(load().lbm_mlp_free(self.ctx))
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ws_problem_struct(problem):
+    """lbm_ws_problem from dict(tau2, modes=[dict(k, p, amp, phase)])."""
+    s = lbm_ws_problem()
+    s.tau2 = problem["tau2"]
+    s.nmodes = len(problem["modes"])
+    for j, m in enumerate(problem["modes"]):
+        for a in range(3):
+            s.k[j][a] = float(m["k"][a])
+            s.p[j][a] = float(m["p"][a])
+        s.amp[j] = m["amp"]
+        s.phase[j] = m["phase"]
+    return s
+
+
+def lbm_ws_features(problem, n, box, x_dev, stream=None):
+    s = ws_problem_struct(problem)
+    U = C.c_double()
+    _check(load().lbm_ws_features(C.byref(s), int(n), int(box), _dptr(x_dev), C.byref(U),
+                                  _stream_handle(stream)))
+    return U.value
+
+
+def lbm_upsample_periodic(coarse, nc, nchan, fine, nf, stream=None):
+    _check(load().lbm_upsample_periodic(_dptr(coarse), int(nc), int(nchan), _dptr(fine), int(nf),
+                                        _stream_handle(stream)))
+
+
+def lbm_reset_fields(ctx, fields, point_major, U=1.0):
+    _check(load().lbm_reset_fields(ctx, _dptr(fields), int(bool(point_major)), float(U)))

@@ -16,7 +16,7 @@ def _declared(header):
     return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
 
 
-@pytest.mark.parametrize("header", ["lbm.h", "lbm_batch.h"])
+@pytest.mark.parametrize("header", ["lbm.h", "lbm_batch.h", "lbm_nn.h"])
 def test_library_exports_every_declared_symbol(header):
     from paper_2212_07494_amd import lbm
     lib = lbm.load()
