@@ -43,9 +43,12 @@ int lbm_mlp_set_params(lbm_mlp *m, const float *host, int64_t n);
 int lbm_mlp_get_params(lbm_mlp *m, float *host, int64_t n);
 int lbm_mlp_get_grads(lbm_mlp *m, float *host, int64_t n);
 
-/* y (rows x outputs, FP32 device) = network(x (rows x inputs, FP32 device)); x is
- * rounded to BF16.  Keeps what backward needs. */
-int lbm_mlp_forward(lbm_mlp *m, const float *x_dev, int64_t rows, float *y_dev);
+/* y (rows x outputs, FP32 device) = scale * network(x (rows x inputs, FP32 device)) +
+ * addend (rows x outputs, FP32 device; NULL = none: the network then learns the residual
+ * over a given field); scale per output channel (lbm_mlp_set_output_scale, default 1);
+ * x is rounded to BF16.  Keeps what backward needs. */
+int lbm_mlp_forward(lbm_mlp *m, const float *x_dev, int64_t rows, const float *addend_dev,
+                    float *y_dev);
 
 /* Weighted mean-square loss of the last forward's output against target (rows x
  * outputs, device): L = sum_{r,c} w_c (y - t)^2 / (rows * outputs), w = channel_weight
@@ -53,6 +56,16 @@ int lbm_mlp_forward(lbm_mlp *m, const float *x_dev, int64_t rows, float *y_dev);
  * lbm_mlp_zero_grads first) and returns L in *loss (may be NULL). */
 int lbm_mlp_loss_backward(lbm_mlp *m, const float *target_dev, const float *channel_weight,
                           double *loss);
+
+/* Output scale per channel (host, outputs entries, each > 0): lets the last layer work
+ * at unit scale when the targets are small.  Applies to later forward / backward calls. */
+int lbm_mlp_set_output_scale(lbm_mlp *m, const float *scale);
+
+/* The same weighted mean-square loss for any y (rows x outputs, device, rows >= 1)
+ * against target: L into *loss (may be NULL) and dL/dy into dy_dev (device).  Does not
+ * touch the network's gradients (for a loss on a field derived from the output). */
+int lbm_mlp_loss_grad(lbm_mlp *m, const float *y_dev, const float *target_dev,
+                      const float *channel_weight, int64_t rows, float *dy_dev, double *loss);
 
 /* Accumulate the gradients of sum(dy * y) for a given dL/dy (rows x outputs, device)
  * of the last forward. */
@@ -74,27 +87,74 @@ typedef struct {
   double phase[8];
 } lbm_ws_problem;
 
-#define LBM_WS_FEATURES 34  /* features per point (8 per mode for 4 modes + 2) */
+#define LBM_WS_FEATURES 46  /* features per point (11 per mode for 4 modes + 2) */
 
 /* Per-point network inputs on an n^3 grid spanning the box (point (i,j,l) sits at lattice
  * position (i, j, l) * box / n), rows in x-fastest order.  Needs nmodes == 4.  Also
- * returns the velocity scale U of the problem (outputs are velocity / U and
- * (rho - 1) / U^2).  Features per mode j, with K_j = 2 pi |k_j| / box and
- * s_j = amp_j / (nu K_j^2): p_j sin(theta_j) (3), p_j cos(theta_j) (3), s_j / U,
- * K_j; then tau2 - 1/2 and the Reynolds number U / (nu K_min). */
+ * returns the velocity scale U = sum_j |s_j| of the problem (the network's outputs are
+ * velocity / U and (rho - rho0) / (U rho_scale)).  Features per mode j, with K_j = 2 pi |k_j| / box,
+ * s_j = amp_j / (nu K_j^2) and theta_j = 2 pi k_j . x / box + phase_j:
+ * p_j sin(theta_j) (3), p_j cos(theta_j) (3), s_j / U, K_j, k_j / |k_j| (3); then
+ * tau2 - 1/2 and the Reynolds number U / (nu K_min).
+ * base_dev (rows x 4, may be NULL) receives the perturbative steady solution of the
+ * incompressible equations in the same units (rho0 = 1; rho_scale > 0 is used only
+ * here):
+ *   base_order 1: the Stokes superposition u1 = sum_j s_j p_j sin(theta_j), density 0
+ *     (each mode alone, with advection dropped, is steady there);
+ *   base_order 2: plus u2 and its pressure, nu lap u2 = (u1 . grad) u1 + grad p2 / rho0,
+ *     solved exactly: every pair i != j forces the waves theta_i +- theta_j with
+ *     A = s_i s_j (p_i . k_j) p_j / 2, giving u2 = -P_q A / (nu |q|^2) sin(.) (P_q the
+ *     projection normal to q = k_i +- k_j, q = 0 skipped) and
+ *     rho - rho0 = 3 p2 = 3 (q . A) / |q|^2 cos(.). */
 int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_dev,
-                    double *U_out, void *hip_stream);
+                    float *base_dev, int32_t base_order, double rho_scale, double *U_out,
+                    void *hip_stream);
+/* (x_dev may be NULL when base_dev is not: the base alone, e.g. on the full lattice.) */
 
-/* Periodic trilinear upsampling of nchan fields (channel-major planes, nc^3 each, x
- * fastest) to nf^3 (nf a multiple of nc): fine point x takes the coarse grid at x nc/nf. */
-int lbm_upsample_periodic(const float *coarse_dev, int32_t nc, int32_t nchan, float *fine_dev,
+/* Solenoidal composition of the network's output on count stacked periodic n^3 grids
+ * (rows n^3 per grid, x fastest, 4 channels): out = base + (curl psi, r) where psi is
+ * channels 0..2 of y, r channel 3, and the curl takes central differences of unit grid
+ * spacing, so the velocity correction has zero discrete divergence.  base may be NULL;
+ * then the map is linear and its own adjoint (the transpose of the central difference is
+ * its negative), which is how a loss gradient on out is taken back to y.  out must not
+ * alias y. */
+int lbm_ws_compose(const float *y_dev, const float *base_dev, int32_t n, int32_t count,
+                   float *out_dev, void *hip_stream);
+
+/* Periodic trilinear upsampling of nchan fields on an nc^3 grid (x fastest) to nf^3 (nf
+ * a multiple of nc): fine point x takes the coarse grid at x nc/nf.  Input channel-major
+ * planes (point_major_in == 0) or point-major rows of nchan values (the network's
+ * output); output channel-major planes, plus addend (point-major nf^3 x nchan rows,
+ * device; may be NULL).  With an even ratio nf/nc the interpolation has zero transfer
+ * at the fine grid's wavenumber pi. */
+int lbm_upsample_periodic(const float *coarse_dev, int32_t nc, int32_t nchan,
+                          int32_t point_major_in, const float *addend_dev, float *fine_dev,
                           int32_t nf, void *hip_stream);
 
-/* Restart lattice c from device fields: rho (N floats) and u (D x N floats, component
- * planes), or from the network's point-major output (N x (D+1): u / U then
- * (rho - 1) / U^2, when point_major != 0, scaled by U).  The state becomes the
- * force-corrected equilibrium of those fields (as lbm_init), time 0. */
-int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t point_major, double U);
+/* Restart lattice c from device fields (N nodes, D velocity components):
+ *   layout 0: planes rho (N), then u (D x N) (U and R unused);
+ *   layout 1: the network's point-major rows (N x (D+1)): u / U, then (rho - rho0) / R;
+ *   layout 2: the same quantities as channel-major planes ((D+1) x N).
+ * flags (bits) transform the fields, in binary64 and in this order, before the state is
+ * built:
+ *   LBM_RESET_FILTER: along every periodic axis, the 7-point low-pass filter
+ *     (11/16, 15/64, -3/32, 1/64 at offsets 0, +-1, +-2, +-3), transfer 1 - sin^6(k/2),
+ *     which removes the wavenumber pi.  The linearised step of every velocity set here
+ *     has an eigenvalue -1 at k = (pi, 0, 0) (and its permutations), a checkerboard
+ *     along one axis that never decays, so a start with content there never becomes
+ *     steady;
+ *   LBM_RESET_MASS: adds one constant to rho so that sum rho = N rho0 (the mass of the
+ *     plain start);
+ *   LBM_RESET_MOMENTUM: subtracts one constant vector from u so that sum rho u = 0.
+ *     With no walls the dynamics conserve total mass and momentum (the forcing sums to
+ *     zero over the periodic box), so a start that differs from the plain start in
+ *     them ends in a different, drifting state.
+ * The state becomes the force-corrected equilibrium of the fields (as lbm_init), time 0. */
+#define LBM_RESET_MASS 1
+#define LBM_RESET_MOMENTUM 2
+#define LBM_RESET_FILTER 4
+int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t layout, double U, double R,
+                     int32_t flags);
 
 #ifdef __cplusplus
 }

@@ -178,3 +178,49 @@ def e2_error(u, ua) -> float:
     u = np.asarray(u, dtype=np.float64)
     ua = np.asarray(ua, dtype=np.float64)
     return math.sqrt(float(np.sum((u - ua) ** 2) / np.sum(ua ** 2)))
+
+
+def fourier_perturbative_steady(box: int, tau2: float, modes, order: int = 2, rho0: float = 1.0):
+    """Steady periodic flow of the incompressible equations forced by solenoidal Fourier
+    modes g = sum_j amp_j p_j sin(theta_j), theta_j = 2 pi k_j . x / box + phase_j, in
+    powers of the forcing (this is not from the paper: it is the analytic start the warm
+    start is measured against).
+
+    order 1 (Stokes): nu lap u1 = -g, so u1 = sum_j s_j p_j sin(theta_j) with
+    s_j = amp_j / (nu K_j^2).  order 2: nu lap u2 = (u1 . grad) u1 + grad p2 / rho0; the
+    advection of mode j by mode i is s_i s_j (p_i . K_j) p_j sin(theta_i) cos(theta_j),
+    half a wave at theta_i + theta_j and half at theta_i - theta_j; for a wave
+    A sin(q . x + phi) the solenoidal part P_q A = A - q (q . A) / |q|^2 gives
+    u2 = -P_q A sin(.) / (nu |q|^2) and the rest the pressure p2 = rho0 (q . A) cos(.) /
+    |q|^2 (q = 0 waves are uniform and drop out).  Density rho0 + p2 / c_s^2.
+
+    Returns (rho (N,), u (3, N)) on the box^3 lattice, x fastest."""
+    nu = (tau2 - 0.5) / 3.0
+    x, y, z = (np.arange(box ** 3) % box, (np.arange(box ** 3) // box) % box,
+               np.arange(box ** 3) // box ** 2)
+    pos = np.stack([x, y, z]).astype(np.float64)
+    kp = 2.0 * math.pi / box
+    ks = [kp * np.asarray(m["k"], np.float64) for m in modes]
+    ps = [np.asarray(m["p"], np.float64) for m in modes]
+    th = [k @ pos + m["phase"] for k, m in zip(ks, modes)]
+    s = [m["amp"] / (nu * float(k @ k)) for k, m in zip(ks, modes)]
+    u = np.zeros((3, box ** 3))
+    rho = np.full(box ** 3, rho0)
+    for j in range(len(modes)):
+        u += s[j] * np.outer(ps[j], np.sin(th[j]))
+    if order >= 2:
+        for i in range(len(modes)):
+            for j in range(len(modes)):
+                if i == j:
+                    continue
+                A = 0.5 * s[i] * s[j] * float(ps[i] @ ks[j]) * ps[j]
+                for sg in (1.0, -1.0):
+                    q = ks[i] + sg * ks[j]
+                    q2 = float(q @ q)
+                    if q2 < 1e-300:
+                        continue
+                    phase = th[i] + sg * th[j]
+                    PA = A - q * float(q @ A) / q2
+                    u -= np.outer(PA / (nu * q2), np.sin(phase))
+                    rho += 3.0 * rho0 * float(q @ A) / q2 * np.cos(phase)
+    return rho, u

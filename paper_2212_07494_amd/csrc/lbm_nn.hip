@@ -128,23 +128,30 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * z * z);
 }
 
-// Z += bias (per column); act: X_next = bf16(gelu(Z)) or, for the output layer, y = Z.
+// Z += bias (per column); act: X_next = bf16(gelu(Z)) or, for the output layer,
+// y = scale_c Z (+ addend, a field the network's output is added to).
 __global__ void bias_act_kernel(float *Z, const float *bias, int64_t rows, int cols,
-                                bf16 *x_next, float *y_out) {
+                                bf16 *x_next, float *y_out, const float *oscale,
+                                const float *addend) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows * cols) return;
-  const float z = Z[i] + bias[i % cols];
+  const int c = (int)(i % cols);
+  const float z = Z[i] + bias[c];
   Z[i] = z;
   if (x_next) x_next[i] = bf16(gelu(z));
-  if (y_out) y_out[i] = z;
+  if (y_out) {
+    const float y = oscale[c] * z;
+    y_out[i] = addend ? y + addend[i] : y;
+  }
 }
 
-// dZ = dA * gelu'(Z) (or dZ = dA for the output layer); also the BF16 copy.
-__global__ void act_back_kernel(const float *dA, const float *Z, int64_t n, int use_gelu,
-                                float *dZ, bf16 *dZb) {
+// dZ = dA * gelu'(Z) for hidden layers, dZ = scale_c dA for the output layer; also the
+// BF16 copy.
+__global__ void act_back_kernel(const float *dA, const float *Z, int64_t n, int cols,
+                                const float *oscale, float *dZ, bf16 *dZb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float d = use_gelu ? dA[i] * gelu_grad(Z[i]) : dA[i];
+  const float d = oscale ? dA[i] * oscale[i % cols] : dA[i] * gelu_grad(Z[i]);
   dZ[i] = d;
   dZb[i] = bf16(d);
 }
@@ -227,6 +234,8 @@ struct lbm_mlp {
   int64_t part_elems = 0;
   double *lossp = nullptr;
   float *dy = nullptr, *cw = nullptr;
+  float *oscale = nullptr;          // output scale per channel (device)
+  std::vector<float> cw_host, oscale_host;  // stay valid while copies are in flight
   float *last_y = nullptr;
   std::vector<void *> owned;
 
@@ -332,7 +341,8 @@ int lbm_mlp_create(const int32_t *widths, int32_t nlayers, int64_t max_rows, voi
       (rc = m->alloc((void **)&m->part, m->part_elems * 4)) ||
       (rc = m->alloc((void **)&m->lossp, 1024 * 8)) ||
       (rc = m->alloc((void **)&m->dy, max_rows * m->w[nlayers] * 4)) ||
-      (rc = m->alloc((void **)&m->cw, 4096 * 4)))
+      (rc = m->alloc((void **)&m->cw, 4096 * 4)) ||
+      (rc = m->alloc((void **)&m->oscale, 4096 * 4)))
     return fail_free(rc);
   m->X.resize(nlayers);
   m->Z.resize(nlayers);
@@ -346,8 +356,13 @@ int lbm_mlp_create(const int32_t *widths, int32_t nlayers, int64_t max_rows, voi
       hipMemsetAsync(m->grads, 0, off * 4, s) != hipSuccess ||
       hipMemsetAsync(m->m1, 0, off * 4, s) != hipSuccess ||
       hipMemsetAsync(m->m2, 0, off * 4, s) != hipSuccess ||
-      hipMemsetAsync(m->wb, 0, off * 2, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      hipMemsetAsync(m->wb, 0, off * 2, s) != hipSuccess)
     return fail_free(set_error(LBM_EDEVICE, "clearing the parameters failed"));
+  m->oscale_host.assign(m->w[nlayers], 1.0f);
+  if (hipMemcpyAsync(m->oscale, m->oscale_host.data(), m->w[nlayers] * 4, hipMemcpyHostToDevice,
+                     s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail_free(set_error(LBM_EDEVICE, "setting the output scale failed"));
   *out = m;
   return LBM_OK;
 }
@@ -393,7 +408,8 @@ int lbm_mlp_zero_grads(lbm_mlp *m) {
   return LBM_OK;
 }
 
-int lbm_mlp_forward(lbm_mlp *m, const float *x_dev, int64_t rows, float *y_dev) {
+int lbm_mlp_forward(lbm_mlp *m, const float *x_dev, int64_t rows, const float *addend_dev,
+                    float *y_dev) {
   if (!valid(m)) return set_error(LBM_ESTATE, "invalid network");
   if (!x_dev || !y_dev) return set_error(LBM_EINVAL, "NULL device array");
   if (rows < 1 || rows > m->max_rows) return set_error(LBM_EINVAL, "rows %lld out of range", (long long)rows);
@@ -408,7 +424,7 @@ int lbm_mlp_forward(lbm_mlp *m, const float *x_dev, int64_t rows, float *y_dev) 
     const bool last = l == m->L - 1;
     hipLaunchKernelGGL(bias_act_kernel, dim3(blocks_for(rows * N)), dim3(256), 0, s, m->Z[l],
                        m->params + m->boff[l], rows, N, last ? nullptr : m->X[l + 1],
-                       last ? y_dev : nullptr);
+                       last ? y_dev : nullptr, m->oscale, last ? addend_dev : nullptr);
     HIP_TRY(hipGetLastError());
   }
   m->rows = rows;
@@ -426,7 +442,7 @@ int lbm_mlp_backward(lbm_mlp *m, const float *dy_dev) {
     const int K = m->w[l], N = m->w[l + 1];
     const bool last = l == m->L - 1;
     hipLaunchKernelGGL(act_back_kernel, dim3(blocks_for(rows * N)), dim3(256), 0, s, dA, m->Z[l],
-                       rows * N, last ? 0 : 1, m->dZ, m->dZb);
+                       rows * N, N, last ? m->oscale : nullptr, m->dZ, m->dZb);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(colsum_kernel, dim3(N), dim3(256), 0, s, m->dZ, rows, N,
                        m->grads + m->boff[l]);
@@ -444,24 +460,63 @@ int lbm_mlp_backward(lbm_mlp *m, const float *dy_dev) {
   return LBM_OK;
 }
 
+int lbm_mlp_set_output_scale(lbm_mlp *m, const float *scale) {
+  if (!valid(m)) return set_error(LBM_ESTATE, "invalid network");
+  if (!scale) return set_error(LBM_EINVAL, "scale is NULL");
+  const int C = m->w[m->L];
+  for (int c = 0; c < C; ++c)
+    if (!(std::isfinite(scale[c]) && scale[c] > 0))
+      return set_error(LBM_EINVAL, "output scale %d must be positive", c);
+  HIP_TRY(hipStreamSynchronize(m->stream));  // earlier copies from oscale_host are done
+  m->oscale_host.assign(scale, scale + C);
+  HIP_TRY(hipMemcpyAsync(m->oscale, m->oscale_host.data(), C * 4, hipMemcpyHostToDevice,
+                         m->stream));
+  return LBM_OK;
+}
+
+// Weighted mean-square loss of y against target and its gradient dy (device, rows x C).
+static int mse_grad(lbm_mlp *m, const float *y, const float *target, const float *channel_weight,
+                    int64_t rows, float *dy, double *loss) {
+  const int C = m->w[m->L];
+  HIP_TRY(hipStreamSynchronize(m->stream));  // earlier copies from cw_host are done
+  m->cw_host.assign(C, 1.0f);
+  if (channel_weight)
+    for (int c = 0; c < C; ++c) m->cw_host[c] = channel_weight[c];
+  HIP_TRY(hipMemcpyAsync(m->cw, m->cw_host.data(), C * 4, hipMemcpyHostToDevice, m->stream));
+  const int nb = 1024;
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, m->stream, y, target, m->cw, rows, C, dy,
+                     m->lossp);
+  HIP_TRY(hipGetLastError());
+  if (loss) {
+    std::vector<double> h(nb);
+    HIP_TRY(hipMemcpyAsync(h.data(), m->lossp, nb * 8, hipMemcpyDeviceToHost, m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    double s = 0;
+    for (double v : h) s += v;
+    *loss = s;
+  }
+  return LBM_OK;
+}
+
+int lbm_mlp_loss_grad(lbm_mlp *m, const float *y_dev, const float *target_dev,
+                      const float *channel_weight, int64_t rows, float *dy_dev, double *loss) {
+  if (!valid(m)) return set_error(LBM_ESTATE, "invalid network");
+  if (!y_dev || !target_dev || !dy_dev) return set_error(LBM_EINVAL, "NULL device array");
+  if (rows < 1) return set_error(LBM_EINVAL, "rows must be positive");
+  return mse_grad(m, y_dev, target_dev, channel_weight, rows, dy_dev, loss);
+}
+
 int lbm_mlp_loss_backward(lbm_mlp *m, const float *target_dev, const float *channel_weight,
                           double *loss) {
   if (!valid(m)) return set_error(LBM_ESTATE, "invalid network");
   if (!target_dev || m->rows < 1) return set_error(LBM_EINVAL, "loss needs a forward first");
-  const int C = m->w[m->L];
-  std::vector<float> w(C, 1.0f);
-  if (channel_weight)
-    for (int c = 0; c < C; ++c) w[c] = channel_weight[c];
-  HIP_TRY(hipMemcpyAsync(m->cw, w.data(), C * 4, hipMemcpyHostToDevice, m->stream));
-  const int nb = 1024;
-  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, m->stream, m->last_y, target_dev, m->cw,
-                     m->rows, C, m->dy, m->lossp);
-  HIP_TRY(hipGetLastError());
-  int rc = lbm_mlp_backward(m, m->dy);
+  int rc = mse_grad(m, m->last_y, target_dev, channel_weight, m->rows, m->dy, nullptr);
+  if (rc) return rc;
+  rc = lbm_mlp_backward(m, m->dy);
   if (rc) return rc;
   if (loss) {
-    std::vector<double> h(nb);
-    HIP_TRY(hipMemcpyAsync(h.data(), m->lossp, nb * 8, hipMemcpyDeviceToHost, m->stream));
+    std::vector<double> h(1024);
+    HIP_TRY(hipMemcpyAsync(h.data(), m->lossp, 1024 * 8, hipMemcpyDeviceToHost, m->stream));
     HIP_TRY(hipStreamSynchronize(m->stream));
     double s = 0;
     for (double v : h) s += v;
@@ -503,34 +558,104 @@ struct ModeDev {
 };
 
 __global__ void features_kernel(ModeDev m0, ModeDev m1, ModeDev m2, ModeDev m3, int n, float step,
-                                float inv_box2pi, float tau_m, float re, float invU,
-                                float *__restrict__ x) {
+                                float inv_box2pi, float tau_m, float re, float invU, float U,
+                                int order, float inv_rho_scale, float *__restrict__ x,
+                                float *__restrict__ base) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = (int64_t)n * n * n;
   if (idx >= N) return;
   const float px = (float)(idx % n) * step;
   const float py = (float)((idx / n) % n) * step;
   const float pz = (float)(idx / ((int64_t)n * n)) * step;
-  float *o = x + idx * LBM_WS_FEATURES;
+  float tmp[LBM_WS_FEATURES];
+  float *o = x ? x + idx * LBM_WS_FEATURES : tmp;
   const ModeDev ms[4] = {m0, m1, m2, m3};
+  float th[4];
+  float ub[3] = {0.0f, 0.0f, 0.0f};
   for (int j = 0; j < 4; ++j) {
     const ModeDev &m = ms[j];
     // theta = 2 pi k . x / box + phase
-    const float th = (m.k[0] * px + m.k[1] * py + m.k[2] * pz) * inv_box2pi + m.phase;
-    const float sn = sinf(th), cs = cosf(th);
+    th[j] = (m.k[0] * px + m.k[1] * py + m.k[2] * pz) * inv_box2pi + m.phase;
+    const float sn = sinf(th[j]), cs = cosf(th[j]);
+    const float a_j = m.s * invU;
+    const float kn = m.K / inv_box2pi;  // |k_j| in integer units
     for (int a = 0; a < 3; ++a) {
-      o[8 * j + a] = m.p[a] * sn;
-      o[8 * j + 3 + a] = m.p[a] * cs;
+      o[11 * j + a] = m.p[a] * sn;
+      o[11 * j + 3 + a] = m.p[a] * cs;
+      o[11 * j + 8 + a] = m.k[a] / kn;
+      ub[a] += a_j * (m.p[a] * sn);
     }
-    o[8 * j + 6] = m.s * invU;
-    o[8 * j + 7] = m.K;
+    o[11 * j + 6] = a_j;
+    o[11 * j + 7] = m.K;
   }
-  o[32] = tau_m;
-  o[33] = re;
+  o[44] = tau_m;
+  o[45] = re;
+  if (!base) return;
+  float rb = 0.0f;
+  if (order >= 2) {
+    // (u1 . grad) u1 = sum_{i != j} s_i s_j (p_i . k_j) p_j sin(theta_i) cos(theta_j): each
+    // product is half a wave at theta_i + theta_j and half at theta_i - theta_j.  Its
+    // solenoidal part is balanced by viscosity, the rest by the pressure 3 rho0 delta-rho.
+    const float nu = tau_m / 3.0f;
+    for (int i = 0; i < 4; ++i) {
+      for (int j = 0; j < 4; ++j) {
+        if (i == j) continue;
+        const ModeDev &mi = ms[i], &mj = ms[j];
+        const float pk = (mi.p[0] * mj.k[0] + mi.p[1] * mj.k[1] + mi.p[2] * mj.k[2]) * inv_box2pi;
+        if (pk == 0.0f) continue;
+        const float c = 0.5f * (mi.s * invU) * (mj.s * invU) * U * pk;  // |A| / U
+        for (int sg = -1; sg <= 1; sg += 2) {
+          float q[3];
+          for (int a = 0; a < 3; ++a) q[a] = (mi.k[a] + sg * mj.k[a]) * inv_box2pi;
+          const float q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+          if (q2 == 0.0f) continue;
+          const float qA = c * (q[0] * mj.p[0] + q[1] * mj.p[1] + q[2] * mj.p[2]);
+          const float ph = th[i] + sg * th[j];
+          const float sn = sinf(ph), cs = cosf(ph);
+          for (int a = 0; a < 3; ++a) ub[a] -= (c * mj.p[a] - q[a] * qA / q2) / (nu * q2) * sn;
+          rb += 3.0f * qA / q2 * cs;
+        }
+      }
+    }
+  }
+  float *b = base + idx * 4;
+  b[0] = ub[0];
+  b[1] = ub[1];
+  b[2] = ub[2];
+  b[3] = rb * inv_rho_scale;
 }
 
-__global__ void upsample_kernel(const float *__restrict__ c, int nc, int nch, float *__restrict__ f,
-                                int nf) {
+// out = base + (curl of y's channels 0..2, y's channel 3) on count stacked periodic n^3
+// grids (x fastest), curl by central differences of unit spacing.  Without base this is
+// its own adjoint (the central difference is antisymmetric, so the curl is symmetric).
+__global__ void compose_kernel(const float *__restrict__ y, const float *__restrict__ base, int n,
+                               int64_t total, float *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t N = (int64_t)n * n * n;
+  const int64_t g0 = idx / N * N, r = idx - g0;
+  const int x = (int)(r % n), yy = (int)((r / n) % n), z = (int)(r / ((int64_t)n * n));
+  auto at = [&](int i, int j, int k, int ch) {
+    return y[(g0 + ((int64_t)k * n + j) * n + i) * 4 + ch];
+  };
+  const int xp = (x + 1) % n, xm = (x + n - 1) % n;
+  const int yp = (yy + 1) % n, ym = (yy + n - 1) % n;
+  const int zp = (z + 1) % n, zm = (z + n - 1) % n;
+  // d_b psi_c = (psi_c(+e_b) - psi_c(-e_b)) / 2
+  const float dy_pz = 0.5f * (at(x, yp, z, 2) - at(x, ym, z, 2));
+  const float dz_py = 0.5f * (at(x, yy, zp, 1) - at(x, yy, zm, 1));
+  const float dz_px = 0.5f * (at(x, yy, zp, 0) - at(x, yy, zm, 0));
+  const float dx_pz = 0.5f * (at(xp, yy, z, 2) - at(xm, yy, z, 2));
+  const float dx_py = 0.5f * (at(xp, yy, z, 1) - at(xm, yy, z, 1));
+  const float dy_px = 0.5f * (at(x, yp, z, 0) - at(x, ym, z, 0));
+  float v[4] = {dy_pz - dz_py, dz_px - dx_pz, dx_py - dy_px, y[idx * 4 + 3]};
+  if (base)
+    for (int c = 0; c < 4; ++c) v[c] += base[idx * 4 + c];
+  for (int c = 0; c < 4; ++c) out[idx * 4 + c] = v[c];
+}
+
+__global__ void upsample_kernel(const float *__restrict__ c, int nc, int nch, int pm,
+                                const float *__restrict__ addend, float *__restrict__ f, int nf) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t Nf = (int64_t)nf * nf * nf;
   if (idx >= Nf) return;
@@ -542,13 +667,15 @@ __global__ void upsample_kernel(const float *__restrict__ c, int nc, int nch, fl
   const int x1 = (x0 + 1) % nc, y1 = (y0 + 1) % nc, z1 = (z0 + 1) % nc;
   const int64_t Nc = (int64_t)nc * nc * nc;
   for (int ch = 0; ch < nch; ++ch) {
-    const float *p = c + ch * Nc;
-    auto at = [&](int i, int j, int k) { return p[((int64_t)k * nc + j) * nc + i]; };
+    auto at = [&](int i, int j, int k) {
+      const int64_t q = ((int64_t)k * nc + j) * nc + i;
+      return pm ? c[q * nch + ch] : c[ch * Nc + q];
+    };
     const float v = (1 - az) * ((1 - ay) * ((1 - ax) * at(x0, y0, z0) + ax * at(x1, y0, z0)) +
                                 ay * ((1 - ax) * at(x0, y1, z0) + ax * at(x1, y1, z0))) +
                     az * ((1 - ay) * ((1 - ax) * at(x0, y0, z1) + ax * at(x1, y0, z1)) +
                           ay * ((1 - ax) * at(x0, y1, z1) + ax * at(x1, y1, z1)));
-    f[ch * Nf + idx] = v;
+    f[ch * Nf + idx] = addend ? v + addend[idx * nch + ch] : v;
   }
 }
 
@@ -556,12 +683,17 @@ __global__ void upsample_kernel(const float *__restrict__ c, int nc, int nch, fl
 
 extern "C" {
 
-int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_dev, double *U_out,
+int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_dev,
+                    float *base_dev, int32_t base_order, double rho_scale, double *U_out,
                     void *hip_stream) {
-  if (!p || !x_dev) return set_error(LBM_EINVAL, "NULL argument");
+  if (!p || (!x_dev && !base_dev)) return set_error(LBM_EINVAL, "NULL argument");
   if (p->nmodes != 4) return set_error(LBM_EINVAL, "the feature layout needs 4 modes");
   if (n < 1 || box < 1 || n > 1024) return set_error(LBM_EINVAL, "invalid grid");
   if (!(p->tau2 > 0.5)) return set_error(LBM_EINVAL, "tau2 must exceed 1/2");
+  if (base_dev && base_order != 1 && base_order != 2)
+    return set_error(LBM_EINVAL, "base_order must be 1 or 2");
+  if (base_dev && !(std::isfinite(rho_scale) && rho_scale > 0))
+    return set_error(LBM_EINVAL, "rho_scale must be positive");
   const double nu = (p->tau2 - 0.5) / 3.0;
   const double two_pi = 6.283185307179586;
   ModeDev md[4];
@@ -588,20 +720,35 @@ int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_de
   hipLaunchKernelGGL(features_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
                      static_cast<hipStream_t>(hip_stream), md[0], md[1], md[2], md[3], n,
                      (float)box / (float)n, (float)(two_pi / box), (float)(p->tau2 - 0.5),
-                     (float)re, (float)(1.0 / U), x_dev);
+                     (float)re, (float)(1.0 / U), (float)U, (int)base_order,
+                     base_dev ? (float)(1.0 / rho_scale) : 1.0f, x_dev, base_dev);
   HIP_TRY(hipGetLastError());
   if (U_out) *U_out = U;
   return LBM_OK;
 }
 
-int lbm_upsample_periodic(const float *coarse_dev, int32_t nc, int32_t nchan, float *fine_dev,
+int lbm_upsample_periodic(const float *coarse_dev, int32_t nc, int32_t nchan,
+                          int32_t point_major_in, const float *addend_dev, float *fine_dev,
                           int32_t nf, void *hip_stream) {
   if (!coarse_dev || !fine_dev) return set_error(LBM_EINVAL, "NULL argument");
   if (nc < 1 || nf < nc || nf % nc || nchan < 1 || nf > 2048)
     return set_error(LBM_EINVAL, "invalid sizes");
   const int64_t N = (int64_t)nf * nf * nf;
   hipLaunchKernelGGL(upsample_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
-                     static_cast<hipStream_t>(hip_stream), coarse_dev, nc, nchan, fine_dev, nf);
+                     static_cast<hipStream_t>(hip_stream), coarse_dev, nc, nchan,
+                     point_major_in ? 1 : 0, addend_dev, fine_dev, nf);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_ws_compose(const float *y_dev, const float *base_dev, int32_t n, int32_t count,
+                   float *out_dev, void *hip_stream) {
+  if (!y_dev || !out_dev) return set_error(LBM_EINVAL, "NULL argument");
+  if (n < 1 || n > 1024 || count < 1) return set_error(LBM_EINVAL, "invalid sizes");
+  if (y_dev == out_dev) return set_error(LBM_EINVAL, "out must not alias y");
+  const int64_t total = (int64_t)n * n * n * count;
+  hipLaunchKernelGGL(compose_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(hip_stream), y_dev, base_dev, n, total, out_dev);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }

@@ -13,6 +13,7 @@
 
 #include "lbm.h"
 #include "lbm_internal.h"
+#include "lbm_nn.h"
 
 namespace {
 
@@ -248,20 +249,102 @@ int refresh_monitors(lbm_ctx *c, int mode) {
 
 namespace {
 
-// Network output (point-major rows: D velocity channels / U, then (rho - rho0) / U^2) or
-// plain planes (rho, then D velocity planes) -> binary64 planes for the init kernel.
-__global__ void fields_to_planes_kernel(const float *in, int point_major, int64_t N, int D,
-                                        double U, double rho0, double *rho, double *u) {
+// Fields -> binary64 planes for the init kernel.  layout 0: planes rho, u; 1: the
+// network's point-major rows (u / U, (rho - rho0) / R); 2: the same as planes.
+__global__ void fields_to_planes_kernel(const float *in, int layout, int64_t N, int D, double U,
+                                        double R, double rho0, double *rho, double *u) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  if (point_major) {
+  if (layout == 1) {
     const float *row = in + n * (D + 1);
-    rho[n] = rho0 + U * U * (double)row[D];
+    rho[n] = rho0 + R * (double)row[D];
     for (int c = 0; c < D; ++c) u[c * N + n] = U * (double)row[c];
+  } else if (layout == 2) {
+    rho[n] = rho0 + R * (double)in[D * N + n];
+    for (int c = 0; c < D; ++c) u[c * N + n] = U * (double)in[c * N + n];
   } else {
     rho[n] = (double)in[n];
     for (int c = 0; c < D; ++c) u[c * N + n] = (double)in[N + c * N + n];
   }
+}
+
+// Totals for the conservation projection: per block, sum rho, sum rho u_a, sum u_a
+// (1 + 2D slots), then one block reduces the partials in block order and writes the
+// density shift delta and the velocity shift c_a.
+constexpr int CONS_BLOCKS = 512;
+constexpr int CONS_SLOTS = 7;
+
+__global__ void __launch_bounds__(256) conserve_partials_kernel(const double *rho, const double *u,
+                                                                int64_t N, int D, double *part) {
+  double v[CONS_SLOTS] = {-0.0, -0.0, -0.0, -0.0, -0.0, -0.0, -0.0};
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const double r = rho[n];
+    v[0] += r;
+    for (int a = 0; a < D; ++a) {
+      const double ua = u[a * N + n];
+      v[1 + a] += r * ua;
+      v[1 + D + a] += ua;
+    }
+  }
+  __shared__ double red[CONS_SLOTS][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = 0; k < 1 + 2 * D; ++k) {
+    double w = v[k];
+    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+    if (lane == 0) red[k][wave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 1 + 2 * D) {
+    const int k = threadIdx.x;
+    part[(int64_t)blockIdx.x * CONS_SLOTS + k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+  }
+}
+
+// shift[0] = delta, shift[1 + a] = c_a such that rho' = rho + delta, u' = u - c give
+// sum rho' = N rho0 (mass) and sum rho' u' = 0 (momentum), each only if requested.
+__global__ void conserve_finalize_kernel(const double *part, int nb, int64_t N, int D,
+                                         double rho0, int flags, double *shift) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t[CONS_SLOTS] = {-0.0, -0.0, -0.0, -0.0, -0.0, -0.0, -0.0};
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < 1 + 2 * D; ++k) t[k] += part[(int64_t)b * CONS_SLOTS + k];
+  const double delta = (flags & LBM_RESET_MASS) ? ((double)N * rho0 - t[0]) / (double)N : 0.0;
+  shift[0] = delta;
+  const double mass = t[0] + (double)N * delta;
+  for (int a = 0; a < D; ++a)
+    shift[1 + a] = (flags & LBM_RESET_MOMENTUM) ? (t[1 + a] + delta * t[1 + D + a]) / mass : 0.0;
+}
+
+// One pass of the periodic 7-point low-pass filter (transfer 1 - sin^6(k/2)) along one
+// axis of nplanes planes nx x ny x nz (x fastest); the offsets are summed in a fixed
+// order, each wrapped periodically (any axis length, also below 7).
+__global__ void filter_axis_kernel(const double *in, double *out, int nx, int ny, int nz,
+                                   int axis, int nplanes) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * nplanes) return;
+  const int64_t pl = idx / N, n = idx - pl * N;
+  const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((int64_t)nx * ny));
+  const int len = axis == 0 ? nx : axis == 1 ? ny : nz;
+  const int pos = axis == 0 ? x : axis == 1 ? y : z;
+  const int64_t stride = axis == 0 ? 1 : axis == 1 ? nx : (int64_t)nx * ny;
+  const double *src = in + pl * N + (n - (int64_t)pos * stride);
+  const double c[4] = {11.0 / 16.0, 15.0 / 64.0, -3.0 / 32.0, 1.0 / 64.0};
+  double acc = c[0] * src[(int64_t)pos * stride];
+  for (int o = 1; o <= 3; ++o) {
+    const int lo = ((pos - o) % len + len) % len, hi = (pos + o) % len;
+    acc += c[o] * (src[(int64_t)lo * stride] + src[(int64_t)hi * stride]);
+  }
+  out[idx] = acc;
+}
+
+__global__ void conserve_apply_kernel(double *rho, double *u, int64_t N, int D,
+                                      const double *shift) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  rho[n] += shift[0];
+  for (int a = 0; a < D; ++a) u[a * N + n] -= shift[1 + a];
 }
 
 }  // namespace
@@ -504,19 +587,55 @@ int lbm_set_populations(lbm_ctx *c, const double *f) {
   return LBM_OK;
 }
 
-int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t point_major, double U) {
+int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t layout, double U, double R,
+                     int32_t flags) {
   if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
   if (!fields_dev) return fail(LBM_EINVAL, "fields_dev is NULL");
-  if (point_major && !(std::isfinite(U) && U > 0)) return fail(LBM_EINVAL, "U must be positive");
+  if (layout < 0 || layout > 2) return fail(LBM_EINVAL, "unknown field layout %d", layout);
+  if (layout && !(std::isfinite(U) && U > 0 && std::isfinite(R) && R > 0))
+    return fail(LBM_EINVAL, "U and R must be positive");
+  if (flags & ~(LBM_RESET_MASS | LBM_RESET_MOMENTUM | LBM_RESET_FILTER))
+    return fail(LBM_EINVAL, "unknown reset flags 0x%x", (unsigned)flags);
+  const int nplanes = 1 + c->D;
   const size_t fld = (size_t)c->N * sizeof(double);
-  int rc = c->need_scratch(fld * (1 + c->D));
+  const bool filter = flags & LBM_RESET_FILTER;
+  const bool conserve = flags & (LBM_RESET_MASS | LBM_RESET_MOMENTUM);
+  // planes (rho, u), the filter's second copy, the conservation partials and shifts
+  const size_t planes = fld * nplanes;
+  const size_t extra = conserve ? (size_t)(CONS_BLOCKS + 1) * CONS_SLOTS * sizeof(double) : 0;
+  int rc = c->need_scratch(planes * (filter ? 2 : 1) + extra);
   if (rc) return rc;
-  double *rho_d = static_cast<double *>(c->scratch);
-  double *u_d = reinterpret_cast<double *>(static_cast<char *>(c->scratch) + fld);
-  hipLaunchKernelGGL(fields_to_planes_kernel, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0,
-                     c->stream, fields_dev, point_major ? 1 : 0, c->N, c->D, U, c->p.rho0, rho_d,
-                     u_d);
+  double *A = static_cast<double *>(c->scratch);
+  double *B = A + (size_t)nplanes * c->N;
+  const unsigned grid = (unsigned)((c->N + 255) / 256);
+  hipLaunchKernelGGL(fields_to_planes_kernel, dim3(grid), dim3(256), 0, c->stream, fields_dev,
+                     layout, c->N, c->D, U, R, c->p.rho0, A, A + c->N);
   HIP_TRY(hipGetLastError());
+  double *cur = A;
+  if (filter) {
+    const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
+    const unsigned fgrid = (unsigned)((c->N * nplanes + 255) / 256);
+    for (int axis = 0; axis < 3; ++axis) {
+      if (c->p.bc[axis] != LBM_PERIODIC || dims[axis] == 1) continue;
+      double *dst = cur == A ? B : A;
+      hipLaunchKernelGGL(filter_axis_kernel, dim3(fgrid), dim3(256), 0, c->stream, cur, dst,
+                         c->p.nx, c->p.ny, c->p.nz, axis, nplanes);
+      HIP_TRY(hipGetLastError());
+      cur = dst;
+    }
+  }
+  double *rho_d = cur, *u_d = cur + c->N;
+  if (conserve) {
+    double *part = A + (size_t)(filter ? 2 : 1) * nplanes * c->N;
+    double *shift = part + (size_t)CONS_BLOCKS * CONS_SLOTS;
+    hipLaunchKernelGGL(conserve_partials_kernel, dim3(CONS_BLOCKS), dim3(256), 0, c->stream, rho_d,
+                       u_d, c->N, c->D, part);
+    hipLaunchKernelGGL(conserve_finalize_kernel, dim3(1), dim3(64), 0, c->stream, part,
+                       CONS_BLOCKS, c->N, c->D, c->p.rho0, (int)flags, shift);
+    hipLaunchKernelGGL(conserve_apply_kernel, dim3(grid), dim3(256), 0, c->stream, rho_d, u_d, c->N,
+                       c->D, shift);
+    HIP_TRY(hipGetLastError());
+  }
   c->cur = 0;
   lbm::LaunchDesc d = c->desc(1.0);
   d.fout = c->buf[0];

@@ -510,7 +510,8 @@ class lbm_ws_problem(C.Structure):
                 ("p", (C.c_double * 3) * 8), ("amp", C.c_double * 8), ("phase", C.c_double * 8)]
 
 
-WS_FEATURES = 34
+WS_FEATURES = 46
+RESET_MASS, RESET_MOMENTUM, RESET_FILTER = 1, 2, 4
 
 EXPORTS_NN = {
     "lbm_mlp_create": ([C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)],
@@ -519,7 +520,7 @@ EXPORTS_NN = {
     "lbm_mlp_set_params": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
     "lbm_mlp_get_params": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
     "lbm_mlp_get_grads": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
-    "lbm_mlp_forward": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+    "lbm_mlp_forward": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_mlp_loss_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)],
                               C.c_int),
     "lbm_mlp_backward": ([C.c_void_p, C.c_void_p], C.c_int),
@@ -527,11 +528,17 @@ EXPORTS_NN = {
     "lbm_mlp_adam": ([C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64],
                      C.c_int),
     "lbm_mlp_free": ([C.c_void_p], C.c_int),
-    "lbm_ws_features": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double),
-                         C.c_void_p], C.c_int),
-    "lbm_upsample_periodic": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
-                               C.c_void_p], C.c_int),
-    "lbm_reset_fields": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double], C.c_int),
+    "lbm_ws_features": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                         C.c_double, C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "lbm_upsample_periodic": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                               C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "lbm_ws_compose": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
+                       C.c_int),
+    "lbm_mlp_set_output_scale": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_mlp_loss_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                           C.POINTER(C.c_double)], C.c_int),
+    "lbm_reset_fields": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32],
+                         C.c_int),
 }
 EXPORTS.update(EXPORTS_NN)
 
@@ -571,11 +578,25 @@ class MLP:
         _check(load().lbm_mlp_get_grads(self.ctx, _ptr(out), out.size))
         return out
 
-    def forward(self, x, y):
-        _check(load().lbm_mlp_forward(self.ctx, _dptr(x), int(x.shape[0]), _dptr(y)))
+    def forward(self, x, y, addend=None):
+        """y = network(x) (+ addend, same shape as y)."""
+        _check(load().lbm_mlp_forward(self.ctx, _dptr(x), int(x.shape[0]),
+                                      _optr(addend), _dptr(y)))
 
     def zero_grads(self):
         _check(load().lbm_mlp_zero_grads(self.ctx))
+
+    def set_output_scale(self, scale):
+        s = np.ascontiguousarray(scale, np.float32)
+        _check(load().lbm_mlp_set_output_scale(self.ctx, _ptr(s)))
+
+    def loss_grad(self, y, target, dy, weight=None):
+        """Weighted mean-square loss of any y against target; dL/dy into dy."""
+        w = None if weight is None else np.ascontiguousarray(weight, np.float32)
+        loss = C.c_double()
+        _check(load().lbm_mlp_loss_grad(self.ctx, _dptr(y), _dptr(target), _ptr(w),
+                                        int(y.shape[0]), _dptr(dy), C.byref(loss)))
+        return loss.value
 
     def loss_backward(self, target, weight=None):
         w = None if weight is None else np.ascontiguousarray(weight, np.float32)
@@ -615,18 +636,39 @@ def ws_problem_struct(problem):
     return s
 
 
-def lbm_ws_features(problem, n, box, x_dev, stream=None):
+def lbm_ws_features(problem, n, box, x_dev, base_dev=None, base_order=2, rho_scale=1.0,
+                    stream=None):
+    """Features into x_dev (n^3 x WS_FEATURES), the perturbative steady solution of
+    order base_order (1: Stokes, 2: with the first advective correction) into base_dev
+    (n^3 x 4: u / U, (rho - 1) / (U rho_scale)) if given; returns the velocity scale U."""
     s = ws_problem_struct(problem)
     U = C.c_double()
-    _check(load().lbm_ws_features(C.byref(s), int(n), int(box), _dptr(x_dev), C.byref(U),
-                                  _stream_handle(stream)))
+    _check(load().lbm_ws_features(C.byref(s), int(n), int(box), _optr(x_dev),
+                                  _optr(base_dev), int(base_order),
+                                  float(rho_scale), C.byref(U), _stream_handle(stream)))
     return U.value
 
 
-def lbm_upsample_periodic(coarse, nc, nchan, fine, nf, stream=None):
-    _check(load().lbm_upsample_periodic(_dptr(coarse), int(nc), int(nchan), _dptr(fine), int(nf),
-                                        _stream_handle(stream)))
+def _optr(t):
+    return None if t is None else _dptr(t)
 
 
-def lbm_reset_fields(ctx, fields, point_major, U=1.0):
-    _check(load().lbm_reset_fields(ctx, _dptr(fields), int(bool(point_major)), float(U)))
+def lbm_upsample_periodic(coarse, nc, nchan, fine, nf, point_major_in=False, addend=None,
+                          stream=None):
+    _check(load().lbm_upsample_periodic(_dptr(coarse), int(nc), int(nchan), int(bool(point_major_in)),
+                                        _optr(addend), _dptr(fine), int(nf), _stream_handle(stream)))
+
+
+def lbm_ws_compose(y, base, n, count, out, stream=None):
+    """out = base + (curl of y[:, :3], y[:, 3]) on count stacked periodic n^3 grids; with
+    base None the linear part, which is its own adjoint."""
+    _check(load().lbm_ws_compose(_dptr(y), _optr(base), int(n), int(count), _dptr(out),
+                                 _stream_handle(stream)))
+
+
+def lbm_reset_fields(ctx, fields, layout, U=1.0, R=None, flags=0):
+    """layout 0: planes rho, u; 1: network rows (u/U, (rho-rho0)/R); 2: those as planes
+    (R defaults to U).  flags: RESET_FILTER (periodic low-pass removing wavenumber pi),
+    RESET_MASS and RESET_MOMENTUM (project onto the plain start's totals)."""
+    R = U if R is None else R
+    _check(load().lbm_reset_fields(ctx, _dptr(fields), int(layout), float(U), float(R), int(flags)))

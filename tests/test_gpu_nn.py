@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import mlp
+from oracle import closed_forms, mlp
 from paper_2212_07494_amd import inputs
 from tests.helpers import gpu_available
 
@@ -58,6 +58,37 @@ def test_forward_and_gradients(widths, rows):
     assert rel(y, y_f) < 2e-2 and rel(g, g_f) < 2e-2, (rel(y, y_f), rel(g, g_f))
 
 
+def test_forward_with_addend():
+    """y = network(x) + a: the loss against t is the plain network's loss against t - a."""
+    import torch
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    widths, rows = [34, 96, 96, 4], 700
+    p = inputs.mlp_init_params(widths, seed=11).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((rows, 34)).astype(np.float32)
+    t = rng.standard_normal((rows, 4)).astype(np.float32)
+    a = rng.standard_normal((rows, 4)).astype(np.float32)
+    net = L.MLP(widths, max_rows=rows)
+    try:
+        net.set_params(p)
+        xd, td, ad = (torch.tensor(v, device="cuda") for v in (x, t, a))
+        y0 = torch.empty((rows, 4), device="cuda")
+        y1 = torch.empty((rows, 4), device="cuda")
+        net.forward(xd, y0)
+        net.forward(xd, y1, ad)
+        assert np.array_equal(y1.cpu().numpy(), y0.cpu().numpy() + a)
+        net.zero_grads()
+        loss = net.loss_backward(td)
+        g = net.grads()
+    finally:
+        net.close()
+    t_res = t.astype(np.float64) - a.astype(np.float64)
+    l_e, g_e = mlp.loss_and_grad(p, widths, x, t_res, None, bf16=True)
+    assert abs(loss - l_e) < 1e-3 * l_e
+    assert rel(g, g_e) < 1e-3, rel(g, g_e)
+
+
 def test_adam_step():
     import torch
     from paper_2212_07494_amd import lbm as L
@@ -95,8 +126,23 @@ def test_features_and_upsampling():
     prob = inputs.warmstart_problem(seed=8, box=64)
     n, box = 16, 64
     xd = torch.empty((n ** 3, L.WS_FEATURES), device="cuda")
-    U = L.lbm_ws_features(prob, n, box, xd)
+    bd = torch.empty((n ** 3, 4), device="cuda")
+    bd2 = torch.empty((n ** 3, 4), device="cuda")
+    U = L.lbm_ws_features(prob, n, box, xd, bd, base_order=1)
+    U2 = L.lbm_ws_features(prob, n, box, xd, bd2, base_order=2)
+    assert U2 == U
     x = xd.cpu().numpy().astype(np.float64)
+    base = bd.cpu().numpy().astype(np.float64)
+    base2 = bd2.cpu().numpy().astype(np.float64)
+    # the perturbative steady solutions on the lattice, sampled at the grid points
+    sub = (slice(None), slice(None, None, box // n), slice(None, None, box // n),
+           slice(None, None, box // n))
+    for b, order in ((base, 1), (base2, 2)):
+        rho_c, u_c = closed_forms.fourier_perturbative_steady(box, prob["tau2"], prob["modes"], order)
+        want_u = (u_c.reshape(3, box, box, box)[sub].reshape(3, -1) / U).T
+        want_r = ((rho_c - 1.0).reshape(1, box, box, box)[sub].reshape(-1)) / U
+        assert np.max(np.abs(b[:, :3] - want_u)) < 1e-4 * max(1.0, np.abs(want_u).max())
+        assert np.max(np.abs(b[:, 3] - want_r)) < 1e-4 * max(1e-3, np.abs(want_r).max())
     nu = (prob["tau2"] - 0.5) / 3
     Ks = [2 * math.pi * np.linalg.norm(m["k"]) / box for m in prob["modes"]]
     s = [m["amp"] / (nu * K * K) for m, K in zip(prob["modes"], Ks)]
@@ -104,18 +150,25 @@ def test_features_and_upsampling():
     pos = np.stack(inputs.coords((n, n, n)), 1) * (box / n)
     for j, m in enumerate(prob["modes"]):
         th = 2 * math.pi * pos @ np.asarray(m["k"], np.float64) / box + m["phase"]
-        assert np.max(np.abs(x[:, 8 * j: 8 * j + 3] - np.outer(np.sin(th), m["p"]))) < 2e-5
-        assert np.max(np.abs(x[:, 8 * j + 3: 8 * j + 6] - np.outer(np.cos(th), m["p"]))) < 2e-5
-        assert np.allclose(x[:, 8 * j + 6], s[j] / U, rtol=1e-6)
-        assert np.allclose(x[:, 8 * j + 7], Ks[j], rtol=1e-6)
-    assert np.allclose(x[:, 32], prob["tau2"] - 0.5, rtol=1e-6)
-    assert np.allclose(x[:, 33], U / (nu * min(Ks)), rtol=1e-5)
+        assert np.max(np.abs(x[:, 11 * j: 11 * j + 3] - np.outer(np.sin(th), m["p"]))) < 2e-5
+        assert np.max(np.abs(x[:, 11 * j + 3: 11 * j + 6] - np.outer(np.cos(th), m["p"]))) < 2e-5
+        assert np.allclose(x[:, 11 * j + 6], s[j] / U, rtol=1e-6)
+        assert np.allclose(x[:, 11 * j + 7], Ks[j], rtol=1e-6)
+        khat = np.asarray(m["k"], np.float64) / np.linalg.norm(m["k"])
+        assert np.max(np.abs(x[:, 11 * j + 8: 11 * j + 11] - khat)) < 1e-6
+    assert np.all(base[:, 3] == 0)
+    assert np.allclose(x[:, 44], prob["tau2"] - 0.5, rtol=1e-6)
+    assert np.allclose(x[:, 45], U / (nu * min(Ks)), rtol=1e-5)
     # upsampling: a periodic field sampled on 8^3 and interpolated to 32^3
     nc, nf = 8, 32
     c = np.random.default_rng(1).standard_normal((2, nc ** 3)).astype(np.float32)
     fd = torch.empty((2, nf ** 3), device="cuda")
     L.lbm_upsample_periodic(torch.tensor(c, device="cuda"), nc, 2, fd, nf)
     f = fd.cpu().numpy().reshape(2, nf, nf, nf)
+    fd2 = torch.empty((2, nf ** 3), device="cuda")
+    L.lbm_upsample_periodic(torch.tensor(np.ascontiguousarray(c.T), device="cuda"), nc, 2, fd2,
+                            nf, point_major_in=True)
+    assert np.array_equal(fd2.cpu().numpy(), fd.cpu().numpy())
     cc = c.reshape(2, nc, nc, nc).astype(np.float64)
     r = nc / nf
     for (z, y, xx) in [(0, 0, 0), (5, 17, 31), (31, 2, 9), (12, 30, 30)]:
@@ -131,8 +184,8 @@ def test_features_and_upsampling():
     assert np.allclose(f[:, ::4, ::4, ::4].reshape(2, -1), c, atol=1e-6)
 
 
-@pytest.mark.parametrize("point_major", [0, 1])
-def test_reset_fields_equals_init(point_major):
+@pytest.mark.parametrize("layout", [0, 1, 2])
+def test_reset_fields_equals_init(layout):
     import torch
     from paper_2212_07494_amd import lbm as L
     L.load()
@@ -140,11 +193,12 @@ def test_reset_fields_equals_init(point_major):
     N = int(np.prod(shape))
     rng = np.random.default_rng(9)
     U = 0.02
-    if point_major:
+    if layout:
         net_out = rng.uniform(-1, 1, (N, 4)).astype(np.float32)
-        rho = 1.0 + U * U * net_out[:, 3].astype(np.float64)
+        rho = 1.0 + U * net_out[:, 3].astype(np.float64)
         u = (U * net_out[:, :3].astype(np.float64)).T
-        dev = torch.tensor(net_out, device="cuda")
+        arr = net_out if layout == 1 else np.ascontiguousarray(net_out.T)
+        dev = torch.tensor(arr, device="cuda")
     else:
         rho = (1.0 + 0.01 * rng.uniform(-1, 1, N)).astype(np.float32).astype(np.float64)
         u = (0.02 * rng.uniform(-1, 1, (3, N))).astype(np.float32).astype(np.float64)
@@ -154,6 +208,171 @@ def test_reset_fields_equals_init(point_major):
                    g_field=g) as a, \
          L.Lattice("D3Q27", "smrt", "f32s", shape, (0, 0, 0), (0.7, 1.0, 1.0), g_field=g) as b:
         b.step(3)
-        L.lbm_reset_fields(b.ctx, dev, point_major, U)
+        L.lbm_reset_fields(b.ctx, dev, layout, U)
         assert b.time == 0
         assert np.array_equal(a.populations(), b.populations())
+
+
+def lowpass_periodic(a, axis):
+    """The 7-point periodic filter with transfer 1 - sin^6(k/2), by its definition."""
+    c = (11 / 16, 15 / 64, -3 / 32, 1 / 64)
+    out = c[0] * a
+    for o in (1, 2, 3):
+        out = out + c[o] * (np.roll(a, o, axis) + np.roll(a, -o, axis))
+    return out
+
+
+@pytest.mark.parametrize("walls", [(0, 0, 0), (0, 1, 0)])
+def test_reset_fields_filter_and_projection(walls):
+    """Filtered (periodic axes only) and projected onto mass N rho0 and zero momentum,
+    then the same state as lbm_init of those fields; checked against numpy."""
+    import torch
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    shape = (12, 10, 6)   # includes an axis shorter than the filter
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    rng = np.random.default_rng(21)
+    U = 0.03
+    rows = rng.uniform(-1, 1, (N, 4)).astype(np.float32)
+    rows[:, :3] += 0.2   # a net momentum and mass to remove
+    rows[:, 3] += 0.1
+    rho = 1.0 + U * rows[:, 3].astype(np.float64)
+    u = U * rows[:, :3].astype(np.float64).T
+    planes = np.concatenate([rho[None], u]).reshape(4, nz, ny, nx)
+    for ax, w in enumerate(walls):      # array axes are (plane, z, y, x)
+        if not w:
+            planes = lowpass_periodic(planes, 3 - ax)
+    planes = planes.reshape(4, N)
+    rho_f, u_f = planes[0], planes[1:]
+    delta = (N * 1.0 - rho_f.sum()) / N
+    rho_p = rho_f + delta
+    c = (rho_p * u_f).sum(1) / rho_p.sum()
+    u_p = u_f - c[:, None]
+    g = inputs.fourier_force(shape, inputs.fourier_modes(seed=3))
+    with L.Lattice("D3Q27", "smrt", "f64", shape, walls, (0.7, 1.0, 1.0), rho=rho_p, u=u_p,
+                   g_field=g) as a, \
+         L.Lattice("D3Q27", "smrt", "f64", shape, walls, (0.7, 1.0, 1.0), g_field=g) as b:
+        b.step(2)
+        flags = L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM
+        L.lbm_reset_fields(b.ctx, torch.tensor(rows, device="cuda"), 1, U, flags=flags)
+        fa, fb = a.populations(), b.populations()
+        assert np.max(np.abs(fa - fb)) < 1e-15
+        m = b.monitors()
+        assert abs(m.mass - N) < 1e-12 * N
+        assert max(abs(v) for v in m.mom) < 1e-14 * N
+        # the checkerboard along every periodic axis is gone
+        r_b, u_b = b.moments()
+        for ax, w in enumerate(walls):
+            if w:
+                continue
+            sign = (-1.0) ** np.asarray(inputs.coords(shape)[ax])
+            assert abs(np.sum(u_b * sign)) < 1e-13 * N
+
+
+def test_output_scale_and_loss_grad():
+    """With an output scale S the network is S * net; its gradients are those of the
+    reference network whose last layer is multiplied by S.  loss_grad gives the weighted
+    mean-square loss of any array and its gradient."""
+    import torch
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    widths, rows = [34, 64, 4], 500
+    p = inputs.mlp_init_params(widths, seed=13).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(14)
+    p += 0.01 * rng.standard_normal(p.size)
+    p = p.astype(np.float32).astype(np.float64)
+    x = rng.standard_normal((rows, 34)).astype(np.float32)
+    t = rng.standard_normal((rows, 4)).astype(np.float32)
+    S = np.array([0.5, 2.0, 0.125, 1.0], np.float32)
+    w = np.array([1.0, 0.5, 2.0, 1.5], np.float32)
+    net = L.MLP(widths, max_rows=rows)
+    try:
+        net.set_params(p)
+        net.set_output_scale(S)
+        xd, td = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+        yd = torch.empty((rows, 4), device="cuda")
+        net.forward(xd, yd)
+        net.zero_grads()
+        loss = net.loss_backward(td, w)
+        g = net.grads()
+        dy = torch.empty_like(yd)
+        loss2 = net.loss_grad(yd, td, dy, w)
+        y = yd.cpu().numpy().astype(np.float64)
+    finally:
+        net.close()
+    # reference: scale the last layer's weights and bias by S (exact in BF16 for these S)
+    ps = p.copy()
+    nW = 4 * 64
+    ps[-(nW + 4):-4] = (p[-(nW + 4):-4].reshape(4, 64) * S[:, None]).ravel()
+    ps[-4:] = p[-4:] * S
+    y_e, _ = mlp.forward(ps, widths, x, bf16=True)
+    l_e, g_e = mlp.loss_and_grad(ps, widths, x, t, w, bf16=True)
+    assert rel(y, y_e) < 1e-3
+    assert abs(loss - l_e) < 1e-3 * l_e and abs(loss2 - loss) < 1e-9 * loss
+    # chain rule back to the unscaled parameters: d/dW_last = S * d/d(S W_last)
+    g_e = g_e.copy()
+    g_e[-(nW + 4):-4] = (g_e[-(nW + 4):-4].reshape(4, 64) * S[:, None]).ravel()
+    g_e[-4:] *= S
+    assert rel(g, g_e) < 1e-3, rel(g, g_e)
+    d = y - t
+    want = 2 * w * d / d.size
+    assert np.max(np.abs(dy.cpu().numpy() - want)) < 1e-6 * np.abs(want).max()
+
+
+def curl_np(psi, n):
+    """Central-difference curl on a periodic n^3 grid; psi (3, n, n, n) indexed [c, z, y, x]."""
+    def d(a, axis):   # axis 0 = x, 1 = y, 2 = z
+        ax = 3 - axis
+        return 0.5 * (np.roll(a, -1, ax - 1) - np.roll(a, 1, ax - 1))
+    px, py, pz = psi
+    return np.stack([d(pz, 1) - d(py, 2), d(px, 2) - d(pz, 0), d(py, 0) - d(px, 1)])
+
+
+def test_compose_curl_adjoint_and_divergence():
+    import torch
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    n, count = 6, 3
+    N = n ** 3
+    rng = np.random.default_rng(15)
+    y = rng.standard_normal((count * N, 4)).astype(np.float32)
+    b = rng.standard_normal((count * N, 4)).astype(np.float32)
+    v = rng.standard_normal((count * N, 4)).astype(np.float32)
+    yd, bd, vd = (torch.tensor(a, device="cuda") for a in (y, b, v))
+    out = torch.empty_like(yd)
+    L.lbm_ws_compose(yd, bd, n, count, out)
+    o = out.cpu().numpy().astype(np.float64)
+    for g in range(count):
+        rows = slice(g * N, (g + 1) * N)
+        psi = y[rows, :3].T.astype(np.float64).reshape(3, n, n, n)
+        want = curl_np(psi, n).reshape(3, N).T + b[rows, :3]
+        assert np.max(np.abs(o[rows, :3] - want)) < 1e-5
+        assert np.array_equal(o[rows, 3], (y[rows, 3] + b[rows, 3]).astype(np.float32))
+        # zero central-difference divergence of the velocity correction
+        c = (o[rows, :3] - b[rows, :3]).T.reshape(3, n, n, n)
+        div = sum(0.5 * (np.roll(c[a], -1, 2 - a) - np.roll(c[a], 1, 2 - a)) for a in range(3))
+        assert np.max(np.abs(div)) < 1e-5
+    # the linear part is its own adjoint: <A y, v> = <y, A v>
+    Ay = torch.empty_like(yd)
+    Av = torch.empty_like(yd)
+    L.lbm_ws_compose(yd, None, n, count, Ay)
+    L.lbm_ws_compose(vd, None, n, count, Av)
+    lhs = float(np.sum(Ay.cpu().numpy().astype(np.float64) * v))
+    rhs = float(np.sum(y.astype(np.float64) * Av.cpu().numpy()))
+    assert abs(lhs - rhs) < 1e-5 * (abs(lhs) + 1)
+
+
+def test_upsample_with_addend():
+    import torch
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    nc, nf, ch = 4, 8, 4
+    rng = np.random.default_rng(16)
+    c = torch.tensor(rng.standard_normal((nc ** 3, ch)).astype(np.float32), device="cuda")
+    a = torch.tensor(rng.standard_normal((nf ** 3, ch)).astype(np.float32), device="cuda")
+    f0 = torch.empty((ch, nf ** 3), device="cuda")
+    f1 = torch.empty((ch, nf ** 3), device="cuda")
+    L.lbm_upsample_periodic(c, nc, ch, f0, nf, point_major_in=True)
+    L.lbm_upsample_periodic(c, nc, ch, f1, nf, point_major_in=True, addend=a)
+    assert np.array_equal(f1.cpu().numpy(), f0.cpu().numpy() + a.cpu().numpy().T)

@@ -227,3 +227,61 @@ def test_smrt_equal_rates_one_is_half_force(L):
                 r_[a] -= 1
                 aF += m[a] * np.prod([uu[b] ** r_[b] for b in range(3)]) * F[a]
         assert math.isclose(mom[k], r * up + aF / 2, rel_tol=0, abs_tol=1e-15)
+
+
+# Number of independent Hermite moments of order 3 each velocity set resolves: D2Q9 has
+# xxy, xyy; D3Q19 the six with one repeated index; D3Q27 those and xyz.
+ORDER3 = {"D2Q9": 2, "D3Q19": 6, "D3Q27": 7}
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("coll,tau2,tau3", [("bgk", 0.8, 1.0), ("smrt", 0.8, 1.0),
+                                            ("smrt", 0.62, 0.7), ("smrt", 1.3, 2.5)])
+def test_linearised_collision_spectrum(L, coll, tau2, tau3):
+    """About rest and unforced, the collision relaxes each Hermite order n by 1 - 1/tau_n
+    (eq:domg with a_F = 0): eigenvalue 1 for mass and momentum; for SMRT 1 - 1/tau2 on
+    the D(D+1)/2 second-order moments, 1 - 1/tau3 on the third-order ones and 0 above
+    (order 4 trimmed, higher orders dropped); for BGK 1 - 1/tau on all non-conserved
+    ones.  Central differences of the oracle's collision are exact here up to rounding
+    because the linearisation is taken at a point where the map is a polynomial."""
+    o = Oracle(L, coll, (1, 1, 1), tau=(tau2, tau3, 1.0))
+    Q, D = o.Q, o.D
+    f0 = o.init_node(1.0, [0, 0, 0], [0, 0, 0])
+    h = 1e-5
+    J = np.empty((Q, Q))
+    for q in range(Q):
+        d = np.zeros(Q)
+        d[q] = h
+        J[:, q] = (o.collide_node(f0 + d, [0, 0, 0]) - o.collide_node(f0 - d, [0, 0, 0])) / (2 * h)
+    lam = np.sort(np.linalg.eigvals(J).real)
+    if coll == "bgk":
+        want = [1.0] * (1 + D) + [1 - 1 / tau2] * (Q - 1 - D)
+    else:
+        n2 = D * (D + 1) // 2
+        n3 = ORDER3[L]
+        want = ([1.0] * (1 + D) + [1 - 1 / tau2] * n2 + [1 - 1 / tau3] * n3
+                + [0.0] * (Q - 1 - D - n2 - n3))
+    assert np.max(np.abs(lam - np.sort(want))) < 1e-8, (lam, sorted(want))
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+def test_staggered_momentum_mode_never_decays(L, coll):
+    """u_x = eps (-1)^x at rest density is an equilibrium, so collision keeps it; streaming
+    carries every population with e_x = +-1 to the other sublattice and keeps the e_x = 0
+    ones, whose equilibrium is even in u_x, so the state becomes the equilibrium of
+    -u_x: the checkerboard flips sign every step for ever, whatever the relaxation
+    times (the eigenvalue -1 of the step at wavenumber (pi, 0, 0))."""
+    shape = (4, 3, 1) if lat.dim(L) == 2 else (4, 3, 2)
+    o = Oracle(L, coll, shape, tau=(0.6, 0.9, 1.0))
+    x = np.arange(o.N) % shape[0]
+    eps = 0.01
+    u = np.zeros((3, o.N))
+    u[0] = eps * (-1.0) ** x
+    f = o.init(1.0, u, None)
+    for t in range(1, 4):
+        f = o.step(f, None)
+        rho, ut = o.moments(f, None)
+        assert np.max(np.abs(rho - 1.0)) < 1e-14
+        assert np.max(np.abs(ut[0] - eps * (-1.0) ** (x + t))) < 1e-15
+        assert np.max(np.abs(ut[1:])) < 1e-15
