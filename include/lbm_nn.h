@@ -107,9 +107,20 @@ typedef struct {
  *     projection normal to q = k_i +- k_j, q = 0 skipped) and
  *     rho - rho0 = 3 p2 = 3 (q . A) / |q|^2 cos(.). */
 int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_dev,
-                    float *base_dev, int32_t base_order, double rho_scale, double *U_out,
-                    void *hip_stream);
-/* (x_dev may be NULL when base_dev is not: the base alone, e.g. on the full lattice.) */
+                    float *base_dev, int32_t base_order, double rho_scale,
+                    const float *mode_coef_dev, double *U_out, void *hip_stream);
+/* x_dev may be NULL when base_dev is not (the base alone, e.g. on the full lattice).
+ * mode_coef_dev (device, 4 x 8, may be NULL) corrects each mode's own response in the
+ * base: u_j = s_j ((p_j + c_0..2) sin(theta_j) + c_3..5 cos(theta_j)) and
+ * rho_j - rho0 = s_j (c_6 sin(theta_j) + c_7 cos(theta_j)) (the network's output). */
+
+#define LBM_WS_MODE_FEATURES 13
+/* Per-mode network inputs (rows nmodes x 13, device, copied before return): the phase
+ * advance per lattice link kappa_a = 2 pi k_a / box (3), sin(kappa_a) (3),
+ * 1 - cos(kappa_a) (3), p_j (3), tau2 - 1/2 -- what a single mode's linear lattice
+ * response depends on (the lattice sees a wave through its values on the links). */
+int lbm_ws_mode_features(const lbm_ws_problem *p, int32_t box, float *out_dev,
+                         void *hip_stream);
 
 /* Solenoidal composition of the network's output on count stacked periodic n^3 grids
  * (rows n^3 per grid, x fastest, 4 channels): out = base + (curl psi, r) where psi is
@@ -149,10 +160,17 @@ int lbm_upsample_periodic(const float *coarse_dev, int32_t nc, int32_t nchan,
  *     With no walls the dynamics conserve total mass and momentum (the forcing sums to
  *     zero over the periodic box), so a start that differs from the plain start in
  *     them ends in a different, drifting state.
- * The state becomes the force-corrected equilibrium of the fields (as lbm_init), time 0. */
+ * The state becomes the force-corrected equilibrium of the fields (as lbm_init), time 0,
+ * and with
+ *   LBM_RESET_NONEQ: plus the non-equilibrium second moment the velocity gradient implies
+ *     to leading order, Pi = -c_s^2 tau2 rho (grad u + grad u^T) (tau2 = tau[2]; central
+ *     differences, one-sided at walls), as the Hermite term w_i (e_i e_i - c_s^2 I) : Pi /
+ *     (2 c_s^4).  Without it the start carries no stress; the jump relaxes within a few
+ *     steps but launches pressure waves that hold the per-step residual up for many. */
 #define LBM_RESET_MASS 1
 #define LBM_RESET_MOMENTUM 2
 #define LBM_RESET_FILTER 4
+#define LBM_RESET_NONEQ 8
 int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t layout, double U, double R,
                      int32_t flags);
 

@@ -450,7 +450,7 @@ int lbm_batch_init(const lbm_domain *domains, int32_t ndom, int32_t lattice, int
       }
     }
     lbm::LaunchDesc L = b->desc(d);
-    if (b->ops->init(L, rho_d, u_d, rho0, b->stream) != hipSuccess)
+    if (b->ops->init(L, rho_d, u_d, rho0, nullptr, b->stream) != hipSuccess)
       return bail(set_error(LBM_EDEVICE, "init kernel failed for domain %d", d));
     if ((s.rho_init || s.u_init) && hipStreamSynchronize(b->stream) != hipSuccess)
       return bail(set_error(LBM_EDEVICE, "init failed for domain %d", d));

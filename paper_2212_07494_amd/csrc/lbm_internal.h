@@ -52,8 +52,9 @@ struct BatchLaunch {
 struct LatticeOps {
   int D, Q;
   hipError_t (*step)(const LaunchDesc &, hipStream_t);
+  // pi: optional non-equilibrium second moment, 6 binary64 planes (xx, yy, zz, xy, xz, yz)
   hipError_t (*init)(const LaunchDesc &, const double *rho, const double *u, double rho0,
-                     hipStream_t);
+                     const double *pi, hipStream_t);
   hipError_t (*gather)(const LaunchDesc &, const int64_t *nodes, int64_t nn, double *out,
                        hipStream_t);
   hipError_t (*scatter)(const LaunchDesc &, const double *in, hipStream_t);

@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
 template <class L, int COLL, class S, class T, int GK>
 __global__ void __launch_bounds__(256) init_kernel(StepArgs<T> a, const double *rho,
                                                    const double *u, int has_rho, int has_u,
-                                                   T rho0) {
+                                                   T rho0, const double *pi) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -168,6 +168,20 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<T> a, const double *
   load_force<T, GK>(a.force, x, y, z, node, N, L::D, g);
   T out[L::Q];
   init_node<L, T, COLL>(r, uu, g, a.shift, out);
+  if (pi) {
+    // A non-equilibrium second moment Pi (planes xx, yy, zz, xy, xz, yz): the Hermite
+    // term w_i (e_i e_i - I/3) : Pi / (2 c_s^4), which has no mass or momentum.
+    T P[6];
+    for (int c = 0; c < 6; ++c) P[c] = T(pi[(int64_t)c * N + node]);
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
+      const T q = ((T(ex * ex) - T(1) / T(3)) * P[0] + (T(ey * ey) - T(1) / T(3)) * P[1] +
+                   (T(ez * ez) - T(1) / T(3)) * P[2]) +
+                  T(2) * ((T(ex * ey) * P[3] + T(ex * ez) * P[4]) + T(ey * ez) * P[5]);
+      out[i] = out[i] + Tab<L, T>::w(i) * (T(4.5) * q);
+    });
+  }
   S *__restrict__ f = static_cast<S *>(a.fout);
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;

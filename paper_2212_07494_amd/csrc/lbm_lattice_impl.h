@@ -79,21 +79,21 @@ struct Ops {
   }
   template <int COLL, class S, class T, int GK>
   static hipError_t init_t(const LaunchDesc &d, const double *rho, const double *u,
-                           double rho0, hipStream_t s) {
+                           double rho0, const double *pi, hipStream_t s) {
     hipLaunchKernelGGL((init_kernel<L, COLL, S, T, GK>), grid_of(d), dim3(d.bx, d.by), 0, s,
-                       make_args<T>(d), rho, u, rho != nullptr, u != nullptr, T(rho0));
+                       make_args<T>(d), rho, u, rho != nullptr, u != nullptr, T(rho0), pi);
     return hipGetLastError();
   }
   static hipError_t init(const LaunchDesc &d, const double *rho, const double *u, double rho0,
-                         hipStream_t s) {
+                         const double *pi, hipStream_t s) {
     return with_types(d.storage, [&](auto *sp, auto *tp) -> hipError_t {
       using S = std::remove_pointer_t<decltype(sp)>;
       using T = std::remove_pointer_t<decltype(tp)>;
       if (d.coll == 0)
-        return d.gk ? init_t<0, S, T, GK_FIELD>(d, rho, u, rho0, s)
-                    : init_t<0, S, T, GK_PROFILE>(d, rho, u, rho0, s);
-      return d.gk ? init_t<1, S, T, GK_FIELD>(d, rho, u, rho0, s)
-                  : init_t<1, S, T, GK_PROFILE>(d, rho, u, rho0, s);
+        return d.gk ? init_t<0, S, T, GK_FIELD>(d, rho, u, rho0, pi, s)
+                    : init_t<0, S, T, GK_PROFILE>(d, rho, u, rho0, pi, s);
+      return d.gk ? init_t<1, S, T, GK_FIELD>(d, rho, u, rho0, pi, s)
+                  : init_t<1, S, T, GK_PROFILE>(d, rho, u, rho0, pi, s);
     });
   }
   static hipError_t gather(const LaunchDesc &d, const int64_t *nodes, int64_t nn, double *out,

@@ -559,7 +559,8 @@ struct ModeDev {
 
 __global__ void features_kernel(ModeDev m0, ModeDev m1, ModeDev m2, ModeDev m3, int n, float step,
                                 float inv_box2pi, float tau_m, float re, float invU, float U,
-                                int order, float inv_rho_scale, float *__restrict__ x,
+                                int order, float inv_rho_scale,
+                                const float *__restrict__ mode_coef, float *__restrict__ x,
                                 float *__restrict__ base) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t N = (int64_t)n * n * n;
@@ -572,6 +573,7 @@ __global__ void features_kernel(ModeDev m0, ModeDev m1, ModeDev m2, ModeDev m3, 
   const ModeDev ms[4] = {m0, m1, m2, m3};
   float th[4];
   float ub[3] = {0.0f, 0.0f, 0.0f};
+  float rmode = 0.0f;
   for (int j = 0; j < 4; ++j) {
     const ModeDev &m = ms[j];
     // theta = 2 pi k . x / box + phase
@@ -585,13 +587,20 @@ __global__ void features_kernel(ModeDev m0, ModeDev m1, ModeDev m2, ModeDev m3, 
       o[11 * j + 8 + a] = m.k[a] / kn;
       ub[a] += a_j * (m.p[a] * sn);
     }
+    if (mode_coef) {
+      // the mode's own response corrected: a_j ((p_j + c_0..2) sin + c_3..5 cos), density
+      // a_j (c_6 sin + c_7 cos)
+      const float *cj = mode_coef + 8 * j;
+      for (int a = 0; a < 3; ++a) ub[a] += a_j * (cj[a] * sn + cj[3 + a] * cs);
+      rmode += a_j * (cj[6] * sn + cj[7] * cs);
+    }
     o[11 * j + 6] = a_j;
     o[11 * j + 7] = m.K;
   }
   o[44] = tau_m;
   o[45] = re;
   if (!base) return;
-  float rb = 0.0f;
+  float rb = rmode;
   if (order >= 2) {
     // (u1 . grad) u1 = sum_{i != j} s_i s_j (p_i . k_j) p_j sin(theta_i) cos(theta_j): each
     // product is half a wave at theta_i + theta_j and half at theta_i - theta_j.  Its
@@ -684,8 +693,8 @@ __global__ void upsample_kernel(const float *__restrict__ c, int nc, int nch, in
 extern "C" {
 
 int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_dev,
-                    float *base_dev, int32_t base_order, double rho_scale, double *U_out,
-                    void *hip_stream) {
+                    float *base_dev, int32_t base_order, double rho_scale,
+                    const float *mode_coef_dev, double *U_out, void *hip_stream) {
   if (!p || (!x_dev && !base_dev)) return set_error(LBM_EINVAL, "NULL argument");
   if (p->nmodes != 4) return set_error(LBM_EINVAL, "the feature layout needs 4 modes");
   if (n < 1 || box < 1 || n > 1024) return set_error(LBM_EINVAL, "invalid grid");
@@ -721,9 +730,38 @@ int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_de
                      static_cast<hipStream_t>(hip_stream), md[0], md[1], md[2], md[3], n,
                      (float)box / (float)n, (float)(two_pi / box), (float)(p->tau2 - 0.5),
                      (float)re, (float)(1.0 / U), (float)U, (int)base_order,
-                     base_dev ? (float)(1.0 / rho_scale) : 1.0f, x_dev, base_dev);
+                     base_dev ? (float)(1.0 / rho_scale) : 1.0f, mode_coef_dev, x_dev,
+                     base_dev);
   HIP_TRY(hipGetLastError());
   if (U_out) *U_out = U;
+  return LBM_OK;
+}
+
+int lbm_ws_mode_features(const lbm_ws_problem *p, int32_t box, float *out_dev,
+                         void *hip_stream) {
+  if (!p || !out_dev) return set_error(LBM_EINVAL, "NULL argument");
+  if (p->nmodes < 1 || p->nmodes > 8) return set_error(LBM_EINVAL, "nmodes must be 1..8");
+  if (box < 1) return set_error(LBM_EINVAL, "invalid box");
+  if (!(p->tau2 > 0.5)) return set_error(LBM_EINVAL, "tau2 must exceed 1/2");
+  const double two_pi = 6.283185307179586;
+  std::vector<float> h((size_t)p->nmodes * LBM_WS_MODE_FEATURES);
+  for (int j = 0; j < p->nmodes; ++j) {
+    const double kk = std::sqrt(p->k[j][0] * p->k[j][0] + p->k[j][1] * p->k[j][1] +
+                                p->k[j][2] * p->k[j][2]);
+    if (!(kk > 0)) return set_error(LBM_EINVAL, "mode %d has a zero wavevector", j);
+    float *o = h.data() + (size_t)j * LBM_WS_MODE_FEATURES;
+    for (int a = 0; a < 3; ++a) {
+      const double ka = two_pi * p->k[j][a] / box;  // phase advance per lattice link
+      o[a] = (float)ka;
+      o[3 + a] = (float)std::sin(ka);
+      o[6 + a] = (float)(1.0 - std::cos(ka));
+      o[9 + a] = (float)p->p[j][a];
+    }
+    o[12] = (float)(p->tau2 - 0.5);
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  HIP_TRY(hipMemcpyAsync(out_dev, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // h is released on return
   return LBM_OK;
 }
 

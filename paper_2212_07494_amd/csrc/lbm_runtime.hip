@@ -339,6 +339,48 @@ __global__ void filter_axis_kernel(const double *in, double *out, int nx, int ny
   out[idx] = acc;
 }
 
+// Non-equilibrium second moment of a start state, to leading (Chapman-Enskog) order:
+// Pi_ab = -c_s^2 tau2 rho (d_a u_b + d_b u_a), planes xx, yy, zz, xy, xz, yz.  Central
+// differences of unit spacing, one-sided at the faces of walled axes, zero along axes of
+// length 1.
+__global__ void strain_kernel(const double *rho, const double *u, int nx, int ny, int nz, int D,
+                              int wx, int wy, int wz, double coef, double *pi) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int p[3] = {(int)(n % nx), (int)((n / nx) % ny), (int)(n / ((int64_t)nx * ny))};
+  const int len[3] = {nx, ny, nz};
+  const int wall[3] = {wx, wy, wz};
+  const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
+  double g[3][3];  // g[a][b] = d_b u_a
+  for (int b = 0; b < 3; ++b) {
+    int lo = p[b] - 1, hi = p[b] + 1;
+    double h = 0.5;
+    if (len[b] == 1) {
+      for (int a = 0; a < 3; ++a) g[a][b] = 0.0;
+      continue;
+    }
+    if (wall[b]) {
+      if (lo < 0) { lo = p[b]; h = 1.0; }
+      if (hi >= len[b]) { hi = p[b]; h = 1.0; }
+    } else {
+      lo = (lo + len[b]) % len[b];
+      hi = hi % len[b];
+    }
+    const int64_t nl = n + (int64_t)(lo - p[b]) * stride[b];
+    const int64_t nh = n + (int64_t)(hi - p[b]) * stride[b];
+    for (int a = 0; a < 3; ++a)
+      g[a][b] = a < D ? h * (u[a * N + nh] - u[a * N + nl]) : 0.0;
+  }
+  const double c = coef * rho[n];
+  pi[0 * N + n] = c * (g[0][0] + g[0][0]);
+  pi[1 * N + n] = c * (g[1][1] + g[1][1]);
+  pi[2 * N + n] = c * (g[2][2] + g[2][2]);
+  pi[3 * N + n] = c * (g[0][1] + g[1][0]);
+  pi[4 * N + n] = c * (g[0][2] + g[2][0]);
+  pi[5 * N + n] = c * (g[1][2] + g[2][1]);
+}
+
 __global__ void conserve_apply_kernel(double *rho, double *u, int64_t N, int D,
                                       const double *shift) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -464,7 +506,7 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   }
   lbm::LaunchDesc d = c->desc(1.0);
   d.fout = c->buf[0];
-  if (c->ops->init(d, rho_d, u_d, p->rho0, c->stream) != hipSuccess)
+  if (c->ops->init(d, rho_d, u_d, p->rho0, nullptr, c->stream) != hipSuccess)
     return bail(fail(LBM_EDEVICE, "init kernel launch failed"));
   if (hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(fail(LBM_EDEVICE, "init failed: %s", hipGetErrorString(hipGetLastError())));
@@ -594,27 +636,31 @@ int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t layout, double
   if (layout < 0 || layout > 2) return fail(LBM_EINVAL, "unknown field layout %d", layout);
   if (layout && !(std::isfinite(U) && U > 0 && std::isfinite(R) && R > 0))
     return fail(LBM_EINVAL, "U and R must be positive");
-  if (flags & ~(LBM_RESET_MASS | LBM_RESET_MOMENTUM | LBM_RESET_FILTER))
+  if (flags & ~(LBM_RESET_MASS | LBM_RESET_MOMENTUM | LBM_RESET_FILTER | LBM_RESET_NONEQ))
     return fail(LBM_EINVAL, "unknown reset flags 0x%x", (unsigned)flags);
   const int nplanes = 1 + c->D;
-  const size_t fld = (size_t)c->N * sizeof(double);
+  const int64_t N = c->N;
   const bool filter = flags & LBM_RESET_FILTER;
   const bool conserve = flags & (LBM_RESET_MASS | LBM_RESET_MOMENTUM);
-  // planes (rho, u), the filter's second copy, the conservation partials and shifts
-  const size_t planes = fld * nplanes;
-  const size_t extra = conserve ? (size_t)(CONS_BLOCKS + 1) * CONS_SLOTS * sizeof(double) : 0;
-  int rc = c->need_scratch(planes * (filter ? 2 : 1) + extra);
+  const bool noneq = flags & LBM_RESET_NONEQ;
+  // scratch (binary64): planes A (rho, u), the filter's second copy B, the
+  // non-equilibrium moment (6 planes), the conservation partials and shifts
+  const size_t nA = (size_t)nplanes * N, nB = filter ? nA : 0, nP = noneq ? (size_t)6 * N : 0;
+  const size_t nC = conserve ? (size_t)(CONS_BLOCKS + 1) * CONS_SLOTS : 0;
+  int rc = c->need_scratch((nA + nB + nP + nC) * sizeof(double));
   if (rc) return rc;
   double *A = static_cast<double *>(c->scratch);
-  double *B = A + (size_t)nplanes * c->N;
-  const unsigned grid = (unsigned)((c->N + 255) / 256);
+  double *B = A + nA;
+  double *P = B + nB;
+  double *part = P + nP;
+  const unsigned grid = (unsigned)((N + 255) / 256);
   hipLaunchKernelGGL(fields_to_planes_kernel, dim3(grid), dim3(256), 0, c->stream, fields_dev,
-                     layout, c->N, c->D, U, R, c->p.rho0, A, A + c->N);
+                     layout, N, c->D, U, R, c->p.rho0, A, A + N);
   HIP_TRY(hipGetLastError());
   double *cur = A;
   if (filter) {
     const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
-    const unsigned fgrid = (unsigned)((c->N * nplanes + 255) / 256);
+    const unsigned fgrid = (unsigned)((N * nplanes + 255) / 256);
     for (int axis = 0; axis < 3; ++axis) {
       if (c->p.bc[axis] != LBM_PERIODIC || dims[axis] == 1) continue;
       double *dst = cur == A ? B : A;
@@ -624,22 +670,27 @@ int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t layout, double
       cur = dst;
     }
   }
-  double *rho_d = cur, *u_d = cur + c->N;
+  double *rho_d = cur, *u_d = cur + N;
   if (conserve) {
-    double *part = A + (size_t)(filter ? 2 : 1) * nplanes * c->N;
     double *shift = part + (size_t)CONS_BLOCKS * CONS_SLOTS;
     hipLaunchKernelGGL(conserve_partials_kernel, dim3(CONS_BLOCKS), dim3(256), 0, c->stream, rho_d,
-                       u_d, c->N, c->D, part);
+                       u_d, N, c->D, part);
     hipLaunchKernelGGL(conserve_finalize_kernel, dim3(1), dim3(64), 0, c->stream, part,
-                       CONS_BLOCKS, c->N, c->D, c->p.rho0, (int)flags, shift);
-    hipLaunchKernelGGL(conserve_apply_kernel, dim3(grid), dim3(256), 0, c->stream, rho_d, u_d, c->N,
+                       CONS_BLOCKS, N, c->D, c->p.rho0, (int)flags, shift);
+    hipLaunchKernelGGL(conserve_apply_kernel, dim3(grid), dim3(256), 0, c->stream, rho_d, u_d, N,
                        c->D, shift);
+    HIP_TRY(hipGetLastError());
+  }
+  if (noneq) {
+    hipLaunchKernelGGL(strain_kernel, dim3(grid), dim3(256), 0, c->stream, rho_d, u_d, c->p.nx,
+                       c->p.ny, c->p.nz, c->D, c->p.bc[0] == LBM_WALLS, c->p.bc[1] == LBM_WALLS,
+                       c->p.bc[2] == LBM_WALLS, -c->p.tau[2] / 3.0, P);
     HIP_TRY(hipGetLastError());
   }
   c->cur = 0;
   lbm::LaunchDesc d = c->desc(1.0);
   d.fout = c->buf[0];
-  HIP_TRY(c->ops->init(d, rho_d, u_d, c->p.rho0, c->stream));
+  HIP_TRY(c->ops->init(d, rho_d, u_d, c->p.rho0, noneq ? P : nullptr, c->stream));
   c->t = 0;
   c->uprev_time = -2;
   c->mon.step = -1;

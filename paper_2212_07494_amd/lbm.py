@@ -511,7 +511,8 @@ class lbm_ws_problem(C.Structure):
 
 
 WS_FEATURES = 46
-RESET_MASS, RESET_MOMENTUM, RESET_FILTER = 1, 2, 4
+WS_MODE_FEATURES = 13
+RESET_MASS, RESET_MOMENTUM, RESET_FILTER, RESET_NONEQ = 1, 2, 4, 8
 
 EXPORTS_NN = {
     "lbm_mlp_create": ([C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)],
@@ -529,7 +530,8 @@ EXPORTS_NN = {
                      C.c_int),
     "lbm_mlp_free": ([C.c_void_p], C.c_int),
     "lbm_ws_features": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
-                         C.c_double, C.POINTER(C.c_double), C.c_void_p], C.c_int),
+                         C.c_double, C.c_void_p, C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "lbm_ws_mode_features": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_upsample_periodic": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "lbm_ws_compose": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
@@ -637,16 +639,24 @@ def ws_problem_struct(problem):
 
 
 def lbm_ws_features(problem, n, box, x_dev, base_dev=None, base_order=2, rho_scale=1.0,
-                    stream=None):
-    """Features into x_dev (n^3 x WS_FEATURES), the perturbative steady solution of
-    order base_order (1: Stokes, 2: with the first advective correction) into base_dev
-    (n^3 x 4: u / U, (rho - 1) / (U rho_scale)) if given; returns the velocity scale U."""
+                    mode_coef=None, stream=None):
+    """Features into x_dev (n^3 x WS_FEATURES, may be None), the perturbative steady
+    solution of order base_order (1: Stokes, 2: with the first advective correction) into
+    base_dev (n^3 x 4: u / U, (rho - 1) / (U rho_scale)) if given, each mode's own
+    response corrected by mode_coef (device, 4 x 8) if given; returns the scale U."""
     s = ws_problem_struct(problem)
     U = C.c_double()
     _check(load().lbm_ws_features(C.byref(s), int(n), int(box), _optr(x_dev),
-                                  _optr(base_dev), int(base_order),
-                                  float(rho_scale), C.byref(U), _stream_handle(stream)))
+                                  _optr(base_dev), int(base_order), float(rho_scale),
+                                  _optr(mode_coef), C.byref(U), _stream_handle(stream)))
     return U.value
+
+
+def lbm_ws_mode_features(problem, box, out_dev, stream=None):
+    """Per-mode network inputs (nmodes x WS_MODE_FEATURES, device)."""
+    s = ws_problem_struct(problem)
+    _check(load().lbm_ws_mode_features(C.byref(s), int(box), _dptr(out_dev),
+                                       _stream_handle(stream)))
 
 
 def _optr(t):

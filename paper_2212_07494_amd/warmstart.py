@@ -2,19 +2,20 @@
 
 Problem family: a periodic box^3 D3Q27 SMRT lattice driven by four seeded Fourier modes
 (inputs.warmstart_problem).  The start is the second-order perturbative steady solution
-of the modes (an analytic base, lbm_ws_features) plus a learned correction: the network
-(lbm.MLP, BF16 matrix-core kernels) maps per-point features of the problem to a vector
-potential and a density residual on a coarse nc^3 grid, composed as (curl psi, r) so
-that the velocity correction is divergence-free (lbm_ws_compose).  The correction is
-interpolated to the lattice (lbm_upsample_periodic) and the lattice restarted from
-base + correction (lbm_reset_fields, low-pass filtered and projected onto the plain
-start's mass and momentum).  Training targets are lattice-Boltzmann solutions computed
-by the batched engine from the plain start.  The converged lattice-Boltzmann solution
-decides the prediction's error; the plain start (rest, rho0) remains the fallback.
+of the modes (an analytic base, lbm_ws_features) with each mode's own response
+corrected by a network (lbm.MLP, BF16 matrix-core kernels) that maps the mode's
+wavevector, polarisation and tau2 to 8 amplitude coefficients.  The lattice is
+restarted from that field on the full lattice (lbm_reset_fields: low-pass filtered,
+projected onto the plain start's mass and momentum, with the non-equilibrium stress the
+velocity gradient implies).  Training targets are projections of lattice-Boltzmann
+solutions computed by the batched engine from the plain start; the parameters are
+selected by the steps to steady state they give on validation problems.  The converged
+lattice-Boltzmann solution decides the prediction's error; the plain start (rest, rho0)
+remains the fallback.
 
 torch supplies device buffers and the stream only.
 
-CLI:  python -m paper_2212_07494_amd.warmstart --box 128 --train 80 --val 16 --test 16 --out <dir>
+CLI:  python -m paper_2212_07494_amd.warmstart --box 128 --train 80 --val 12 --test 16 --out <dir>
 """
 from __future__ import annotations
 
@@ -29,9 +30,10 @@ import numpy as np
 from . import inputs
 from . import lbm as L
 
-WIDTHS = [L.WS_FEATURES, 576, 576, 576, 576, 4]  # 1.02M parameters
+WIDTHS = [L.WS_MODE_FEATURES, 576, 576, 576, 576, 8]  # 1.00M parameters
 TAU3 = 1.0
 BASE_ORDER = 2
+NMODES = 4
 
 
 def domain_of(problem, box):
@@ -40,16 +42,24 @@ def domain_of(problem, box):
     return dict(shape=shape, walls=(0, 0, 0), tau=(problem["tau2"], TAU3, 1.0), g_field=g)
 
 
-def coarse_targets(rho, u, box, nc, U, rho0=1.0):
-    """Rows (nc^3 x 4) of (u / U, (rho - rho0) / U) sampled at lattice nodes
-    (i, j, l) * box / nc, x fastest."""
-    s = box // nc
-    r = rho.reshape(box, box, box)[::s, ::s, ::s].ravel()
-    uu = u.reshape(3, box, box, box)[:, ::s, ::s, ::s].reshape(3, -1)
-    out = np.empty((nc ** 3, 4), np.float32)
-    out[:, :3] = (uu / U).T
-    out[:, 3] = (r - rho0) / U
-    return out
+def mode_phases(problem, box):
+    """theta_j(x) = 2 pi k_j . x / box + phase_j on the box^3 lattice, x fastest (nmodes x N)."""
+    N = box ** 3
+    n = np.arange(N)
+    pos = np.stack([n % box, (n // box) % box, n // (box * box)]).astype(np.float64)
+    return np.stack([2 * math.pi * (np.asarray(m["k"], np.float64) @ pos) / box + m["phase"]
+                     for m in problem["modes"]])
+
+
+def separable(problem):
+    """Whether each mode's own wave can be told apart: no two wavevectors equal or
+    opposite (their sine and cosine projections would mix)."""
+    ks = [np.asarray(m["k"]) for m in problem["modes"]]
+    for i in range(len(ks)):
+        for j in range(i):
+            if np.array_equal(ks[i], ks[j]) or np.array_equal(ks[i], -ks[j]):
+                return False
+    return True
 
 
 def solve_batch(problems, box, tol, max_steps, storage="f64", check_every=200, stall=40,
@@ -65,34 +75,39 @@ def solve_batch(problems, box, tol, max_steps, storage="f64", check_every=200, s
 
 
 class WarmStart:
-    """The network plus the buffers to evaluate and train it.
+    """The per-mode network plus the buffers to train and apply it.
 
-    The start is base + (curl psi, r): base the second-order perturbative steady solution
-    (lbm_ws_features), psi and r the network's outputs on the nc^3 grid, composed by
-    lbm_ws_compose.  The velocity correction is a discrete curl, so it adds no
-    compressive error (which would excite slowly damped sound); the output layer starts
-    at zero, so the untrained start is the base.  Scales fitted on the training set: the
-    density channel is carried in units of U * rho_scale and the potential in units of
-    u_scale (the RMS residuals of the base), and the loss weighs the velocity channels
-    by 1 / u_scale^2."""
+    The start is the second-order perturbative steady solution of the forcing modes
+    (lbm_ws_features) in which each mode's own response is corrected by the network:
+    from the mode's phase advance per lattice link, polarisation and tau2
+    (lbm_ws_mode_features) it predicts 8 coefficients -- the velocity amplitude's
+    deviation from s_j p_j on sin(theta_j) (3) and on cos(theta_j) (3) and the density
+    amplitudes (2), in units of s_j.  At small Reynolds numbers the steady state's error
+    against the analytic base is mostly this per-mode lattice response, and a correction
+    confined to the modes' own waves adds nothing to slowly decaying waves the solution
+    does not have.  The output layer starts at zero (the untrained start is the base);
+    per-channel output scales are the RMS targets.  The lattice is restarted with the
+    low-pass filter, the plain start's mass and momentum and the non-equilibrium stress
+    of the field (lbm_reset_fields)."""
 
-    def __init__(self, nc=32, box=128, max_batch=4, widths=WIDTHS, seed=0, stream=None,
-                 base_order=BASE_ORDER):
+    FLAGS = L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM | L.RESET_NONEQ
+
+    def __init__(self, box=128, widths=WIDTHS, seed=0, max_rows=4096, stream=None,
+                 base_order=BASE_ORDER, flags=None):
         import torch
         self.torch = torch
-        self.nc, self.box = nc, box
+        self.box = box
         self.widths = list(widths)
-        self.rows = nc ** 3
         self.stream = stream
         self.base_order = base_order
-        self.rho_scale = 1.0
-        self.u_scale = 1.0
-        self.max_batch = max_batch
-        self.net = L.MLP(self.widths, max_rows=self.rows * max_batch, stream=stream)
+        self.flags = self.FLAGS if flags is None else flags
+        self.scale = np.ones(self.widths[-1], np.float32)
+        self.max_rows = max_rows
+        self.net = L.MLP(self.widths, max_rows=max_rows, stream=stream)
         self.reset_params(seed)
-        shape = (self.rows * max_batch, self.widths[-1])
-        self.y = torch.empty(shape, device="cuda")
-        self.v = torch.empty(shape, device="cuda")
+        self.y = torch.empty((max_rows, self.widths[-1]), device="cuda")
+        self.best_iter = None
+        self.val_curve = []
 
     def reset_params(self, seed):
         p = inputs.mlp_init_params(self.widths, seed)
@@ -101,55 +116,77 @@ class WarmStart:
         self.net.set_params(p.astype(np.float32))
         self.step = 0
 
-    def _set_scales(self, rho_scale, u_scale):
-        self.rho_scale, self.u_scale = float(rho_scale), float(u_scale)
-        self.net.set_output_scale([self.u_scale] * 3 + [1.0])
-
-    def loss_weight(self):
-        return np.array([1.0 / self.u_scale ** 2] * 3 + [1.0], np.float32)
+    def set_scale(self, scale):
+        """Output scales; channels far below the largest (round-off, e.g. amplitudes
+        that vanish by symmetry) are floored at 1e-3 of it so their noise is not fitted."""
+        scale = np.asarray(scale, np.float64)
+        self.scale = np.maximum(scale, 1e-3 * max(float(scale.max()), 1e-30)).astype(np.float32)
+        self.net.set_output_scale(self.scale)
 
     # -- data -------------------------------------------------------------------------
-    def features(self, problem, x=None, base=None):
-        """Features and base (device, rows x F and rows x 4) and the scale U."""
+    def mode_features(self, problem, out=None):
         torch = self.torch
-        x = x if x is not None else torch.empty((self.rows, self.widths[0]), device="cuda")
-        base = base if base is not None else torch.empty((self.rows, 4), device="cuda")
-        U = L.lbm_ws_features(problem, self.nc, self.box, x, base, self.base_order,
-                              self.rho_scale, stream=self.stream)
-        return x, base, U
+        out = out if out is not None else torch.empty((NMODES, self.widths[0]), device="cuda")
+        L.lbm_ws_mode_features(problem, self.box, out, stream=self.stream)
+        return out
+
+    def mode_targets(self, problem, rho, u):
+        """The 8 coefficients per mode that make the base's own mode responses match a
+        converged lattice state (rho, u on the box^3 lattice): projections on
+        sin(theta_j), cos(theta_j) of the state minus the base's pair terms."""
+        torch = self.torch
+        N = self.box ** 3
+        b1 = torch.empty((N, 4), device="cuda")
+        b2 = torch.empty((N, 4), device="cuda")
+        U = L.lbm_ws_features(problem, self.box, self.box, None, b1, 1, stream=self.stream)
+        L.lbm_ws_features(problem, self.box, self.box, None, b2, 2, stream=self.stream)
+        pair = (b2 - b1).double().cpu().numpy().T        # (4, N), units of U
+        r = np.concatenate([u / U, (rho[None] - 1.0) / U]) - pair
+        th = mode_phases(problem, self.box)
+        sn, cs = np.sin(th), np.cos(th)
+        nu = (problem["tau2"] - 0.5) / 3.0
+        out = np.empty((NMODES, 8))
+        for j, m in enumerate(problem["modes"]):
+            K = 2 * math.pi * np.linalg.norm(m["k"]) / self.box
+            a = m["amp"] / (nu * K * K) / U
+            ps = 2.0 / N * (r @ sn[j])
+            pc = 2.0 / N * (r @ cs[j])
+            out[j, 0:3] = ps[:3] / a - np.asarray(m["p"])
+            out[j, 3:6] = pc[:3] / a
+            out[j, 6] = ps[3] / a
+            out[j, 7] = pc[3] / a
+        return out.astype(np.float32)
 
     def dataset(self, problems, fields, fit_scale=False):
-        """Device tensors X (n x rows x F), B (n x rows x 4, base), T (n x rows x 4).
-        fit_scale sets rho_scale and u_scale from these problems first."""
+        """Device tensors X (4n x 8 features), T (4n x 8 targets) from solved problems
+        (those with separable modes); fit_scale sets the output scales from them."""
         torch = self.torch
-        n = len(problems)
+        keep = [(p, f) for p, f in zip(problems, fields) if separable(p)]
+        X = torch.empty((NMODES * len(keep), self.widths[0]), device="cuda")
+        T = np.empty((NMODES * len(keep), self.widths[-1]), np.float32)
+        for i, (p, (rho, u)) in enumerate(keep):
+            self.mode_features(p, out=X[NMODES * i: NMODES * (i + 1)])
+            T[NMODES * i: NMODES * (i + 1)] = self.mode_targets(p, rho, u)
         if fit_scale:
-            self._set_scales(1.0, 1.0)
-        X = torch.empty((n, self.rows, self.widths[0]), device="cuda")
-        B = torch.empty((n, self.rows, 4), device="cuda")
-        T = torch.empty((n, self.rows, self.widths[-1]), device="cuda")
-        for i, (p, (rho, u)) in enumerate(zip(problems, fields)):
-            _, _, U = self.features(p, x=X[i], base=B[i])
-            T[i] = torch.from_numpy(coarse_targets(rho, u, self.box, self.nc, U)).cuda()
-        if fit_scale:
-            r = (T[..., 3] - B[..., 3]).double()
-            e = (T[..., :3] - B[..., :3]).double()
-            self._set_scales(max(float(torch.sqrt(torch.mean(r * r))), 1e-12),
-                             max(float(torch.sqrt(torch.mean(e * e))), 1e-12))
-            B[..., 3] /= self.rho_scale
-        T[..., 3] /= self.rho_scale
-        return X, B, T
+            self.set_scale(np.sqrt(np.mean(T.astype(np.float64) ** 2, axis=0)))
+        return X, torch.from_numpy(T).cuda()
 
     # -- training ---------------------------------------------------------------------
-    def train(self, X, B, T, iters=2000, batch=4, lr=1e-3, lr_min=1e-5, seed=1, log_every=0,
-              val=None, eval_every=250):
-        """Adam with a cosine learning rate over random batches of problems.  val, a
-        callable returning a score (lower is better, e.g. validation_steps), selects
-        the parameters: it is evaluated at the start and every eval_every iterations and
-        the best parameters are kept, so the result is never worse on it than the base
-        (the zero correction training starts from).  The curve is left in
-        self.val_curve as (iteration, score) pairs, the kept iteration in best_iter."""
+    def train(self, X, T, iters=6000, batch=256, lr=1e-3, lr_min=1e-5, seed=1, log_every=0,
+              val=None, eval_every=1000):
+        """Adam with a cosine learning rate over random batches of modes, loss the mean
+        square error in units of the output scales.  val, a callable returning a score
+        (lower is better, e.g. validation_steps), selects the parameters: evaluated at the
+        start and every eval_every iterations, the best are kept, so the result is never
+        worse on it than the base (the zero correction training starts from).  The curve
+        is left in self.val_curve as (iteration, score), the kept iteration in best_iter."""
         torch = self.torch
+        n = X.shape[0]
+        rng = np.random.default_rng(seed)
+        batch = min(batch, n, self.max_rows)
+        xb = torch.empty((batch, self.widths[0]), device="cuda")
+        tb = torch.empty((batch, self.widths[-1]), device="cuda")
+        w = (1.0 / self.scale.astype(np.float64) ** 2).astype(np.float32)
         self.val_curve = []
         self.best_iter = None
         best = None
@@ -163,29 +200,15 @@ class WarmStart:
             if best is None or score < best[0]:
                 best = (score, self.net.params(), it)
 
-        n = X.shape[0]
-        rng = np.random.default_rng(seed)
-        batch = min(batch, n, self.max_batch)
-        rows = batch * self.rows
-        xb = torch.empty((rows, self.widths[0]), device="cuda")
-        bb = torch.empty((rows, 4), device="cuda")
-        tb = torch.empty((rows, 4), device="cuda")
-        dv = torch.empty((rows, 4), device="cuda")
-        dy = torch.empty((rows, 4), device="cuda")
-        w = self.loss_weight()
         losses = []
         check(0)
         for it in range(iters):
             idx = torch.as_tensor(rng.choice(n, batch, replace=False))
-            xb.copy_(X[idx].reshape(rows, -1))
-            bb.copy_(B[idx].reshape(rows, -1))
-            tb.copy_(T[idx].reshape(rows, -1))
-            self.net.forward(xb, self.y[:rows])
-            L.lbm_ws_compose(self.y[:rows], bb, self.nc, batch, self.v[:rows], stream=self.stream)
-            loss = self.net.loss_grad(self.v[:rows], tb, dv, w)
-            L.lbm_ws_compose(dv, None, self.nc, batch, dy, stream=self.stream)
+            xb.copy_(X[idx])
+            tb.copy_(T[idx])
+            self.net.forward(xb, self.y[:batch])
             self.net.zero_grads()
-            self.net.backward(dy)
+            loss = self.net.loss_backward(tb, w)
             self.step += 1
             rate = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * it / max(1, iters)))
             self.net.adam(rate, self.step)
@@ -199,62 +222,39 @@ class WarmStart:
             self.best_iter = best[2]
         return losses
 
-    def _compose(self, x, base, out):
-        self.net.forward(x, self.y[: self.rows])
-        L.lbm_ws_compose(self.y[: self.rows], base, self.nc, 1, out, stream=self.stream)
-
-    def evaluate(self, X, B, T):
-        """Relative L2 error of the velocity channels per problem, for the prediction and
-        for the base alone."""
-        errs, base_errs = [], []
-        for i in range(X.shape[0]):
-            self._compose(X[i], B[i], self.v[: self.rows])
-            y = self.v[: self.rows].cpu().numpy()
-            b = B[i].cpu().numpy()
-            t = T[i].cpu().numpy()
-            nt = np.linalg.norm(t[:, :3])
-            errs.append(float(np.linalg.norm(y[:, :3] - t[:, :3]) / nt))
-            base_errs.append(float(np.linalg.norm(b[:, :3] - t[:, :3]) / nt))
-        return errs, base_errs
+    def evaluate(self, X, T):
+        """RMS error of the predicted coefficients in units of the output scales, and of
+        the base (zero correction), over a set of modes."""
+        self.net.forward(X, self.y[: X.shape[0]])
+        y = self.y[: X.shape[0]].cpu().numpy().astype(np.float64)
+        t = T.cpu().numpy().astype(np.float64)
+        sc = self.scale.astype(np.float64)
+        return (float(np.sqrt(np.mean(((y - t) / sc) ** 2))),
+                float(np.sqrt(np.mean((t / sc) ** 2))))
 
     # -- inference ----------------------------------------------------------------------
     def predict(self, problem):
-        """The composed prediction rows (nc^3 x 4, device) and the problem's velocity scale."""
-        x, base, U = self.features(problem)
-        self._compose(x, base, self.v[: self.rows])
-        return self.v[: self.rows], U
+        """Start fields (box^3 x 4 rows, device: u / U, (rho - 1) / U) and U."""
+        torch = self.torch
+        x = self.mode_features(problem)
+        self.net.forward(x, self.y[:NMODES])
+        rows = torch.empty((self.box ** 3, 4), device="cuda")
+        U = L.lbm_ws_features(problem, self.box, self.box, None, rows, self.base_order, 1.0,
+                              mode_coef=self.y[:NMODES], stream=self.stream)
+        return rows, U
 
     def start(self, lattice, problem):
-        """Restart `lattice` (a box^3 lbm.Lattice of this problem) from the prediction,
-        low-pass filtered and projected onto the plain start's mass and momentum.  With
-        nc < box only the network's correction is interpolated; the base is evaluated on
-        the lattice itself."""
-        torch = self.torch
-        flags = L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM
-        if self.nc == self.box:
-            v, U = self.predict(problem)
-            L.lbm_reset_fields(lattice.ctx, v, 1, U, U * self.rho_scale, flags)
-            return U
-        x, _, U = self.features(problem)
-        self.net.forward(x, self.y[: self.rows])
-        corr = self.v[: self.rows]
-        L.lbm_ws_compose(self.y[: self.rows], None, self.nc, 1, corr, stream=self.stream)
-        fine_base = torch.empty((self.box ** 3, 4), device="cuda")
-        L.lbm_ws_features(problem, self.box, self.box, None, fine_base, self.base_order,
-                          self.rho_scale, stream=self.stream)
-        fine = torch.empty((4, self.box ** 3), device="cuda")
-        L.lbm_upsample_periodic(corr, self.nc, 4, fine, self.box, point_major_in=True,
-                                addend=fine_base, stream=self.stream)
-        L.lbm_reset_fields(lattice.ctx, fine, 2, U, U * self.rho_scale, flags)
+        """Restart `lattice` (a box^3 lbm.Lattice of this problem) from the prediction."""
+        rows, U = self.predict(problem)
+        L.lbm_reset_fields(lattice.ctx, rows, 1, U, U, self.flags)
         return U
 
     def save(self, path):
-        """Parameters (path + '.npy') and the scales (path + '.json')."""
+        """Parameters (path + '.npy') and the settings (path + '.json')."""
         np.save(path + ".npy", self.net.params())
         with open(path + ".json", "w") as fh:
-            json.dump(dict(widths=self.widths, nc=self.nc, box=self.box,
-                           base_order=self.base_order, rho_scale=self.rho_scale,
-                           u_scale=self.u_scale), fh)
+            json.dump(dict(widths=self.widths, box=self.box, base_order=self.base_order,
+                           flags=self.flags, scale=self.scale.tolist()), fh)
 
     def load(self, path):
         with open(path + ".json") as fh:
@@ -262,7 +262,8 @@ class WarmStart:
         if meta["widths"] != self.widths:
             raise ValueError(f"saved widths {meta['widths']} differ from {self.widths}")
         self.base_order = meta["base_order"]
-        self._set_scales(meta["rho_scale"], meta["u_scale"])
+        self.flags = meta["flags"]
+        self.set_scale(meta["scale"])
         self.net.set_params(np.load(path + ".npy", allow_pickle=False))
 
     def close(self):
@@ -305,8 +306,8 @@ def validation_steps(ws, problems, box, tol=1e-8, check_every=50, max_steps=2_00
 def compare_starts(ws, problem, box, tol, storage="f64", check_every=200, max_steps=2_000_000,
                    reference=None, stream=None, plain=None, reference_u=None):
     """Steps and wall time to resid < tol from the plain start and from ws's start
-    (inference, interpolation and restart included in the warm time, and timed on their
-    own as inference_s).  The plain run's final velocity is the reference for the true
+    (inference, field evaluation and restart included in the warm time, and timed on
+    their own as inference_s).  The plain run's final velocity is the reference for the true
     errors (initial_err, final_err) unless `reference` is given.  A plain record and its
     final velocity from an earlier call (plain, reference_u) skip the plain run."""
     torch = ws.torch
@@ -350,13 +351,12 @@ def compare_starts(ws, problem, box, tol, storage="f64", check_every=200, max_st
 def main():
     ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
     ap.add_argument("--box", type=int, default=128)
-    ap.add_argument("--nc", type=int, default=32)
     ap.add_argument("--train", type=int, default=80)
-    ap.add_argument("--val", type=int, default=16)
+    ap.add_argument("--val", type=int, default=12)
     ap.add_argument("--test", type=int, default=16)
-    ap.add_argument("--iters", type=int, default=1500)
+    ap.add_argument("--iters", type=int, default=6000)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--data-tol", type=float, default=1e-8)
+    ap.add_argument("--data-tol", type=float, default=1e-10)
     ap.add_argument("--chunk", type=int, default=32, help="domains per batched data solve")
     ap.add_argument("--seed", type=int, default=2022)
     ap.add_argument("--out", default="warmstart_out")
@@ -367,54 +367,57 @@ def main():
     n_fit = args.train + args.val
     probs = [inputs.warmstart_problem(args.seed + i, box=args.box)
              for i in range(n_fit + args.test)]
-    ws = WarmStart(nc=args.nc, box=args.box, max_batch=8, seed=args.seed)
-    parts = []
+    train_p, val_p, test_p = probs[:args.train], probs[args.train:n_fit], probs[n_fit:]
+    ws = WarmStart(box=args.box, seed=args.seed)
+    Xs, Ts = [], []
     t0 = time.time()
     data_steps = []
-    for c0 in range(0, n_fit, args.chunk):
-        ps = probs[c0:min(c0 + args.chunk, n_fit)]
+    for c0 in range(0, args.train, args.chunk):
+        ps = train_p[c0:c0 + args.chunk]
         steps, _, status, fields = solve_batch(ps, args.box, args.data_tol, 3_000_000)
-        if np.any(status != L.DOM_CONVERGED):
+        if np.any((status != L.DOM_CONVERGED) & (status != L.DOM_FLOOR)):
             raise RuntimeError(f"data solve did not converge: {status.tolist()}")
-        parts.append(ws.dataset(ps, fields, fit_scale=(c0 == 0)))
+        X, T = ws.dataset(ps, fields)
+        Xs.append(X)
+        Ts.append(T)
         data_steps += steps.tolist()
         del fields
-        print(f"data: {c0 + len(ps)}/{n_fit} solved, {time.time() - t0:.1f} s", flush=True)
-    X, B, T = (torch.cat([p[k] for p in parts]) for k in range(3))
-    del parts
-    tr = slice(0, args.train)
-    va = slice(args.train, n_fit)
+        print(f"data: {c0 + len(ps)}/{args.train} solved, {time.time() - t0:.1f} s", flush=True)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    ws.set_scale(torch.sqrt(torch.mean(T.double() ** 2, 0)).cpu().numpy())
     t0 = time.time()
-    val_p = probs[args.train:n_fit]
-    losses = ws.train(X[tr], B[tr], T[tr], iters=args.iters, batch=8, log_every=250,
+    losses = ws.train(X, T, iters=args.iters, log_every=1000,
                       val=lambda: validation_steps(ws, val_p, args.box, args.tol, 100))
     torch.cuda.synchronize()
     t_train = time.time() - t0
     print(f"train: {args.iters} iters, {t_train:.1f} s, final loss {losses[-1]:.3e}, "
-          f"kept iteration {ws.best_iter}", flush=True)
+          f"kept iteration {ws.best_iter}, validation steps {ws.val_curve}", flush=True)
     ws.save(os.path.join(args.out, "warmstart"))
-    base = WarmStart(nc=args.nc, box=args.box, max_batch=1, seed=args.seed)
-    base._set_scales(ws.rho_scale, ws.u_scale)
+    base = WarmStart(box=args.box, seed=args.seed,
+                     flags=L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM)
     results = []
-    for i, p in enumerate(probs[n_fit:]):
+    for i, p in enumerate(test_p):
         r = compare_starts(ws, p, args.box, args.tol, check_every=100)
-        rb = compare_starts(base, p, args.box, args.tol, check_every=100,
-                            reference=None, plain=r["plain"], reference_u=r["reference_u"])
+        rb = compare_starts(base, p, args.box, args.tol, check_every=100, plain=r["plain"],
+                            reference_u=r["reference_u"])
         r["base"] = rb["warm"]
         del r["reference_u"]
         r.update(tau2=p["tau2"], U=p["U"])
         results.append(r)
         print(f"test {i}: plain {r['plain']['steps']} steps {r['plain']['wall_s']:.2f} s | "
               f"base {r['base']['steps']} steps {r['base']['wall_s']:.2f} s | "
-              f"learned {r['warm']['steps']} steps {r['warm']['wall_s']:.2f} s", flush=True)
+              f"learned {r['warm']['steps']} steps {r['warm']['wall_s']:.2f} s "
+              f"(start {r['warm']['inference_s'] * 1e3:.1f} ms, error "
+              f"{r['warm']['initial_err']:.1e} -> {r['warm']['final_err']:.1e})", flush=True)
+    base.close()
 
     def med(key, field):
         return float(np.median([r[key][field] / r["plain"][field] for r in results]))
 
-    summary = dict(box=args.box, nc=args.nc, train=args.train, val=args.val, test=args.test,
+    summary = dict(box=args.box, train=args.train, val=args.val, test=args.test,
                    iters=args.iters, kept_iteration=ws.best_iter, val_curve=ws.val_curve,
                    train_seconds=t_train, final_loss=losses[-1], data_steps=data_steps,
-                   rho_scale=ws.rho_scale, u_scale=ws.u_scale, results=results,
+                   scale=ws.scale.tolist(), results=results,
                    steps_ratio_median=med("warm", "steps"), wall_ratio_median=med("warm", "wall_s"),
                    base_steps_ratio_median=med("base", "steps"),
                    base_wall_ratio_median=med("base", "wall_s"))
@@ -422,6 +425,7 @@ def main():
         json.dump(summary, fh, indent=1)
     print(json.dumps({k: v for k, v in summary.items()
                       if k not in ("results", "data_steps", "val_curve")}))
+    ws.close()
 
 
 if __name__ == "__main__":
