@@ -209,6 +209,22 @@ def batch_domains(n=512, seed=7494, h_range=(16, 128), l_range=(64, 256),
     return out
 
 
+def batch_domain_dicts(specs):
+    """lbm.Batch domain dicts of batch_domains' specs: channels with walls in y and a
+    uniform g_x, periodic boxes with the profile g_x = amp sin(2 pi y / H)."""
+    doms = []
+    for s in specs:
+        nx, ny = s["nx"], s["ny"]
+        tau = (s["tau2"], 1.0, 1.0)
+        if s["kind"] == 0:
+            doms.append(dict(shape=(nx, ny, 1), walls=(0, 1, 0), tau=tau, g=(s["g"], 0, 0)))
+        else:
+            table = np.zeros((3, ny))
+            table[0] = s["g"] * np.sin(2 * math.pi * np.arange(ny) / ny)
+            doms.append(dict(shape=(nx, ny, 1), walls=(0, 0, 0), tau=tau, g_profile=(1, table)))
+    return doms
+
+
 def mlp_init_params(widths, seed: int) -> np.ndarray:
     """Seeded initial network parameters (flat, W_0, b_0, W_1, b_1, ...; W row-major
     out x in): weights uniform in +-sqrt(6 / (in + out)), biases zero."""

@@ -1,0 +1,108 @@
+"""Throughput of the library on the named synthetic workloads (one GPU).
+
+    python -m paper_2212_07494_amd.workloads d3q19 --storage f32s   # 256^3 Taylor-Green + force
+    python -m paper_2212_07494_amd.workloads d3q27 --storage f64    # 128^3, 4 Fourier modes
+    python -m paper_2212_07494_amd.workloads d2q9 --storage f32s    # 1024^2 Kolmogorov flow
+    python -m paper_2212_07494_amd.workloads batch                  # 512 uneven D2Q9 domains
+
+Each run: warm-up steps, the library's launch tuner, then timed steps bracketed by HIP
+events on the library's stream.  Prints one JSON line: lattice updates per second, the
+algorithmic bytes per second (2 Q S per update) and the per-step time.  `batch` also
+times the same domains stepped as separate single-domain launches.  Inputs are the
+seeded generators of `inputs`; torch supplies memory and the stream only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+from . import inputs
+from . import lbm as L
+
+
+def _time(torch, stream, fn, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps  # ms
+
+
+def single(torch, stream, name, storage, steps, warmup):
+    if name == "d3q19":
+        w = inputs.taylor_green_3d(n=256)
+        lat = L.Lattice(w.lattice, w.collision, storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
+                        g_profile=w.g_profile, stream=stream)
+        desc = "D3Q19 SMRT 256^3 periodic, Taylor-Green + sin force"
+    elif name == "d3q27":
+        p = inputs.warmstart_problem(2022, box=128)
+        shape = (128, 128, 128)
+        lat = L.Lattice("D3Q27", "smrt", storage, shape, (0, 0, 0), (p["tau2"], 1.0, 1.0),
+                        g_field=inputs.fourier_force(shape, p["modes"]), stream=stream)
+        desc = "D3Q27 SMRT 128^3 periodic, 4 Fourier forcing modes"
+    elif name == "d2q9":
+        w = inputs.kolmogorov_box(L=1024)
+        lat = L.Lattice(w.lattice, w.collision, storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
+                        g_profile=w.g_profile, stream=stream)
+        desc = "D2Q9 SMRT 1024^2 periodic Kolmogorov flow"
+    else:
+        raise ValueError(name)
+    with lat:
+        lat.step(warmup)
+        tuning = lat.tune(autotune_steps=20)
+        ms = _time(torch, stream, lambda: lat.step(steps), 1) / steps
+        N, Q = lat.N, lat.Q
+    S = L.STORAGE_BYTES[storage]
+    return {"workload": desc, "storage": storage, "nodes": N, "steps": steps,
+            "ms_per_step": round(ms, 5), "MLUPS": round(N / ms / 1e3, 1),
+            "GBps": round(2 * Q * S * N / ms / 1e6, 1),
+            "launch": {"block": list(tuning[:2]), "memory_variant": tuning[2]}}
+
+
+def batch(torch, stream, storage, steps, warmup, n=512):
+    doms = inputs.batch_domain_dicts(inputs.batch_domains(n))
+    with L.Batch(doms, "D2Q9", "smrt", storage, stream=stream) as b:
+        nodes = b.info()["nodes"]
+        b.advance(warmup)
+        tuning = b.tune(autotune_steps=20)
+        ms = _time(torch, stream, lambda: b.advance(steps), 1) / steps
+    singles = [L.Lattice("D2Q9", "smrt", storage, d["shape"], d["walls"], d["tau"], g=d.get("g"),
+                         g_profile=d.get("g_profile"), stream=stream) for d in doms]
+    try:
+        for s in singles:
+            s.step(2)
+        ms1 = _time(torch, stream, lambda: [s.step(1) for s in singles], 20)
+    finally:
+        for s in singles:
+            s.close()
+    S = L.STORAGE_BYTES[storage]
+    return {"workload": f"{n} uneven D2Q9 SMRT domains (channels and shear boxes)",
+            "storage": storage, "nodes": nodes, "steps": steps,
+            "ms_per_step": round(ms, 5), "MLUPS": round(nodes / ms / 1e3, 1),
+            "GBps": round(2 * 9 * S * nodes / ms / 1e6, 1), "tuning": tuning,
+            "single_domain_launches_ms_per_step": round(ms1, 5),
+            "speedup_over_single_launches": round(ms1 / ms, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("workload", choices=["d3q19", "d3q27", "d2q9", "batch"])
+    ap.add_argument("--storage", default="f32s", choices=["f64", "f32", "f32s", "f16s"])
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    args = ap.parse_args()
+    import torch
+    L.load()
+    stream = torch.cuda.Stream()
+    if args.workload == "batch":
+        rec = batch(torch, stream, args.storage, args.steps, args.warmup)
+    else:
+        rec = single(torch, stream, args.workload, args.storage, args.steps, args.warmup)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

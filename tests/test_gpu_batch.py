@@ -30,17 +30,7 @@ def d2_domains(n, seed=7494, h_range=(16, 128), l_range=(64, 256)):
     """Seeded channel / shear-box domains of the batched workload (as dicts for
     lbm.Batch) and their force fields."""
     specs = inputs.batch_domains(n, seed=seed, h_range=h_range, l_range=l_range)
-    doms = []
-    for s in specs:
-        nx, ny = s["nx"], s["ny"]
-        tau = (s["tau2"], 1.0, 1.0)
-        if s["kind"] == 0:
-            doms.append(dict(shape=(nx, ny, 1), walls=(0, 1, 0), tau=tau, g=(s["g"], 0, 0)))
-        else:
-            table = np.zeros((3, ny))
-            table[0] = s["g"] * np.sin(2 * math.pi * np.arange(ny) / ny)
-            doms.append(dict(shape=(nx, ny, 1), walls=(0, 0, 0), tau=tau, g_profile=(1, table)))
-    return specs, doms
+    return specs, inputs.batch_domain_dicts(specs)
 
 
 def g_field_of(dom):
