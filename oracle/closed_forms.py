@@ -88,14 +88,11 @@ def kolmogorov_amplitude_continuum(G: float, k: float, tau2: float) -> float:
 
 # ---- brute force: dense steady solve of the odd sector --------------------------------
 
-def odd_sector_steady(g: np.ndarray, tau2: float, tau3: float, collision: str,
-                      walls: bool) -> np.ndarray:
-    """Steady u_x(y) of the odd sector by one dense linear solve.
-
-    g: acceleration per row (length n).  Unknowns: h_c(y) for c in (-1, 0, 1) after
-    streaming (pre-collision).  One step is an affine map h -> A h + b; the steady
-    state solves (I - A) h = b.
-    """
+def odd_sector_affine(g: np.ndarray, tau2: float, tau3: float, collision: str,
+                      walls: bool):
+    """One step of the odd sector as an affine map h -> A h + b s, for the acceleration
+    g (per row, length n) scaled by s that step.  Unknowns: h_c(y) for c in (-1, 0, 1)
+    after streaming (pre-collision), ordered c-major.  Returns (A, b)."""
     g = np.asarray(g, dtype=np.float64)
     n = g.size
     cs = (-1, 0, 1)
@@ -143,8 +140,20 @@ def odd_sector_steady(g: np.ndarray, tau2: float, tau3: float, collision: str,
             else:
                 # population leaving row y toward the wall returns as -c: h_c(y) <- -h*_{-c}(y)
                 S[idx(c, y), idx(-c, y)] = -1
-    A = S @ Cm
-    b = S @ d
+    return S @ Cm, S @ d
+
+
+def _sector_velocity(h, g, s):
+    n = g.size
+    return h[: n] + h[n: 2 * n] + h[2 * n:] + np.asarray(g) * s / 2
+
+
+def odd_sector_steady(g: np.ndarray, tau2: float, tau3: float, collision: str,
+                      walls: bool) -> np.ndarray:
+    """Steady u_x(y) of the odd sector by one dense linear solve of (I - A) h = b."""
+    g = np.asarray(g, dtype=np.float64)
+    A, b = odd_sector_affine(g, tau2, tau3, collision, walls)
+    nv = b.size
     if walls:
         h = np.linalg.solve(np.eye(nv) - A, b)
     else:
@@ -155,8 +164,49 @@ def odd_sector_steady(g: np.ndarray, tau2: float, tau3: float, collision: str,
         M = np.vstack([np.eye(nv) - A, con])
         r = np.concatenate([b, [-g.sum() / 2]])
         h = np.linalg.lstsq(M, r, rcond=None)[0]
-    X = h[: n] + h[n: 2 * n] + h[2 * n:]
-    return X + g / 2
+    return _sector_velocity(h, g, 1.0)
+
+
+def odd_sector_periodic(g: np.ndarray, omega: float, tau2: float, tau3: float, collision: str,
+                        walls: bool) -> np.ndarray:
+    """Time-periodic response of the odd sector to the acceleration g(y) cos(omega t):
+    with s_t = Re(exp(i omega t)) the step h_{t+1} = A h_t + b s_t has the periodic
+    solution h_t = Re(H exp(i omega t)), (exp(i omega) I - A) H = b.  Returns the complex
+    amplitude of u_x(y): u_x(y, t) = Re(U(y) exp(i omega t)) (u = X + g s / 2)."""
+    g = np.asarray(g, dtype=np.float64)
+    A, b = odd_sector_affine(g, tau2, tau3, collision, walls)
+    H = np.linalg.solve(np.exp(1j * omega) * np.eye(b.size) - A, b.astype(complex))
+    return _sector_velocity(H, g.astype(complex), 1.0)
+
+
+def odd_sector_evolve(g: np.ndarray, s, tau2: float, tau3: float, collision: str,
+                      walls: bool) -> np.ndarray:
+    """u_x(y) after len(s) - 1 steps from rest (rho = 1, u = 0) with the acceleration
+    g(y) s_t at step t (s_0 .. s_{k-1}) and s_k for the final velocity.  The rest state
+    holds f-bar = f_eq - F/2 with the first-order force term F_i = 3 w_i rho e_i . g, whose
+    odd part is h_c = -3 w_c g s_0."""
+    g = np.asarray(g, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    import scipy.sparse
+    A, b = odd_sector_affine(g, tau2, tau3, collision, walls)
+    As = scipy.sparse.csr_matrix(A)  # a few entries per row: the recursion is cheap
+    h = np.concatenate([-3 * w * g * s[0] for w in (1 / 36, 1 / 9, 1 / 36)])
+    for t in range(s.size - 1):
+        h = As @ h + b * s[t]
+    return _sector_velocity(h, g, s[-1])
+
+
+def womersley_profile(ny: int, nu: float, amp: float, omega: float, t: float,
+                      rho0: float = 1.0) -> np.ndarray:
+    """Continuum Womersley flow between plates at y = -1/2 and ny - 1/2 (halfway walls,
+    width 2L = ny) under the uniform force -amp cos(omega t) (paper Sec. III.B):
+    U = Re(i amp/(rho0 omega) {1 - cosh((1+i) y sqrt(omega/2nu)) / cosh((1+i) L
+    sqrt(omega/2nu))} exp(i omega t)), y measured from the mid-plane, at the ny nodes."""
+    y = np.arange(ny) - (ny - 1) / 2.0
+    L = ny / 2.0
+    k = (1 + 1j) * math.sqrt(omega / (2 * nu))
+    prof = 1j * amp / (rho0 * omega) * (1 - np.cosh(k * y) / np.cosh(k * L))
+    return np.real(prof * np.exp(1j * omega * t))
 
 
 def taylor_green_velocity(shape, u0: float, nu: float, t: float):

@@ -4,6 +4,7 @@
     python -m paper_2212_07494_amd.workloads d3q27 --storage f64    # 128^3, 4 Fourier modes
     python -m paper_2212_07494_amd.workloads d2q9 --storage f32s    # 1024^2 Kolmogorov flow
     python -m paper_2212_07494_amd.workloads batch                  # 512 uneven D2Q9 domains
+    python -m paper_2212_07494_amd.workloads womersley              # 50 x 200 channel, 20 periods
 
 Each run: warm-up steps, the library's launch tuner, then timed steps bracketed by HIP
 events on the library's stream.  Prints one JSON line: lattice updates per second, the
@@ -87,9 +88,38 @@ def batch(torch, stream, storage, steps, warmup, n=512):
             "speedup_over_single_launches": round(ms1 / ms, 2)}
 
 
+def womersley(torch, stream, storage, collision="smrt", periods=20, nx=50, ny=200, T=1200,
+              nu=0.1, amp=1e-4):
+    """Paper Sec. III.B: a channel (periodic x, halfway bounce-back plates in y) from rest
+    under the uniform force -amp cos(2 pi t / T), one force factor per step.  Times the
+    whole run and reports the velocity at its end against the continuum solution."""
+    import math
+    import numpy as np
+    k = periods * T
+    s = np.cos(2 * math.pi * np.arange(k + 1) / T)
+    with L.Lattice("D2Q9", collision, storage, (nx, ny, 1), (0, 1, 0), (3 * nu + 0.5, 1.0, 1.0),
+                   g=(-amp, 0.0, 0.0), stream=stream) as lat:
+        tuning = lat.tune(autotune_steps=20)
+        ms = _time(torch, stream, lambda: lat.step(k, g_scale=s[:k]), 1)
+        _, u = lat.moments(g_scale=s[k])
+    om = 2 * math.pi / T
+    y = np.arange(ny) - (ny - 1) / 2.0
+    kk = (1 + 1j) * math.sqrt(om / (2 * nu))
+    uc = np.real(1j * amp / om * (1 - np.cosh(kk * y) / np.cosh(kk * ny / 2.0)) * np.exp(1j * om * k))
+    ux = u[0].reshape(ny, nx)[:, 0]
+    S = L.STORAGE_BYTES[storage]
+    return {"workload": f"Womersley channel {nx} x {ny} D2Q9 {collision.upper()}, T={T}, "
+                        f"nu={nu}, {periods} periods from rest",
+            "storage": storage, "nodes": nx * ny, "steps": k, "seconds": round(ms / 1e3, 4),
+            "ms_per_step": round(ms / k, 5), "MLUPS": round(nx * ny * k / ms / 1e3, 1),
+            "GBps": round(2 * 9 * S * nx * ny * k / ms / 1e6, 1),
+            "launch": {"block": list(tuning[:2]), "memory_variant": tuning[2]},
+            "E2_vs_continuum_at_end": float(np.linalg.norm(ux - uc) / np.linalg.norm(uc))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("workload", choices=["d3q19", "d3q27", "d2q9", "batch"])
+    ap.add_argument("workload", choices=["d3q19", "d3q27", "d2q9", "batch", "womersley"])
     ap.add_argument("--storage", default="f32s", choices=["f64", "f32", "f32s", "f16s"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
@@ -99,6 +129,8 @@ def main():
     stream = torch.cuda.Stream()
     if args.workload == "batch":
         rec = batch(torch, stream, args.storage, args.steps, args.warmup)
+    elif args.workload == "womersley":
+        rec = womersley(torch, stream, args.storage)
     else:
         rec = single(torch, stream, args.workload, args.storage, args.steps, args.warmup)
     print(json.dumps(rec), flush=True)
