@@ -102,6 +102,14 @@ typedef struct {
   const double *g_data;         /* host array, copied at init (see lbm_force_kind) */
   int32_t monitor_every;        /* K >= 1: lbm_step updates the monitors every K steps; 0 = never */
   const lbm_allocator *allocator; /* NULL: hipMalloc / hipFree */
+  /* Force content of the SMRT collision (Sec. II.C): 1 (or 0) = first order only, the
+   * paper's choice when the non-equilibrium parts are neglected (d_F^(n) = 0, n >= 2);
+   * 3 = also d_F^(3) = 3 g d^(2) (eq:Frc at theta = 1) with d^(2) the non-equilibrium
+   * central second moment of f = (1 - 1/(2 tau[2])) times that of the stored f-bar,
+   * added to the relaxed third-order central moments as (1 - 1/(2 tau[3])) d_F^(3),
+   * on the lattice's third-order index set.  The fourth-order force term stays out
+   * (order 4 is trimmed).  BGK: must be 0 or 1. */
+  int32_t force_order;
 } lbm_params;
 
 /* Monitor record (binary64, summed on the device in a fixed order).

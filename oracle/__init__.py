@@ -34,7 +34,7 @@ def _params_struct(real_t):
         _fields_ = [("collision", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
                     ("nz", C.c_int32), ("wall", C.c_int32 * 3), ("store16", C.c_int32),
                     ("shift", real_t), ("omega", real_t), ("hforce", real_t),
-                    ("q2", real_t), ("q3", real_t)]
+                    ("q2", real_t), ("q3", real_t), ("fq3", real_t)]
     return _Params
 
 
@@ -84,7 +84,8 @@ class Oracle:
     """
 
     def __init__(self, lattice: str, collision: str, shape, walls=(0, 0, 0), tau=(0.8, 0.8, 1.0),
-                 shift: float = 0.0, real: str = "f64", store16: bool = False):
+                 shift: float = 0.0, real: str = "f64", store16: bool = False,
+                 force_order: int = 1):
         self.lattice = lattice
         self.collision = collision.lower()
         nx, ny, nz = (tuple(shape) + (1, 1))[:3]
@@ -105,13 +106,16 @@ class Oracle:
                              self.L["mi"].ctypes.data, self.L["w"].ctypes.data,
                              self.L["H"].ctypes.data, self.L["Minv"].ctypes.data)
         omega = 1.0 / tau2
+        if force_order not in (1, 3) or (force_order == 3 and self.collision != "smrt"):
+            raise ValueError("force_order is 1, or 3 with SMRT")
+        fq3 = (1.0 - 0.5 / tau3) * (1.0 - 0.5 / tau2) if force_order == 3 else 0.0
         vals = dict(shift=shift, omega=omega, hforce=1.0 - 0.5 * omega,
-                    q2=1.0 - 1.0 / tau2, q3=1.0 - 1.0 / tau3)
+                    q2=1.0 - 1.0 / tau2, q3=1.0 - 1.0 / tau3, fq3=fq3)
         P = _P64 if real == "f64" else _P32
         cast = float if real == "f64" else (lambda v: float(np.float32(v)))
         self._p = P(1 if self.collision == "smrt" else 0, nx, ny, nz,
                     (C.c_int32 * 3)(*[int(bool(w)) for w in walls]), int(bool(store16)),
-                    *[cast(vals[k]) for k in ("shift", "omega", "hforce", "q2", "q3")])
+                    *[cast(vals[k]) for k in ("shift", "omega", "hforce", "q2", "q3", "fq3")])
         self._l = _lib(real)
         self._lref = C.byref(self._lat)
         self._pref = C.byref(self._p)

@@ -62,6 +62,8 @@ typedef struct {
   real omega;          /* BGK: 1 / tau-hat */
   real hforce;         /* BGK: 1 - omega / 2 */
   real q2, q3;         /* SMRT: 1 - omega_n, omega_n = 1 / tau-hat_n */
+  real fq3;            /* SMRT: (1 - omega_3/2)(1 - omega_2/2) for the third-order force
+                          content, 0 when it is neglected */
 } oracle_params;
 
 /* ---- binary16 rounding (IEEE 754 round to nearest, ties to even) ------------------ */
@@ -248,7 +250,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
   macro_t M;
   macroscopic(L, P, f, g, &M);
   const int NM = L->NM;
-  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ];
+  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ], D2[MAXQ];
   for (int k = 0; k < NM; ++k) {
     U[k] = upow(L->mi + 3 * k, M.u);
     E[k] = M.rho * U[k];
@@ -282,7 +284,23 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       real D = N[k]; /* l = 0 term; l = m multiplies N_0 = 0 */
       for (int t = 0; t < S->n[k]; ++t)
         D = D + (real)S->cdown[k][t] * (U[S->kl[k][t]] * N[S->km[k][t]]);
+      if (n == 2) D2[k] = D;
       Pc[k] = (n == 2 ? P->q2 : P->q3) * D;
+      if (n == 3 && P->fq3 != 0) {
+        /* eq:Frc at theta = 1: d_F^(3) = 3 g d^(2), the symmetric product, per multi-index
+         * sum_a m_a g_a d_{m - e_a}; d^(2) of f is (1 - omega_2/2) times the central
+         * non-equilibrium second moment D of f-bar (its force part d_F^(2) vanishes), and
+         * the force enters the post-collision moment with (1 - omega_3/2) (eq:RHS).
+         * Canonical order puts every order-2 index before the order-3 ones. */
+        real s = -0.0;
+        for (int a = 0; a < 3; ++a) {
+          if (m[a] == 0) continue;
+          int j = find_index(L, m[0] - (a == 0), m[1] - (a == 1), m[2] - (a == 2));
+          if (j < 0) continue;
+          s = s + ((real)m[a] * g[a]) * D2[j];
+        }
+        Pc[k] = Pc[k] + P->fq3 * s;
+      }
     }
   }
   /* back to raw moments; the change of every moment over the collision */

@@ -28,6 +28,7 @@ struct LaunchDesc {
   double gscale;
   double shift;
   double c0, c1;
+  double c2;         // SMRT: coefficient of the third-order force term (0 = off)
   int bx, by;        // block shape (bx * by <= 256, bx a multiple of 64)
   int variant;       // memory-access variant of the step kernel (MEM_*)
 };

@@ -26,6 +26,7 @@ inline StepArgs<T> make_args(const LaunchDesc &d) {
   a.shift = T(d.shift);
   a.c0 = T(d.c0);
   a.c1 = T(d.c1);
+  a.c2 = T(d.c2);
   return a;
 }
 

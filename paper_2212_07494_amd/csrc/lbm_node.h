@@ -112,7 +112,21 @@ struct BGKCoef {
 template <class T>
 struct SMRTCoef {
   T q2, q3;  // 1 - omega_n for orders 2 and 3
+  // Third-order force content with the non-equilibrium stress (0 = neglected, as in the
+  // paper's runs): (1 - omega_3/2)(1 - omega_2/2), see collide_smrt.
+  T fq3;
 };
+
+// Index of the multi-index MI[k] - e_a in L's canonical list (-1 if absent).
+template <class L>
+constexpr int sub_index(int k, int a) {
+  int m[3] = {L::MI[k][0], L::MI[k][1], L::MI[k][2]};
+  if (m[a] == 0) return -1;
+  m[a] -= 1;
+  for (int j = 0; j < L::NM; ++j)
+    if (L::MI[j][0] == m[0] && L::MI[j][1] == m[1] && L::MI[j][2] == m[2]) return j;
+  return -1;
+}
 
 // BGK with the second-order force term (Sec. II.B, eq:explict_eq):
 //   f*_i = f_i - omega (f_i - f_eq_i) + (1 - omega/2) F_i
@@ -190,7 +204,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
                                              const SMRTCoef<T> &c) {
   constexpr int NM = L::NM;
   const Macro<T> M = macroscopic<L>(d, shift, g);
-  T U[NM], E[NM], N[NM], P[NM], dA[NM];
+  T U[NM], E[NM], N[NM], P[NM], dA[NM], C2[NM];
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     U[k] = upow<L, k>(M.u);
@@ -231,7 +245,23 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
         constexpr int kl = L::TL[k][t], km = L::TM[k][t];
         Dm = Dm + T(L::CDN[k][t]) * (U[kl] * N[km]);
       });
+      if constexpr (n == 2) C2[k] = Dm;
       P[k] = (n == 2 ? c.q2 : c.q3) * Dm;
+      if constexpr (n == 3) {
+        // Third-order force content (eq:Frc, d_F^(3) = 3 g d^(2)): the symmetric product
+        // sum_a m_a g_a d_{m - e_a} of the acceleration with the non-equilibrium central
+        // second moment of f, d^(2) = (1 - omega_2/2) of that of f-bar, relaxed as a
+        // force term by (1 - omega_3/2).
+        if (c.fq3 != T(0)) {
+          T sF = T(-0.0);
+          static_for<3>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int j = sub_index<L>(k, a);
+            if constexpr (j >= 0) sF = sF + (T(L::MI[k][a]) * g[a]) * C2[j];
+          });
+          P[k] = P[k] + c.fq3 * sF;
+        }
+      }
     } else {
       P[k] = T(0);
     }

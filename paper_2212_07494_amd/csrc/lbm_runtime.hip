@@ -96,7 +96,7 @@ struct lbm_ctx {
   size_t bytes = 0;
   int64_t t = 0;
   double last_scale = 1.0;
-  double c0 = 0, c1 = 0, shift = 0;
+  double c0 = 0, c1 = 0, c2 = 0, shift = 0;
   int bx = 64, by = 4, variant = 0;
   lbm_monitors mon{};
 
@@ -156,6 +156,7 @@ struct lbm_ctx {
     d.shift = shift;
     d.c0 = c0;
     d.c1 = c1;
+    d.c2 = c2;
     d.bx = bx;
     d.by = by;
     d.variant = variant;
@@ -192,6 +193,10 @@ int validate(const lbm_params *p) {
     if (p->tau[4] != 1.0)
       return fail(LBM_EINVAL, "SMRT trims order 4: tau[4] must be 1 (got %g)", p->tau[4]);
   }
+  if (p->force_order != 0 && p->force_order != 1 && p->force_order != 3)
+    return fail(LBM_EINVAL, "force_order must be 1 or 3 (got %d)", p->force_order);
+  if (p->force_order == 3 && p->collision != LBM_SMRT)
+    return fail(LBM_EINVAL, "force_order 3 needs the SMRT collision");
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0))
     return fail(LBM_EINVAL, "rho0 = %g must be positive", p->rho0);
   if (p->g_kind < LBM_G_UNIFORM || p->g_kind > LBM_G_FIELD)
@@ -433,6 +438,7 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   } else {
     c->c0 = 1.0 - 1.0 / p->tau[2];
     c->c1 = 1.0 - 1.0 / p->tau[3];
+    if (p->force_order == 3) c->c2 = (1.0 - 0.5 / p->tau[3]) * (1.0 - 0.5 / p->tau[2]);
   }
   block_shape(p->nx, c->bx, c->by);
   const dim3 grid((p->nx + c->bx - 1) / c->bx, (p->ny + c->by - 1) / c->by, p->nz);

@@ -47,7 +47,7 @@ class lbm_params(C.Structure):
                 ("bc", C.c_int32 * 3), ("tau", C.c_double * 5), ("rho0", C.c_double),
                 ("g_kind", C.c_int32), ("g_axis", C.c_int32), ("g_uniform", C.c_double * 3),
                 ("g_data", C.c_void_p), ("monitor_every", C.c_int32),
-                ("allocator", C.POINTER(lbm_allocator))]
+                ("allocator", C.POINTER(lbm_allocator)), ("force_order", C.c_int32)]
 
 
 class lbm_tuning(C.Structure):
@@ -151,9 +151,10 @@ class TorchAllocator:
 
 def make_params(lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1), bc=(0, 0, 0),
                 tau=(0.8, 0.8, 1.0), rho0=1.0, g=None, g_profile=None, g_field=None,
-                monitor_every=0, allocator=None):
+                monitor_every=0, allocator=None, force_order=1):
     """Fill an lbm_params.  g: uniform (3,) acceleration; g_profile: (axis, (3, n) table);
-    g_field: (3, N) array.  Returned together with the arrays it points to (keep both)."""
+    g_field: (3, N) array; force_order 1 or 3 (SMRT third-order force content).  Returned
+    together with the arrays it points to (keep both)."""
     nx, ny, nz = (tuple(shape) + (1, 1))[:3]
     p = lbm_params()
     p.lattice = LATTICES[lattice]
@@ -179,6 +180,7 @@ def make_params(lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1),
         p.g_kind = G_UNIFORM
         p.g_uniform = (C.c_double * 3)(*gv)
     p.monitor_every = monitor_every
+    p.force_order = int(force_order)
     if allocator is not None:
         p.allocator = C.pointer(allocator.struct)
         keep.append(allocator)
@@ -279,7 +281,8 @@ class Lattice:
 
     def __init__(self, lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1),
                  walls=(0, 0, 0), tau=(0.8, 0.8, 1.0), rho0=1.0, rho=None, u=None, g=None,
-                 g_profile=None, g_field=None, monitor_every=0, stream=None, allocator=None):
+                 g_profile=None, g_field=None, monitor_every=0, stream=None, allocator=None,
+                 force_order=1):
         self.lattice = lattice
         self.Q = QOF[lattice]
         self.D = 2 if lattice == "D2Q9" else 3
@@ -289,7 +292,7 @@ class Lattice:
         self.storage = storage
         self._params, self._keep = make_params(lattice, collision, storage, self.shape, walls, tau,
                                                rho0, g, g_profile, g_field, monitor_every,
-                                               allocator)
+                                               allocator, force_order)
         if u is not None:
             u = np.asarray(u, dtype=np.float64)[: self.D]
         self.ctx = lbm_init(self._params, rho, u, stream)

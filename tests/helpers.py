@@ -19,10 +19,11 @@ def gpu_available() -> bool:
         return False
 
 
-def oracle_for(lattice, collision, storage, shape, walls, tau, rho0=1.0):
+def oracle_for(lattice, collision, storage, shape, walls, tau, rho0=1.0, force_order=1):
     real, shifted, s16 = EMUL[storage]
     return Oracle(lattice, collision, shape, walls=walls, tau=tau,
-                  shift=rho0 if shifted else 0.0, real=real, store16=s16)
+                  shift=rho0 if shifted else 0.0, real=real, store16=s16,
+                  force_order=force_order)
 
 
 def to_storage(x: np.ndarray, storage: str) -> np.ndarray:

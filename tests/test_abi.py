@@ -43,6 +43,8 @@ def test_version_and_strerror():
     (dict(shape=(0, 8, 1)), "positive"),
     (dict(rho0=0.0), "rho0"),
     (dict(lattice="D3Q19", shape=(2048, 2048, 1024)), "2^31"),
+    (dict(force_order=2), "force_order"),
+    (dict(force_order=3), "SMRT"),
 ])
 def test_invalid_parameters_rejected(change, fragment):
     from paper_2212_07494_amd import lbm

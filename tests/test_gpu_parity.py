@@ -80,6 +80,35 @@ def test_step_parity_random_state(lat, coll, storage):
 
 
 @pytest.mark.parametrize("storage", STORES)
+@pytest.mark.parametrize("lat", LATS)
+def test_third_order_force_parity(lat, storage):
+    """SMRT with the third-order force content (force_order 3): random state and force
+    field, three steps with force scales (1, 0.5, -2), bit-identical to the oracle; and it
+    does change the state against force_order 1."""
+    L = lbm()
+    shape = SHAPES[lat]
+    N = int(np.prod(shape))
+    walls = WALLS[lat][-1]
+    kw, g = _force(lat, shape, "field", seed=8)
+    f0 = _state(lat, storage, N, seed=12)
+    o = oracle_for(lat, "smrt", storage, shape, walls, TAU["smrt"], force_order=3)
+    scales = [1.0, 0.5, -2.0]
+    fo = f0.astype(o.dtype)
+    for s in scales:
+        fo = o.step(fo, g, s)
+    got = {}
+    for order in (1, 3):
+        with L.Lattice(lat, "smrt", storage, shape, walls, TAU["smrt"], force_order=order,
+                       **kw) as gpu:
+            gpu.set_populations(f0)
+            gpu.step(3, g_scale=scales)
+            got[order] = gpu.populations()
+    assert exact_mismatch(got[3], fo.astype(np.float64)) == 0
+    if storage != "f16s":  # binary16 may round the small change away
+        assert exact_mismatch(got[3], got[1]) > 0
+
+
+@pytest.mark.parametrize("storage", STORES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt"])
 @pytest.mark.parametrize("lat", LATS)
 def test_init_and_moments_parity(lat, coll, storage):

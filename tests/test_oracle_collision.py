@@ -285,3 +285,60 @@ def test_staggered_momentum_mode_never_decays(L, coll):
         assert np.max(np.abs(rho - 1.0)) < 1e-14
         assert np.max(np.abs(ut[0] - eps * (-1.0) ** (x + t))) < 1e-15
         assert np.max(np.abs(ut[1:])) < 1e-15
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("seed", range(3))
+def test_third_order_force_content(L, seed):
+    """force_order 3 (eq:Frc at theta = 1, d_F^(3) = 3 g d^(2)): against force_order 1 the
+    post-collision state changes only in the raw third-order Hermite moments on the
+    lattice's index set, by (1 - omega_3/2) sum_a m_a g_a d_{m-e_a} with d = (1 -
+    omega_2/2) D, D the central non-equilibrium second moment of the pre-collision state
+    -- here recomputed from the populations with numpy, not through the oracle's tables
+    (the order-4 raw moments move too, by the shift of the changed central moments)."""
+    rho, u, g = _setup(L, seed)
+    tau2, tau3 = 0.7, 0.9
+    o1 = Oracle(L, "smrt", (1, 1, 1), tau=(tau2, tau3, 1.0))
+    o3 = Oracle(L, "smrt", (1, 1, 1), tau=(tau2, tau3, 1.0), force_order=3)
+    D = lat.dim(L)
+    Lt = lat.tables(L, np.float64)
+    e = np.asarray(Lt["e"], np.float64).reshape(o1.Q, -1)
+    e3 = np.zeros((o1.Q, 3))
+    e3[:, :D] = e[:, :D]
+    rng = np.random.default_rng(seed + 40)
+    f = o1.init_node(rho, u, g) * (1 + 0.05 * rng.uniform(-1, 1, o1.Q))
+    diff = o3.collide_node(f, g) - o1.collide_node(f, g)
+    # pre-collision macroscopic state (eq:half_F) and central non-equilibrium second moment
+    r = f.sum()
+    j = e3.T @ f
+    uu = j / r + g / 2
+    F = r * g
+    A2 = np.einsum("i,ia,ib->ab", f, e3, e3) - r * np.eye(3) / 3 * (np.arange(3) < D)[:, None]
+    N2 = A2 - r * np.outer(uu, uu)
+    N1 = -F / 2
+    Dc = N2 - np.outer(uu, N1) - np.outer(N1, uu)
+    d2 = (1 - 0.5 / tau2) * Dc
+    mi = np.asarray(Lt["mi"]).reshape(-1, 3)
+    biggest = 0.0
+    for m in mi[mi.sum(1) == 3]:
+        want = 0.0
+        for a in range(3):
+            if m[a]:
+                b = m.copy()
+                b[a] -= 1
+                pair = [c for c in range(3) for _ in range(b[c])]
+                want += m[a] * g[a] * d2[pair[0], pair[1]]
+        want *= (1 - 0.5 / tau3)
+        # raw third-order Hermite moment of the change: sum_i diff_i H_m(e_i)
+        H = np.ones(o1.Q)
+        for c in range(3):
+            x = e3[:, c]
+            H *= {0: 1.0, 1: x, 2: x * x - 1 / 3, 3: x ** 3 - x}[int(m[c])]
+        got = float(diff @ H)
+        assert abs(got - want) <= 1e-13 + 1e-9 * abs(want), (m, got, want)
+        biggest = max(biggest, abs(want))
+    assert biggest > 1e-7  # the term is exercised
+    # mass, momentum and the second-order moments are untouched
+    assert abs(diff.sum()) < 1e-16
+    assert np.max(np.abs(e3.T @ diff)) < 1e-16
+    assert np.max(np.abs(np.einsum("i,ia,ib->ab", diff, e3, e3))) < 1e-16
