@@ -56,7 +56,12 @@ typedef enum {
 } lbm_status;
 
 typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_lattice;
-typedef enum { LBM_BGK = 0, LBM_SMRT = 1 } lbm_collision;
+/* LBM_BGK: single relaxation time with the second-order force term (eq:explict_eq).
+ * LBM_SMRT: central-moment relaxation per Hermite order with the force in the first
+ * central moment (Sec. II.C).  LBM_RMRT: the raw-moment MRT of the paper's appendix
+ * (eq:RHS_a, explicit form, raw force moments a_F^(n) of eq:bbd1): same rates and the
+ * same trimming of order 4 as SMRT; differs from it at order 3. */
+typedef enum { LBM_BGK = 0, LBM_SMRT = 1, LBM_RMRT = 2 } lbm_collision;
 
 /* Storage of the populations in HBM and the arithmetic of the step.
  *   LBM_F64          binary64 values of f-bar_i, binary64 arithmetic (reference mode).
@@ -91,7 +96,7 @@ typedef struct {
   int32_t nx, ny, nz;  /* nz must be 1 for D2Q9 */
   int32_t bc[3];       /* lbm_bc per axis (both faces of the axis) */
   /* tau-hat per Hermite order n (tau-hat = tau + 1/2 of Sec. II.B, omega_n = 1/tau-hat_n,
-   * viscosity (tau[2] - 1/2)/3).  BGK uses tau[2] only.  SMRT relaxes order 2 with
+   * viscosity (tau[2] - 1/2)/3).  BGK uses tau[2] only.  SMRT and RMRT relax order 2 with
    * tau[2] and order 3 with tau[3]; order 4 is trimmed, which is tau[4] == 1 (required).
    * tau[0], tau[1] are ignored (mass and momentum are conserved).  Each used value > 1/2. */
   double tau[5];

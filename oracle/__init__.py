@@ -34,7 +34,8 @@ def _params_struct(real_t):
         _fields_ = [("collision", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
                     ("nz", C.c_int32), ("wall", C.c_int32 * 3), ("store16", C.c_int32),
                     ("shift", real_t), ("omega", real_t), ("hforce", real_t),
-                    ("q2", real_t), ("q3", real_t), ("fq3", real_t)]
+                    ("q2", real_t), ("q3", real_t), ("fq3", real_t), ("h2", real_t),
+                    ("h3", real_t)]
     return _Params
 
 
@@ -75,10 +76,11 @@ def round_half(x: float) -> float:
 class Oracle:
     """Plain forced LB step on one periodic / walled box.
 
-    lattice: 'D2Q9' | 'D3Q19' | 'D3Q27'; collision: 'bgk' | 'smrt';
+    lattice: 'D2Q9' | 'D3Q19' | 'D3Q27'; collision: 'bgk' | 'smrt' | 'rmrt' (the raw-moment
+    MRT of the paper's appendix);
     shape (nx, ny, nz) (nz = 1 in 2-D); walls: per-axis flags (halfway bounce-back
     on both faces); tau: dict or tuple of tau-hat per Hermite order (tau2, tau3,
-    tau4) -- BGK uses tau2 only, SMRT requires tau4 == 1 (order 4 is trimmed);
+    tau4) -- BGK uses tau2 only, SMRT and RMRT require tau4 == 1 (order 4 is trimmed);
     shift: constant s removed from stored populations (f-bar_i - w_i s);
     real: 'f64' (reference) or 'f32' (emulation); store16: round stores to binary16.
     """
@@ -99,8 +101,10 @@ class Oracle:
         tau2, tau3, tau4 = tau
         if min(tau2, tau3) <= 0.5:
             raise ValueError("tau-hat must exceed 1/2")
-        if self.collision == "smrt" and tau4 != 1.0:
-            raise ValueError("SMRT trims order 4: tau4 must be 1")
+        if self.collision not in ("bgk", "smrt", "rmrt"):
+            raise ValueError(f"unknown collision {collision}")
+        if self.collision in ("smrt", "rmrt") and tau4 != 1.0:
+            raise ValueError("SMRT and RMRT trim order 4: tau4 must be 1")
         self._lat = _Lattice(self.L["D"], self.L["Q"], self.L["NM"],
                              self.L["e"].ctypes.data, self.L["opp"].ctypes.data,
                              self.L["mi"].ctypes.data, self.L["w"].ctypes.data,
@@ -110,12 +114,14 @@ class Oracle:
             raise ValueError("force_order is 1, or 3 with SMRT")
         fq3 = (1.0 - 0.5 / tau3) * (1.0 - 0.5 / tau2) if force_order == 3 else 0.0
         vals = dict(shift=shift, omega=omega, hforce=1.0 - 0.5 * omega,
-                    q2=1.0 - 1.0 / tau2, q3=1.0 - 1.0 / tau3, fq3=fq3)
+                    q2=1.0 - 1.0 / tau2, q3=1.0 - 1.0 / tau3, fq3=fq3,
+                    h2=1.0 - 0.5 / tau2, h3=1.0 - 0.5 / tau3)
         P = _P64 if real == "f64" else _P32
         cast = float if real == "f64" else (lambda v: float(np.float32(v)))
-        self._p = P(1 if self.collision == "smrt" else 0, nx, ny, nz,
+        self._p = P({"bgk": 0, "smrt": 1, "rmrt": 2}[self.collision], nx, ny, nz,
                     (C.c_int32 * 3)(*[int(bool(w)) for w in walls]), int(bool(store16)),
-                    *[cast(vals[k]) for k in ("shift", "omega", "hforce", "q2", "q3", "fq3")])
+                    *[cast(vals[k]) for k in ("shift", "omega", "hforce", "q2", "q3", "fq3",
+                                              "h2", "h3")])
         self._l = _lib(real)
         self._lref = C.byref(self._lat)
         self._pref = C.byref(self._p)

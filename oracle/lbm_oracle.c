@@ -54,7 +54,7 @@ typedef struct {
 } oracle_lattice;
 
 typedef struct {
-  int32_t collision;   /* 0 = BGK, 1 = SMRT */
+  int32_t collision;   /* 0 = BGK, 1 = SMRT, 2 = RMRT */
   int32_t nx, ny, nz;
   int32_t wall[3];     /* per axis: 1 = halfway bounce-back walls on both faces, 0 = periodic */
   int32_t store16;     /* 1: round every stored value to binary16 (emulation only) */
@@ -64,6 +64,7 @@ typedef struct {
   real q2, q3;         /* SMRT: 1 - omega_n, omega_n = 1 / tau-hat_n */
   real fq3;            /* SMRT: (1 - omega_3/2)(1 - omega_2/2) for the third-order force
                           content, 0 when it is neglected */
+  real h2, h3;         /* RMRT: 1 - omega_n / 2 */
 } oracle_params;
 
 /* ---- binary16 rounding (IEEE 754 round to nearest, ties to even) ------------------ */
@@ -351,10 +352,81 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
   }
 }
 
+/* ---- raw-moment MRT (the appendix: eq:RHS_a in its explicit form, eq:bbd1) ------- */
+/*
+ * Every raw Hermite moment relaxes in the rest frame:
+ *   a*_m = a0_m + (1 - omega_n) abar1_m + (1 - omega_n/2) aF_m,   n = |m| >= 1,
+ * with a0_m = rho u^m, abar1_m = A_m - rho u^m the non-equilibrium raw moment of f-bar
+ * (abar1_{e_a} = -F_a/2), and the raw force moments of eq:bbd1 at theta = 1,
+ * aF_m = sum_a m_a u^{m - e_a} F_a (aF_{e_a} = F_a: the momentum gains F for any omega_1).
+ * Order 4 is trimmed (omega_4 = 1, so a*_m = rho u^m + aF_m/2); orders above 4 are set
+ * to 0 (the reconstruction sums to order 4).  As in collide_smrt the state is advanced by
+ * the reconstruction of the changes a*_m - A_m.
+ */
+static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const real *f,
+                         const real g[3], real *out) {
+  macro_t M;
+  macroscopic(L, P, f, g, &M);
+  const int NM = L->NM;
+  real U[MAXQ], dA[MAXQ];
+  for (int k = 0; k < NM; ++k) U[k] = upow(L->mi + 3 * k, M.u);
+  for (int k = 0; k < NM; ++k) {
+    const int32_t *m = L->mi + 3 * k;
+    int n = mabs(m);
+    if (n == 0) {
+      dA[k] = 0;
+      continue;
+    }
+    if (n == 1) {
+      int a = m[0] ? 0 : (m[1] ? 1 : 2);
+      dA[k] = M.F[a];
+      continue;
+    }
+    real A = -0.0;
+    for (int i = 0; i < L->Q; ++i) {
+      real h = L->H[k * L->Q + i];
+      if (h != 0) A = A + h * f[i];
+    }
+    if (n > 4) {
+      dA[k] = -A;
+      continue;
+    }
+    real N = A - M.rho * U[k];
+    real aF = -0.0;
+    for (int a = 0; a < 3; ++a) {
+      if (m[a] == 0) continue;
+      int j = find_index(L, m[0] - (a == 0), m[1] - (a == 1), m[2] - (a == 2));
+      if (j < 0) continue;
+      aF = aF + ((real)m[a] * U[j]) * M.F[a];
+    }
+    real t;
+    if (n == 2) {
+      t = P->q2 * N;
+      t = t + P->h2 * aF;
+    } else if (n == 3) {
+      t = P->q3 * N;
+      t = t + P->h3 * aF;
+    } else {
+      t = (real)0.5 * aF;
+    }
+    dA[k] = t - N;
+  }
+  for (int i = 0; i < L->Q; ++i) {
+    real acc = -0.0;
+    for (int k = 1; k < NM; ++k) {
+      real c = L->Minv[i * NM + k];
+      if (c != 0) acc = acc + c * dA[k];
+    }
+    out[i] = f[i] + acc;
+  }
+}
+
 static void collide(const oracle_lattice *L, const oracle_params *P, const smrt_plan *S,
                     const real *f, const real *g, real *out) {
   if (P->collision == 0)
     collide_bgk(L, P, f, g, out);
+  else if (P->collision == 2)
+    collide_rmrt(L, P, f, g, out);
   else
     collide_smrt(L, P, S, f, g, out);
 }

@@ -17,7 +17,7 @@ struct GeomDesc {
 // One launch of a lattice kernel.  Coefficients are binary64 on the host and are
 // rounded once to the arithmetic type of the storage mode.
 struct LaunchDesc {
-  int coll;      // 0 BGK, 1 SMRT
+  int coll;      // 0 BGK, 1 SMRT, 2 RMRT
   int storage;   // lbm_storage
   int gk;        // 0 profile/uniform table, 1 full field
   const void *fin;
@@ -28,7 +28,8 @@ struct LaunchDesc {
   double gscale;
   double shift;
   double c0, c1;
-  double c2;         // SMRT: coefficient of the third-order force term (0 = off)
+  double c2;         // SMRT: coefficient of the third-order force term (0 = off); RMRT: h2
+  double c3;         // RMRT: h3 = 1 - omega_3 / 2
   int bx, by;        // block shape (bx * by <= 256, bx a multiple of 64)
   int variant;       // memory-access variant of the step kernel (MEM_*)
 };

@@ -112,7 +112,8 @@ struct StepArgs {
   ForceRef<T> force;
   T shift;
   T c0, c1;  // BGK: omega, 1 - omega/2;  SMRT: q2, q3
-  T c2;      // SMRT: coefficient of the third-order force term (0 = off)
+  T c2;      // SMRT: coefficient of the third-order force term (0 = off); RMRT: h2
+  T c3;      // RMRT: h3
 };
 
 // One node of the fused step: pull the populations (periodic wrap or halfway
@@ -121,7 +122,7 @@ template <class L, int COLL, class S, class T, int MEM>
 __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restrict__ fout,
                                           const Geom &geo, int x, int y, int z, int node,
                                           const T (&g)[3], T shift, T c0, T c1,
-                                          T c2 = T(0)) {
+                                          T c2 = T(0), T c3 = T(0)) {
   T d[L::Q];
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -130,7 +131,10 @@ __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restri
   if constexpr (COLL == 0) {
     collide_bgk<L>(d, shift, g, BGKCoef<T>{c0, c1});
   } else {
-    collide_smrt<L>(d, shift, g, SMRTCoef<T>{c0, c1, c2});
+    if constexpr (COLL == 1)
+      collide_smrt<L>(d, shift, g, SMRTCoef<T>{c0, c1, c2});
+    else
+      collide_rmrt<L>(d, shift, g, RMRTCoef<T>{c0, c1, c2, c3});
   }
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -148,7 +152,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   T g[3];
   load_force<T, GK>(a.force, x, y, z, node, a.geo.N, L::D, g);
   step_node<L, COLL, S, T, MEM>(static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.geo,
-                                x, y, z, node, g, a.shift, a.c0, a.c1, a.c2);
+                                x, y, z, node, g, a.shift, a.c0, a.c1, a.c2, a.c3);
 }
 
 // Initial state: compute f-bar(x, 0) at every node and place each population in the

@@ -27,6 +27,7 @@ inline StepArgs<T> make_args(const LaunchDesc &d) {
   a.c0 = T(d.c0);
   a.c1 = T(d.c1);
   a.c2 = T(d.c2);
+  a.c3 = T(d.c3);
   return a;
 }
 
@@ -75,6 +76,8 @@ struct Ops {
       using T = std::remove_pointer_t<decltype(tp)>;
       if (d.coll == 0)
         return d.gk ? step_t<0, S, T, GK_FIELD>(d, s) : step_t<0, S, T, GK_PROFILE>(d, s);
+      if (d.coll == 2)
+        return d.gk ? step_t<2, S, T, GK_FIELD>(d, s) : step_t<2, S, T, GK_PROFILE>(d, s);
       return d.gk ? step_t<1, S, T, GK_FIELD>(d, s) : step_t<1, S, T, GK_PROFILE>(d, s);
     });
   }

@@ -298,6 +298,80 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
   });
 }
 
+// Raw-moment MRT with force (the paper's appendix, eq:RHS_a in its explicit form): every
+// raw Hermite moment of order n relaxes as a*_m = rho u^m + (1 - omega_n) N_m +
+// (1 - omega_n/2) a_F,m with the raw force moments a_F,m = sum_a m_a u^{m - e_a} F_a
+// (non-equilibrium force content neglected, theta = 1).  Momentum gains F (a*_e =
+// rho u + F/2 whatever omega_1); order 4 is trimmed (omega_4 = 1: a* = rho u^m + a_F/2);
+// orders above 4 are dropped.  The state is advanced by the reconstruction of the moment
+// changes, as in collide_smrt.
+template <class T>
+struct RMRTCoef {
+  T q2, q3;  // 1 - omega_n
+  T h2, h3;  // 1 - omega_n / 2
+};
+
+template <class L, class T>
+__device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)[3],
+                                             const RMRTCoef<T> &c) {
+  constexpr int NM = L::NM;
+  const Macro<T> M = macroscopic<L>(d, shift, g);
+  T U[NM], dA[NM];
+  static_for<NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    U[k] = upow<L, k>(M.u);
+  });
+  static_for<NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int n = L::ORD[k];
+    if constexpr (n == 0) {
+      dA[k] = T(0);
+    } else if constexpr (n == 1) {
+      constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
+      dA[k] = M.F[a];
+    } else {
+      T acc = T(-0.0);
+      static_for<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr T h = Tab<L, T>::h(k, i);
+        if constexpr (h != T(0)) acc = acc + h * d[i];
+      });
+      if constexpr (n > 4) {
+        dA[k] = -acc;
+      } else {
+        const T Nk = acc - M.rho * U[k];
+        T aF = T(-0.0);
+        static_for<3>([&](auto A) {
+          constexpr int a = decltype(A)::value;
+          constexpr int j = sub_index<L>(k, a);
+          if constexpr (j >= 0) aF = aF + (T(L::MI[k][a]) * U[j]) * M.F[a];
+        });
+        T t;
+        if constexpr (n == 2) {
+          t = c.q2 * Nk;
+          t = t + c.h2 * aF;
+        } else if constexpr (n == 3) {
+          t = c.q3 * Nk;
+          t = t + c.h3 * aF;
+        } else {
+          t = T(0.5) * aF;
+        }
+        dA[k] = t - Nk;
+      }
+    }
+  });
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    T acc = T(-0.0);
+    static_for<NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr T cf = Tab<L, T>::minv(i, k);
+      if constexpr (k > 0 && cf != T(0)) acc = acc + cf * dA[k];
+    });
+    d[i] = d[i] + acc;
+  });
+}
+
 // Initial stored state f-bar = f_eq - F_i/2 (eq:newf with Omega = 0): density and
 // physical velocity are then exactly rho and u.  BGK: its second-order equilibrium
 // and force term.  SMRT: equilibrium moments rho u^m and raw force moments

@@ -96,7 +96,7 @@ struct lbm_ctx {
   size_t bytes = 0;
   int64_t t = 0;
   double last_scale = 1.0;
-  double c0 = 0, c1 = 0, c2 = 0, shift = 0;
+  double c0 = 0, c1 = 0, c2 = 0, c3 = 0, shift = 0;
   int bx = 64, by = 4, variant = 0;
   lbm_monitors mon{};
 
@@ -157,6 +157,7 @@ struct lbm_ctx {
     d.c0 = c0;
     d.c1 = c1;
     d.c2 = c2;
+    d.c3 = c3;
     d.bx = bx;
     d.by = by;
     d.variant = variant;
@@ -172,7 +173,7 @@ int validate(const lbm_params *p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->lattice < LBM_D2Q9 || p->lattice > LBM_D3Q27)
     return fail(LBM_EINVAL, "unknown lattice %d", p->lattice);
-  if (p->collision != LBM_BGK && p->collision != LBM_SMRT)
+  if (p->collision != LBM_BGK && p->collision != LBM_SMRT && p->collision != LBM_RMRT)
     return fail(LBM_EINVAL, "unknown collision %d", p->collision);
   if (p->storage < LBM_F64 || p->storage > LBM_F16_SHIFTED)
     return fail(LBM_EINVAL, "unknown storage %d", p->storage);
@@ -187,7 +188,7 @@ int validate(const lbm_params *p) {
       return fail(LBM_EINVAL, "unknown boundary kind %d on axis %d", p->bc[a], a);
   if (!(p->tau[2] > 0.5) || !std::isfinite(p->tau[2]))
     return fail(LBM_EINVAL, "tau[2] = %g must exceed 1/2", p->tau[2]);
-  if (p->collision == LBM_SMRT) {
+  if (p->collision == LBM_SMRT || p->collision == LBM_RMRT) {
     if (!(p->tau[3] > 0.5) || !std::isfinite(p->tau[3]))
       return fail(LBM_EINVAL, "tau[3] = %g must exceed 1/2", p->tau[3]);
     if (p->tau[4] != 1.0)
@@ -438,7 +439,12 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   } else {
     c->c0 = 1.0 - 1.0 / p->tau[2];
     c->c1 = 1.0 - 1.0 / p->tau[3];
-    if (p->force_order == 3) c->c2 = (1.0 - 0.5 / p->tau[3]) * (1.0 - 0.5 / p->tau[2]);
+    if (p->collision == LBM_RMRT) {
+      c->c2 = 1.0 - 0.5 / p->tau[2];
+      c->c3 = 1.0 - 0.5 / p->tau[3];
+    } else if (p->force_order == 3) {
+      c->c2 = (1.0 - 0.5 / p->tau[3]) * (1.0 - 0.5 / p->tau[2]);
+    }
   }
   block_shape(p->nx, c->bx, c->by);
   const dim3 grid((p->nx + c->bx - 1) / c->bx, (p->ny + c->by - 1) / c->by, p->nz);

@@ -130,7 +130,7 @@ def taylor_green_2d(L=64, u0=0.005, Re=50.0, collision="smrt", tau3=1.0) -> Work
     g[1] = -(u0 ** 2) / 2 * k * np.sin(2 * k * y)
     T = math.log(2) / (2 * nu * k * k)
     return Workload("taylor_green_2d", "D2Q9", collision, shape, (0, 0, 0),
-                    (tau, tau3 if collision == "smrt" else tau, 1.0), np.ones(N), u, g,
+                    (tau, tau if collision == "bgk" else tau3, 1.0), np.ones(N), u, g,
                     int(round(T)), meta=dict(nu=nu, u0=u0))
 
 

@@ -32,23 +32,23 @@ def _time(torch, stream, fn, reps):
     return e0.elapsed_time(e1) / reps  # ms
 
 
-def single(torch, stream, name, storage, steps, warmup):
+def single(torch, stream, name, storage, steps, warmup, collision="smrt"):
     if name == "d3q19":
         w = inputs.taylor_green_3d(n=256)
-        lat = L.Lattice(w.lattice, w.collision, storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
+        lat = L.Lattice(w.lattice, collision, storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
                         g_profile=w.g_profile, stream=stream)
-        desc = "D3Q19 SMRT 256^3 periodic, Taylor-Green + sin force"
+        desc = f"D3Q19 {collision.upper()} 256^3 periodic, Taylor-Green + sin force"
     elif name == "d3q27":
         p = inputs.warmstart_problem(2022, box=128)
         shape = (128, 128, 128)
-        lat = L.Lattice("D3Q27", "smrt", storage, shape, (0, 0, 0), (p["tau2"], 1.0, 1.0),
+        lat = L.Lattice("D3Q27", collision, storage, shape, (0, 0, 0), (p["tau2"], 1.0, 1.0),
                         g_field=inputs.fourier_force(shape, p["modes"]), stream=stream)
-        desc = "D3Q27 SMRT 128^3 periodic, 4 Fourier forcing modes"
+        desc = f"D3Q27 {collision.upper()} 128^3 periodic, 4 Fourier forcing modes"
     elif name == "d2q9":
         w = inputs.kolmogorov_box(L=1024)
-        lat = L.Lattice(w.lattice, w.collision, storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
+        lat = L.Lattice(w.lattice, collision, storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
                         g_profile=w.g_profile, stream=stream)
-        desc = "D2Q9 SMRT 1024^2 periodic Kolmogorov flow"
+        desc = f"D2Q9 {collision.upper()} 1024^2 periodic Kolmogorov flow"
     else:
         raise ValueError(name)
     with lat:
@@ -121,6 +121,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("workload", choices=["d3q19", "d3q27", "d2q9", "batch", "womersley"])
     ap.add_argument("--storage", default="f32s", choices=["f64", "f32", "f32s", "f16s"])
+    ap.add_argument("--collision", default="smrt", choices=["bgk", "smrt", "rmrt"],
+                    help="collision of the single-lattice workloads")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     args = ap.parse_args()
@@ -132,7 +134,8 @@ def main():
     elif args.workload == "womersley":
         rec = womersley(torch, stream, args.storage)
     else:
-        rec = single(torch, stream, args.workload, args.storage, args.steps, args.warmup)
+        rec = single(torch, stream, args.workload, args.storage, args.steps, args.warmup,
+                     args.collision)
     print(json.dumps(rec), flush=True)
 
 

@@ -21,7 +21,7 @@ STORES = ["f64", "f32", "f32s", "f16s"]
 SHAPES = {"D2Q9": (70, 37, 1), "D3Q19": (67, 13, 9), "D3Q27": (67, 11, 7)}
 WALLS = {"D2Q9": [(0, 0, 0), (0, 1, 0), (1, 1, 0)], "D3Q19": [(0, 0, 0), (1, 0, 1)],
          "D3Q27": [(0, 0, 0), (1, 0, 1)]}
-TAU = {"bgk": (0.63, 0.63, 1.0), "smrt": (0.58, 0.87, 1.0)}
+TAU = {"bgk": (0.63, 0.63, 1.0), "smrt": (0.58, 0.87, 1.0), "rmrt": (0.58, 0.87, 1.0)}
 
 
 def lbm():
@@ -53,7 +53,7 @@ def _force(lat, shape, kind, seed):
 
 
 @pytest.mark.parametrize("storage", STORES)
-@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 @pytest.mark.parametrize("lat", LATS)
 def test_step_parity_random_state(lat, coll, storage):
     """Random pre-collision state, random force field, three steps with force scales
@@ -109,7 +109,7 @@ def test_third_order_force_parity(lat, storage):
 
 
 @pytest.mark.parametrize("storage", STORES)
-@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 @pytest.mark.parametrize("lat", LATS)
 def test_init_and_moments_parity(lat, coll, storage):
     """lbm_init from (rho, u, g) fields and lbm_moments match the oracle exactly."""

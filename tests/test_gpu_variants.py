@@ -16,11 +16,11 @@ CASES = {
     "D3Q19": [((70, 5, 4), (0, 0, 0)), ((70, 5, 4), (1, 1, 1)), ((131, 3, 3), (1, 0, 1))],
     "D3Q27": [((70, 4, 3), (0, 0, 0)), ((70, 4, 3), (1, 0, 1)), ((65, 3, 3), (0, 1, 0))],
 }
-TAU = {"bgk": (0.61, 0.61, 1.0), "smrt": (0.57, 0.91, 1.0)}
+TAU = {"bgk": (0.61, 0.61, 1.0), "smrt": (0.57, 0.91, 1.0), "rmrt": (0.57, 0.91, 1.0)}
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32s", "f16s"])
-@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 @pytest.mark.parametrize("lat", ["D2Q9", "D3Q19", "D3Q27"])
 def test_all_launch_configurations(lat, coll, storage):
     from paper_2212_07494_amd import lbm as L

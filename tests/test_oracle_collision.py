@@ -342,3 +342,34 @@ def test_third_order_force_content(L, seed):
     assert abs(diff.sum()) < 1e-16
     assert np.max(np.abs(e3.T @ diff)) < 1e-16
     assert np.max(np.abs(np.einsum("i,ia,ib->ab", diff, e3, e3))) < 1e-16
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("seed", range(3))
+def test_raw_moment_mrt_against_central(L, seed):
+    """The appendix's raw-moment MRT (RMRT) against the central-moment SMRT on one node:
+    post-collision moments of orders 0..2 agree for any rates (at order 2 the central
+    shift of the force, (1 + q_2)/2, equals the raw force factor 1 - omega_2/2); with every
+    tau-hat = 1 the two collisions are the same map; with tau3 != 1 their third-order
+    moments differ (the frames of relaxation differ by u-dependent terms)."""
+    rho, u, g = _setup(L, seed)
+    rng = np.random.default_rng(seed + 70)
+    D = lat.dim(L)
+    Lt = lat.tables(L, np.float64)
+    e = np.zeros((len(Lt["w"]), 3))
+    e[:, :D] = np.asarray(Lt["e"], np.float64).reshape(len(Lt["w"]), -1)[:, :D]
+
+    def moments(f):
+        return (f.sum(), e.T @ f, np.einsum("i,ia,ib->ab", f, e, e))
+
+    for tau, third_differs in (((0.7, 0.9, 1.0), True), ((1.0, 1.0, 1.0), False)):
+        cm = Oracle(L, "smrt", (1, 1, 1), tau=tau)
+        rm = Oracle(L, "rmrt", (1, 1, 1), tau=tau)
+        f = cm.init_node(rho, u, g) * (1 + 0.05 * rng.uniform(-1, 1, cm.Q))
+        a, b = cm.collide_node(f, g), rm.collide_node(f, g)
+        for x, y in zip(moments(a), moments(b)):
+            assert np.max(np.abs(np.asarray(x) - np.asarray(y))) < 1e-15
+        if third_differs:
+            assert np.max(np.abs(a - b)) > 1e-9
+        else:
+            assert np.max(np.abs(a - b)) < 1e-15

@@ -14,7 +14,7 @@ from paper_2212_07494_amd import inputs
 # ---- P-U: uniform force in a periodic box ---------------------------------------------
 
 @pytest.mark.parametrize("L", lat.LATTICES)
-@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_uniform_force_momentum_balance(L, coll):
     """Periodic box, uniform g, any initial field: mass is conserved and the total
     momentum J = sum rho u grows by exactly t M g (each step adds F = rho g per node,
@@ -38,7 +38,7 @@ def test_uniform_force_momentum_balance(L, coll):
 
 
 @pytest.mark.parametrize("L", lat.LATTICES)
-@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_uniform_state_accelerates_exactly(L, coll):
     """A uniform state under uniform g stays uniform with u(t) = u0 + t g."""
     D = lat.dim(L)
@@ -58,7 +58,7 @@ def test_uniform_state_accelerates_exactly(L, coll):
 
 
 @pytest.mark.parametrize("L", lat.LATTICES)
-@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_equilibrium_is_fixed_point_without_force(L, coll):
     """Zero force: the equilibrium of a uniform moving state is a fixed point."""
     D = lat.dim(L)
@@ -84,7 +84,7 @@ def test_closed_forms_equal_brute_force(coll, tau2, tau3):
     G = 1e-7
     y = np.arange(L)
     bf = cf.odd_sector_steady(G * np.sin(k * y), tau2, tau3, coll, walls=False)
-    U = (cf.kolmogorov_amplitude(G, k, tau2, tau3) if coll == "smrt"
+    U = (cf.kolmogorov_amplitude(G, k, tau2, tau3) if coll in ("smrt", "rmrt")
          else cf.kolmogorov_amplitude_bgk(G, k, tau2))
     assert np.max(np.abs(bf - U * np.sin(k * y))) <= 1e-11 * U
     if coll == "bgk":
@@ -104,11 +104,14 @@ def test_closed_form_limits():
         assert abs(r - 1) < 200 * k * k
 
 
-@pytest.mark.parametrize("coll,tau3", [("bgk", None), ("smrt", 1.0), ("smrt", 0.7)])
+@pytest.mark.parametrize("coll,tau3", [("bgk", None), ("smrt", 1.0), ("smrt", 0.7),
+                                       ("rmrt", 1.0), ("rmrt", 0.7)])
 def test_poiseuille_matches_closed_form(coll, tau3):
     """Channel 4 (periodic x) x 32 (walls), tau-hat 0.8, g = 1e-6: at convergence the
     profile equals the exact discrete parabola-plus-slip to 1e-12 relative for SMRT
-    (the odd sector's slowest mode has decayed to ~1e-19 by 45,000 steps).  BGK's
+    (the odd sector's slowest mode has decayed to ~1e-19 by 45,000 steps).  RMRT relaxes
+    this sector exactly as SMRT does (u_y = 0 and the raw force moments of orders 2 and 3
+    vanish in it), so the same closed form holds.  BGK's
     population-form update (eq:explict_eq) takes the equilibrium's momentum through
     the rounded weights, which leaves a round-off drift of a few 1e-12 here."""
     tau = 0.8
@@ -138,7 +141,8 @@ def test_poiseuille_config_transient():
     assert 1e-5 < err < 2e-4
 
 
-@pytest.mark.parametrize("coll,tau2,tau3", [("smrt", 0.6, 1.0), ("bgk", 0.6, 0.6)])
+@pytest.mark.parametrize("coll,tau2,tau3", [("smrt", 0.6, 1.0), ("bgk", 0.6, 0.6),
+                                            ("rmrt", 0.6, 0.8)])
 def test_kolmogorov_matches_discrete_closed_form(coll, tau2, tau3):
     """Periodic shear flow g_x = G sin(ky), L = 64: converged amplitude equals the exact
     discrete amplitude to 1e-10 relative (the continuum value differs by ~1e-3)."""
@@ -155,7 +159,7 @@ def test_kolmogorov_matches_discrete_closed_form(coll, tau2, tau3):
     _, uo = o.moments(f, g)
     k = w.meta["k"]
     G = w.meta["A"]
-    U = (cf.kolmogorov_amplitude(G, k, tau2, tau3) if coll == "smrt"
+    U = (cf.kolmogorov_amplitude(G, k, tau2, tau3) if coll in ("smrt", "rmrt")
          else cf.kolmogorov_amplitude_bgk(G, k, tau2))
     y = np.arange(64)
     assert np.max(np.abs(uo[0].reshape(64, nx)[:, 0] - U * np.sin(k * y))) <= 1e-10 * U
@@ -163,7 +167,7 @@ def test_kolmogorov_matches_discrete_closed_form(coll, tau2, tau3):
 
 # ---- P-TG: the paper's convergence claim ------------------------------------------------
 
-@pytest.mark.parametrize("coll", ["smrt", "bgk"])
+@pytest.mark.parametrize("coll", ["smrt", "bgk", "rmrt"])
 def test_taylor_green_second_order(coll):
     """Sec. III.A: forced 2-D Taylor-Green, Re = 50, u0 = 0.005, E2 at t = ln2/(2 nu k^2)
     for L = 16, 32, 64 falls by ~4 per doubling (observed order in [1.8, 2.2])."""
@@ -201,13 +205,13 @@ def _rotate_scalar(s, shape):
 
 
 @pytest.mark.parametrize("L", lat.LATTICES)
-@pytest.mark.parametrize("coll", ["bgk", "smrt"])
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_rotation_symmetry(L, coll):
     """Rotating the inputs by 90 degrees about z rotates the outputs (to round-off)."""
     D = lat.dim(L)
     shape = (6, 6, 3) if D == 3 else (6, 6, 1)
     rho, u, g = inputs.random_fields(shape, seed=21, dim=D, g_amp=1e-3)
-    o = Oracle(L, coll, shape, tau=(0.62, 0.85 if coll == "smrt" else 0.62, 1.0))
+    o = Oracle(L, coll, shape, tau=(0.62, 0.62 if coll == "bgk" else 0.85, 1.0))
 
     def run(rho, u, g):
         f = o.run(o.init(rho, u, g), g, 12)
