@@ -176,6 +176,18 @@ int lbm_device_bytes(const lbm_ctx *c, size_t *bytes);
 
 int lbm_free(lbm_ctx *c);
 
+/* Checkpoint / resume.  lbm_save writes the state as stored (populations in the storage
+ * format and the library's slot layout), the time, and a hash of everything the dynamics
+ * depend on (lattice, collision, storage, sizes, boundaries, rates, rho0, force content
+ * and the force table as uploaded); it synchronises the stream.  lbm_load restores time
+ * and state into a context created with the same parameters (LBM_EINVAL with a message
+ * if the file is not a checkpoint, is truncated or does not match; the context is then
+ * unchanged).  Running n steps, saving, loading into a fresh context and running n more
+ * gives the same state bit for bit as 2n steps.  The residual monitor restarts (it
+ * needs a previous record).  Files are for this library version and machine byte order. */
+int lbm_save(lbm_ctx *c, const char *path);
+int lbm_load(lbm_ctx *c, const char *path);
+
 /* Launch configuration of the step kernel: block shape bx x by (bx in {64, 128, 256},
  * bx * by <= 256) and memory-access variant (0 plain loads and stores, 1 non-temporal
  * stores, 2 non-temporal loads and stores).  Results are identical for every

@@ -54,6 +54,17 @@ namespace {
 constexpr uint32_t kMagic = 0x4c424d31u;  // "LBM1"
 
 size_t storage_bytes(int s) { return s == LBM_F64 ? 8 : (s == LBM_F16_SHIFTED ? 2 : 4); }
+
+// FNV-1a, 64-bit (Fowler, Noll and Vo): identity of the parameters a checkpoint needs.
+uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
+  const unsigned char *b = static_cast<const unsigned char *>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
 size_t arith_bytes(int s) { return s == LBM_F64 ? 8 : 4; }
 bool shifted(int s) { return s == LBM_F32_SHIFTED || s == LBM_F16_SHIFTED; }
 
@@ -86,6 +97,7 @@ struct lbm_ctx {
   int cur = 0;
   void *gtab = nullptr;
   int g_n = 1, g_axis = -1, gk = 0;
+  uint64_t g_hash = 0;  // FNV-1a of the force table as uploaded (checkpoint identity)
   void *uprev = nullptr;
   int64_t uprev_time = -2;
   double *partials = nullptr;
@@ -478,6 +490,7 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
     convert<double>(gh.data(), gh.size(), gconv);
   else
     convert<float>(gh.data(), gh.size(), gconv);
+  c->g_hash = fnv1a(kFnvBasis, gconv.data(), gconv.size());
 
   if ((rc = c->dalloc(&c->buf[0], pop_bytes)) || (rc = c->dalloc(&c->buf[1], pop_bytes)) ||
       (rc = c->dalloc(&c->gtab, gconv.size())) ||
@@ -726,6 +739,115 @@ int lbm_device_bytes(const lbm_ctx *c, size_t *bytes) {
 int lbm_free(lbm_ctx *c) {
   if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
   release(c);
+  return LBM_OK;
+}
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t kCkptVersion = 1;
+
+// Everything the dynamics of a context depend on, besides its state and time.
+uint64_t params_hash(const lbm_ctx *c) {
+  const lbm_params &p = c->p;
+  uint64_t h = kFnvBasis;
+  const int32_t ints[] = {p.lattice, p.collision, p.storage, p.nx,     p.ny,     p.nz,
+                          p.bc[0],   p.bc[1],     p.bc[2],   p.g_kind, p.g_axis,
+                          p.force_order == 3 ? 3 : 1};
+  h = fnv1a(h, ints, sizeof(ints));
+  const double reals[] = {p.tau[2], p.tau[3], p.tau[4], p.rho0};
+  h = fnv1a(h, reals, sizeof(reals));
+  return fnv1a(h, &c->g_hash, sizeof(c->g_hash));
+}
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t lattice, collision, storage, nx, ny, nz;
+  int64_t t;
+  uint64_t hash, payload;
+};
+
+bool write_all(FILE *f, const void *p, size_t n) { return fwrite(p, 1, n, f) == n; }
+bool read_all(FILE *f, void *p, size_t n) { return fread(p, 1, n, f) == n; }
+
+bool write_header(FILE *f, const CkptHeader &h) {
+  return write_all(f, h.magic, 8) && write_all(f, &h.version, 4) &&
+         write_all(f, &h.lattice, 4) && write_all(f, &h.collision, 4) &&
+         write_all(f, &h.storage, 4) && write_all(f, &h.nx, 4) && write_all(f, &h.ny, 4) &&
+         write_all(f, &h.nz, 4) && write_all(f, &h.t, 8) && write_all(f, &h.hash, 8) &&
+         write_all(f, &h.payload, 8);
+}
+bool read_header(FILE *f, CkptHeader &h) {
+  return read_all(f, h.magic, 8) && read_all(f, &h.version, 4) && read_all(f, &h.lattice, 4) &&
+         read_all(f, &h.collision, 4) && read_all(f, &h.storage, 4) && read_all(f, &h.nx, 4) &&
+         read_all(f, &h.ny, 4) && read_all(f, &h.nz, 4) && read_all(f, &h.t, 8) &&
+         read_all(f, &h.hash, 8) && read_all(f, &h.payload, 8);
+}
+
+}  // namespace
+
+int lbm_save(lbm_ctx *c, const char *path) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!path) return fail(LBM_EINVAL, "path is NULL");
+  const size_t bytes = (size_t)c->Q * c->N * storage_bytes(c->p.storage);
+  std::vector<unsigned char> host(bytes);
+  HIP_TRY(hipMemcpyAsync(host.data(), c->buf[c->cur], bytes, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  CkptHeader h{};
+  memcpy(h.magic, kCkptMagic, 8);
+  h.version = kCkptVersion;
+  h.lattice = c->p.lattice;
+  h.collision = c->p.collision;
+  h.storage = c->p.storage;
+  h.nx = c->p.nx;
+  h.ny = c->p.ny;
+  h.nz = c->p.nz;
+  h.t = c->t;
+  h.hash = params_hash(c);
+  h.payload = bytes;
+  FILE *f = fopen(path, "wb");
+  if (!f) return fail(LBM_EINVAL, "cannot open %s for writing", path);
+  const bool ok = write_header(f, h) && write_all(f, host.data(), bytes);
+  const bool closed = fclose(f) == 0;
+  if (!ok || !closed) return fail(LBM_EINVAL, "writing %s failed", path);
+  return LBM_OK;
+}
+
+int lbm_load(lbm_ctx *c, const char *path) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!path) return fail(LBM_EINVAL, "path is NULL");
+  FILE *f = fopen(path, "rb");
+  if (!f) return fail(LBM_EINVAL, "cannot open %s", path);
+  CkptHeader h{};
+  if (!read_header(f, h) || memcmp(h.magic, kCkptMagic, 8) != 0) {
+    fclose(f);
+    return fail(LBM_EINVAL, "%s is not a checkpoint of this library", path);
+  }
+  if (h.version != kCkptVersion) {
+    fclose(f);
+    return fail(LBM_EINVAL, "checkpoint version %u, expected %u", h.version, kCkptVersion);
+  }
+  const size_t bytes = (size_t)c->Q * c->N * storage_bytes(c->p.storage);
+  if (h.lattice != c->p.lattice || h.collision != c->p.collision || h.storage != c->p.storage ||
+      h.nx != c->p.nx || h.ny != c->p.ny || h.nz != c->p.nz || h.payload != bytes) {
+    fclose(f);
+    return fail(LBM_EINVAL, "checkpoint lattice, collision, storage or size differ");
+  }
+  if (h.hash != params_hash(c)) {
+    fclose(f);
+    return fail(LBM_EINVAL, "checkpoint parameters (rates, walls, force) differ");
+  }
+  std::vector<unsigned char> host(bytes);
+  const bool ok = read_all(f, host.data(), bytes);
+  fclose(f);
+  if (!ok) return fail(LBM_EINVAL, "%s is truncated", path);
+  HIP_TRY(hipMemcpyAsync(c->buf[0], host.data(), bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));  // host is released on return
+  c->cur = 0;
+  c->t = h.t;
+  c->uprev_time = -2;
+  c->mon.step = -1;
   return LBM_OK;
 }
 

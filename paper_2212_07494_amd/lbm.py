@@ -69,6 +69,8 @@ class lbm_monitors(C.Structure):
 EXPORTS = {
     "lbm_init": ([C.POINTER(lbm_params), C.c_void_p, C.c_void_p, C.c_void_p,
                   C.POINTER(C.c_void_p)], C.c_int),
+    "lbm_save": ([C.c_void_p, C.c_char_p], C.c_int),
+    "lbm_load": ([C.c_void_p, C.c_char_p], C.c_int),
     "lbm_step": ([C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "lbm_moments": ([C.c_void_p, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_monitors_get": ([C.c_void_p, C.POINTER(lbm_monitors)], C.c_int),
@@ -299,6 +301,14 @@ class Lattice:
 
     def step(self, n=1, g_scale=None):
         lbm_step(self.ctx, n, g_scale)
+
+    def save(self, path):
+        """Checkpoint: state as stored, time and parameter identity (lbm_save)."""
+        _check(load().lbm_save(self.ctx, os.fsencode(path)))
+
+    def load(self, path):
+        """Resume from a checkpoint of a lattice with the same parameters (lbm_load)."""
+        _check(load().lbm_load(self.ctx, os.fsencode(path)))
 
     def moments(self, g_scale=1.0):
         return lbm_moments(self.ctx, self.N, self.D, g_scale)

@@ -121,3 +121,11 @@ def test_library_constants_equal_oracle_rationals():
         assert ms == olat.index_set(name)
         assert [list(r) for r in olat.reconstruction(name)] == minv
         assert np.all(np.isfinite(np.array([[float(x) for x in r] for r in minv])))
+
+
+def test_checkpoint_calls_validate_arguments(tmp_path):
+    """lbm_save / lbm_load reject a NULL or foreign context before touching the GPU."""
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    assert lib.lbm_save(None, str(tmp_path / "x").encode()) == lbm.LBM_ESTATE
+    assert lib.lbm_load(None, str(tmp_path / "x").encode()) == lbm.LBM_ESTATE
