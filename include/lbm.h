@@ -115,6 +115,13 @@ typedef struct {
    * on the lattice's third-order index set.  The fourth-order force term stays out
    * (order 4 is trimmed).  BGK: must be 0 or 1. */
   int32_t force_order;
+  /* Solid nodes: host array of N bytes (nonzero = solid), copied at init; NULL = none.
+   * A fluid node whose pull source x - e_i is solid takes halfway bounce-back from its
+   * own node, f-bar_i(x, t+1) = f-bar*_opp(i)(x, t), as at a wall face (a stationary wall
+   * halfway between the two nodes).  Solid nodes are not stepped; lbm_moments reports
+   * rho = 0 and u = 0 there, the monitors sum over fluid nodes only, and populations
+   * stored at solid nodes are unspecified.  At least one node must be fluid. */
+  const uint8_t *solid;
 } lbm_params;
 
 /* Monitor record (binary64, summed on the device in a fixed order).

@@ -35,7 +35,7 @@ def _params_struct(real_t):
                     ("nz", C.c_int32), ("wall", C.c_int32 * 3), ("store16", C.c_int32),
                     ("shift", real_t), ("omega", real_t), ("hforce", real_t),
                     ("q2", real_t), ("q3", real_t), ("fq3", real_t), ("h2", real_t),
-                    ("h3", real_t)]
+                    ("h3", real_t), ("solid", C.c_void_p)]
     return _Params
 
 
@@ -82,12 +82,14 @@ class Oracle:
     on both faces); tau: dict or tuple of tau-hat per Hermite order (tau2, tau3,
     tau4) -- BGK uses tau2 only, SMRT and RMRT require tau4 == 1 (order 4 is trimmed);
     shift: constant s removed from stored populations (f-bar_i - w_i s);
-    real: 'f64' (reference) or 'f32' (emulation); store16: round stores to binary16.
+    real: 'f64' (reference) or 'f32' (emulation); store16: round stores to binary16;
+    force_order: 1, or 3 for SMRT's third-order force content; solid: N flags of solid
+    nodes (halfway bounce-back against them; not stepped; zero moments) or None.
     """
 
     def __init__(self, lattice: str, collision: str, shape, walls=(0, 0, 0), tau=(0.8, 0.8, 1.0),
                  shift: float = 0.0, real: str = "f64", store16: bool = False,
-                 force_order: int = 1):
+                 force_order: int = 1, solid=None):
         self.lattice = lattice
         self.collision = collision.lower()
         nx, ny, nz = (tuple(shape) + (1, 1))[:3]
@@ -122,6 +124,12 @@ class Oracle:
                     (C.c_int32 * 3)(*[int(bool(w)) for w in walls]), int(bool(store16)),
                     *[cast(vals[k]) for k in ("shift", "omega", "hforce", "q2", "q3", "fq3",
                                               "h2", "h3")])
+        self.solid = None
+        if solid is not None:
+            self.solid = np.ascontiguousarray(np.asarray(solid).ravel() != 0, dtype=np.uint8)
+            if self.solid.size != self.N:
+                raise ValueError("solid needs one flag per node")
+            self._p.solid = self.solid.ctypes.data
         self._l = _lib(real)
         self._lref = C.byref(self._lat)
         self._pref = C.byref(self._p)

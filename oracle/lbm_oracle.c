@@ -65,6 +65,7 @@ typedef struct {
   real fq3;            /* SMRT: (1 - omega_3/2)(1 - omega_2/2) for the third-order force
                           content, 0 when it is neglected */
   real h2, h3;         /* RMRT: 1 - omega_n / 2 */
+  const uint8_t *solid; /* N flags, nonzero = solid node (no fluid); NULL = none */
 } oracle_params;
 
 /* ---- binary16 rounding (IEEE 754 round to nearest, ties to even) ------------------ */
@@ -528,6 +529,10 @@ void oracle_step(const oracle_lattice *L, const oracle_params *P, const real *f,
     for (int y = 0; y < ny; ++y) {
       for (int x = 0; x < nx; ++x) {
         const int64_t n = ((int64_t)z * ny + y) * nx + x;
+        if (P->solid && P->solid[n]) { /* no fluid: nothing streams in or out */
+          for (int i = 0; i < L->Q; ++i) fnew[i * N + n] = f[i * N + n];
+          continue;
+        }
         real fi[MAXQ], out[MAXQ];
         for (int i = 0; i < L->Q; ++i) fi[i] = f[i * N + n];
         real gn[3];
@@ -547,10 +552,13 @@ void oracle_step(const oracle_lattice *L, const oracle_params *P, const real *f,
             }
           }
           real v = store_value(P, out[i]);
-          if (wall_hit)
+          const int64_t dn = ((int64_t)d[2] * ny + d[1]) * nx + d[0];
+          /* halfway bounce-back at a wall face or against a solid node: the population
+           * returns to its own node in the opposite direction */
+          if (wall_hit || (P->solid && P->solid[dn]))
             fnew[(int64_t)L->opp[i] * N + n] = v;
           else
-            fnew[(int64_t)i * N + ((int64_t)d[2] * ny + d[1]) * nx + d[0]] = v;
+            fnew[(int64_t)i * N + dn] = v;
         }
       }
     }
@@ -572,6 +580,12 @@ void oracle_moments(const oracle_lattice *L, const oracle_params *P, const real 
   const int64_t N = node_count(P);
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < N; ++n) {
+    if (P->solid && P->solid[n]) { /* no fluid */
+      if (rho) rho[n] = 0;
+      if (u)
+        for (int a = 0; a < 3; ++a) u[a * N + n] = 0;
+      continue;
+    }
     real fi[MAXQ];
     for (int i = 0; i < L->Q; ++i) fi[i] = f[i * N + n];
     real gn[3];

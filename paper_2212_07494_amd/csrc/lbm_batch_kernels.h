@@ -53,6 +53,7 @@ __device__ __forceinline__ Geom batch_geom(const BatchDom &dm) {
   geo.nz = dm.nz;
   geo.N = dm.N;
   for (int a = 0; a < 3; ++a) geo.wall[a] = dm.wall[a];
+  geo.smask = nullptr;  // batched domains have no solid nodes
   return geo;
 }
 
@@ -73,8 +74,8 @@ __global__ void __launch_bounds__(256)
     const int node = (z * dm.ny + y) * dm.nx + x;
     T g[3];
     batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);
-    step_node<L, COLL, S, T, MEM>(fin + dm.base, fout + dm.base, geo, x, y, z, node, g, shift,
-                                  T(dm.c0), T(dm.c1));
+    step_node<L, COLL, S, T, MEM>(fin + dm.base, fout + dm.base, geo, x, y, z, node, 0u, g,
+                                  shift, T(dm.c0), T(dm.c1));
   }
 }
 
@@ -103,7 +104,7 @@ __global__ void __launch_bounds__(256)
       const S *fd = f + dm.base;
       static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        d[i] = T(fd[pull_slot<L, i>(x, y, z, geo, node)]);
+        d[i] = T(fd[pull_slot<L, i>(x, y, z, geo, node, 0u)]);
       });
       T g[3];
       batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);

@@ -9,9 +9,14 @@
 
 namespace lbm {
 
+// Solid mask word: bit i = the pull source of population i is solid; this bit = the
+// node itself is solid.
+constexpr uint32_t SOLID_NODE = 1u << 31;
+
 struct GeomDesc {
   int nx, ny, nz, N;
   int wall[3];
+  const uint32_t *smask;  // device, per-node solid mask words (NULL: no solid nodes)
 };
 
 // One launch of a lattice kernel.  Coefficients are binary64 on the host and are
@@ -59,6 +64,11 @@ struct LatticeOps {
                      const double *pi, hipStream_t);
   hipError_t (*gather)(const LaunchDesc &, const int64_t *nodes, int64_t nn, double *out,
                        hipStream_t);
+  // Host: per-node solid mask words from a byte mask (bit i: the pull source of
+  // population i is solid, periodic wrap, sources across a wall face not marked; bit 31:
+  // the node is solid).
+  void (*solid_words)(const uint8_t *solid, int nx, int ny, int nz, const int wall[3],
+                      uint32_t *out);
   hipError_t (*scatter)(const LaunchDesc &, const double *in, hipStream_t);
   hipError_t (*moments)(const LaunchDesc &, double *rho, double *u, void *uprev, int mode,
                         double *partials, hipStream_t);

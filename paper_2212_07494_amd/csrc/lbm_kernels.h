@@ -18,6 +18,7 @@
 
 #include <cstdint>
 
+#include "lbm_internal.h"
 #include "lbm_node.h"
 
 namespace lbm {
@@ -27,7 +28,14 @@ enum { GK_PROFILE = 0, GK_FIELD = 1 };
 struct Geom {
   int nx, ny, nz, N;
   int wall[3];
+  // Solid nodes (NULL: none): per node, bit i = the pull source of population i is solid,
+  // bit 31 = the node itself is solid.
+  const uint32_t *smask;
 };
+
+__device__ __forceinline__ uint32_t node_mask(const Geom &G, int node) {
+  return G.smask ? G.smask[node] : 0u;
+}
 
 template <class T>
 struct ForceRef {
@@ -67,13 +75,14 @@ __device__ __forceinline__ void store_v(S *p, T v) {
 }
 
 // Slot that node (x, y, z) pulls population i from: (i, x - e_i) with periodic wrap,
-// or (opp(i), x) when x - e_i crosses a wall face.
+// or (opp(i), x) when x - e_i crosses a wall face or is a solid node (halfway
+// bounce-back); sm is the node's solid mask word.
 template <class L, int i>
 __device__ __forceinline__ int64_t pull_slot(int x, int y, int z, const Geom &G,
-                                             int node) {
+                                             int node, uint32_t sm) {
   constexpr int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
   int xs = x - ex, ys = y - ey, zs = z - ez;
-  bool bounce = false;
+  bool bounce = (sm >> i) & 1u;  // the source node is solid
   if constexpr (ex != 0) {
     const bool o = (xs < 0) | (xs >= G.nx);
     bounce |= o & (G.wall[0] != 0);
@@ -121,12 +130,12 @@ struct StepArgs {
 template <class L, int COLL, class S, class T, int MEM>
 __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restrict__ fout,
                                           const Geom &geo, int x, int y, int z, int node,
-                                          const T (&g)[3], T shift, T c0, T c1,
+                                          uint32_t sm, const T (&g)[3], T shift, T c0, T c1,
                                           T c2 = T(0), T c3 = T(0)) {
   T d[L::Q];
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, geo, node));
+    d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, geo, node, sm));
   });
   if constexpr (COLL == 0) {
     collide_bgk<L>(d, shift, g, BGKCoef<T>{c0, c1});
@@ -149,10 +158,12 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   const int z = blockIdx.z;
   if (x >= a.geo.nx || y >= a.geo.ny) return;
   const int node = (z * a.geo.ny + y) * a.geo.nx + x;
+  const uint32_t sm = node_mask(a.geo, node);
+  if (sm & SOLID_NODE) return;  // no fluid here: nothing pulls from its slots
   T g[3];
   load_force<T, GK>(a.force, x, y, z, node, a.geo.N, L::D, g);
   step_node<L, COLL, S, T, MEM>(static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.geo,
-                                x, y, z, node, g, a.shift, a.c0, a.c1, a.c2, a.c3);
+                                x, y, z, node, sm, g, a.shift, a.c0, a.c1, a.c2, a.c3);
 }
 
 // Initial state: compute f-bar(x, 0) at every node and place each population in the
@@ -166,6 +177,8 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<T> a, const double *
   const int z = blockIdx.z;
   if (x >= a.geo.nx || y >= a.geo.ny) return;
   const int node = (z * a.geo.ny + y) * a.geo.nx + x;
+  const uint32_t sm = node_mask(a.geo, node);
+  if (sm & SOLID_NODE) return;
   const int N = a.geo.N;
   T r = has_rho ? T(rho[node]) : rho0;
   T uu[3];
@@ -191,7 +204,7 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<T> a, const double *
   S *__restrict__ f = static_cast<S *>(a.fout);
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    f[pull_slot<L, i>(x, y, z, a.geo, node)] = store_as<S, T>(out[i]);
+    f[pull_slot<L, i>(x, y, z, a.geo, node, sm)] = store_as<S, T>(out[i]);
   });
 }
 
@@ -206,9 +219,10 @@ __global__ void __launch_bounds__(256) gather_kernel(const S *__restrict__ f, Ge
   const int x = node % geo.nx;
   const int y = (node / geo.nx) % geo.ny;
   const int z = node / (geo.nx * geo.ny);
+  const uint32_t sm = node_mask(geo, node);
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    out[(int64_t)i * nn + j] = double(f[pull_slot<L, i>(x, y, z, geo, node)]);
+    out[(int64_t)i * nn + j] = double(f[pull_slot<L, i>(x, y, z, geo, node, sm)]);
   });
 }
 
@@ -221,13 +235,15 @@ __global__ void __launch_bounds__(256) scatter_kernel(S *__restrict__ f, Geom ge
   const int x = n % geo.nx;
   const int y = (n / geo.nx) % geo.ny;
   const int z = n / (geo.nx * geo.ny);
+  const uint32_t sm = node_mask(geo, n);
+  if (sm & SOLID_NODE) return;
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     const double v = in[(int64_t)i * geo.N + n];
     if constexpr (std::is_same<S, double>::value)
-      f[pull_slot<L, i>(x, y, z, geo, n)] = v;
+      f[pull_slot<L, i>(x, y, z, geo, n, sm)] = v;
     else
-      f[pull_slot<L, i>(x, y, z, geo, n)] = S(float(v));
+      f[pull_slot<L, i>(x, y, z, geo, n, sm)] = S(float(v));
   });
 }
 
@@ -257,16 +273,23 @@ __global__ void __launch_bounds__(256) moments_kernel(StepArgs<T> a, double *rho
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
-  const bool live = (x < a.geo.nx) && (y < a.geo.ny);
+  const bool inside = (x < a.geo.nx) && (y < a.geo.ny);
+  const int node = (z * a.geo.ny + y) * a.geo.nx + x;
+  const uint32_t sm = inside ? node_mask(a.geo, node) : 0u;
+  const bool live = inside && !(sm & SOLID_NODE);
   double v[MON_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (inside && !live && (mode & MOM_WRITE)) {  // solid node: no fluid
+    if (rho_out) rho_out[node] = 0.0;
+    if (u_out)
+      for (int c = 0; c < L::D; ++c) u_out[(int64_t)c * a.geo.N + node] = 0.0;
+  }
   if (live) {
-    const int node = (z * a.geo.ny + y) * a.geo.nx + x;
     const int N = a.geo.N;
     const S *__restrict__ fin = static_cast<const S *>(a.fin);
     T d[L::Q];
     static_for<L::Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      d[i] = load_as<S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, node));
+      d[i] = load_as<S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, node, sm));
     });
     T g[3];
     load_force<T, GK>(a.force, x, y, z, node, N, L::D, g);

@@ -19,6 +19,7 @@ inline StepArgs<T> make_args(const LaunchDesc &d) {
   a.geo.nz = d.geo.nz;
   a.geo.N = d.geo.N;
   for (int c = 0; c < 3; ++c) a.geo.wall[c] = d.geo.wall[c];
+  a.geo.smask = d.geo.smask;
   a.force.tab = static_cast<const T *>(d.gtab);
   a.force.axis = d.g_axis;
   a.force.n = d.g_n;
@@ -38,6 +39,7 @@ inline Geom geom_of(const LaunchDesc &d) {
   g.nz = d.geo.nz;
   g.N = d.geo.N;
   for (int c = 0; c < 3; ++c) g.wall[c] = d.geo.wall[c];
+  g.smask = d.geo.smask;
   return g;
 }
 
@@ -99,6 +101,27 @@ struct Ops {
       return d.gk ? init_t<1, S, T, GK_FIELD>(d, rho, u, rho0, pi, s)
                   : init_t<1, S, T, GK_PROFILE>(d, rho, u, rho0, pi, s);
     });
+  }
+  static void solid_words(const uint8_t *solid, int nx, int ny, int nz, const int wall[3],
+                          uint32_t *out) {
+    const int dims[3] = {nx, ny, nz};
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const int64_t n = ((int64_t)z * ny + y) * nx + x;
+          uint32_t w = solid[n] ? SOLID_NODE : 0u;
+          for (int i = 0; i < L::Q; ++i) {
+            int c[3] = {x - L::E[i][0], y - L::E[i][1], z - L::E[i][2]};
+            bool across_wall = false;
+            for (int a = 0; a < 3; ++a) {
+              if (c[a] >= 0 && c[a] < dims[a]) continue;
+              if (wall[a]) across_wall = true;
+              c[a] = (c[a] + dims[a]) % dims[a];
+            }
+            if (!across_wall && solid[((int64_t)c[2] * ny + c[1]) * nx + c[0]]) w |= 1u << i;
+          }
+          out[n] = w;
+        }
   }
   static hipError_t gather(const LaunchDesc &d, const int64_t *nodes, int64_t nn, double *out,
                            hipStream_t s) {
@@ -183,6 +206,7 @@ const LatticeOps &LBM_OPS() {
                                  &impl::Ops<LBM_LAT>::step,
                                  &impl::Ops<LBM_LAT>::init,
                                  &impl::Ops<LBM_LAT>::gather,
+                                 &impl::Ops<LBM_LAT>::solid_words,
                                  &impl::Ops<LBM_LAT>::scatter,
                                  &impl::Ops<LBM_LAT>::moments,
                                  &impl::Ops<LBM_LAT>::batch_step,

@@ -98,6 +98,8 @@ struct lbm_ctx {
   void *gtab = nullptr;
   int g_n = 1, g_axis = -1, gk = 0;
   uint64_t g_hash = 0;  // FNV-1a of the force table as uploaded (checkpoint identity)
+  uint32_t *smask = nullptr;              // device solid mask words (NULL: none)
+  std::vector<uint32_t> smask_host;       // the same on the host (upload source, identity)
   void *uprev = nullptr;
   int64_t uprev_time = -2;
   double *partials = nullptr;
@@ -161,6 +163,7 @@ struct lbm_ctx {
     d.geo.nz = p.nz;
     d.geo.N = (int)N;
     for (int a = 0; a < 3; ++a) d.geo.wall[a] = p.bc[a] == LBM_WALLS;
+    d.geo.smask = smask;
     d.gtab = gtab;
     d.g_axis = g_axis;
     d.g_n = g_n;
@@ -238,6 +241,7 @@ void release(lbm_ctx *c) {
   c->dfree(c->buf[1]);
   c->dfree(c->gtab);
   c->dfree(c->uprev);
+  c->dfree(c->smask);
   c->dfree(c->partials);
   c->dfree(c->mon_dev);
   c->dfree(c->scratch);
@@ -491,9 +495,21 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   else
     convert<float>(gh.data(), gh.size(), gconv);
   c->g_hash = fnv1a(kFnvBasis, gconv.data(), gconv.size());
+  if (p->solid) {
+    const int walls[3] = {p->bc[0] == LBM_WALLS, p->bc[1] == LBM_WALLS, p->bc[2] == LBM_WALLS};
+    c->smask_host.resize((size_t)c->N);
+    c->ops->solid_words(p->solid, p->nx, p->ny, p->nz, walls, c->smask_host.data());
+    int64_t fluid = 0;
+    for (uint32_t w : c->smask_host) fluid += (w & lbm::SOLID_NODE) ? 0 : 1;
+    if (fluid == 0) {
+      delete c;
+      return fail(LBM_EINVAL, "every node is solid");
+    }
+  }
 
   if ((rc = c->dalloc(&c->buf[0], pop_bytes)) || (rc = c->dalloc(&c->buf[1], pop_bytes)) ||
       (rc = c->dalloc(&c->gtab, gconv.size())) ||
+      (p->solid && (rc = c->dalloc((void **)&c->smask, (size_t)c->N * sizeof(uint32_t)))) ||
       (rc = c->dalloc(&c->uprev, 3 * (size_t)c->N * ab)) ||
       (rc = c->dalloc((void **)&c->partials, (size_t)c->nblocks * 8 * sizeof(double))) ||
       (rc = c->dalloc((void **)&c->mon_dev, 8 * sizeof(double)))) {
@@ -509,6 +525,10 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   if (hipMemcpyAsync(c->gtab, gconv.data(), gconv.size(), hipMemcpyHostToDevice, c->stream) !=
       hipSuccess)
     return bail(fail(LBM_EDEVICE, "uploading the force table failed"));
+  if (c->smask &&
+      hipMemcpyAsync(c->smask, c->smask_host.data(), c->smask_host.size() * sizeof(uint32_t),
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return bail(fail(LBM_EDEVICE, "uploading the solid mask failed"));
   // upload initial fields
   const size_t fld = (size_t)c->N * sizeof(double);
   if ((rho_init || u_init) && (rc = c->need_scratch(fld * (1 + c->D)))) return bail(rc);
@@ -757,6 +777,7 @@ uint64_t params_hash(const lbm_ctx *c) {
   h = fnv1a(h, ints, sizeof(ints));
   const double reals[] = {p.tau[2], p.tau[3], p.tau[4], p.rho0};
   h = fnv1a(h, reals, sizeof(reals));
+  h = fnv1a(h, c->smask_host.data(), c->smask_host.size() * sizeof(uint32_t));
   return fnv1a(h, &c->g_hash, sizeof(c->g_hash));
 }
 
