@@ -122,6 +122,10 @@ typedef struct {
    * rho = 0 and u = 0 there, the monitors sum over fluid nodes only, and populations
    * stored at solid nodes are unspecified.  At least one node must be fluid. */
   const uint8_t *solid;
+  /* SMRT only: relaxation time (tau-hat) of the trace of the second-order moment, the
+   * irreducible component S^(2,0) of eq:domg (bulk viscosity (2/D)(tau_bulk - 1/2)/3);
+   * the traceless part keeps tau[2] (shear).  0 = tau[2] (one rate for order 2). */
+  double tau_bulk;
 } lbm_params;
 
 /* Monitor record (binary64, summed on the device in a fixed order).

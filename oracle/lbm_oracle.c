@@ -65,6 +65,7 @@ typedef struct {
   real fq3;            /* SMRT: (1 - omega_3/2)(1 - omega_2/2) for the third-order force
                           content, 0 when it is neglected */
   real h2, h3;         /* RMRT: 1 - omega_n / 2 */
+  real dqb;            /* SMRT: (q_bulk - q2)/D for the trace of order 2 (0 = one rate) */
   const uint8_t *solid; /* N flags, nonzero = solid node (no fluid); NULL = none */
 } oracle_params;
 
@@ -303,6 +304,20 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
         }
         Pc[k] = Pc[k] + P->fq3 * s;
       }
+    }
+  }
+  if (P->dqb != 0) {
+    /* eq:domg per irreducible component at order 2: the trace (bulk part) relaxes with
+     * its own rate, P_aa += (q_bulk - q2)/D tr(D) (dqb holds (q_bulk - q2)/D), the
+     * traceless part keeps q2 */
+    real tr = -0.0;
+    for (int k = 0; k < NM; ++k) {
+      const int32_t *m = L->mi + 3 * k;
+      if (mabs(m) == 2 && (m[0] == 2 || m[1] == 2 || m[2] == 2)) tr = tr + D2[k];
+    }
+    for (int k = 0; k < NM; ++k) {
+      const int32_t *m = L->mi + 3 * k;
+      if (mabs(m) == 2 && (m[0] == 2 || m[1] == 2 || m[2] == 2)) Pc[k] = Pc[k] + P->dqb * tr;
     }
   }
   /* back to raw moments; the change of every moment over the collision */

@@ -122,7 +122,7 @@ struct StepArgs {
   T shift;
   T c0, c1;  // BGK: omega, 1 - omega/2;  SMRT: q2, q3
   T c2;      // SMRT: coefficient of the third-order force term (0 = off); RMRT: h2
-  T c3;      // RMRT: h3
+  T c3;      // RMRT: h3; SMRT: (q_bulk - q2)/D (0 = one rate at order 2)
 };
 
 // One node of the fused step: pull the populations (periodic wrap or halfway
@@ -141,7 +141,7 @@ __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restri
     collide_bgk<L>(d, shift, g, BGKCoef<T>{c0, c1});
   } else {
     if constexpr (COLL == 1)
-      collide_smrt<L>(d, shift, g, SMRTCoef<T>{c0, c1, c2});
+      collide_smrt<L>(d, shift, g, SMRTCoef<T>{c0, c1, c2, c3});
     else
       collide_rmrt<L>(d, shift, g, RMRTCoef<T>{c0, c1, c2, c3});
   }

@@ -115,7 +115,29 @@ struct SMRTCoef {
   // Third-order force content with the non-equilibrium stress (0 = neglected, as in the
   // paper's runs): (1 - omega_3/2)(1 - omega_2/2), see collide_smrt.
   T fq3;
+  // Bulk rate: (q_bulk - q2) / D for the trace of the second-order moment (0 = one
+  // rate for the whole order).
+  T dqb;
 };
+
+// Whether MI[k] is a diagonal second-order index (2 e_a).
+template <class L>
+constexpr bool is_diag2(int k) {
+  return L::ORD[k] == 2 && (L::MI[k][0] == 2 || L::MI[k][1] == 2 || L::MI[k][2] == 2);
+}
+
+// Central moment D_m = sum_{l <= m} C(m,l) (-u)^l N_{m-l} from the non-equilibrium raw
+// moments N (the shift to the frame moving with u).
+template <class L, int K, class T>
+__device__ __forceinline__ T central(const T (&U)[L::NM], const T (&N)[L::NM]) {
+  T Dm = N[K];
+  static_for<L::NT[K]>([&](auto Tt) {
+    constexpr int t = decltype(Tt)::value;
+    constexpr int kl = L::TL[K][t], km = L::TM[K][t];
+    Dm = Dm + T(L::CDN[K][t]) * (U[kl] * N[km]);
+  });
+  return Dm;
+}
 
 // Index of the multi-index MI[k] - e_a in L's canonical list (-1 if absent).
 template <class L>
@@ -232,6 +254,15 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       N[k] = T(0);
     }
   });
+  // eq:domg per irreducible component at order 2: the trace S^(2,0) (bulk part) may relax
+  // at its own rate, P_aa += (q_bulk - q2)/D tr(D), the traceless part keeps q2 (a zero
+  // coefficient leaves every P unchanged).
+  T tb = T(-0.0);
+  static_for<NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    if constexpr (is_diag2<L>(k)) tb = tb + central<L, k>(U, N);
+  });
+  tb = c.dqb * tb;
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int n = L::ORD[k];
@@ -239,14 +270,10 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
       P[k] = T(0.5) * M.F[a];
     } else if constexpr (n == 2 || n == 3) {
-      T Dm = N[k];
-      static_for<L::NT[k]>([&](auto Tt) {
-        constexpr int t = decltype(Tt)::value;
-        constexpr int kl = L::TL[k][t], km = L::TM[k][t];
-        Dm = Dm + T(L::CDN[k][t]) * (U[kl] * N[km]);
-      });
+      const T Dm = central<L, k>(U, N);
       if constexpr (n == 2) C2[k] = Dm;
       P[k] = (n == 2 ? c.q2 : c.q3) * Dm;
+      if constexpr (is_diag2<L>(k)) P[k] = P[k] + tb;
       if constexpr (n == 3) {
         // Third-order force content (eq:Frc, d_F^(3) = 3 g d^(2)): the symmetric product
         // sum_a m_a g_a d_{m - e_a} of the acceleration with the non-equilibrium central

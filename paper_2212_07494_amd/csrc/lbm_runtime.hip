@@ -213,6 +213,12 @@ int validate(const lbm_params *p) {
     return fail(LBM_EINVAL, "force_order must be 1 or 3 (got %d)", p->force_order);
   if (p->force_order == 3 && p->collision != LBM_SMRT)
     return fail(LBM_EINVAL, "force_order 3 needs the SMRT collision");
+  if (p->tau_bulk != 0) {
+    if (p->collision != LBM_SMRT)
+      return fail(LBM_EINVAL, "tau_bulk needs the SMRT collision");
+    if (!(p->tau_bulk > 0.5) || !std::isfinite(p->tau_bulk))
+      return fail(LBM_EINVAL, "tau_bulk = %g must exceed 1/2 (or be 0)", p->tau_bulk);
+  }
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0))
     return fail(LBM_EINVAL, "rho0 = %g must be positive", p->rho0);
   if (p->g_kind < LBM_G_UNIFORM || p->g_kind > LBM_G_FIELD)
@@ -458,8 +464,10 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
     if (p->collision == LBM_RMRT) {
       c->c2 = 1.0 - 0.5 / p->tau[2];
       c->c3 = 1.0 - 0.5 / p->tau[3];
-    } else if (p->force_order == 3) {
-      c->c2 = (1.0 - 0.5 / p->tau[3]) * (1.0 - 0.5 / p->tau[2]);
+    } else {
+      if (p->force_order == 3) c->c2 = (1.0 - 0.5 / p->tau[3]) * (1.0 - 0.5 / p->tau[2]);
+      if (p->tau_bulk != 0 && p->tau_bulk != p->tau[2])
+        c->c3 = ((1.0 - 1.0 / p->tau_bulk) - (1.0 - 1.0 / p->tau[2])) / c->D;
     }
   }
   block_shape(p->nx, c->bx, c->by);
@@ -775,7 +783,8 @@ uint64_t params_hash(const lbm_ctx *c) {
                           p.bc[0],   p.bc[1],     p.bc[2],   p.g_kind, p.g_axis,
                           p.force_order == 3 ? 3 : 1};
   h = fnv1a(h, ints, sizeof(ints));
-  const double reals[] = {p.tau[2], p.tau[3], p.tau[4], p.rho0};
+  const double reals[] = {p.tau[2], p.tau[3], p.tau[4], p.rho0,
+                          p.tau_bulk == 0 ? p.tau[2] : p.tau_bulk};
   h = fnv1a(h, reals, sizeof(reals));
   h = fnv1a(h, c->smask_host.data(), c->smask_host.size() * sizeof(uint32_t));
   return fnv1a(h, &c->g_hash, sizeof(c->g_hash));

@@ -45,6 +45,10 @@ def test_version_and_strerror():
     (dict(lattice="D3Q19", shape=(2048, 2048, 1024)), "2^31"),
     (dict(force_order=2), "force_order"),
     (dict(force_order=3), "SMRT"),
+    (dict(tau_bulk=1.2), "tau_bulk needs the SMRT"),
+    (dict(collision="rmrt", tau_bulk=1.2), "tau_bulk needs the SMRT"),
+    (dict(collision="smrt", tau_bulk=0.5), "must exceed 1/2"),
+    (dict(collision="smrt", tau_bulk=float("nan")), "must exceed 1/2"),
 ])
 def test_invalid_parameters_rejected(change, fragment):
     from paper_2212_07494_amd import lbm

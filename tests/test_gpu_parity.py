@@ -109,6 +109,34 @@ def test_third_order_force_parity(lat, storage):
 
 
 @pytest.mark.parametrize("storage", STORES)
+@pytest.mark.parametrize("lat", LATS)
+def test_bulk_rate_parity(lat, storage):
+    """SMRT with its own rate for the trace of the second-order moment (tau_bulk): random
+    state, force field and walls, three steps, bit-identical to the oracle; and the state
+    differs from the one-rate step."""
+    L = lbm()
+    shape = SHAPES[lat]
+    N = int(np.prod(shape))
+    walls = WALLS[lat][-1]
+    kw, g = _force(lat, shape, "field", seed=9)
+    f0 = _state(lat, storage, N, seed=13)
+    o = oracle_for(lat, "smrt", storage, shape, walls, TAU["smrt"], tau_bulk=1.7)
+    scales = [1.0, 0.5, -2.0]
+    fo = f0.astype(o.dtype)
+    for s in scales:
+        fo = o.step(fo, g, s)
+    got = {}
+    for tb in (0.0, 1.7):
+        with L.Lattice(lat, "smrt", storage, shape, walls, TAU["smrt"], tau_bulk=tb,
+                       **kw) as gpu:
+            gpu.set_populations(f0)
+            gpu.step(3, g_scale=scales)
+            got[tb] = gpu.populations()
+    assert exact_mismatch(got[1.7], fo.astype(np.float64)) == 0
+    assert exact_mismatch(got[1.7], got[0.0]) > 0
+
+
+@pytest.mark.parametrize("storage", STORES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 @pytest.mark.parametrize("lat", LATS)
 def test_init_and_moments_parity(lat, coll, storage):

@@ -264,6 +264,69 @@ def test_linearised_collision_spectrum(L, coll, tau2, tau3):
     assert np.max(np.abs(lam - np.sort(want))) < 1e-8, (lam, sorted(want))
 
 
+def _collision_jacobian(o):
+    """Central differences of the collision about rest, unforced (exact up to rounding:
+    the map is a polynomial there)."""
+    Q = o.Q
+    f0 = o.init_node(1.0, [0, 0, 0], [0, 0, 0])
+    h = 1e-5
+    J = np.empty((Q, Q))
+    for q in range(Q):
+        d = np.zeros(Q)
+        d[q] = h
+        J[:, q] = (o.collide_node(f0 + d, [0, 0, 0]) - o.collide_node(f0 - d, [0, 0, 0])) / (2 * h)
+    return J
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("tau_b", [0.55, 0.9, 1.7])
+def test_bulk_rate_collision_spectrum(L, tau_b):
+    """eq:domg per irreducible component at order 2: with its own rate for the trace,
+    exactly one second-order eigenvalue moves to 1 - 1/tau_bulk, the D(D+1)/2 - 1
+    traceless ones keep 1 - 1/tau2."""
+    tau2, tau3 = 0.8, 1.0
+    o = Oracle(L, "smrt", (1, 1, 1), tau=(tau2, tau3, 1.0), tau_bulk=tau_b)
+    Q, D = o.Q, o.D
+    lam = np.sort(np.linalg.eigvals(_collision_jacobian(o)).real)
+    n2 = D * (D + 1) // 2
+    n3 = ORDER3[L]
+    want = ([1.0] * (1 + D) + [1 - 1 / tau_b] + [1 - 1 / tau2] * (n2 - 1)
+            + [1 - 1 / tau3] * n3 + [0.0] * (Q - 1 - D - n2 - n3))
+    assert np.max(np.abs(lam - np.sort(want))) < 1e-8, (lam, sorted(want))
+
+
+@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("tau_b", [0.0, 0.9, 1.7])
+def test_bulk_rate_sound_attenuation(L, tau_b):
+    """Hydrodynamic limit of the linearised step at small wavenumber k (along x): the
+    sound pair decays as exp(-Gamma k^2 t) with Gamma = ((2 - 2/D) nu + zeta)/2, the
+    shear modes as exp(-nu k^2 t), with nu = c_s^2 (tau2 - 1/2) and the bulk viscosity
+    zeta = (2/D) c_s^2 (tau_bulk - 1/2) (zeta = 2 nu / D with one rate, the textbook
+    value of the lattice BGK).  The step about rest is diag(exp(-i k e_ix)) J (pull
+    streaming after the collision J); the O(k^2) relative error must shrink ~4x when k
+    halves."""
+    tau2 = 0.8
+    o = Oracle(L, "smrt", (1, 1, 1), tau=(tau2, 1.0, 1.0), tau_bulk=tau_b)
+    D = o.D
+    J = _collision_jacobian(o)
+    ex = np.array(lat.velocities(L))[:, 0]
+    cs = math.sqrt(CS2)
+    nu = CS2 * (tau2 - 0.5)
+    zeta = (2.0 / D) * CS2 * ((tau_b or tau2) - 0.5)
+    gam = 0.5 * ((2 - 2.0 / D) * nu + zeta)
+    errs = []
+    for k in (2 * math.pi / 64, 2 * math.pi / 128):
+        ev = np.linalg.eigvals(np.diag(np.exp(-1j * k * ex)) @ J)
+        sound = ev[(np.abs(np.abs(np.angle(ev)) - cs * k) < 0.2 * cs * k) & (np.abs(ev) > 0.5)]
+        shear = ev[(np.abs(np.angle(ev)) < 1e-6) & (np.abs(ev) > 0.5) & (np.abs(ev) < 1 - 1e-12)]
+        assert sound.size == 2 and shear.size == D - 1, (sound, shear)
+        g_meas = -np.log(np.abs(sound)) / k ** 2
+        n_meas = -np.log(np.abs(shear)) / k ** 2
+        assert np.max(np.abs(n_meas / nu - 1)) < 5e-4
+        errs.append(np.max(np.abs(g_meas / gam - 1)))
+    assert errs[1] < 2e-4 and errs[1] < 0.3 * errs[0], errs
+
+
 @pytest.mark.parametrize("L", lat.LATTICES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt"])
 def test_staggered_momentum_mode_never_decays(L, coll):
