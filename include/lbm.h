@@ -126,6 +126,12 @@ typedef struct {
    * irreducible component S^(2,0) of eq:domg (bulk viscosity (2/D)(tau_bulk - 1/2)/3);
    * the traceless part keeps tau[2] (shear).  0 = tau[2] (one rate for order 2). */
   double tau_bulk;
+  /* SMRT on D3Q19 / D3Q27 only: relaxation time of the third-order trace S^(3,1) of
+   * eq:domg, the vector sum_b D_abb of the central third moment; the lattices carry it as
+   * D_abb + D_acc (b, c the other two axes; D_aaa is not carried).  The traceless rest
+   * (the differences D_abb - D_acc and D_xyz) keeps tau[3].  0 = tau[3].  Not with
+   * force_order 3. */
+  double tau_31;
 } lbm_params;
 
 /* Monitor record (binary64, summed on the device in a fixed order).

@@ -66,6 +66,7 @@ typedef struct {
                           content, 0 when it is neglected */
   real h2, h3;         /* RMRT: 1 - omega_n / 2 */
   real dqb;            /* SMRT: (q_bulk - q2)/D for the trace of order 2 (0 = one rate) */
+  real dq31;           /* SMRT: (q_31 - q3)/2 for the trace of order 3 (0 = one rate) */
   const uint8_t *solid; /* N flags, nonzero = solid node (no fluid); NULL = none */
 } oracle_params;
 
@@ -253,7 +254,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
   macro_t M;
   macroscopic(L, P, f, g, &M);
   const int NM = L->NM;
-  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ], D2[MAXQ];
+  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ], D2[MAXQ], D3[MAXQ];
   for (int k = 0; k < NM; ++k) {
     U[k] = upow(L->mi + 3 * k, M.u);
     E[k] = M.rho * U[k];
@@ -288,6 +289,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       for (int t = 0; t < S->n[k]; ++t)
         D = D + (real)S->cdown[k][t] * (U[S->kl[k][t]] * N[S->km[k][t]]);
       if (n == 2) D2[k] = D;
+      if (n == 3) D3[k] = D;
       Pc[k] = (n == 2 ? P->q2 : P->q3) * D;
       if (n == 3 && P->fq3 != 0) {
         /* eq:Frc at theta = 1: d_F^(3) = 3 g d^(2), the symmetric product, per multi-index
@@ -318,6 +320,30 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
     for (int k = 0; k < NM; ++k) {
       const int32_t *m = L->mi + 3 * k;
       if (mabs(m) == 2 && (m[0] == 2 || m[1] == 2 || m[2] == 2)) Pc[k] = Pc[k] + P->dqb * tr;
+    }
+  }
+  if (P->dq31 != 0) {
+    /* eq:domg at order 3: the trace S^(3,1), sum_b D_abb, relaxes with its own rate.  The
+     * lattice carries its axis-a component as D_abb + D_acc (D_aaa has no Hermite moment
+     * on it), so each such pair gains (q_31 - q3)/2 (D_abb + D_acc) (dq31 holds the half
+     * difference); the pair's difference and D_xyz keep q3 */
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      int mb[3] = {0, 0, 0}, mc[3] = {0, 0, 0};
+      mb[a] = 1;
+      mb[b] = 2;
+      mc[a] = 1;
+      mc[c] = 2;
+      int jb = find_index(L, mb[0], mb[1], mb[2]), jc = find_index(L, mc[0], mc[1], mc[2]);
+      if (jb < 0 || jc < 0) continue;
+      if (jb > jc) {
+        const int t = jb;
+        jb = jc;
+        jc = t;
+      }
+      const real s = D3[jb] + D3[jc];
+      Pc[jb] = Pc[jb] + P->dq31 * s;
+      Pc[jc] = Pc[jc] + P->dq31 * s;
     }
   }
   /* back to raw moments; the change of every moment over the collision */

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256)
       const S *fd = f + dm.base;
       static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        d[i] = T(fd[pull_slot<L, i>(x, y, z, geo, node, 0u)]);
+        d[i] = T(fd[pull_slot<L, i>(x, y, z, geo, 0u)]);
       });
       T g[3];
       batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);

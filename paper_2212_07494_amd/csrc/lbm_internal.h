@@ -35,6 +35,7 @@ struct LaunchDesc {
   double c0, c1;
   double c2;         // SMRT: coefficient of the third-order force term (0 = off); RMRT: h2
   double c3;         // RMRT: h3 = 1 - omega_3 / 2; SMRT: (q_bulk - q2)/D (0 = one rate)
+  double c4;         // SMRT: (q_31 - q3)/2 for the third-order trace pairs (0 = one rate)
   int bx, by;        // block shape (bx * by <= 256, bx a multiple of 64)
   int variant;       // memory-access variant of the step kernel (MEM_*)
 };

@@ -74,12 +74,21 @@ __device__ __forceinline__ void store_v(S *p, T v) {
     *p = S(v);
 }
 
+// Storage slot of population i at node (x, y, z).  Layout: one slab per z layer holding
+// the layer's Q planes back to back, slot = (z Q + i) nx ny + y nx + x.  Compared with Q
+// planes of the whole grid it keeps every access of a workgroup (its layer and the two
+// beside it) inside 3 Q nx ny contiguous values, which the memory system streams faster.
+// The slab base is uniform across a wave when blocks span one row.
+template <class L>
+__device__ __forceinline__ int64_t pop_slot(int i, int x, int y, int z, const Geom &G) {
+  return ((int64_t)z * L::Q + i) * ((int64_t)G.nx * G.ny) + (y * G.nx + x);
+}
+
 // Slot that node (x, y, z) pulls population i from: (i, x - e_i) with periodic wrap,
 // or (opp(i), x) when x - e_i crosses a wall face or is a solid node (halfway
 // bounce-back); sm is the node's solid mask word.
 template <class L, int i>
-__device__ __forceinline__ int64_t pull_slot(int x, int y, int z, const Geom &G,
-                                             int node, uint32_t sm) {
+__device__ __forceinline__ int64_t pull_slot(int x, int y, int z, const Geom &G, uint32_t sm) {
   constexpr int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
   int xs = x - ex, ys = y - ey, zs = z - ez;
   bool bounce = (sm >> i) & 1u;  // the source node is solid
@@ -98,8 +107,7 @@ __device__ __forceinline__ int64_t pull_slot(int x, int y, int z, const Geom &G,
     bounce |= o & (G.wall[2] != 0);
     zs = (zs < 0) ? zs + G.nz : ((zs >= G.nz) ? zs - G.nz : zs);
   }
-  const int src = (zs * G.ny + ys) * G.nx + xs;
-  return bounce ? (int64_t)L::OPP[i] * G.N + node : (int64_t)i * G.N + src;
+  return bounce ? pop_slot<L>(L::OPP[i], x, y, z, G) : pop_slot<L>(i, xs, ys, zs, G);
 }
 
 template <class T, int GK>
@@ -123,6 +131,7 @@ struct StepArgs {
   T c0, c1;  // BGK: omega, 1 - omega/2;  SMRT: q2, q3
   T c2;      // SMRT: coefficient of the third-order force term (0 = off); RMRT: h2
   T c3;      // RMRT: h3; SMRT: (q_bulk - q2)/D (0 = one rate at order 2)
+  T c4;      // SMRT: (q_31 - q3)/2 (0 = one rate at order 3)
 };
 
 // One node of the fused step: pull the populations (periodic wrap or halfway
@@ -131,23 +140,23 @@ template <class L, int COLL, class S, class T, int MEM>
 __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restrict__ fout,
                                           const Geom &geo, int x, int y, int z, int node,
                                           uint32_t sm, const T (&g)[3], T shift, T c0, T c1,
-                                          T c2 = T(0), T c3 = T(0)) {
+                                          T c2 = T(0), T c3 = T(0), T c4 = T(0)) {
   T d[L::Q];
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, geo, node, sm));
+    d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, geo, sm));
   });
   if constexpr (COLL == 0) {
     collide_bgk<L>(d, shift, g, BGKCoef<T>{c0, c1});
   } else {
     if constexpr (COLL == 1)
-      collide_smrt<L>(d, shift, g, SMRTCoef<T>{c0, c1, c2, c3});
+      collide_smrt<L>(d, shift, g, SMRTCoef<T>{c0, c1, c2, c3, c4});
     else
       collide_rmrt<L>(d, shift, g, RMRTCoef<T>{c0, c1, c2, c3});
   }
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    store_v<MEM, S, T>(fout + (int64_t)i * geo.N + node, d[i]);
+    store_v<MEM, S, T>(fout + pop_slot<L>(i, x, y, z, geo), d[i]);
   });
 }
 
@@ -163,7 +172,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   T g[3];
   load_force<T, GK>(a.force, x, y, z, node, a.geo.N, L::D, g);
   step_node<L, COLL, S, T, MEM>(static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.geo,
-                                x, y, z, node, sm, g, a.shift, a.c0, a.c1, a.c2, a.c3);
+                                x, y, z, node, sm, g, a.shift, a.c0, a.c1, a.c2, a.c3, a.c4);
 }
 
 // Initial state: compute f-bar(x, 0) at every node and place each population in the
@@ -204,7 +213,7 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<T> a, const double *
   S *__restrict__ f = static_cast<S *>(a.fout);
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    f[pull_slot<L, i>(x, y, z, a.geo, node, sm)] = store_as<S, T>(out[i]);
+    f[pull_slot<L, i>(x, y, z, a.geo, sm)] = store_as<S, T>(out[i]);
   });
 }
 
@@ -222,7 +231,7 @@ __global__ void __launch_bounds__(256) gather_kernel(const S *__restrict__ f, Ge
   const uint32_t sm = node_mask(geo, node);
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    out[(int64_t)i * nn + j] = double(f[pull_slot<L, i>(x, y, z, geo, node, sm)]);
+    out[(int64_t)i * nn + j] = double(f[pull_slot<L, i>(x, y, z, geo, sm)]);
   });
 }
 
@@ -241,9 +250,9 @@ __global__ void __launch_bounds__(256) scatter_kernel(S *__restrict__ f, Geom ge
     constexpr int i = decltype(I)::value;
     const double v = in[(int64_t)i * geo.N + n];
     if constexpr (std::is_same<S, double>::value)
-      f[pull_slot<L, i>(x, y, z, geo, n, sm)] = v;
+      f[pull_slot<L, i>(x, y, z, geo, sm)] = v;
     else
-      f[pull_slot<L, i>(x, y, z, geo, n, sm)] = S(float(v));
+      f[pull_slot<L, i>(x, y, z, geo, sm)] = S(float(v));
   });
 }
 
@@ -289,7 +298,7 @@ __global__ void __launch_bounds__(256) moments_kernel(StepArgs<T> a, double *rho
     T d[L::Q];
     static_for<L::Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      d[i] = load_as<S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, node, sm));
+      d[i] = load_as<S, T>(fin + pull_slot<L, i>(x, y, z, a.geo, sm));
     });
     T g[3];
     load_force<T, GK>(a.force, x, y, z, node, N, L::D, g);

@@ -29,6 +29,7 @@ inline StepArgs<T> make_args(const LaunchDesc &d) {
   a.c1 = T(d.c1);
   a.c2 = T(d.c2);
   a.c3 = T(d.c3);
+  a.c4 = T(d.c4);
   return a;
 }
 

@@ -118,6 +118,8 @@ struct SMRTCoef {
   // Bulk rate: (q_bulk - q2) / D for the trace of the second-order moment (0 = one
   // rate for the whole order).
   T dqb;
+  // Third-order trace rate: (q_31 - q3) / 2 for the pairs D_abb + D_acc (0 = one rate).
+  T dq31;
 };
 
 // Whether MI[k] is a diagonal second-order index (2 e_a).
@@ -137,6 +139,27 @@ __device__ __forceinline__ T central(const T (&U)[L::NM], const T (&N)[L::NM]) {
     Dm = Dm + T(L::CDN[K][t]) * (U[kl] * N[km]);
   });
   return Dm;
+}
+
+// For a third-order index a + 2b (one axis with exponent 1, another with 2), the index of
+// its trace partner a + 2c (c the third axis), which carries with it the axis-a component
+// of the third-order trace; -1 otherwise or if the lattice lacks the partner.
+template <class L>
+constexpr int trace_partner3(int k) {
+  if (L::ORD[k] != 3) return -1;
+  int a = -1, b = -1;
+  for (int t = 0; t < 3; ++t) {
+    if (L::MI[k][t] == 1) a = t;
+    if (L::MI[k][t] == 2) b = t;
+  }
+  if (a < 0 || b < 0) return -1;
+  const int c = 3 - a - b;
+  int m[3] = {0, 0, 0};
+  m[a] = 1;
+  m[c] = 2;
+  for (int j = 0; j < L::NM; ++j)
+    if (L::MI[j][0] == m[0] && L::MI[j][1] == m[1] && L::MI[j][2] == m[2]) return j;
+  return -1;
 }
 
 // Index of the multi-index MI[k] - e_a in L's canonical list (-1 if absent).
@@ -263,6 +286,18 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
     if constexpr (is_diag2<L>(k)) tb = tb + central<L, k>(U, N);
   });
   tb = c.dqb * tb;
+  // The same at order 3: the trace S^(3,1), carried per axis a by D_abb + D_acc, may relax
+  // at its own rate, P_abb += (q_31 - q3)/2 (D_abb + D_acc) and likewise P_acc; the
+  // differences D_abb - D_acc and D_xyz keep q3.
+  T t3[NM];
+  static_for<NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr int p = trace_partner3<L>(k);
+    if constexpr (p > k) {
+      t3[k] = c.dq31 * (central<L, k>(U, N) + central<L, p>(U, N));
+      t3[p] = t3[k];
+    }
+  });
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int n = L::ORD[k];
@@ -274,6 +309,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       if constexpr (n == 2) C2[k] = Dm;
       P[k] = (n == 2 ? c.q2 : c.q3) * Dm;
       if constexpr (is_diag2<L>(k)) P[k] = P[k] + tb;
+      if constexpr (trace_partner3<L>(k) >= 0) P[k] = P[k] + t3[k];
       if constexpr (n == 3) {
         // Third-order force content (eq:Frc, d_F^(3) = 3 g d^(2)): the symmetric product
         // sum_a m_a g_a d_{m - e_a} of the acceleration with the non-equilibrium central

@@ -110,7 +110,7 @@ struct lbm_ctx {
   size_t bytes = 0;
   int64_t t = 0;
   double last_scale = 1.0;
-  double c0 = 0, c1 = 0, c2 = 0, c3 = 0, shift = 0;
+  double c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, shift = 0;
   int bx = 64, by = 4, variant = 0;
   lbm_monitors mon{};
 
@@ -173,6 +173,7 @@ struct lbm_ctx {
     d.c1 = c1;
     d.c2 = c2;
     d.c3 = c3;
+    d.c4 = c4;
     d.bx = bx;
     d.by = by;
     d.variant = variant;
@@ -218,6 +219,16 @@ int validate(const lbm_params *p) {
       return fail(LBM_EINVAL, "tau_bulk needs the SMRT collision");
     if (!(p->tau_bulk > 0.5) || !std::isfinite(p->tau_bulk))
       return fail(LBM_EINVAL, "tau_bulk = %g must exceed 1/2 (or be 0)", p->tau_bulk);
+  }
+  if (p->tau_31 != 0) {
+    if (p->collision != LBM_SMRT)
+      return fail(LBM_EINVAL, "tau_31 needs the SMRT collision");
+    if (p->lattice == LBM_D2Q9)
+      return fail(LBM_EINVAL, "tau_31: D2Q9 carries no traceless third-order component");
+    if (p->force_order == 3)
+      return fail(LBM_EINVAL, "tau_31 is not combined with force_order 3");
+    if (!(p->tau_31 > 0.5) || !std::isfinite(p->tau_31))
+      return fail(LBM_EINVAL, "tau_31 = %g must exceed 1/2 (or be 0)", p->tau_31);
   }
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0))
     return fail(LBM_EINVAL, "rho0 = %g must be positive", p->rho0);
@@ -468,6 +479,8 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
       if (p->force_order == 3) c->c2 = (1.0 - 0.5 / p->tau[3]) * (1.0 - 0.5 / p->tau[2]);
       if (p->tau_bulk != 0 && p->tau_bulk != p->tau[2])
         c->c3 = ((1.0 - 1.0 / p->tau_bulk) - (1.0 - 1.0 / p->tau[2])) / c->D;
+      if (p->tau_31 != 0 && p->tau_31 != p->tau[3])
+        c->c4 = ((1.0 - 1.0 / p->tau_31) - (1.0 - 1.0 / p->tau[3])) / 2;
     }
   }
   block_shape(p->nx, c->bx, c->by);
@@ -773,7 +786,7 @@ int lbm_free(lbm_ctx *c) {
 namespace {
 
 constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;  // 2: z-slab population layout
 
 // Everything the dynamics of a context depend on, besides its state and time.
 uint64_t params_hash(const lbm_ctx *c) {
@@ -784,7 +797,8 @@ uint64_t params_hash(const lbm_ctx *c) {
                           p.force_order == 3 ? 3 : 1};
   h = fnv1a(h, ints, sizeof(ints));
   const double reals[] = {p.tau[2], p.tau[3], p.tau[4], p.rho0,
-                          p.tau_bulk == 0 ? p.tau[2] : p.tau_bulk};
+                          p.tau_bulk == 0 ? p.tau[2] : p.tau_bulk,
+                          p.tau_31 == 0 ? p.tau[3] : p.tau_31};
   h = fnv1a(h, reals, sizeof(reals));
   h = fnv1a(h, c->smask_host.data(), c->smask_host.size() * sizeof(uint32_t));
   return fnv1a(h, &c->g_hash, sizeof(c->g_hash));

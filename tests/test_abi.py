@@ -49,6 +49,11 @@ def test_version_and_strerror():
     (dict(collision="rmrt", tau_bulk=1.2), "tau_bulk needs the SMRT"),
     (dict(collision="smrt", tau_bulk=0.5), "must exceed 1/2"),
     (dict(collision="smrt", tau_bulk=float("nan")), "must exceed 1/2"),
+    (dict(lattice="D3Q19", shape=(8, 8, 8), tau_31=0.7), "tau_31 needs the SMRT"),
+    (dict(collision="smrt", tau_31=0.7), "D2Q9 carries no"),
+    (dict(lattice="D3Q19", shape=(8, 8, 8), collision="smrt", tau_31=0.7, force_order=3),
+     "not combined with force_order 3"),
+    (dict(lattice="D3Q27", shape=(8, 8, 8), collision="smrt", tau_31=0.4), "must exceed 1/2"),
 ])
 def test_invalid_parameters_rejected(change, fragment):
     from paper_2212_07494_amd import lbm

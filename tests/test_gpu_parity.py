@@ -137,6 +137,34 @@ def test_bulk_rate_parity(lat, storage):
 
 
 @pytest.mark.parametrize("storage", STORES)
+@pytest.mark.parametrize("lat", ["D3Q19", "D3Q27"])
+def test_split_rates_parity(lat, storage):
+    """SMRT with separate rates for the traces at orders 2 and 3 (tau_bulk, tau_31) and
+    for the third-order trace alone: bit-identical to the oracle; each changes the state."""
+    L = lbm()
+    shape = SHAPES[lat]
+    N = int(np.prod(shape))
+    walls = WALLS[lat][-1]
+    kw, g = _force(lat, shape, "field", seed=10)
+    f0 = _state(lat, storage, N, seed=14)
+    scales = [1.0, 0.5, -2.0]
+    got = {}
+    for tb, t31 in ((0.0, 0.0), (0.0, 0.7), (1.7, 0.7)):
+        o = oracle_for(lat, "smrt", storage, shape, walls, TAU["smrt"], tau_bulk=tb, tau_31=t31)
+        fo = f0.astype(o.dtype)
+        for s in scales:
+            fo = o.step(fo, g, s)
+        with L.Lattice(lat, "smrt", storage, shape, walls, TAU["smrt"], tau_bulk=tb,
+                       tau_31=t31, **kw) as gpu:
+            gpu.set_populations(f0)
+            gpu.step(3, g_scale=scales)
+            got[(tb, t31)] = gpu.populations()
+        assert exact_mismatch(got[(tb, t31)], fo.astype(np.float64)) == 0, (tb, t31)
+    assert exact_mismatch(got[(0.0, 0.7)], got[(0.0, 0.0)]) > 0
+    assert exact_mismatch(got[(1.7, 0.7)], got[(0.0, 0.7)]) > 0
+
+
+@pytest.mark.parametrize("storage", STORES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 @pytest.mark.parametrize("lat", LATS)
 def test_init_and_moments_parity(lat, coll, storage):

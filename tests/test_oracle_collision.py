@@ -295,6 +295,53 @@ def test_bulk_rate_collision_spectrum(L, tau_b):
     assert np.max(np.abs(lam - np.sort(want))) < 1e-8, (lam, sorted(want))
 
 
+def _hermite3(E):
+    """The lattice's third-order Hermite polynomials at c_s^2 = 1/3, written out:
+    H_abb(e) = e_a (e_b^2 - 1/3) for a != b, H_xyz(e) = e_x e_y e_z."""
+    e = np.asarray(E, float)
+    H = {}
+    for a in range(3):
+        for b in range(3):
+            if a != b:
+                H[(a, b)] = e[:, a] * (e[:, b] ** 2 - CS2)
+    H["xyz"] = e[:, 0] * e[:, 1] * e[:, 2]
+    return H
+
+
+@pytest.mark.parametrize("L", ["D3Q19", "D3Q27"])
+@pytest.mark.parametrize("tau_31", [0.6, 1.6])
+def test_third_order_trace_rate(L, tau_31):
+    """eq:domg at order 3 with its own rate for the trace S^(3,1): about rest, for any
+    perturbation, the collision scales each axis's trace pair H_abb + H_acc by
+    1 - 1/tau_31 and the differences H_abb - H_acc and H_xyz by 1 - 1/tau3 (moments taken
+    with the Hermite polynomials written out, not the oracle's tables); the spectrum has
+    exactly three eigenvalues at 1 - 1/tau_31."""
+    tau2, tau3 = 0.8, 1.0
+    o = Oracle(L, "smrt", (1, 1, 1), tau=(tau2, tau3, 1.0), tau_31=tau_31)
+    J = _collision_jacobian(o)
+    H = _hermite3(lat.velocities(L))
+    q3, q31 = 1 - 1 / tau3, 1 - 1 / tau_31
+    rng = np.random.default_rng(4)
+    for _ in range(4):
+        d = rng.standard_normal(o.Q)
+        d2 = J @ d
+        for a in range(3):
+            b, c = (a + 1) % 3, (a + 2) % 3
+            s0 = H[(a, b)] @ d + H[(a, c)] @ d
+            s1 = H[(a, b)] @ d2 + H[(a, c)] @ d2
+            t0 = H[(a, b)] @ d - H[(a, c)] @ d
+            t1 = H[(a, b)] @ d2 - H[(a, c)] @ d2
+            assert abs(s1 - q31 * s0) < 1e-8 and abs(t1 - q3 * t0) < 1e-8, (a, s0, s1, t0, t1)
+        if L == "D3Q27":
+            assert abs(H["xyz"] @ d2 - q3 * (H["xyz"] @ d)) < 1e-8
+    n2 = 6
+    n3 = ORDER3[L]
+    lam = np.sort(np.linalg.eigvals(J).real)
+    want = ([1.0] * 4 + [1 - 1 / tau2] * n2 + [q31] * 3 + [q3] * (n3 - 3)
+            + [0.0] * (o.Q - 4 - n2 - n3))
+    assert np.max(np.abs(lam - np.sort(want))) < 1e-8, (lam, sorted(want))
+
+
 @pytest.mark.parametrize("L", lat.LATTICES)
 @pytest.mark.parametrize("tau_b", [0.0, 0.9, 1.7])
 def test_bulk_rate_sound_attenuation(L, tau_b):

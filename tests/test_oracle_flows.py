@@ -240,6 +240,61 @@ def test_rotation_symmetry(L, coll):
     assert np.allclose(_rotate_xy(u1, shape), u2, rtol=0, atol=1e-14)
 
 
+def _cycle_axes(field3, shape):
+    """Relabel the axes of a (3, N) vector field on an n^3 grid cyclically, x -> y -> z ->
+    x (a 120-degree rotation about (1, 1, 1)): the value at old (x, y, z) moves to new
+    (z, x, y) and (vx, vy, vz) becomes (vz, vx, vy)."""
+    n = shape[0]
+    a = field3.reshape(3, n, n, n)
+    out = np.empty_like(a)
+    for c in range(3):
+        out[(c + 1) % 3] = np.transpose(a[c], (1, 2, 0))
+    return out.reshape(3, -1)
+
+
+def _cycle_scalar(s, shape):
+    n = shape[0]
+    return np.transpose(s.reshape(n, n, n), (1, 2, 0)).reshape(-1)
+
+
+@pytest.mark.parametrize("L", ["D3Q19", "D3Q27"])
+def test_cubic_symmetry_with_split_rates(L):
+    """With separate rates for the trace and traceless parts at orders 2 and 3, the step
+    still commutes with the cube's rotations (the decomposition of eq:domg preserves
+    rotational symmetry): a 90-degree turn about z and the cyclic relabelling of the axes
+    both map the 12-step result onto the result from the rotated inputs."""
+    shape = (6, 6, 6)
+    rho, u, g = inputs.random_fields(shape, seed=22, dim=3, g_amp=1e-3)
+    o = Oracle(L, "smrt", shape, tau=(0.62, 0.85, 1.0), tau_bulk=1.4, tau_31=0.7)
+
+    def run(rho, u, g):
+        f = o.run(o.init(rho, u, g), g, 12)
+        return o.moments(f, g)
+
+    r1, u1 = run(rho, u, g)
+    for rs, rv in ((_rotate_scalar, _rotate_xy), (_cycle_scalar, _cycle_axes)):
+        r2, u2 = run(rs(rho, shape), rv(u, shape), rv(g, shape))
+        assert np.allclose(rs(r1, shape), r2, rtol=0, atol=1e-14)
+        assert np.allclose(rv(u1, shape), u2, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("L", ["D3Q19", "D3Q27"])
+@pytest.mark.parametrize("tau3", [1.0, 0.7])
+def test_channel_3d_equals_2d_closed_form(L, tau3):
+    """A channel that is invariant along z on the 3D lattices (walls in y, g along x) has
+    the exact D2Q9 SMRT profile, slip included, to 1e-12 relative."""
+    ny, g, tau = 32, 1e-6, 0.8
+    o = Oracle(L, "smrt", (2, ny, 2), walls=(0, 1, 0), tau=(tau, tau3, 1.0))
+    gg = np.zeros((3, o.N))
+    gg[0] = g
+    f = o.run(o.init(1.0, None, gg), gg, 45_000)
+    _, u = o.moments(f, gg)
+    ux = u[0].reshape(2, ny, 2)
+    assert np.ptp(ux, axis=(0, 2)).max() == 0.0
+    want = cf.poiseuille_profile(ny, g, tau, tau3)
+    assert np.max(np.abs(ux[0, :, 0] - want)) <= 1e-12 * want.max()
+
+
 # ---- reduced-precision emulation ---------------------------------------------------------
 
 def test_half_rounding_pins():
