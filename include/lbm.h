@@ -132,6 +132,11 @@ typedef struct {
    * (the differences D_abb - D_acc and D_xyz) keeps tau[3].  0 = tau[3].  Not with
    * force_order 3. */
   double tau_31;
+  /* Highest Hermite order carried after the collision.  0 or 4: raw moments above order
+   * 4 are set to zero (the reconstruction sums to order 4, as the paper does).  6 (SMRT on
+   * D3Q27 only): orders 5 and 6 are carried as rho u^m plus the back-shift of the
+   * relaxed central moments, their own central parts trimmed to zero like order 4. */
+  int32_t max_order;
 } lbm_params;
 
 /* Monitor record (binary64, summed on the device in a fixed order).

@@ -35,7 +35,8 @@ def _params_struct(real_t):
                     ("nz", C.c_int32), ("wall", C.c_int32 * 3), ("store16", C.c_int32),
                     ("shift", real_t), ("omega", real_t), ("hforce", real_t),
                     ("q2", real_t), ("q3", real_t), ("fq3", real_t), ("h2", real_t),
-                    ("h3", real_t), ("dqb", real_t), ("dq31", real_t), ("solid", C.c_void_p)]
+                    ("h3", real_t), ("dqb", real_t), ("dq31", real_t), ("max_order", C.c_int32),
+                    ("solid", C.c_void_p)]
     return _Params
 
 
@@ -86,13 +87,15 @@ class Oracle:
     force_order: 1, or 3 for SMRT's third-order force content; solid: N flags of solid
     nodes (halfway bounce-back against them; not stepped; zero moments) or None;
     tau_bulk: SMRT rate of the trace of order 2 (0 = tau2); tau_31: SMRT rate of the trace
-    of order 3 on D3Q19/D3Q27 (0 = tau3).
+    of order 3 on D3Q19/D3Q27 (0 = tau3); max_order: 4 (raw moments above order 4
+    dropped after the collision), or 6 on D3Q27 (orders 5-6 carried, their central
+    parts trimmed).
     """
 
     def __init__(self, lattice: str, collision: str, shape, walls=(0, 0, 0), tau=(0.8, 0.8, 1.0),
                  shift: float = 0.0, real: str = "f64", store16: bool = False,
                  force_order: int = 1, solid=None, tau_bulk: float = 0.0,
-                 tau_31: float = 0.0):
+                 tau_31: float = 0.0, max_order: int = 4):
         self.lattice = lattice
         self.collision = collision.lower()
         nx, ny, nz = (tuple(shape) + (1, 1))[:3]
@@ -128,6 +131,9 @@ class Oracle:
             raise ValueError("tau_31 is for SMRT on D3Q19/D3Q27, without force_order 3, "
                              "and must exceed 1/2")
         dq31 = ((1.0 - 1.0 / tau_31) - (1.0 - 1.0 / tau3)) / 2 if tau_31 and tau_31 != tau3 else 0.0
+        if max_order not in (4, 6) or (max_order == 6 and (self.collision != "smrt"
+                                                            or lattice != "D3Q27")):
+            raise ValueError("max_order is 4, or 6 for SMRT on D3Q27")
         vals = dict(shift=shift, omega=omega, hforce=1.0 - 0.5 * omega,
                     q2=1.0 - 1.0 / tau2, q3=1.0 - 1.0 / tau3, fq3=fq3,
                     h2=1.0 - 0.5 / tau2, h3=1.0 - 0.5 / tau3, dqb=dqb, dq31=dq31)
@@ -136,7 +142,7 @@ class Oracle:
         self._p = P({"bgk": 0, "smrt": 1, "rmrt": 2}[self.collision], nx, ny, nz,
                     (C.c_int32 * 3)(*[int(bool(w)) for w in walls]), int(bool(store16)),
                     *[cast(vals[k]) for k in ("shift", "omega", "hforce", "q2", "q3", "fq3",
-                                              "h2", "h3", "dqb", "dq31")])
+                                              "h2", "h3", "dqb", "dq31")], int(max_order))
         self.solid = None
         if solid is not None:
             self.solid = np.ascontiguousarray(np.asarray(solid).ravel() != 0, dtype=np.uint8)

@@ -67,6 +67,7 @@ typedef struct {
   real h2, h3;         /* RMRT: 1 - omega_n / 2 */
   real dqb;            /* SMRT: (q_bulk - q2)/D for the trace of order 2 (0 = one rate) */
   real dq31;           /* SMRT: (q_31 - q3)/2 for the trace of order 3 (0 = one rate) */
+  int32_t max_order;   /* SMRT: highest Hermite order carried after the collision, 4 or 6 */
   const uint8_t *solid; /* N flags, nonzero = solid node (no fluid); NULL = none */
 } oracle_params;
 
@@ -368,10 +369,12 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
         real h = L->H[k * L->Q + i];
         if (h != 0) A = A + h * f[i];
       }
-      if (n > 4) { /* orders above 4 are not carried: a*_m = 0 */
+      if (n > 4 && P->max_order < n) { /* orders above 4 are not carried: a*_m = 0 */
         dA[k] = -A;
         continue;
       }
+      /* carried orders: equilibrium plus the back-shift of the relaxed central moments,
+       * whose own parts at orders 4 and above are trimmed to zero */
       Nk = A - E[k];
     }
     real R = (n <= 3) ? Pc[k] : (real)-0.0; /* l = 0 term; P_m = 0 for |m| = 4 */

@@ -150,7 +150,9 @@ __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restri
     collide_bgk<L>(d, shift, g, BGKCoef<T>{c0, c1});
   } else {
     if constexpr (COLL == 1)
-      collide_smrt<L>(d, shift, g, SMRTCoef<T>{c0, c1, c2, c3, c4});
+      collide_smrt<L, false>(d, shift, g, SMRTCoef<T>{c0, c1, c2, c3, c4});
+    else if constexpr (COLL == 3)
+      collide_smrt<L, true>(d, shift, g, SMRTCoef<T>{c0, c1, c2, c3, c4});
     else
       collide_rmrt<L>(d, shift, g, RMRTCoef<T>{c0, c1, c2, c3});
   }

@@ -81,6 +81,10 @@ struct Ops {
         return d.gk ? step_t<0, S, T, GK_FIELD>(d, s) : step_t<0, S, T, GK_PROFILE>(d, s);
       if (d.coll == 2)
         return d.gk ? step_t<2, S, T, GK_FIELD>(d, s) : step_t<2, S, T, GK_PROFILE>(d, s);
+      if constexpr (L::ORD[L::NM - 1] > 4) {
+        if (d.coll == 3)
+          return d.gk ? step_t<3, S, T, GK_FIELD>(d, s) : step_t<3, S, T, GK_PROFILE>(d, s);
+      }
       return d.gk ? step_t<1, S, T, GK_FIELD>(d, s) : step_t<1, S, T, GK_PROFILE>(d, s);
     });
   }

@@ -244,7 +244,9 @@ __device__ __forceinline__ void reconstruct(const T (&a)[L::NM], T (&out)[L::Q])
 // R_m - N_m for orders 2..4 and -A_m above.  Equal to MINV a* in real arithmetic; in
 // floating point the conserved moments never pass through the rounded coefficients,
 // so they carry no per-step bias.
-template <class L, class T>
+// HI56: carry the orders above 4 (D3Q27's 5 and 6) as rho u^m + R_m, their central parts
+// trimmed like order 4, instead of dropping them.
+template <class L, bool HI56, class T>
 __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)[3],
                                              const SMRTCoef<T> &c) {
   constexpr int NM = L::NM;
@@ -338,7 +340,18 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
       dA[k] = M.F[a];
     } else if constexpr (n > 4) {
-      dA[k] = -N[k];
+      if constexpr (HI56) {
+        // a*_m = rho u^m + R_m with the central parts of orders >= 4 trimmed
+        T R = T(-0.0);
+        static_for<L::NT[k]>([&](auto Tt) {
+          constexpr int t = decltype(Tt)::value;
+          constexpr int kl = L::TL[k][t], km = L::TM[k][t];
+          if constexpr (L::ORD[km] <= 3) R = R + T(L::CUP[k][t]) * (U[kl] * P[km]);
+        });
+        dA[k] = R - (N[k] - E[k]);
+      } else {
+        dA[k] = -N[k];
+      }
     } else {
       T R = (n <= 3) ? P[k] : T(-0.0);
       static_for<L::NT[k]>([&](auto Tt) {

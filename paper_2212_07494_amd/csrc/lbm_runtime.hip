@@ -153,7 +153,7 @@ struct lbm_ctx {
   }
   lbm::LaunchDesc desc(double gscale) const {
     lbm::LaunchDesc d{};
-    d.coll = p.collision;
+    d.coll = (p.collision == LBM_SMRT && p.max_order == 6) ? 3 : p.collision;
     d.storage = p.storage;
     d.gk = gk;
     d.fin = buf[cur];
@@ -219,6 +219,12 @@ int validate(const lbm_params *p) {
       return fail(LBM_EINVAL, "tau_bulk needs the SMRT collision");
     if (!(p->tau_bulk > 0.5) || !std::isfinite(p->tau_bulk))
       return fail(LBM_EINVAL, "tau_bulk = %g must exceed 1/2 (or be 0)", p->tau_bulk);
+  }
+  if (p->max_order != 0 && p->max_order != 4) {
+    if (p->max_order != 6)
+      return fail(LBM_EINVAL, "max_order = %d: 4 (default) or 6", (int)p->max_order);
+    if (p->collision != LBM_SMRT || p->lattice != LBM_D3Q27)
+      return fail(LBM_EINVAL, "max_order 6 needs SMRT on D3Q27 (the lattice with orders 5-6)");
   }
   if (p->tau_31 != 0) {
     if (p->collision != LBM_SMRT)
@@ -794,7 +800,7 @@ uint64_t params_hash(const lbm_ctx *c) {
   uint64_t h = kFnvBasis;
   const int32_t ints[] = {p.lattice, p.collision, p.storage, p.nx,     p.ny,     p.nz,
                           p.bc[0],   p.bc[1],     p.bc[2],   p.g_kind, p.g_axis,
-                          p.force_order == 3 ? 3 : 1};
+                          p.force_order == 3 ? 3 : 1, p.max_order == 6 ? 6 : 4};
   h = fnv1a(h, ints, sizeof(ints));
   const double reals[] = {p.tau[2], p.tau[3], p.tau[4], p.rho0,
                           p.tau_bulk == 0 ? p.tau[2] : p.tau_bulk,

@@ -48,7 +48,8 @@ class lbm_params(C.Structure):
                 ("g_kind", C.c_int32), ("g_axis", C.c_int32), ("g_uniform", C.c_double * 3),
                 ("g_data", C.c_void_p), ("monitor_every", C.c_int32),
                 ("allocator", C.POINTER(lbm_allocator)), ("force_order", C.c_int32),
-                ("solid", C.c_void_p), ("tau_bulk", C.c_double), ("tau_31", C.c_double)]
+                ("solid", C.c_void_p), ("tau_bulk", C.c_double), ("tau_31", C.c_double),
+                ("max_order", C.c_int32)]
 
 
 class lbm_tuning(C.Structure):
@@ -155,7 +156,7 @@ class TorchAllocator:
 def make_params(lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1), bc=(0, 0, 0),
                 tau=(0.8, 0.8, 1.0), rho0=1.0, g=None, g_profile=None, g_field=None,
                 monitor_every=0, allocator=None, force_order=1, solid=None, tau_bulk=0.0,
-                tau_31=0.0):
+                tau_31=0.0, max_order=4):
     """Fill an lbm_params.  g: uniform (3,) acceleration; g_profile: (axis, (3, n) table);
     g_field: (3, N) array; force_order 1 or 3 (SMRT third-order force content); solid: N
     flags (nonzero = solid node) or None.  Returned together with the arrays it points to
@@ -188,6 +189,7 @@ def make_params(lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1),
     p.force_order = int(force_order)
     p.tau_bulk = float(tau_bulk)
     p.tau_31 = float(tau_31)
+    p.max_order = int(max_order)
     if solid is not None:
         mask = np.ascontiguousarray(np.asarray(solid).ravel() != 0, dtype=np.uint8)
         if mask.size != nx * ny * nz:
@@ -295,7 +297,7 @@ class Lattice:
     def __init__(self, lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1),
                  walls=(0, 0, 0), tau=(0.8, 0.8, 1.0), rho0=1.0, rho=None, u=None, g=None,
                  g_profile=None, g_field=None, monitor_every=0, stream=None, allocator=None,
-                 force_order=1, solid=None, tau_bulk=0.0, tau_31=0.0):
+                 force_order=1, solid=None, tau_bulk=0.0, tau_31=0.0, max_order=4):
         self.lattice = lattice
         self.Q = QOF[lattice]
         self.D = 2 if lattice == "D2Q9" else 3
@@ -306,7 +308,7 @@ class Lattice:
         self._params, self._keep = make_params(lattice, collision, storage, self.shape, walls, tau,
                                                rho0, g, g_profile, g_field, monitor_every,
                                                allocator, force_order, solid, tau_bulk,
-                                               tau_31)
+                                               tau_31, max_order)
         if u is not None:
             u = np.asarray(u, dtype=np.float64)[: self.D]
         self.ctx = lbm_init(self._params, rho, u, stream)

@@ -20,11 +20,12 @@ def gpu_available() -> bool:
 
 
 def oracle_for(lattice, collision, storage, shape, walls, tau, rho0=1.0, force_order=1,
-               tau_bulk=0.0, tau_31=0.0):
+               tau_bulk=0.0, tau_31=0.0, max_order=4):
     real, shifted, s16 = EMUL[storage]
     return Oracle(lattice, collision, shape, walls=walls, tau=tau,
                   shift=rho0 if shifted else 0.0, real=real, store16=s16,
-                  force_order=force_order, tau_bulk=tau_bulk, tau_31=tau_31)
+                  force_order=force_order, tau_bulk=tau_bulk, tau_31=tau_31,
+                  max_order=max_order)
 
 
 def to_storage(x: np.ndarray, storage: str) -> np.ndarray:

@@ -54,6 +54,9 @@ def test_version_and_strerror():
     (dict(lattice="D3Q19", shape=(8, 8, 8), collision="smrt", tau_31=0.7, force_order=3),
      "not combined with force_order 3"),
     (dict(lattice="D3Q27", shape=(8, 8, 8), collision="smrt", tau_31=0.4), "must exceed 1/2"),
+    (dict(lattice="D3Q27", shape=(8, 8, 8), collision="smrt", max_order=5), "4 (default) or 6"),
+    (dict(lattice="D3Q19", shape=(8, 8, 8), collision="smrt", max_order=6), "SMRT on D3Q27"),
+    (dict(lattice="D3Q27", shape=(8, 8, 8), max_order=6), "SMRT on D3Q27"),
 ])
 def test_invalid_parameters_rejected(change, fragment):
     from paper_2212_07494_amd import lbm

@@ -342,6 +342,52 @@ def test_third_order_trace_rate(L, tau_31):
     assert np.max(np.abs(lam - np.sort(want))) < 1e-8, (lam, sorted(want))
 
 
+def _central_hermite(E, f, u, m):
+    """sum_i f_i H_m(e_i - u) with the one-dimensional Hermite polynomials at c_s^2 = 1/3
+    written out (1, x, x^2 - 1/3): the Hermite central moment of f about u."""
+    he = (lambda x: np.ones_like(x), lambda x: x, lambda x: x * x - CS2)
+    h = np.ones(len(E))
+    for a in range(3):
+        h = h * he[m[a]](E[:, a] - u[a])
+    return h @ f
+
+
+@pytest.mark.parametrize("max_order", [4, 6])
+@pytest.mark.parametrize("seed", range(3))
+def test_high_orders_on_d3q27(max_order, seed):
+    """D3Q27 carries Hermite orders up to 6.  After an unforced collision (u = j/rho), the
+    central moments about u of orders 2 and 3 are the relaxed ones (1 - 1/tau_n times the
+    pre-collision value) and order 4 is trimmed to zero.  With max_order 4 the raw moments
+    of orders 5 and 6 are zero (the reconstruction sums to order 4) while their central
+    moments are not; with max_order 6 the central moments of orders 5 and 6 are zero too
+    (trimmed like order 4, Galilean invariant).  All moments are taken with the Hermite
+    polynomials written out, not the oracle's tables."""
+    tau2, tau3 = 0.8, 0.9
+    o = Oracle("D3Q27", "smrt", (1, 1, 1), tau=(tau2, tau3, 1.0), max_order=max_order)
+    E = np.array(lat.velocities("D3Q27"), float)
+    rng = np.random.default_rng(seed)
+    u0 = rng.uniform(-0.08, 0.08, 3)
+    f = o.init_node(1.02, u0, [0, 0, 0]) + 1e-3 * rng.standard_normal(27)
+    rho = f.sum()
+    u = (E.T @ f) / rho
+    fs = o.collide_node(f, [0, 0, 0])
+    assert abs(fs.sum() - rho) < 1e-14 and np.max(np.abs(E.T @ fs - rho * u)) < 1e-15
+    raw = {}
+    for m in itertools.product(range(3), repeat=3):
+        n = sum(m)
+        c_post = _central_hermite(E, fs, u, m)
+        if n in (2, 3):
+            q = 1 - 1 / (tau2 if n == 2 else tau3)
+            assert abs(c_post - q * _central_hermite(E, f, u, m)) < 1e-14, m
+        elif n == 4 or (n > 4 and max_order == 6):
+            assert abs(c_post) < 1e-15, (m, c_post)
+        elif n > 4:
+            raw[m] = (_central_hermite(E, fs, np.zeros(3), m), c_post)
+    if max_order == 4:
+        assert all(abs(r) < 1e-15 for r, _ in raw.values()), raw
+        assert max(abs(c) for _, c in raw.values()) > 1e-8, raw
+
+
 @pytest.mark.parametrize("L", lat.LATTICES)
 @pytest.mark.parametrize("tau_b", [0.0, 0.9, 1.7])
 def test_bulk_rate_sound_attenuation(L, tau_b):
