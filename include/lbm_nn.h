@@ -114,6 +114,23 @@ int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_de
  * base: u_j = s_j ((p_j + c_0..2) sin(theta_j) + c_3..5 cos(theta_j)) and
  * rho_j - rho0 = s_j (c_6 sin(theta_j) + c_7 cos(theta_j)) (the network's output). */
 
+/* Each mode's exact linear steady response on the periodic lattice, as mode_coef
+ * coefficients (host, nmodes x 8, binary64): the steady state of the step linearised
+ * about rest under the forcing g = p_j sin(theta_j), relative to the Stokes amplitude
+ * s_j = 1/(nu K_j^2) per unit amp_j, nu = (tau[2] - 1/2)/3, K_j = 2 pi |k_j| / box.  It
+ * is what mode_coef approaches at small Reynolds numbers, independent of amp_j and
+ * phase_j.  params gives the lattice, collision and rates (with tau_bulk, tau_31,
+ * max_order, force_order) and rho0 (0 = 1); its sizes, storage, boundaries, force and
+ * solid fields are ignored.  Method: the collision's Jacobians in the populations and in
+ * g at rest, by central differences of this library's step on a one-node periodic
+ * lattice in binary64 (there the pull streaming is the identity); then per mode the Q x Q
+ * complex system (I - S J) f = S G g_hat with S = diag(exp(-i kappa . e_i)),
+ * kappa = 2 pi k_j / box, g_hat = -i p_j.  Uses the device (a few tiny contexts).
+ * Errors: LBM_EINVAL (NULL, box < 1, nmodes outside 1..8, k_j = 0, a D2Q9 mode off the
+ * x-y plane, invalid params as for lbm_init, a singular system). */
+int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_problem *p, int32_t box,
+                            double *coef);
+
 #define LBM_WS_MODE_FEATURES 13
 /* Per-mode network inputs (rows nmodes x 13, device, copied before return): the phase
  * advance per lattice link kappa_a = 2 pi k_a / box (3), sin(kappa_a) (3),

@@ -31,13 +31,7 @@ constexpr uint32_t kMagic = 0x4c424231u;  // "LBB1"
 size_t storage_bytes(int s) { return s == LBM_F64 ? 8 : (s == LBM_F16_SHIFTED ? 2 : 4); }
 size_t arith_bytes(int s) { return s == LBM_F64 ? 8 : 4; }
 
-const lbm::LatticeOps &ops_for(int lattice) {
-  switch (lattice) {
-    case LBM_D2Q9: return lbm::ops_d2q9();
-    case LBM_D3Q19: return lbm::ops_d3q19();
-    default: return lbm::ops_d3q27();
-  }
-}
+using lbm::ops_for;
 
 void block_shape(int nx, int &bx, int &by) {
   bx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);

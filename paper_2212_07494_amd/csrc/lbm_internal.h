@@ -59,6 +59,7 @@ struct BatchLaunch {
 
 struct LatticeOps {
   int D, Q;
+  const int *E;  // host: the Q velocities, Q x 3 (x, y, z)
   hipError_t (*step)(const LaunchDesc &, hipStream_t);
   // pi: optional non-equilibrium second moment, 6 binary64 planes (xx, yy, zz, xy, xz, yz)
   hipError_t (*init)(const LaunchDesc &, const double *rho, const double *u, double rho0,
@@ -93,6 +94,15 @@ hipError_t add_domain_steps(const int *active, void *state, int ndom, int64_t n,
 const LatticeOps &ops_d2q9();
 const LatticeOps &ops_d3q19();
 const LatticeOps &ops_d3q27();
+
+// Launcher table of an lbm_lattice value (0 D2Q9, 1 D3Q19, else D3Q27).
+inline const LatticeOps &ops_for(int lattice) {
+  switch (lattice) {
+    case 0: return ops_d2q9();
+    case 1: return ops_d3q19();
+    default: return ops_d3q27();
+  }
+}
 
 // Error reporting shared by the runtime units (lbm_runtime.hip): records the message
 // for lbm_last_error() and returns status.

@@ -208,6 +208,7 @@ struct Ops {
 const LatticeOps &LBM_OPS() {
   static const LatticeOps ops = {LBM_LAT::D,
                                  LBM_LAT::Q,
+                                 &LBM_LAT::E[0][0],
                                  &impl::Ops<LBM_LAT>::step,
                                  &impl::Ops<LBM_LAT>::init,
                                  &impl::Ops<LBM_LAT>::gather,

@@ -68,13 +68,7 @@ constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
 size_t arith_bytes(int s) { return s == LBM_F64 ? 8 : 4; }
 bool shifted(int s) { return s == LBM_F32_SHIFTED || s == LBM_F16_SHIFTED; }
 
-const lbm::LatticeOps &ops_for(int lattice) {
-  switch (lattice) {
-    case LBM_D2Q9: return lbm::ops_d2q9();
-    case LBM_D3Q19: return lbm::ops_d3q19();
-    default: return lbm::ops_d3q27();
-  }
-}
+using lbm::ops_for;
 
 // Block shape: 64-wide rows (one wavefront per row segment), up to 256 threads.
 void block_shape(int nx, int &bx, int &by) {

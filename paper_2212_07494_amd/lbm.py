@@ -559,6 +559,7 @@ EXPORTS_NN = {
     "lbm_ws_features": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                          C.c_double, C.c_void_p, C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "lbm_ws_mode_features": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_ws_lattice_response": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "lbm_upsample_periodic": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "lbm_ws_compose": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
@@ -684,6 +685,20 @@ def lbm_ws_mode_features(problem, box, out_dev, stream=None):
     s = ws_problem_struct(problem)
     _check(load().lbm_ws_mode_features(C.byref(s), int(box), _dptr(out_dev),
                                        _stream_handle(stream)))
+
+
+def lbm_ws_lattice_response(problem, box, lattice="D3Q27", collision="smrt", tau3=1.0,
+                            rho0=1.0, **rates):
+    """Each mode's exact linear steady response on the periodic lattice as mode_coef
+    coefficients (nmodes x 8, binary64, host); rates: tau_bulk, tau_31, max_order,
+    force_order as for make_params."""
+    s = ws_problem_struct(problem)
+    params, keep = make_params(lattice, collision, "f64", (1, 1, 1),
+                               tau=(problem["tau2"], tau3, 1.0), rho0=rho0, **rates)
+    out = np.zeros((int(s.nmodes), 8), np.float64)
+    _check(load().lbm_ws_lattice_response(C.byref(params), C.byref(s), int(box),
+                                          out.ctypes.data))
+    return out
 
 
 def _optr(t):

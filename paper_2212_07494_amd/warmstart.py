@@ -93,10 +93,13 @@ class WarmStart:
     FLAGS = L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM | L.RESET_NONEQ
 
     def __init__(self, box=128, widths=WIDTHS, seed=0, max_rows=4096, stream=None,
-                 base_order=BASE_ORDER, flags=None):
+                 base_order=BASE_ORDER, flags=None, linear=False):
         import torch
         self.torch = torch
         self.box = box
+        # linear: add each mode's exact linear lattice response (lbm_ws_lattice_response)
+        # to the correction; the network then predicts only what that misses
+        self.linear = linear
         self.widths = list(widths)
         self.stream = stream
         self.base_order = base_order
@@ -130,6 +133,10 @@ class WarmStart:
         L.lbm_ws_mode_features(problem, self.box, out, stream=self.stream)
         return out
 
+    def lattice_response(self, problem):
+        """Each mode's exact linear lattice response (nmodes x 8) as mode coefficients."""
+        return L.lbm_ws_lattice_response(problem, self.box, tau3=TAU3)
+
     def mode_targets(self, problem, rho, u):
         """The 8 coefficients per mode that make the base's own mode responses match a
         converged lattice state (rho, u on the box^3 lattice): projections on
@@ -155,6 +162,8 @@ class WarmStart:
             out[j, 3:6] = pc[:3] / a
             out[j, 6] = ps[3] / a
             out[j, 7] = pc[3] / a
+        if self.linear:
+            out -= self.lattice_response(problem)
         return out.astype(np.float32)
 
     def dataset(self, problems, fields, fit_scale=False):
@@ -237,10 +246,14 @@ class WarmStart:
         """Start fields (box^3 x 4 rows, device: u / U, (rho - 1) / U) and U."""
         torch = self.torch
         x = self.mode_features(problem)
-        self.net.forward(x, self.y[:NMODES])
+        coef = self.y[:NMODES]
+        self.net.forward(x, coef)
+        if self.linear:
+            c = coef.cpu().numpy().astype(np.float64) + self.lattice_response(problem)
+            coef = torch.from_numpy(c.astype(np.float32)).cuda()
         rows = torch.empty((self.box ** 3, 4), device="cuda")
         U = L.lbm_ws_features(problem, self.box, self.box, None, rows, self.base_order, 1.0,
-                              mode_coef=self.y[:NMODES], stream=self.stream)
+                              mode_coef=coef, stream=self.stream)
         return rows, U
 
     def start(self, lattice, problem):
@@ -254,7 +267,8 @@ class WarmStart:
         np.save(path + ".npy", self.net.params())
         with open(path + ".json", "w") as fh:
             json.dump(dict(widths=self.widths, box=self.box, base_order=self.base_order,
-                           flags=self.flags, scale=self.scale.tolist()), fh)
+                           flags=self.flags, linear=self.linear,
+                           scale=self.scale.tolist()), fh)
 
     def load(self, path):
         with open(path + ".json") as fh:
@@ -263,6 +277,7 @@ class WarmStart:
             raise ValueError(f"saved widths {meta['widths']} differ from {self.widths}")
         self.base_order = meta["base_order"]
         self.flags = meta["flags"]
+        self.linear = bool(meta.get("linear", False))
         self.set_scale(meta["scale"])
         self.net.set_params(np.load(path + ".npy", allow_pickle=False))
 

@@ -141,3 +141,20 @@ def test_checkpoint_calls_validate_arguments(tmp_path):
     lib = lbm.load()
     assert lib.lbm_save(None, str(tmp_path / "x").encode()) == lbm.LBM_ESTATE
     assert lib.lbm_load(None, str(tmp_path / "x").encode()) == lbm.LBM_ESTATE
+
+
+def test_lattice_response_rejects_bad_arguments():
+    """lbm_ws_lattice_response validates its arguments before creating any context."""
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    params, keep = lbm.make_params("D3Q27", "smrt", "f64", (1, 1, 1), tau=(0.8, 1.0, 1.0))
+    prob = lbm.ws_problem_struct(dict(tau2=0.8, modes=[]))
+    out = np.zeros(64)
+    assert lib.lbm_ws_lattice_response(None, C.byref(prob), 32, out.ctypes.data) == lbm.LBM_EINVAL
+    assert lib.lbm_ws_lattice_response(C.byref(params), C.byref(prob), 32,
+                                       out.ctypes.data) == lbm.LBM_EINVAL  # no modes
+    assert b"nmodes" in lib.lbm_last_error()
+    prob1 = lbm.ws_problem_struct(dict(tau2=0.8, modes=[dict(k=[1, 0, 0], p=[0, 1, 0],
+                                                              amp=1e-6, phase=0.0)]))
+    assert lib.lbm_ws_lattice_response(C.byref(params), C.byref(prob1), 0,
+                                       out.ctypes.data) == lbm.LBM_EINVAL  # box < 1

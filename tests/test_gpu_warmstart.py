@@ -92,3 +92,60 @@ def test_warm_start_beats_plain_start():
     finally:
         ws.close()
         base.close()
+
+
+def test_lattice_response_is_the_small_amplitude_steady_state():
+    """lbm_ws_lattice_response (the step linearised about rest, one Q x Q complex solve
+    per mode) against the converged lattice itself: at 1% of the family's forcing the
+    per-mode coefficients projected from the steady state equal the computed response to
+    1e-6 (they are 1e-2 to 1e-1)."""
+    import copy
+    from paper_2212_07494_amd import lbm as L
+    from paper_2212_07494_amd import warmstart as W
+    L.load()
+    probs = []
+    for i in range(3):
+        p = copy.deepcopy(inputs.warmstart_problem(600 + i, box=BOX))
+        for m in p["modes"]:
+            m["amp"] *= 0.01
+        if W.separable(p):
+            probs.append(p)
+    steps, resid, status, fields = W.solve_batch(probs, BOX, 1e-13, 800_000)
+    assert np.all((status == L.DOM_CONVERGED) | (status == L.DOM_FLOOR)), (status, resid)
+    ws = W.WarmStart(box=BOX, seed=1)
+    try:
+        for p, (rho, u) in zip(probs, fields):
+            t = ws.mode_targets(p, rho, u).astype(np.float64)
+            lin = ws.lattice_response(p)
+            assert np.abs(t).max() > 1e-2
+            assert np.abs(t - lin).max() < 1e-6, (t, lin)
+    finally:
+        ws.close()
+
+
+def test_linear_response_start_beats_base_start():
+    """The start with each mode's exact lattice response and the non-equilibrium stress
+    needs fewer steps than the analytic base alone, and ends at the plain start's steady
+    state."""
+    from paper_2212_07494_amd import lbm as L
+    from paper_2212_07494_amd import warmstart as W
+    L.load()
+    probs = [p for p in (inputs.warmstart_problem(700 + i, box=BOX) for i in range(6))
+             if W.separable(p)]
+    lin = W.WarmStart(box=BOX, seed=1, linear=True)
+    base = W.WarmStart(box=BOX, seed=1, flags=L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM)
+    try:
+        s_lin, s_base, s_plain = 0, 0, 0
+        for p in probs:
+            r = W.compare_starts(lin, p, BOX, 1e-8, check_every=50)
+            rb = W.compare_starts(base, p, BOX, 1e-8, check_every=50, plain=r["plain"],
+                                  reference_u=r["reference_u"])
+            assert r["warm"]["final_err"] < 1e-5 and rb["warm"]["final_err"] < 1e-5
+            s_lin += r["warm"]["steps"]
+            s_base += rb["warm"]["steps"]
+            s_plain += r["plain"]["steps"]
+        print("steps: plain", s_plain, "base", s_base, "linear response", s_lin)
+        assert s_lin < 0.8 * s_base, (s_lin, s_base)
+    finally:
+        lin.close()
+        base.close()
