@@ -1,9 +1,9 @@
 // Kernels of the batched engine: many independent domains, one persistent launch per
 // step.
 //
-// Layout: the domains' population planes are packed one domain after another in each
-// of the two population buffers (domain d occupies Q planes of N_d values starting at
-// element base_d); velocities recorded for the residual are packed the same way (D
+// Layout: the domains' populations are packed one domain after another in each of the
+// two population buffers (domain d occupies Q N_d values starting at element base_d, in
+// the single-lattice layout of pop_slot); velocities recorded for the residual are packed the same way (D
 // planes per domain); force tables / fields are packed into one table buffer.
 //
 // Work decomposition: a flattened table of tiles, each tile = one 256-thread workgroup

@@ -1,13 +1,13 @@
 // Kernels of the forced lattice-Boltzmann library (gfx950).
 //
-// Memory layout in HBM: structure of arrays, one plane of N values per population
-// (population-major, node index n = (z ny + y) nx + x, x fastest).  Two such buffers
-// alternate between steps.  The buffer a step writes holds, at slot (i, x), the
-// post-collision population f*_i(x, t); the next step pulls slot (i, x - e_i) into node
-// x (or, when x - e_i lies beyond a wall, slot (opp(i), x): halfway bounce-back).
-// Reads of each population plane are therefore row-contiguous with a one-element
-// x offset, writes are aligned and contiguous: every wavefront moves 64 consecutive
-// values per plane in each direction.
+// Memory layout in HBM: one slab per z layer, each holding that layer's Q population
+// planes of nx ny values back to back (pop_slot; node index n = (z ny + y) nx + x,
+// x fastest).  Two such buffers alternate between steps.  The buffer a step writes
+// holds, at slot (i, x), the post-collision population f*_i(x, t); the next step pulls
+// slot (i, x - e_i) into node x (or, when x - e_i lies beyond a wall or is solid, slot
+// (opp(i), x): halfway bounce-back).  Reads of each population plane are therefore
+// row-contiguous with a one-element x offset, writes are aligned and contiguous: every
+// wavefront moves 64 consecutive values per plane in each direction.
 //
 // A thread owns one node.  Blocks tile (x, y) rows with blockDim = (bx, by), one z
 // slice per blockIdx.z.  Each node is read and written once per step and no value is

@@ -149,3 +149,27 @@ def test_linear_response_start_beats_base_start():
     finally:
         lin.close()
         base.close()
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19", "D3Q27"])
+@pytest.mark.parametrize("coll,tau2,tau3", [("smrt", 0.6, 1.0), ("smrt", 0.9, 0.7),
+                                            ("bgk", 0.7, 0.7)])
+def test_lattice_response_equals_kolmogorov_closed_form(lattice, coll, tau2, tau3):
+    """For a shear wave g_x = sin(k y) the linear response is the exact discrete
+    Kolmogorov amplitude U of the odd-sector closed form (which the oracle pins):
+    coefficient 0 is U/s - 1 with s = 1/(nu k^2), every other coefficient vanishes."""
+    import math
+    from oracle import closed_forms as cf
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    box = 64
+    for ky in (1, 3):
+        prob = dict(tau2=tau2, modes=[dict(k=[0, ky, 0], p=[1.0, 0.0, 0.0], amp=1e-6,
+                                           phase=0.3)])
+        c = L.lbm_ws_lattice_response(prob, box, lattice=lattice, collision=coll, tau3=tau3)
+        k = 2 * math.pi * ky / box
+        U = (cf.kolmogorov_amplitude(1.0, k, tau2, tau3) if coll == "smrt"
+             else cf.kolmogorov_amplitude_bgk(1.0, k, tau2))
+        s = 1.0 / ((tau2 - 0.5) / 3 * k * k)
+        assert abs(c[0, 0] - (U / s - 1)) < 1e-7 * abs(U / s), (c[0], U / s - 1)
+        assert np.max(np.abs(c[0, 1:])) < 1e-8, c[0]
