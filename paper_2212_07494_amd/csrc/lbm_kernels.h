@@ -84,6 +84,42 @@ __device__ __forceinline__ int64_t pop_slot(int i, int x, int y, int z, const Ge
   return ((int64_t)z * L::Q + i) * ((int64_t)G.nx * G.ny) + (y * G.nx + x);
 }
 
+// Start of population i's plane in layer z.  z comes from blockIdx.z, so the address is
+// the same across the workgroup and lives in scalar registers.
+template <class L, class S>
+__device__ __forceinline__ S *plane_ptr(S *f, int i, int z, const Geom &G) {
+  return f + ((int64_t)z * L::Q + i) * ((int64_t)G.nx * G.ny);
+}
+
+// Element o of a plane through a 32-bit byte offset (the scalar-base + vector-offset
+// form of the memory instructions); needs nx ny sizeof(S) < 2^32 (fast_layout).
+template <class S>
+__device__ __forceinline__ S *at_offset(S *plane, uint32_t o) {
+  using B = std::conditional_t<std::is_const_v<S>, const char, char>;
+  return reinterpret_cast<S *>(reinterpret_cast<B *>(plane) + o * (uint32_t)sizeof(S));
+}
+
+// Whether every pull of the lattice wraps periodically (no wall face, no solid node) and
+// a plane's bytes fit 32 bits: then pulls need no bounce-back test and address through
+// at_offset.
+template <class S>
+__device__ __forceinline__ bool fast_layout(const Geom &G) {
+  return (G.wall[0] | G.wall[1] | G.wall[2]) == 0 && G.smask == nullptr &&
+         (uint64_t)G.nx * G.ny * sizeof(S) < (1ull << 32);
+}
+
+// The periodic pull of population i (fast_layout lattices): (i, x - e_i) wrapped.
+template <class L, int i, class S>
+__device__ __forceinline__ const S *pull_ptr_periodic(const S *f, int x, int y, int z,
+                                                      const Geom &G) {
+  constexpr int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
+  int xs = x - ex, ys = y - ey, zs = z - ez;
+  if constexpr (ex != 0) xs = (xs < 0) ? xs + G.nx : ((xs >= G.nx) ? xs - G.nx : xs);
+  if constexpr (ey != 0) ys = (ys < 0) ? ys + G.ny : ((ys >= G.ny) ? ys - G.ny : ys);
+  if constexpr (ez != 0) zs = (zs < 0) ? zs + G.nz : ((zs >= G.nz) ? zs - G.nz : zs);
+  return at_offset(plane_ptr<L>(f, i, zs, G), (uint32_t)(ys * G.nx + xs));
+}
+
 // Slot that node (x, y, z) pulls population i from: (i, x - e_i) with periodic wrap,
 // or (opp(i), x) when x - e_i crosses a wall face or is a solid node (halfway
 // bounce-back); sm is the node's solid mask word.
@@ -142,10 +178,18 @@ __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restri
                                           uint32_t sm, const T (&g)[3], T shift, T c0, T c1,
                                           T c2 = T(0), T c3 = T(0), T c4 = T(0)) {
   T d[L::Q];
-  static_for<L::Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, geo, sm));
-  });
+  const bool fast = fast_layout<S>(geo);
+  if (fast) {
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      d[i] = load_v<MEM, S, T>(pull_ptr_periodic<L, i>(fin, x, y, z, geo));
+    });
+  } else {
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      d[i] = load_v<MEM, S, T>(fin + pull_slot<L, i>(x, y, z, geo, sm));
+    });
+  }
   if constexpr (COLL == 0) {
     collide_bgk<L>(d, shift, g, BGKCoef<T>{c0, c1});
   } else {
@@ -156,10 +200,18 @@ __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restri
     else
       collide_rmrt<L>(d, shift, g, RMRTCoef<T>{c0, c1, c2, c3});
   }
-  static_for<L::Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    store_v<MEM, S, T>(fout + pop_slot<L>(i, x, y, z, geo), d[i]);
-  });
+  if (fast) {
+    const uint32_t o = (uint32_t)(y * geo.nx + x);
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      store_v<MEM, S, T>(at_offset(plane_ptr<L>(fout, i, z, geo), o), d[i]);
+    });
+  } else {
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      store_v<MEM, S, T>(fout + pop_slot<L>(i, x, y, z, geo), d[i]);
+    });
+  }
 }
 
 template <class L, int COLL, class S, class T, int GK, int MEM>
