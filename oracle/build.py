@@ -4,8 +4,9 @@ Two builds of lbm_oracle.c:
   liboracle_f64.so  REAL = double  (the FP64 reference)
   liboracle_f32.so  REAL = float   (emulation of the reduced-precision storage modes)
 
-Flags: -O2 -ffp-contract=off (no fused multiply-add, so every product and sum is
-rounded as written), no fast-math, OpenMP over the outermost lattice axis (each
+Flags: -O2 -ffp-contract=off (no fused multiply-add the source does not write, so
+every product and sum is rounded as written; the SMRT moment transforms call fma
+explicitly), no fast-math, OpenMP over the outermost lattice axis (each
 node's arithmetic is independent of the thread count).
 """
 from __future__ import annotations

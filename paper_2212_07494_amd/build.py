@@ -3,9 +3,10 @@
 Steps: regenerate the constant tables (csrc/gen_tables.py), compile every csrc/*.hip
 unit with hipcc in parallel, link the shared library next to this file.
 
-Device flags: -O3, -ffp-contract=off (no fused multiply-add anywhere, so binary64
-results follow the written operation order exactly), packed FP32 instructions
-disabled, C++20 (compile-time loops).
+Device flags: -O3, -ffp-contract=off (no fused multiply-add the source does not write,
+so results follow the written operation order exactly; the SMRT moment transforms
+call fma explicitly, as the oracle does), packed FP32 instructions disabled, C++20
+(compile-time loops).
 """
 from __future__ import annotations
 

@@ -122,6 +122,11 @@ struct SMRTCoef {
   T dq31;
 };
 
+// a * b + c rounded once (fused multiply-add).  The SMRT collision accumulates its moment
+// transforms with it, in the same places as the oracle.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Whether MI[k] is a diagonal second-order index (2 e_a).
 template <class L>
 constexpr bool is_diag2(int k) {
@@ -136,7 +141,7 @@ __device__ __forceinline__ T central(const T (&U)[L::NM], const T (&N)[L::NM]) {
   static_for<L::NT[K]>([&](auto Tt) {
     constexpr int t = decltype(Tt)::value;
     constexpr int kl = L::TL[K][t], km = L::TM[K][t];
-    Dm = Dm + T(L::CDN[K][t]) * (U[kl] * N[km]);
+    Dm = fmadd(T(L::CDN[K][t]), U[kl] * N[km], Dm);
   });
   return Dm;
 }
@@ -268,7 +273,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr T h = Tab<L, T>::h(k, i);
-        if constexpr (h != T(0)) acc = acc + h * d[i];
+        if constexpr (h != T(0)) acc = fmadd(h, d[i], acc);
       });
       // orders 2..4: non-equilibrium part; above 4: the raw moment itself
       if constexpr (n <= 4)
@@ -346,7 +351,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
         static_for<L::NT[k]>([&](auto Tt) {
           constexpr int t = decltype(Tt)::value;
           constexpr int kl = L::TL[k][t], km = L::TM[k][t];
-          if constexpr (L::ORD[km] <= 3) R = R + T(L::CUP[k][t]) * (U[kl] * P[km]);
+          if constexpr (L::ORD[km] <= 3) R = fmadd(T(L::CUP[k][t]), U[kl] * P[km], R);
         });
         dA[k] = R - (N[k] - E[k]);
       } else {
@@ -357,7 +362,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       static_for<L::NT[k]>([&](auto Tt) {
         constexpr int t = decltype(Tt)::value;
         constexpr int kl = L::TL[k][t], km = L::TM[k][t];
-        if constexpr (L::ORD[km] <= 3) R = R + T(L::CUP[k][t]) * (U[kl] * P[km]);
+        if constexpr (L::ORD[km] <= 3) R = fmadd(T(L::CUP[k][t]), U[kl] * P[km], R);
       });
       dA[k] = R - N[k];
     }
@@ -368,7 +373,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
     static_for<NM>([&](auto K) {
       constexpr int k = decltype(K)::value;
       constexpr T cf = Tab<L, T>::minv(i, k);
-      if constexpr (k > 0 && cf != T(0)) acc = acc + cf * dA[k];
+      if constexpr (k > 0 && cf != T(0)) acc = fmadd(cf, dA[k], acc);
     });
     d[i] = d[i] + acc;
   });
