@@ -30,7 +30,9 @@
  * is exactly zero.  Products of velocity components are formed left to right
  * over x, y, z.  Constants are exact rationals rounded once.  The SMRT
  * projection, central shift, back-shift and reconstruction accumulate each term
- * with one fused multiply-add (fmar); nothing else is fused.  Compiled with
+ * with one fused multiply-add (fmar); in the shifts the binomial coefficient (a
+ * power of two on these lattices, so exactly) scales u^l first.  Nothing else is
+ * fused.  Compiled with
  * -ffp-contract=off, no fast-math.
  */
 #include <math.h>
@@ -298,7 +300,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
     } else if (n == 2 || n == 3) {
       real D = N[k]; /* l = 0 term; l = m multiplies N_0 = 0 */
       for (int t = 0; t < S->n[k]; ++t)
-        D = fmar((real)S->cdown[k][t], U[S->kl[k][t]] * N[S->km[k][t]], D);
+        D = fmar((real)S->cdown[k][t] * U[S->kl[k][t]], N[S->km[k][t]], D);
       if (n == 2) D2[k] = D;
       if (n == 3) D3[k] = D;
       Pc[k] = (n == 2 ? P->q2 : P->q3) * D;
@@ -391,7 +393,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
     for (int t = 0; t < S->n[k]; ++t) {
       int km = S->km[k][t];
       if (mabs(L->mi + 3 * km) > 3) continue; /* P = 0 at order 4 */
-      R = fmar((real)S->cup[k][t], U[S->kl[k][t]] * Pc[km], R);
+      R = fmar((real)S->cup[k][t] * U[S->kl[k][t]], Pc[km], R);
     }
     /* a*_m - a_m = (rho u^m + R_m) - (rho u^m + N_m) */
     dA[k] = R - Nk;

@@ -127,6 +127,13 @@ struct SMRTCoef {
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Whether c is +-2^n: then c u^l is exact, and c u^l N rounds once inside an fma.  The
+// shift coefficients C(m,l) are products of binomials C(m_a, l_a) with m_a <= 2.
+constexpr bool pow2_coef(int c) {
+  const int a = c < 0 ? -c : c;
+  return a > 0 && (a & (a - 1)) == 0;
+}
+
 // Whether MI[k] is a diagonal second-order index (2 e_a).
 template <class L>
 constexpr bool is_diag2(int k) {
@@ -141,7 +148,8 @@ __device__ __forceinline__ T central(const T (&U)[L::NM], const T (&N)[L::NM]) {
   static_for<L::NT[K]>([&](auto Tt) {
     constexpr int t = decltype(Tt)::value;
     constexpr int kl = L::TL[K][t], km = L::TM[K][t];
-    Dm = fmadd(T(L::CDN[K][t]), U[kl] * N[km], Dm);
+    static_assert(pow2_coef(L::CDN[K][t]));
+    Dm = fmadd(T(L::CDN[K][t]) * U[kl], N[km], Dm);
   });
   return Dm;
 }
@@ -351,7 +359,8 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
         static_for<L::NT[k]>([&](auto Tt) {
           constexpr int t = decltype(Tt)::value;
           constexpr int kl = L::TL[k][t], km = L::TM[k][t];
-          if constexpr (L::ORD[km] <= 3) R = fmadd(T(L::CUP[k][t]), U[kl] * P[km], R);
+          static_assert(pow2_coef(L::CUP[k][t]));
+          if constexpr (L::ORD[km] <= 3) R = fmadd(T(L::CUP[k][t]) * U[kl], P[km], R);
         });
         dA[k] = R - (N[k] - E[k]);
       } else {
@@ -362,7 +371,8 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       static_for<L::NT[k]>([&](auto Tt) {
         constexpr int t = decltype(Tt)::value;
         constexpr int kl = L::TL[k][t], km = L::TM[k][t];
-        if constexpr (L::ORD[km] <= 3) R = fmadd(T(L::CUP[k][t]), U[kl] * P[km], R);
+        static_assert(pow2_coef(L::CUP[k][t]));
+        if constexpr (L::ORD[km] <= 3) R = fmadd(T(L::CUP[k][t]) * U[kl], P[km], R);
       });
       dA[k] = R - N[k];
     }
