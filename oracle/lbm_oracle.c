@@ -28,7 +28,7 @@
  * so an empty sum is -0 and a one-term sum is that term exactly), adds its
  * terms in the stated index order, and skips terms whose constant coefficient
  * is exactly zero.  Products of velocity components are formed left to right
- * over x, y, z.  Constants are exact rationals rounded once.  The SMRT
+ * over x, y, z.  Constants are exact rationals rounded once.  The SMRT and RMRT
  * projection, central shift, back-shift and reconstruction accumulate each term
  * with one fused multiply-add (fmar); in the shifts the binomial coefficient (a
  * power of two on these lattices, so exactly) scales u^l first.  Nothing else is
@@ -442,7 +442,7 @@ static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const 
     real A = -0.0;
     for (int i = 0; i < L->Q; ++i) {
       real h = L->H[k * L->Q + i];
-      if (h != 0) A = A + h * f[i];
+      if (h != 0) A = fmar(h, f[i], A);
     }
     if (n > 4) {
       dA[k] = -A;
@@ -472,7 +472,7 @@ static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const 
     real acc = -0.0;
     for (int k = 1; k < NM; ++k) {
       real c = L->Minv[i * NM + k];
-      if (c != 0) acc = acc + c * dA[k];
+      if (c != 0) acc = fmar(c, dA[k], acc);
     }
     out[i] = f[i] + acc;
   }

@@ -11,7 +11,9 @@
 //   * each sum starts from -0.0 (the additive identity) and adds its non-zero terms
 //     in index order;
 //   * products of velocity components are formed left to right over x, y, z;
-//   * constants are exact rationals rounded once; no fused multiply-add (the
+//   * constants are exact rationals rounded once;
+//   * the MRT moment transforms (projection, shifts, reconstruction) add each term
+//     with one explicit fused multiply-add (fmadd); nothing else is fused (the
 //     library is compiled with -ffp-contract=off).
 // With T = double this reproduces an FP64 implementation written in that order
 // bit for bit.
@@ -122,7 +124,7 @@ struct SMRTCoef {
   T dq31;
 };
 
-// a * b + c rounded once (fused multiply-add).  The SMRT collision accumulates its moment
+// a * b + c rounded once (fused multiply-add).  The MRT collisions accumulate their moment
 // transforms with it, in the same places as the oracle.
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -425,7 +427,7 @@ __device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)
       static_for<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr T h = Tab<L, T>::h(k, i);
-        if constexpr (h != T(0)) acc = acc + h * d[i];
+        if constexpr (h != T(0)) acc = fmadd(h, d[i], acc);
       });
       if constexpr (n > 4) {
         dA[k] = -acc;
@@ -457,7 +459,7 @@ __device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)
     static_for<NM>([&](auto K) {
       constexpr int k = decltype(K)::value;
       constexpr T cf = Tab<L, T>::minv(i, k);
-      if constexpr (k > 0 && cf != T(0)) acc = acc + cf * dA[k];
+      if constexpr (k > 0 && cf != T(0)) acc = fmadd(cf, dA[k], acc);
     });
     d[i] = d[i] + acc;
   });
