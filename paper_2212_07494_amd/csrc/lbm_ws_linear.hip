@@ -5,7 +5,6 @@
 // each mode is then one Q x Q complex solve.
 #include <cmath>
 #include <complex>
-#include <cstring>
 #include <vector>
 
 #include "lbm.h"
@@ -44,12 +43,11 @@ bool solve_complex(int n, std::vector<cplx> &A, std::vector<cplx> &b) {
 
 // One collision of the populations f (Q values) with uniform acceleration g_scale * g of
 // the context: set, step once, read back.
-int collide_once(lbm_ctx *c, int Q, const std::vector<double> &f, double g_scale,
+int collide_once(lbm_ctx *c, const std::vector<double> &f, double g_scale,
                  std::vector<double> &out) {
   int rc = lbm_set_populations(c, f.data());
   if (!rc) rc = lbm_step(c, 1, &g_scale);
   if (!rc) rc = lbm_get_populations(c, 1, nullptr, out.data());
-  (void)Q;
   return rc;
 }
 
@@ -85,8 +83,6 @@ extern "C" int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_pr
   if (rc) return rc;
   const int Q = lbm::ops_for(q.lattice).Q;
   const int D = lbm::ops_for(q.lattice).D;
-  if (D == 2 && (p->k[0][2] != 0 || p->p[0][2] != 0))
-    return set_error(LBM_EINVAL, "a D2Q9 mode must lie in the x-y plane");
   std::vector<double> f0(Q), fp(Q), fm(Q), cp(Q), cm(Q);
   if ((rc = lbm_get_populations(c0.c, 1, nullptr, f0.data()))) return rc;
 
@@ -98,7 +94,7 @@ extern "C" int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_pr
     fm = f0;
     fp[col] += h;
     fm[col] -= h;
-    if ((rc = collide_once(c0.c, Q, fp, 0.0, cp)) || (rc = collide_once(c0.c, Q, fm, 0.0, cm)))
+    if ((rc = collide_once(c0.c, fp, 0.0, cp)) || (rc = collide_once(c0.c, fm, 0.0, cm)))
       return rc;
     for (int i = 0; i < Q; ++i) J[(size_t)i * Q + col] = (cp[i] - cm[i]) / (2 * h);
   }
@@ -107,7 +103,7 @@ extern "C" int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_pr
     qa.g_uniform[a] = h;
     CtxGuard ca;
     if ((rc = lbm_init(&qa, nullptr, nullptr, nullptr, &ca.c))) return rc;
-    if ((rc = collide_once(ca.c, Q, f0, 1.0, cp)) || (rc = collide_once(ca.c, Q, f0, -1.0, cm)))
+    if ((rc = collide_once(ca.c, f0, 1.0, cp)) || (rc = collide_once(ca.c, f0, -1.0, cm)))
       return rc;
     for (int i = 0; i < Q; ++i) G[(size_t)i * 3 + a] = (cp[i] - cm[i]) / (2 * h);
   }
@@ -120,6 +116,8 @@ extern "C" int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_pr
     const double *pol = p->p[j];
     const double K = two_pi * std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]) / box;
     if (K == 0) return set_error(LBM_EINVAL, "mode %d has k = 0", j);
+    if (D == 2 && (k[2] != 0 || pol[2] != 0))
+      return set_error(LBM_EINVAL, "mode %d: a D2Q9 mode must lie in the x-y plane", j);
     // g = p sin(theta) = Re[(-i p) e^{i theta}]; the state's perturbation is
     // Re[fhat e^{i theta}] with fhat = S (J fhat + G ghat), S_i = e^{-i kappa . e_i}
     std::vector<cplx> A((size_t)Q * Q), b(Q);
