@@ -206,7 +206,8 @@ def main():
             "measured_copy_GBps": None if copy_gbps is None else round(copy_gbps, 1),
             "copy_probe": copy_cfg,
             "launch": {"block": [tuning[0], tuning[1]],
-                       "memory_variant": ["plain", "nt-store", "nt-load+store"][tuning[2]]},
+                       "memory_variant": ["plain", "nt-store", "nt-load+store"][tuning[2] % 3],
+                       "addressing": "scalar-base" if tuning[2] >= 3 else "general"},
             "frac_of_copy": None if copy_gbps is None else round(achieved / copy_gbps, 4)}
     dtype = {"f64": "f64", "f32": "f32", "f32s": "f32", "f16s": "f32"}[args.storage]
     rec = {

@@ -211,9 +211,11 @@ int lbm_save(lbm_ctx *c, const char *path);
 int lbm_load(lbm_ctx *c, const char *path);
 
 /* Launch configuration of the step kernel: block shape bx x by (bx in {64, 128, 256},
- * bx * by <= 256) and memory-access variant (0 plain loads and stores, 1 non-temporal
- * stores, 2 non-temporal loads and stores).  Results are identical for every
- * configuration; only the speed differs. */
+ * bx * by <= 256) and variant 0..5: memory access variant % 3 (0 plain loads and
+ * stores, 1 non-temporal stores, 2 non-temporal loads and stores); variants 3..5 also
+ * let workgroups that cannot bounce back (no solid nodes, away from wall faces) address
+ * each population plane through a scalar base and 32-bit offsets.  Results are
+ * identical for every configuration; only the speed differs. */
 typedef struct {
   int32_t bx, by;
   int32_t variant;

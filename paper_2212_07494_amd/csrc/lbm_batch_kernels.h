@@ -74,8 +74,10 @@ __global__ void __launch_bounds__(256)
     const int node = (z * dm.ny + y) * dm.nx + x;
     T g[3];
     batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);
-    step_node<L, COLL, S, T, MEM>(fin + dm.base, fout + dm.base, geo, x, y, z, node, 0u, g,
-                                  shift, T(dm.c0), T(dm.c1));
+    const bool fast = fast_block<S>(geo, tile.x0, tile.x0 + (1 << dm.tbx_log2) - 1, tile.y0,
+                                    tile.y0 + (256 >> dm.tbx_log2) - 1, z);
+    step_node<L, COLL, S, T, MEM>(fin + dm.base, fout + dm.base, geo, x, y, z, node, 0u, fast,
+                                  g, shift, T(dm.c0), T(dm.c1));
   }
 }
 

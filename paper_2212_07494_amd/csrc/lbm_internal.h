@@ -38,6 +38,7 @@ struct LaunchDesc {
   double c4;         // SMRT: (q_31 - q3)/2 for the third-order trace pairs (0 = one rate)
   int bx, by;        // block shape (bx * by <= 256, bx a multiple of 64)
   int variant;       // memory-access variant of the step kernel (MEM_*)
+  int fast_ok;       // 1: blocks that cannot bounce back may take the scalar-base path
 };
 
 // One launch of the batched engine's persistent kernels.

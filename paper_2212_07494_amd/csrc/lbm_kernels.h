@@ -92,23 +92,29 @@ __device__ __forceinline__ S *plane_ptr(S *f, int i, int z, const Geom &G) {
 }
 
 // Element o of a plane through a 32-bit byte offset (the scalar-base + vector-offset
-// form of the memory instructions); needs nx ny sizeof(S) < 2^32 (fast_layout).
+// form of the memory instructions); needs nx ny sizeof(S) < 2^32 (fast_block).
 template <class S>
 __device__ __forceinline__ S *at_offset(S *plane, uint32_t o) {
   using B = std::conditional_t<std::is_const_v<S>, const char, char>;
   return reinterpret_cast<S *>(reinterpret_cast<B *>(plane) + o * (uint32_t)sizeof(S));
 }
 
-// Whether every pull of the lattice wraps periodically (no wall face, no solid node) and
-// a plane's bytes fit 32 bits: then pulls need no bounce-back test and address through
-// at_offset.
+// Whether no pull of a workgroup covering x0..x1, y0..y1 of layer z can bounce back (no
+// solid nodes, and the block keeps off the first and last index of every walled axis)
+// and a plane's bytes fit 32 bits: then its pulls need no bounce-back test (any wrap is
+// periodic) and address through at_offset.  Uniform across the workgroup.
 template <class S>
-__device__ __forceinline__ bool fast_layout(const Geom &G) {
-  return (G.wall[0] | G.wall[1] | G.wall[2]) == 0 && G.smask == nullptr &&
-         (uint64_t)G.nx * G.ny * sizeof(S) < (1ull << 32);
+__device__ __forceinline__ bool fast_block(const Geom &G, int x0, int x1, int y0, int y1,
+                                           int z) {
+  if (G.smask != nullptr || (uint64_t)G.nx * G.ny * sizeof(S) >= (1ull << 32)) return false;
+  if (G.wall[0] && (x0 == 0 || x1 >= G.nx - 1)) return false;
+  if (G.wall[1] && (y0 == 0 || y1 >= G.ny - 1)) return false;
+  if (G.wall[2] && (z == 0 || z >= G.nz - 1)) return false;
+  return true;
 }
 
-// The periodic pull of population i (fast_layout lattices): (i, x - e_i) wrapped.
+// The pull of population i where no bounce-back can occur (fast_block): (i, x - e_i),
+// wrapped periodically.
 template <class L, int i, class S>
 __device__ __forceinline__ const S *pull_ptr_periodic(const S *f, int x, int y, int z,
                                                       const Geom &G) {
@@ -168,6 +174,7 @@ struct StepArgs {
   T c2;      // SMRT: coefficient of the third-order force term (0 = off); RMRT: h2
   T c3;      // RMRT: h3; SMRT: (q_bulk - q2)/D (0 = one rate at order 2)
   T c4;      // SMRT: (q_31 - q3)/2 (0 = one rate at order 3)
+  int fast_ok;  // 1: fast_block workgroups take the scalar-base path
 };
 
 // One node of the fused step: pull the populations (periodic wrap or halfway
@@ -175,10 +182,9 @@ struct StepArgs {
 template <class L, int COLL, class S, class T, int MEM>
 __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restrict__ fout,
                                           const Geom &geo, int x, int y, int z, int node,
-                                          uint32_t sm, const T (&g)[3], T shift, T c0, T c1,
-                                          T c2 = T(0), T c3 = T(0), T c4 = T(0)) {
+                                          uint32_t sm, bool fast, const T (&g)[3], T shift,
+                                          T c0, T c1, T c2 = T(0), T c3 = T(0), T c4 = T(0)) {
   T d[L::Q];
-  const bool fast = fast_layout<S>(geo);
   if (fast) {
     static_for<L::Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
@@ -225,8 +231,12 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
   if (sm & SOLID_NODE) return;  // no fluid here: nothing pulls from its slots
   T g[3];
   load_force<T, GK>(a.force, x, y, z, node, a.geo.N, L::D, g);
+  const int x0 = blockIdx.x * blockDim.x, y0 = blockIdx.y * blockDim.y;
+  const bool fast = a.fast_ok && fast_block<S>(a.geo, x0, x0 + (int)blockDim.x - 1, y0,
+                                               y0 + (int)blockDim.y - 1, z);
   step_node<L, COLL, S, T, MEM>(static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.geo,
-                                x, y, z, node, sm, g, a.shift, a.c0, a.c1, a.c2, a.c3, a.c4);
+                                x, y, z, node, sm, fast, g, a.shift, a.c0, a.c1, a.c2, a.c3,
+                                a.c4);
 }
 
 // Initial state: compute f-bar(x, 0) at every node and place each population in the

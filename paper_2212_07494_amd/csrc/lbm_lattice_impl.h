@@ -30,6 +30,7 @@ inline StepArgs<T> make_args(const LaunchDesc &d) {
   a.c2 = T(d.c2);
   a.c3 = T(d.c3);
   a.c4 = T(d.c4);
+  a.fast_ok = d.fast_ok;
   return a;
 }
 

@@ -64,6 +64,10 @@ uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
   }
   return h;
 }
+// Memory-access variants of the step (plain, non-temporal stores, non-temporal loads and
+// stores); a tuning variant v selects v % kMemVariants and, for v >= kMemVariants, the
+// scalar-base addressing path where no bounce-back can occur.
+constexpr int kMemVariants = 3;
 constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
 size_t arith_bytes(int s) { return s == LBM_F64 ? 8 : 4; }
 bool shifted(int s) { return s == LBM_F32_SHIFTED || s == LBM_F16_SHIFTED; }
@@ -170,7 +174,8 @@ struct lbm_ctx {
     d.c4 = c4;
     d.bx = bx;
     d.by = by;
-    d.variant = variant;
+    d.variant = variant % kMemVariants;
+    d.fast_ok = variant / kMemVariants;
     return d;
   }
 };
@@ -911,7 +916,7 @@ int lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t reps, int32
 }
 
 namespace {
-constexpr int kVariants = 3;
+constexpr int kVariants = 2 * kMemVariants;  // memory access x addressing path
 bool tuning_ok(const lbm_tuning *t) {
   return t && (t->bx == 64 || t->bx == 128 || t->bx == 256) && t->by >= 1 &&
          t->bx * t->by <= 256 && t->variant >= 0 && t->variant < kVariants;
