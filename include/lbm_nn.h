@@ -10,7 +10,7 @@
  * tanh form of GELU, the output layer is linear.  The lattice is then started from
  * the predicted fields (lbm_reset_fields: force-corrected equilibrium of (rho, u), the
  * same state lbm_init builds), and the converged lattice-Boltzmann solution remains the
- * judge of the prediction's error.  The plain start (rest, rho0) stays the fallback.
+ * reference for the prediction's error.  The plain start (rest, rho0) stays the fallback.
  *
  * Device arrays (float*, row-major, one row per point) are caller-owned device memory;
  * host arrays are copied during the call.  Work is enqueued on the stream given at
