@@ -88,9 +88,11 @@ int lbm_batch_get_populations(lbm_batch *b, int32_t dom, double *f);
 /* Replace domain dom's state (Q x N doubles as stored); it becomes active again. */
 int lbm_batch_set_populations(lbm_batch *b, int32_t dom, const double *f);
 
-/* Launch configuration: tile width policy (tile_bx 64, 128, 256, or 0 = per domain the
- * smallest of those covering nx), persistent workgroups per compute unit (1..32) and
- * the memory variant of lbm_tuning.  Results do not depend on it. */
+/* Launch configuration: tile policy (tile_bx 64, 128, 256: tiles of that width and
+ * 256/tile_bx rows; 0: per domain the smallest of those covering nx; 1: linear tiles
+ * of 256 consecutive nodes of a layer, every lane busy whatever the width), persistent
+ * workgroups per compute unit (1..32) and the memory variant of lbm_tuning.  Results do
+ * not depend on it. */
 typedef struct {
   int32_t tile_bx;
   int32_t blocks_per_cu;

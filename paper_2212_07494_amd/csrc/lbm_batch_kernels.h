@@ -25,14 +25,42 @@ struct BatchDom {
   int wall[3];
   int gaxis;      // 0, 1, 2: profile along that axis; -1: uniform (3 values); 3: full field
   int gn;         // profile length
-  int tbx_log2;   // tile width 2^tbx_log2; tile height 256 >> tbx_log2
+  int tbx_log2;   // tile width 2^tbx_log2, height 256 >> tbx_log2; -1: linear tiles
   int tile_begin, tile_end;
   double c0, c1;  // collision coefficients (see StepArgs)
 };
 
+// A tile: the block of nodes (x0.., y0..) of layer z, or for linear tiles (tbx_log2 -1)
+// the 256 nodes from offset x0 within layer z.
 struct BatchTile {
   int dom, x0, y0, z;
 };
+
+// This lane's node of a tile; false if it lies beyond the domain.
+__device__ __forceinline__ bool tile_xy(const BatchTile &t, const BatchDom &dm, int &x, int &y) {
+  if (dm.tbx_log2 < 0) {
+    const int r = t.x0 + (int)threadIdx.x;
+    if (r >= dm.nx * dm.ny) return false;
+    y = r / dm.nx;
+    x = r - y * dm.nx;
+    return true;
+  }
+  x = t.x0 + (threadIdx.x & ((1 << dm.tbx_log2) - 1));
+  y = t.y0 + (threadIdx.x >> dm.tbx_log2);
+  return x < dm.nx && y < dm.ny;
+}
+
+// Whether no node of the tile can bounce back (fast_block over the rows it covers).
+template <class S>
+__device__ __forceinline__ bool tile_fast(const BatchTile &t, const BatchDom &dm,
+                                          const Geom &geo) {
+  if (dm.tbx_log2 < 0) {
+    const int last = min(t.x0 + 255, dm.nx * dm.ny - 1);
+    return fast_block<S>(geo, 0, dm.nx - 1, t.x0 / dm.nx, last / dm.nx, t.z);
+  }
+  return fast_block<S>(geo, t.x0, t.x0 + (1 << dm.tbx_log2) - 1, t.y0,
+                       t.y0 + (256 >> dm.tbx_log2) - 1, t.z);
+}
 
 template <class T>
 __device__ __forceinline__ void batch_force(const T *__restrict__ gbuf, const BatchDom &dm, int x,
@@ -66,16 +94,14 @@ __global__ void __launch_bounds__(256)
     const BatchTile tile = tiles[t];
     if (!active[tile.dom]) continue;
     const BatchDom dm = doms[tile.dom];
-    const int x = tile.x0 + (threadIdx.x & ((1 << dm.tbx_log2) - 1));
-    const int y = tile.y0 + (threadIdx.x >> dm.tbx_log2);
+    int x, y;
     const int z = tile.z;
-    if (x >= dm.nx || y >= dm.ny) continue;
+    if (!tile_xy(tile, dm, x, y)) continue;
     const Geom geo = batch_geom(dm);
     const int node = (z * dm.ny + y) * dm.nx + x;
     T g[3];
     batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);
-    const bool fast = fast_block<S>(geo, tile.x0, tile.x0 + (1 << dm.tbx_log2) - 1, tile.y0,
-                                    tile.y0 + (256 >> dm.tbx_log2) - 1, z);
+    const bool fast = tile_fast<S>(tile, dm, geo);
     step_node<L, COLL, S, T, MEM>(fin + dm.base, fout + dm.base, geo, x, y, z, node, 0u, fast,
                                   g, shift, T(dm.c0), T(dm.c1));
   }
@@ -95,11 +121,10 @@ __global__ void __launch_bounds__(256)
     const BatchTile tile = tiles[t];
     if (!active[tile.dom]) continue;
     const BatchDom dm = doms[tile.dom];
-    const int x = tile.x0 + (threadIdx.x & ((1 << dm.tbx_log2) - 1));
-    const int y = tile.y0 + (threadIdx.x >> dm.tbx_log2);
+    int x = 0, y = 0;
     const int z = tile.z;
     double v[3] = {0.0, 0.0, 0.0};
-    if (x < dm.nx && y < dm.ny) {
+    if (tile_xy(tile, dm, x, y)) {
       const Geom geo = batch_geom(dm);
       const int node = (z * dm.ny + y) * dm.nx + x;
       T d[L::Q];

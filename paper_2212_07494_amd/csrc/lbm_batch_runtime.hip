@@ -38,6 +38,9 @@ void block_shape(int nx, int &bx, int &by) {
   by = 256 / bx;
 }
 
+// Tile policy 1: linear tiles of 256 consecutive nodes (any domain width).
+constexpr int kLinearTiles = 1;
+
 int tile_width(int policy, int nx) {
   if (policy) return policy;
   return nx > 128 ? 256 : (nx > 64 ? 128 : 64);
@@ -198,13 +201,21 @@ int build_tiles(lbm_batch *b) {
   std::vector<int> tb(b->ndom), te(b->ndom);
   for (int d = 0; d < b->ndom; ++d) {
     lbm::BatchDom &m = b->dom[d];
-    const int tbx = tile_width(b->tune.tile_bx, m.nx);
-    const int tby = 256 / tbx;
-    m.tbx_log2 = log2i(tbx);
     m.tile_begin = (int)tiles.size();
-    for (int z = 0; z < m.nz; ++z)
-      for (int y0 = 0; y0 < m.ny; y0 += tby)
-        for (int x0 = 0; x0 < m.nx; x0 += tbx) tiles.push_back({d, x0, y0, z});
+    if (b->tune.tile_bx == kLinearTiles) {
+      // 256 consecutive nodes of one z layer per tile: x0 is the first node's offset in
+      // the layer, every lane busy except in a layer's last tile
+      m.tbx_log2 = -1;
+      for (int z = 0; z < m.nz; ++z)
+        for (int r0 = 0; r0 < m.nx * m.ny; r0 += 256) tiles.push_back({d, r0, 0, z});
+    } else {
+      const int tbx = tile_width(b->tune.tile_bx, m.nx);
+      const int tby = 256 / tbx;
+      m.tbx_log2 = log2i(tbx);
+      for (int z = 0; z < m.nz; ++z)
+        for (int y0 = 0; y0 < m.ny; y0 += tby)
+          for (int x0 = 0; x0 < m.nx; x0 += tbx) tiles.push_back({d, x0, y0, z});
+    }
     m.tile_end = (int)tiles.size();
     tb[d] = m.tile_begin;
     te[d] = m.tile_end;
@@ -228,9 +239,13 @@ int build_tiles(lbm_batch *b) {
 // Largest tile count over the tile-width policies (tbx x 256/tbx tiles).
 int max_tile_count(const std::vector<lbm::BatchDom> &dom) {
   int64_t best = 0;
-  for (int policy : {0, 64, 128, 256}) {
+  for (int policy : {0, 1, 64, 128, 256}) {
     int64_t n = 0;
     for (const auto &m : dom) {
+      if (policy == kLinearTiles) {
+        n += (int64_t)m.nz * (((int64_t)m.nx * m.ny + 255) / 256);
+        continue;
+      }
       const int tbx = tile_width(policy, m.nx), tby = 256 / tbx;
       n += (int64_t)m.nz * ((m.ny + tby - 1) / tby) * ((m.nx + tbx - 1) / tbx);
     }
@@ -586,7 +601,8 @@ int lbm_batch_set_populations(lbm_batch *b, int32_t dom, const double *f) {
 
 int lbm_batch_set_tuning(lbm_batch *b, const lbm_batch_tuning *t) {
   if (!valid(b)) return set_error(LBM_ESTATE, "invalid batch");
-  if (!t || !(t->tile_bx == 0 || t->tile_bx == 64 || t->tile_bx == 128 || t->tile_bx == 256) ||
+  if (!t || !(t->tile_bx == 0 || t->tile_bx == kLinearTiles || t->tile_bx == 64 ||
+              t->tile_bx == 128 || t->tile_bx == 256) ||
       t->blocks_per_cu < 1 || t->blocks_per_cu > 32 || t->variant < 0 || t->variant > 2)
     return set_error(LBM_EINVAL, "invalid batch tuning");
   b->tune = *t;
@@ -615,7 +631,7 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps, lbm_batch_tuning *best, doub
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int status = LBM_OK;
-  for (int tbx : {0, 64, 128, 256}) {
+  for (int tbx : {0, kLinearTiles, 64, 128, 256}) {
     for (int bpc : {2, 4, 8, 16}) {
       for (int v = 0; v < 3 && !status; ++v) {
         lbm_batch_tuning t{tbx, bpc, v};

@@ -62,9 +62,11 @@ def test_batch_matches_oracle_per_domain(storage):
             assert exact_mismatch(u, uo[:2].astype(np.float64)) == 0, d
 
 
-def test_batch_d3q27_field_forced_boxes():
+@pytest.mark.parametrize("tile_bx", [0, 1])
+def test_batch_d3q27_field_forced_boxes(tile_bx):
     """Periodic D3Q27 boxes of different sizes with full Fourier force fields and
-    initial velocity fields (the warm-start data generator's setting)."""
+    initial velocity fields (the warm-start data generator's setting), with the default
+    tiles and with linear tiles (layers of 306-460 nodes, so tiles end inside rows)."""
     L = lbm()
     doms = []
     for k, n in enumerate((16, 12, 20)):
@@ -74,6 +76,7 @@ def test_batch_d3q27_field_forced_boxes():
         rho, u, _ = inputs.random_fields(shape, seed=k, u_amp=0.01)
         doms.append(dict(shape=shape, tau=(0.7, 0.9, 1.0), g_field=g, rho=rho, u=u))
     with L.Batch(doms, "D3Q27", "smrt", "f32s") as b:
+        b.tune(tile_bx, 4, 1)
         b.advance(4)
         for d, dom in enumerate(doms):
             o = oracle_for("D3Q27", "smrt", "f32s", dom["shape"], (0, 0, 0), dom["tau"])
@@ -102,7 +105,7 @@ def test_launch_configurations_identical():
     with L.Batch(doms, "D2Q9", "smrt", "f32s") as ref:
         ref.advance(5)
         want = [ref.populations(d) for d in range(len(doms))]
-    for tbx in (0, 64, 256):
+    for tbx in (0, 1, 64, 256):
         for bpc in (1, 8):
             for v in (0, 2):
                 with L.Batch(doms, "D2Q9", "smrt", "f32s") as b:
