@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -138,6 +140,21 @@ def time_to_steady(torch, L, nprob, box=128, seed=2022, tol=1e-8, check_every=10
             "total_warm_s": round(sum(r["warm_s"] for r in rows), 3)}
 
 
+def precision_vs_f64(L, w, stream, t, rho_t, u_t):
+    """Error of the timed run's fields against the same workload stepped t steps in FP64
+    storage: relative L2 of u (E2, the paper's error norm) and max |rho difference|."""
+    lat = L.Lattice(w.lattice, w.collision, "f64", w.shape, w.walls, w.tau, rho=w.rho,
+                    u=w.u, g_profile=w.g_profile, stream=stream)
+    try:
+        lat.step(t)
+        rho, u = lat.moments()
+    finally:
+        lat.close()
+    e2 = float(np.linalg.norm(u_t - u) / np.linalg.norm(u))
+    return {"vs": "FP64 storage", "steps": int(t), "E2_u": e2,
+            "max_abs_drho": float(np.max(np.abs(rho_t - rho)))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +167,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true", help="skip the stream-copy roofline")
     ap.add_argument("--tuning", default=None,
                     help="fixed launch configuration bx,by,variant instead of the tuner")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the error of the timed run against FP64 storage")
     ap.add_argument("--ttss", type=int, default=6,
                     help="warm-start problems for the time-to-steady comparison (0: skip)")
     args = ap.parse_args()
@@ -192,9 +211,16 @@ def main():
     bytes_launch = 2 * Q * S * w.N
     achieved = bytes_launch / (ms_step * 1e-3) / 1e9
     m = lat.monitors()
+    t_run = lat.time
+    fields = None if (args.no_precision or args.storage == "f64") else lat.moments()
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    precision = None
+    if fields is not None:
+        precision = precision_vs_f64(L, w, stream, t_run, *fields)
+        fields = None
+        torch.cuda.empty_cache()
 
     copy_gbps, copy_cfg = (None, None) if args.no_copy else copy_roofline(torch, L, stream)
     khash = kernel_source_hash()
@@ -231,6 +257,7 @@ def main():
                    "nodes": w.N, "parallelism": "single GPU"},
         "roofline": roof,
         "monitors": {"step": m.step, "mass": m.mass, "umax": m.umax, "nonfinite": m.nonfinite},
+        "precision": precision,
         "kernel_source_hash": khash,
     }
     if args.ttss > 0:
