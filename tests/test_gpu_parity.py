@@ -276,16 +276,19 @@ def test_kolmogorov_full_size_sampled(storage):
         assert _sampled_step_parity(gpu, o, "D2Q9", w.shape, w.walls, g, nodes, storage) == 0
 
 
+@pytest.mark.parametrize("variant", [1, 5])
 @pytest.mark.parametrize("storage", ["f64", "f32s", "f16s"])
-def test_taylor_green_256_sampled(storage):
-    """D3Q19 SMRT 256^3 Taylor-Green + sin(z) force (the benchmark workload and launch
-    configuration): one step matches the oracle's collision at sampled nodes exactly."""
+def test_taylor_green_256_sampled(storage, variant):
+    """D3Q19 SMRT 256^3 Taylor-Green + sin(z) force (the benchmark workload), at the
+    launch configuration the tuner picks for it (256 x 1, non-temporal stores, general
+    addressing) and with the scalar-base addressing path: one step matches the oracle's
+    collision at sampled nodes exactly."""
     L = lbm()
     w = inputs.taylor_green_3d(n=256)
     o = oracle_for("D3Q19", "smrt", storage, w.shape, w.walls, w.tau)
     with L.Lattice("D3Q19", "smrt", storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
                    g_profile=w.g_profile) as gpu:
-        gpu.tune(256, 1, 2)   # what the tuner picks for the benchmark on MI355X
+        gpu.tune(256, 1, variant)
         gpu.step(2)
         nodes = _sample_nodes(w.shape, 200, 2)
         g = w.g.astype(o.dtype)
