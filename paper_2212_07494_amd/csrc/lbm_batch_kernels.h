@@ -102,8 +102,8 @@ __global__ void __launch_bounds__(256)
     T g[3];
     batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);
     const bool fast = tile_fast<S>(tile, dm, geo);
-    step_node<L, COLL, S, T, MEM>(fin + dm.base, fout + dm.base, geo, x, y, z, node, 0u, fast,
-                                  g, shift, T(dm.c0), T(dm.c1));
+    step_node<L, COLL, S, T, MEM>(fin + dm.base, fout + dm.base, geo, x, y, z, 0u, fast, g,
+                                  shift, T(dm.c0), T(dm.c1));
   }
 }
 
