@@ -190,6 +190,22 @@ int lbm_get_populations(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double
  * population-major), rounded to the storage type (nearest-even). */
 int lbm_set_populations(lbm_ctx *c, const double *f);
 
+/* Replace the state by a sum of Fourier waves about rest, synthesised on the device:
+ *   f-bar_i(x) = w_i rho0 + sum_w Re[A_wi exp(i theta_w(x))],
+ *   theta_w(x) = 2 pi (k_w0 x / nx + k_w1 y / ny + k_w2 z / nz) + phase_w,
+ * at every fluid node, evaluated in binary64 and rounded once to the storage type (for
+ * *_SHIFTED storage the stored value is f-bar_i - w_i rho0).  The populations are the
+ * pre-collision f-bar of Sec. II.B, as lbm_set_populations takes them; w_i rho0 is the
+ * unforced rest state.  Arguments (host, read before return): k: nwaves x 3 int32
+ * wavevectors (any integers; k_wa x_a is reduced modulo n_a), phase: nwaves binary64,
+ * amp: nwaves x Q x 2 binary64, the (re, im) pairs of A_wi at 2 (w Q + i).  nwaves = 0
+ * gives the rest state.  Resets the time to 0, like lbm_set_populations; values at solid
+ * nodes are unspecified.  Errors: LBM_EINVAL (nwaves outside 0..LBM_MAX_WAVES, a NULL
+ * array with nwaves > 0, a non-finite amplitude or phase), LBM_ESTATE, LBM_EHIP. */
+#define LBM_MAX_WAVES 4096
+int lbm_set_waves(lbm_ctx *c, int32_t nwaves, const int32_t *k, const double *phase,
+                  const double *amp);
+
 /* Simulation time t (number of steps taken since init or the last set_populations). */
 int lbm_time(const lbm_ctx *c, int64_t *t);
 
@@ -242,6 +258,11 @@ int lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t reps, int32
 const char *lbm_strerror(int status);
 const char *lbm_last_error(void);
 int lbm_version(void); /* 100 * major + minor */
+
+/* The velocity set of a lattice in the population order above: D, Q, the velocities
+ * (e: Q x 3 int32, x y z) and the weights (w: Q binary64); any output may be NULL.  Host
+ * only (no device, no context).  Errors: LBM_EINVAL (unknown lattice). */
+int lbm_lattice_info(int32_t lattice, int32_t *D, int32_t *Q, int32_t *e, double *w);
 
 #ifdef __cplusplus
 }

@@ -131,6 +131,31 @@ int lbm_ws_features(const lbm_ws_problem *p, int32_t n, int32_t box, float *x_de
 int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_problem *p, int32_t box,
                             double *coef);
 
+/* The steady state of the forced periodic lattice expanded in the forcing amplitude to
+ * first (order 1) or second (order 2) order about rest, as population waves for
+ * lbm_set_waves (the state is w_i rho0 + sum_w Re[A_wi exp(i theta_w)]).  Order 1: one
+ * wave per mode j (k_j, phase_j), A = amp_j f_j with f_j the linear response of
+ * lbm_ws_lattice_response (I - S J) f_j = S G g_hat.  Order 2 adds, for every pair
+ * i <= j, the waves at k_i + k_j and k_i - k_j (phases phase_i +- phase_j): each is the
+ * steady response (I - S J) f = S s to the source s that the collision's second
+ * derivative D2 makes of two first-order waves, s = amp_i amp_j D2(z_i, z_j) / 2 for a
+ * sum and amp_i amp_j D2(z_i, conj z_j) / 2 for a difference (1/4 instead of 1/2 when
+ * i = j), with z_j = (f_j, -i p_j) the direction of the expansion in (populations, g).
+ * A wave of zero wavevector (the mean part, k_i - k_i) solves (I - J) f = s with the
+ * mean's mass and momentum held at zero.  D2 is the mixed central second difference of
+ * the library's step on one-node binary64 lattices, taken bilinearly (no conjugation)
+ * for complex directions.  params, box and the problem are
+ * as for lbm_ws_lattice_response (the problem's forcing is g = sum_j amp_j p_j
+ * sin(2 pi k_j . x / box + phase_j)).  Outputs (host): k_out max_waves x 3 (integer
+ * wavevectors), phase_out max_waves, amp_out max_waves x Q x 2 ((re, im) of A_wi at
+ * 2 (w Q + i)), count = the waves written (nmodes for order 1, nmodes (nmodes + 2) for
+ * order 2; max_waves must allow that).  Uses the device (tiny contexts).
+ * Errors: those of lbm_ws_lattice_response, and LBM_EINVAL for an order other than 1 or 2,
+ * max_waves below the bound or a NULL output. */
+int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_problem *p, int32_t box,
+                         int32_t order, int32_t max_waves, int32_t *k_out, double *phase_out,
+                         double *amp_out, int32_t *count);
+
 #define LBM_WS_MODE_FEATURES 13
 /* Per-mode network inputs (rows nmodes x 13, device, copied before return): the phase
  * advance per lattice link kappa_a = 2 pi k_a / box (3), sin(kappa_a) (3),

@@ -60,7 +60,8 @@ struct BatchLaunch {
 
 struct LatticeOps {
   int D, Q;
-  const int *E;  // host: the Q velocities, Q x 3 (x, y, z)
+  const int *E;     // host: the Q velocities, Q x 3 (x, y, z)
+  const double *W;  // host: the Q weights
   hipError_t (*step)(const LaunchDesc &, hipStream_t);
   // pi: optional non-equilibrium second moment, 6 binary64 planes (xx, yy, zz, xy, xz, yz)
   hipError_t (*init)(const LaunchDesc &, const double *rho, const double *u, double rho0,
@@ -73,6 +74,10 @@ struct LatticeOps {
   void (*solid_words)(const uint8_t *solid, int nx, int ny, int nz, const int wall[3],
                       uint32_t *out);
   hipError_t (*scatter)(const LaunchDesc &, const double *in, hipStream_t);
+  // State from nw Fourier waves about the rest state of density base (waves_kernel;
+  // device arrays k: nw x 3, phase: nw, amp: nw x Q x 2)
+  hipError_t (*waves)(const LaunchDesc &, int nw, const int *k, const double *phase,
+                      const double *amp, double base, hipStream_t);
   hipError_t (*moments)(const LaunchDesc &, double *rho, double *u, void *uprev, int mode,
                         double *partials, hipStream_t);
   hipError_t (*batch_step)(const BatchLaunch &, hipStream_t);

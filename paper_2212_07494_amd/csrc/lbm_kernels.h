@@ -320,6 +320,47 @@ __global__ void __launch_bounds__(256) scatter_kernel(S *__restrict__ f, Geom ge
   });
 }
 
+// State from a sum of Fourier waves about rest: f-bar_i(x) = w_i rho0 + sum_w
+// Re[A_wi e^{i theta_w(x)}], theta_w(x) = 2 pi sum_a k_wa x_a / n_a + phase_w, stored as
+// f-bar_i - w_i shift, rounded once from binary64.  k_wa x_a is reduced modulo n_a in
+// integers first, so the angle stays within a few periods at any size.  amp holds the
+// (re, im) pairs of wave w's Q amplitudes at 2 (w Q + i).
+template <class L, class S>
+__global__ void __launch_bounds__(256) waves_kernel(S *__restrict__ f, Geom geo, int nw,
+                                                    const int *__restrict__ k,
+                                                    const double *__restrict__ phase,
+                                                    const double *__restrict__ amp,
+                                                    double base) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= geo.N) return;
+  const int n = (int)node;
+  const int x = n % geo.nx;
+  const int y = (n / geo.nx) % geo.ny;
+  const int z = n / (geo.nx * geo.ny);
+  const uint32_t sm = node_mask(geo, n);
+  if (sm & SOLID_NODE) return;
+  const double two_pi = 6.283185307179586;
+  double acc[L::Q];
+  for (int i = 0; i < L::Q; ++i) acc[i] = 0.0;
+  for (int w = 0; w < nw; ++w) {
+    const int mx = (int)(((int64_t)k[3 * w] * x) % geo.nx);
+    const int my = (int)(((int64_t)k[3 * w + 1] * y) % geo.ny);
+    const int mz = (int)(((int64_t)k[3 * w + 2] * z) % geo.nz);
+    const double t = (double(mx) / geo.nx + double(my) / geo.ny) + double(mz) / geo.nz;
+    double s, c;
+    sincos(two_pi * t + phase[w], &s, &c);
+    const double *a = amp + (int64_t)2 * L::Q * w;
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      acc[i] = acc[i] + (a[2 * i] * c - a[2 * i + 1] * s);
+    });
+  }
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    f[pull_slot<L, i>(x, y, z, geo, sm)] = S(Tab<L, double>::w(i) * base + acc[i]);
+  });
+}
+
 // ---- monitors -------------------------------------------------------------------------
 // Slots of a block partial (binary64): mass, mom x/y/z, sum |du|^2, sum |u|^2, max |u|,
 // non-finite count.

@@ -149,6 +149,16 @@ struct Ops {
       return hipGetLastError();
     });
   }
+  static hipError_t waves(const LaunchDesc &d, int nw, const int *k, const double *phase,
+                          const double *amp, double base, hipStream_t s) {
+    return with_types(d.storage, [&](auto *sp, auto *) -> hipError_t {
+      using S = std::remove_pointer_t<decltype(sp)>;
+      const unsigned blocks = (unsigned)((d.geo.N + 255) / 256);
+      hipLaunchKernelGGL((waves_kernel<L, S>), dim3(blocks), dim3(256), 0, s,
+                         static_cast<S *>(d.fout), geom_of(d), nw, k, phase, amp, base);
+      return hipGetLastError();
+    });
+  }
   template <class S, class T, int GK>
   static hipError_t moments_t(const LaunchDesc &d, double *rho, double *u, void *uprev, int mode,
                               double *partials, hipStream_t s) {
@@ -210,11 +220,13 @@ const LatticeOps &LBM_OPS() {
   static const LatticeOps ops = {LBM_LAT::D,
                                  LBM_LAT::Q,
                                  &LBM_LAT::E[0][0],
+                                 &LBM_LAT::W[0],
                                  &impl::Ops<LBM_LAT>::step,
                                  &impl::Ops<LBM_LAT>::init,
                                  &impl::Ops<LBM_LAT>::gather,
                                  &impl::Ops<LBM_LAT>::solid_words,
                                  &impl::Ops<LBM_LAT>::scatter,
+                                 &impl::Ops<LBM_LAT>::waves,
                                  &impl::Ops<LBM_LAT>::moments,
                                  &impl::Ops<LBM_LAT>::batch_step,
                                  &impl::Ops<LBM_LAT>::batch_monitor};

@@ -439,6 +439,20 @@ extern "C" {
 
 int lbm_version(void) { return 100; }
 
+int lbm_lattice_info(int32_t lattice, int32_t *D, int32_t *Q, int32_t *e, double *w) {
+  if (lattice < LBM_D2Q9 || lattice > LBM_D3Q27)
+    return fail(LBM_EINVAL, "unknown lattice %d", (int)lattice);
+  const lbm::LatticeOps &ops = lbm::ops_for(lattice);
+  if (D) *D = ops.D;
+  if (Q) *Q = ops.Q;
+  for (int i = 0; i < ops.Q; ++i) {
+    if (e)
+      for (int a = 0; a < 3; ++a) e[3 * i + a] = ops.E[3 * i + a];
+    if (w) w[i] = ops.W[i];
+  }
+  return LBM_OK;
+}
+
 const char *lbm_strerror(int status) {
   switch (status) {
     case LBM_OK: return "ok";
@@ -694,6 +708,41 @@ int lbm_set_populations(lbm_ctx *c, const double *f) {
   d.fout = c->buf[c->cur];
   HIP_TRY(c->ops->scatter(d, static_cast<const double *>(c->scratch), c->stream));
   // the host array may be released once this returns
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->t = 0;
+  c->uprev_time = -2;
+  return LBM_OK;
+}
+
+int lbm_set_waves(lbm_ctx *c, int32_t nwaves, const int32_t *k, const double *phase,
+                  const double *amp) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (nwaves < 0 || nwaves > LBM_MAX_WAVES)
+    return fail(LBM_EINVAL, "nwaves = %d must be in 0..%d", (int)nwaves, LBM_MAX_WAVES);
+  if (nwaves > 0 && (!k || !phase || !amp)) return fail(LBM_EINVAL, "k, phase or amp is NULL");
+  for (int64_t j = 0; j < (int64_t)2 * c->Q * nwaves; ++j)
+    if (!std::isfinite(amp[j])) return fail(LBM_EINVAL, "amp[%lld] is not finite", (long long)j);
+  for (int w = 0; w < nwaves; ++w)
+    if (!std::isfinite(phase[w])) return fail(LBM_EINVAL, "phase[%d] is not finite", w);
+  // device copies: amp (binary64), phase, then k (int32)
+  const size_t ab = (size_t)2 * c->Q * nwaves * sizeof(double);
+  const size_t pb = (size_t)nwaves * sizeof(double);
+  const size_t kb = (size_t)3 * nwaves * sizeof(int32_t);
+  int rc = c->need_scratch(ab + pb + kb + 8);
+  if (rc) return rc;
+  char *base = static_cast<char *>(c->scratch);
+  double *amp_d = reinterpret_cast<double *>(base);
+  double *phase_d = reinterpret_cast<double *>(base + ab);
+  int32_t *k_d = reinterpret_cast<int32_t *>(base + ab + pb);
+  if (nwaves > 0) {
+    HIP_TRY(hipMemcpyAsync(amp_d, amp, ab, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(phase_d, phase, pb, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(k_d, k, kb, hipMemcpyHostToDevice, c->stream));
+  }
+  lbm::LaunchDesc d = c->desc(1.0);
+  d.fout = c->buf[c->cur];
+  HIP_TRY(c->ops->waves(d, nwaves, k_d, phase_d, amp_d, c->p.rho0 - c->shift, c->stream));
+  // the host arrays may be released once this returns
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->t = 0;
   c->uprev_time = -2;

@@ -78,6 +78,9 @@ EXPORTS = {
     "lbm_monitors_get": ([C.c_void_p, C.POINTER(lbm_monitors)], C.c_int),
     "lbm_get_populations": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_set_populations": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_set_waves": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_lattice_info": ([C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p,
+                          C.c_void_p], C.c_int),
     "lbm_time": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "lbm_device_bytes": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
     "lbm_free": ([C.c_void_p], C.c_int),
@@ -249,6 +252,28 @@ def lbm_set_populations(ctx, f):
     _check(load().lbm_set_populations(ctx, _ptr(arr)))
 
 
+def lbm_set_waves(ctx, k, phase, amp):
+    """State w_i rho0 + sum_w Re[amp[w, i] exp(i theta_w)] (lbm_set_waves); k: (n, 3)
+    integers, phase: (n,), amp: (n, Q) complex."""
+    k = np.ascontiguousarray(np.asarray(k).reshape(-1, 3), dtype=np.int32)
+    n = k.shape[0]
+    ph = np.ascontiguousarray(np.asarray(phase, np.float64).reshape(n))
+    a = np.asarray(amp, np.complex128)
+    a = a.reshape(n, -1) if n else np.zeros((0, 1), np.complex128)
+    ri = np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))
+    _check(load().lbm_set_waves(ctx, n, _ptr(k), _ptr(ph), _ptr(ri)))
+
+
+def lbm_lattice_info(lattice):
+    """(velocities (Q, 3) int32, weights (Q,) binary64) of a lattice, in population order."""
+    Q = QOF[lattice]
+    e = np.zeros((Q, 3), np.int32)
+    w = np.zeros(Q, np.float64)
+    D, q = C.c_int32(), C.c_int32()
+    _check(load().lbm_lattice_info(LATTICES[lattice], C.byref(D), C.byref(q), _ptr(e), _ptr(w)))
+    return e, w
+
+
 def lbm_time(ctx) -> int:
     t = C.c_int64()
     _check(load().lbm_time(ctx, C.byref(t)))
@@ -344,6 +369,9 @@ class Lattice:
 
     def set_populations(self, f):
         lbm_set_populations(self.ctx, f)
+
+    def set_waves(self, k, phase, amp):
+        lbm_set_waves(self.ctx, k, phase, amp)
 
     @property
     def time(self):
@@ -560,6 +588,9 @@ EXPORTS_NN = {
                          C.c_double, C.c_void_p, C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "lbm_ws_mode_features": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_ws_lattice_response": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "lbm_ws_lattice_waves": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)],
+                             C.c_int),
     "lbm_upsample_periodic": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "lbm_ws_compose": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
@@ -699,6 +730,27 @@ def lbm_ws_lattice_response(problem, box, lattice="D3Q27", collision="smrt", tau
     _check(load().lbm_ws_lattice_response(C.byref(params), C.byref(s), int(box),
                                           out.ctypes.data))
     return out
+
+
+def lbm_ws_lattice_waves(problem, box, order=2, lattice="D3Q27", collision="smrt", tau3=1.0,
+                         rho0=1.0, **rates):
+    """The steady state of the problem's forced periodic lattice to first or second order
+    in the forcing, as waves for lbm_set_waves: k (n, 3) int32, phase (n,), amp (n, Q)
+    complex; rates as for lbm_ws_lattice_response."""
+    s = ws_problem_struct(problem)
+    params, keep = make_params(lattice, collision, "f64", (1, 1, 1),
+                               tau=(problem["tau2"], tau3, 1.0), rho0=rho0, **rates)
+    Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}[lattice.upper()]
+    nm = int(s.nmodes)
+    cap = nm + nm * (nm + 1)
+    k = np.zeros((cap, 3), np.int32)
+    ph = np.zeros(cap, np.float64)
+    amp = np.zeros((cap, Q, 2), np.float64)
+    count = C.c_int32()
+    _check(load().lbm_ws_lattice_waves(C.byref(params), C.byref(s), int(box), int(order), cap,
+                                       _ptr(k), _ptr(ph), _ptr(amp), C.byref(count)))
+    n = count.value
+    return k[:n].copy(), ph[:n].copy(), amp[:n, :, 0] + 1j * amp[:n, :, 1]
 
 
 def _optr(t):

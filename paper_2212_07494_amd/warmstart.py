@@ -93,13 +93,19 @@ class WarmStart:
     FLAGS = L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM | L.RESET_NONEQ
 
     def __init__(self, box=128, widths=WIDTHS, seed=0, max_rows=4096, stream=None,
-                 base_order=BASE_ORDER, flags=None, linear=False):
+                 base_order=BASE_ORDER, flags=None, linear=False, waves=False):
         import torch
         self.torch = torch
         self.box = box
         # linear: add each mode's exact linear lattice response (lbm_ws_lattice_response)
         # to the correction; the network then predicts only what that misses
         self.linear = linear
+        # waves: start from the lattice's own steady state to second order in the forcing
+        # (lbm_ws_lattice_waves, set as populations by lbm_set_waves) instead of the
+        # analytic base; the network's coefficients then correct each mode's own wave
+        # relative to that start (correction_waves)
+        self.waves = waves
+        self.velset = L.lbm_lattice_info("D3Q27") if waves else None
         self.widths = list(widths)
         self.stream = stream
         self.base_order = base_order
@@ -137,10 +143,62 @@ class WarmStart:
         """Each mode's exact linear lattice response (nmodes x 8) as mode coefficients."""
         return L.lbm_ws_lattice_response(problem, self.box, tau3=TAU3)
 
+    def lattice_waves(self, problem):
+        """The problem's steady lattice state to second order in the forcing, as
+        population waves (k, phase, complex amplitudes)."""
+        return L.lbm_ws_lattice_waves(problem, self.box, order=2, tau3=TAU3)
+
+    def correction_waves(self, problem, coef):
+        """Each mode's correction (coef: nmodes x 8, the network's output in units of
+        s_j = amp_j / (nu K_j^2): velocity on sin(theta_j) (3) and cos(theta_j) (3),
+        density on sin and cos) as the equilibrium wave it implies about rest (rho0 = 1):
+        A_i = w_i (rho_hat + 3 e_i . u_hat), u_hat = s_j (c_3..5 - i c_0..2),
+        rho_hat = s_j (c_7 - i c_6), since Re[(a - i b) e^{i theta}] = a cos + b sin."""
+        e, w = self.velset
+        nu = (problem["tau2"] - 0.5) / 3.0
+        ks, phs, amps = [], [], []
+        for j, m in enumerate(problem["modes"]):
+            K = 2 * math.pi * np.linalg.norm(m["k"]) / self.box
+            s = m["amp"] / (nu * K * K)
+            uh = s * (coef[j, 3:6] - 1j * coef[j, 0:3])
+            rh = s * (coef[j, 7] - 1j * coef[j, 6])
+            ks.append(np.asarray(m["k"], np.int32))
+            phs.append(m["phase"])
+            amps.append(w * (rh + 3.0 * (e.astype(np.float64) @ uh)))
+        return np.array(ks), np.array(phs), np.array(amps)
+
+    def waves_targets(self, problem, rho, u):
+        """The coefficients that correct the waves start towards a converged lattice state
+        (rho, u): projections on sin(theta_j), cos(theta_j) of the state minus those of the
+        start's own fields, in units of s_j."""
+        dom = domain_of(problem, self.box)
+        with L.Lattice("D3Q27", "smrt", "f64", dom["shape"], dom["walls"], dom["tau"],
+                       g_field=dom["g_field"], stream=self.stream) as lat:
+            lat.set_waves(*self.lattice_waves(problem))
+            rho_s, u_s = lat.moments()
+        N = self.box ** 3
+        r = np.concatenate([u - u_s, (rho - rho_s)[None]])
+        th = mode_phases(problem, self.box)
+        nu = (problem["tau2"] - 0.5) / 3.0
+        out = np.empty((NMODES, 8))
+        for j, m in enumerate(problem["modes"]):
+            K = 2 * math.pi * np.linalg.norm(m["k"]) / self.box
+            a = m["amp"] / (nu * K * K)
+            ps = 2.0 / N * (r @ np.sin(th[j]))
+            pc = 2.0 / N * (r @ np.cos(th[j]))
+            out[j, 0:3] = ps[:3] / a
+            out[j, 3:6] = pc[:3] / a
+            out[j, 6] = ps[3] / a
+            out[j, 7] = pc[3] / a
+        return out.astype(np.float32)
+
     def mode_targets(self, problem, rho, u):
         """The 8 coefficients per mode that make the base's own mode responses match a
         converged lattice state (rho, u on the box^3 lattice): projections on
-        sin(theta_j), cos(theta_j) of the state minus the base's pair terms."""
+        sin(theta_j), cos(theta_j) of the state minus the base's pair terms (in waves
+        mode: minus the waves start's fields, waves_targets)."""
+        if self.waves:
+            return self.waves_targets(problem, rho, u)
         torch = self.torch
         N = self.box ** 3
         b1 = torch.empty((N, 4), device="cuda")
@@ -256,8 +314,22 @@ class WarmStart:
                               mode_coef=coef, stream=self.stream)
         return rows, U
 
+    def predict_waves(self, problem):
+        """Waves mode: the second-order lattice waves plus the network's correction waves."""
+        x = self.mode_features(problem)
+        coef = self.y[:NMODES]
+        self.net.forward(x, coef)
+        c = coef.cpu().numpy().astype(np.float64)
+        k, ph, A = self.lattice_waves(problem)
+        kc, phc, Ac = self.correction_waves(problem, c)
+        return (np.concatenate([k, kc]), np.concatenate([ph, phc]),
+                np.concatenate([A, Ac]))
+
     def start(self, lattice, problem):
         """Restart `lattice` (a box^3 lbm.Lattice of this problem) from the prediction."""
+        if self.waves:
+            lattice.set_waves(*self.predict_waves(problem))
+            return None
         rows, U = self.predict(problem)
         L.lbm_reset_fields(lattice.ctx, rows, 1, U, U, self.flags)
         return U
@@ -267,7 +339,7 @@ class WarmStart:
         np.save(path + ".npy", self.net.params())
         with open(path + ".json", "w") as fh:
             json.dump(dict(widths=self.widths, box=self.box, base_order=self.base_order,
-                           flags=self.flags, linear=self.linear,
+                           flags=self.flags, linear=self.linear, waves=self.waves,
                            scale=self.scale.tolist()), fh)
 
     def load(self, path):
@@ -278,6 +350,8 @@ class WarmStart:
         self.base_order = meta["base_order"]
         self.flags = meta["flags"]
         self.linear = bool(meta.get("linear", False))
+        self.waves = bool(meta.get("waves", False))
+        self.velset = L.lbm_lattice_info("D3Q27") if self.waves else None
         self.set_scale(meta["scale"])
         self.net.set_params(np.load(path + ".npy", allow_pickle=False))
 

@@ -158,3 +158,38 @@ def test_lattice_response_rejects_bad_arguments():
                                                               amp=1e-6, phase=0.0)]))
     assert lib.lbm_ws_lattice_response(C.byref(params), C.byref(prob1), 0,
                                        out.ctypes.data) == lbm.LBM_EINVAL  # box < 1
+
+
+def test_lattice_waves_rejects_bad_arguments():
+    """lbm_ws_lattice_waves validates its arguments before creating any context."""
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    params, keep = lbm.make_params("D3Q27", "smrt", "f64", (1, 1, 1), tau=(0.8, 1.0, 1.0))
+    modes = [dict(k=[1, 0, 0], p=[0, 1, 0], amp=1e-6, phase=0.0),
+             dict(k=[0, 2, 0], p=[0, 0, 1], amp=1e-6, phase=0.5)]
+    prob = lbm.ws_problem_struct(dict(tau2=0.8, modes=modes))
+    k = np.zeros((8, 3), np.int32)
+    ph = np.zeros(8)
+    amp = np.zeros((8, 27, 2))
+    n = C.c_int32()
+    args = (k.ctypes.data, ph.ctypes.data, amp.ctypes.data, C.byref(n))
+    assert lib.lbm_ws_lattice_waves(C.byref(params), C.byref(prob), 32, 3, 8,
+                                    *args) == lbm.LBM_EINVAL
+    assert b"order" in lib.lbm_last_error()
+    # two modes to second order give 2 + 2 * 3 = 8 waves
+    assert lib.lbm_ws_lattice_waves(C.byref(params), C.byref(prob), 32, 2, 7,
+                                    *args) == lbm.LBM_EINVAL
+    assert b"max_waves" in lib.lbm_last_error()
+    assert lib.lbm_ws_lattice_waves(C.byref(params), C.byref(prob), 32, 2, 8,
+                                    None, *args[1:]) == lbm.LBM_EINVAL
+    bad = lbm.ws_problem_struct(dict(tau2=0.8, modes=[dict(k=[0, 0, 0], p=[0, 1, 0],
+                                                            amp=1e-6, phase=0.0)]))
+    assert lib.lbm_ws_lattice_waves(C.byref(params), C.byref(bad), 32, 1, 8,
+                                    *args) == lbm.LBM_EINVAL
+    assert b"k = 0" in lib.lbm_last_error()
+
+
+def test_set_waves_rejects_invalid_context():
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    assert lib.lbm_set_waves(None, 0, None, None, None) == lbm.LBM_ESTATE

@@ -173,3 +173,61 @@ def test_lattice_response_equals_kolmogorov_closed_form(lattice, coll, tau2, tau
         s = 1.0 / ((tau2 - 0.5) / 3 * k * k)
         assert abs(c[0, 0] - (U / s - 1)) < 1e-7 * abs(U / s), (c[0], U / s - 1)
         assert np.max(np.abs(c[0, 1:])) < 1e-8, c[0]
+
+
+def test_waves_start_beats_linear_response_start():
+    """The lattice's own steady state to second order in the forcing (population waves
+    from lbm_ws_lattice_waves, set on the device by lbm_set_waves) starts closer to the
+    steady state and needs fewer steps than the linear-response start, and ends at the
+    plain start's steady state."""
+    from paper_2212_07494_amd import lbm as L
+    from paper_2212_07494_amd import warmstart as W
+    L.load()
+    probs = [p for p in (inputs.warmstart_problem(700 + i, box=BOX) for i in range(6))
+             if W.separable(p)]
+    lin = W.WarmStart(box=BOX, seed=1, linear=True)
+    wav = W.WarmStart(box=BOX, seed=1, waves=True)
+    try:
+        s_lin, s_wav, e_lin, e_wav = 0, 0, 0.0, 0.0
+        for p in probs:
+            r = W.compare_starts(wav, p, BOX, 1e-8, check_every=50)
+            rl = W.compare_starts(lin, p, BOX, 1e-8, check_every=50, plain=r["plain"],
+                                  reference_u=r["reference_u"])
+            assert r["warm"]["final_err"] < 1e-5 and rl["warm"]["final_err"] < 1e-5
+            s_wav += r["warm"]["steps"]
+            s_lin += rl["warm"]["steps"]
+            e_wav += r["warm"]["initial_err"]
+            e_lin += rl["warm"]["initial_err"]
+        print("steps: linear response", s_lin, "waves", s_wav,
+              "initial errors", e_lin, e_wav)
+        assert e_wav < 0.5 * e_lin, (e_wav, e_lin)
+        assert s_wav < s_lin, (s_wav, s_lin)
+    finally:
+        lin.close()
+        wav.close()
+
+
+def test_waves_targets_recover_a_correction():
+    """The waves mode's targets and its correction waves use one convention: a start
+    corrected by known coefficients c (correction_waves added to the lattice waves)
+    projects back to c (to first order in the correction)."""
+    from paper_2212_07494_amd import lbm as L
+    from paper_2212_07494_amd import warmstart as W
+    L.load()
+    p = inputs.warmstart_problem(705, box=BOX)
+    ws = W.WarmStart(box=BOX, seed=1, waves=True)
+    try:
+        rng = np.random.default_rng(3)
+        c = rng.uniform(-0.02, 0.02, size=(4, 8))
+        k, ph, A = ws.lattice_waves(p)
+        kc, phc, Ac = ws.correction_waves(p, c)
+        dom = W.domain_of(p, BOX)
+        with L.Lattice("D3Q27", "smrt", "f64", dom["shape"], dom["walls"], dom["tau"],
+                       g_field=dom["g_field"]) as lat:
+            lat.set_waves(np.concatenate([k, kc]), np.concatenate([ph, phc]),
+                          np.concatenate([A, Ac]))
+            rho, u = lat.moments()
+        t = ws.waves_targets(p, rho, u).astype(np.float64)
+        assert np.abs(t - c).max() < 0.05 * np.abs(c).max(), (t, c)
+    finally:
+        ws.close()
