@@ -132,29 +132,39 @@ int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_problem *p, i
                             double *coef);
 
 /* The steady state of the forced periodic lattice expanded in the forcing amplitude to
- * first (order 1) or second (order 2) order about rest, as population waves for
- * lbm_set_waves (the state is w_i rho0 + sum_w Re[A_wi exp(i theta_w)]).  Order 1: one
- * wave per mode j (k_j, phase_j), A = amp_j f_j with f_j the linear response of
- * lbm_ws_lattice_response (I - S J) f_j = S G g_hat.  Order 2 adds, for every pair
- * i <= j, the waves at k_i + k_j and k_i - k_j (phases phase_i +- phase_j): each is the
- * steady response (I - S J) f = S s to the source s that the collision's second
- * derivative D2 makes of two first-order waves, s = amp_i amp_j D2(z_i, z_j) / 2 for a
- * sum and amp_i amp_j D2(z_i, conj z_j) / 2 for a difference (1/4 instead of 1/2 when
- * i = j), with z_j = (f_j, -i p_j) the direction of the expansion in (populations, g).
- * A wave of zero wavevector (the mean part, k_i - k_i) solves (I - J) f = s with the
- * mean's mass and momentum held at zero.  D2 is the mixed central second difference of
- * the library's step on one-node binary64 lattices, taken bilinearly (no conjugation)
- * for complex directions.  params, box and the problem are
- * as for lbm_ws_lattice_response (the problem's forcing is g = sum_j amp_j p_j
- * sin(2 pi k_j . x / box + phase_j)).  Outputs (host): k_out max_waves x 3 (integer
- * wavevectors), phase_out max_waves, amp_out max_waves x Q x 2 ((re, im) of A_wi at
- * 2 (w Q + i)), count = the waves written (nmodes for order 1, nmodes (nmodes + 2) for
- * order 2; max_waves must allow that).  Uses the device (tiny contexts).
- * Errors: those of lbm_ws_lattice_response, and LBM_EINVAL for an order other than 1 or 2,
- * max_waves below the bound or a NULL output. */
+ * order 1, 2 or 3 about rest, as population waves for lbm_set_waves (the state is
+ * w_i rho0 + sum_w Re[A_wi exp(i theta_w)]).  C(f, g) below is the collision of one node
+ * as this library's step computes it, and a_j = amp_j e^{i phase_j} (f_j, -i p_j) the
+ * direction of mode j in (populations, g).
+ *   Order 1: one wave per mode (k_j, phase_j, A = amp_j f_j), f_j the linear response of
+ *     lbm_ws_lattice_response, (I - S J) f_j = S G g_hat.
+ *   Order 2 adds, for every pair i <= j, the waves k_i + k_j and k_i - k_j: the steady
+ *     responses (I - S J) f = S s to the sources D2(a_i, a_j) / 2 and D2(a_i, conj a_j) / 2
+ *     (1/4 instead of 1/2 when i = j) of the collision's second derivative D2.
+ *   Order 3 adds the waves of the cross term D2(a_j, b_w) / 2 and D2(a_j, conj b_w) / 2
+ *     (b_w the second-order waves, at k_j +- q_w) and of the cubic term: per unordered
+ *     triple of signed modes, m D3(a_c1, a_c2, a_c3) / 24 at k_c1 + k_c2 + k_c3 (m its
+ *     orderings, a_c = a_j or conj a_j for k_c = +-k_j; each triple counted once with its
+ *     all-flipped conjugate).  Sources at one wavevector are summed, one wave each.
+ * A wave of zero wavevector (a mean part) solves (I - J) f = s with the mean's mass and
+ * momentum held at zero.  Waves of order 2 and 3 carry their phase in A (phase 0).  J, G
+ * and the derivatives D2, D3 along directions are central differences of the library's
+ * step on binary64 lattices, extended multilinearly (no conjugation) to complex
+ * directions; all evaluations of one order run as one step of an n x 1 x 1 lattice.
+ * params, box and the problem are as for lbm_ws_lattice_response (forcing
+ * g = sum_j amp_j p_j sin(2 pi k_j . x / box + phase_j), integer k_j).  Outputs (host):
+ * k_out max_waves x 3, phase_out max_waves, amp_out max_waves x Q x 2 ((re, im) of A_wi
+ * at 2 (w Q + i)), count = the waves written; max_waves must be at least
+ * lbm_ws_max_waves(nmodes, order).  Uses the device (small contexts).  Errors: those of
+ * lbm_ws_lattice_response, and LBM_EINVAL for an order outside 1..3, max_waves below the
+ * bound, a non-integer k or a NULL output. */
 int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_problem *p, int32_t box,
                          int32_t order, int32_t max_waves, int32_t *k_out, double *phase_out,
                          double *amp_out, int32_t *count);
+
+/* The number of waves lbm_ws_lattice_waves may write for nmodes modes (1..8) to order
+ * 1..3 (0 for arguments outside those ranges). */
+int32_t lbm_ws_max_waves(int32_t nmodes, int32_t order);
 
 #define LBM_WS_MODE_FEATURES 13
 /* Per-mode network inputs (rows nmodes x 13, device, copied before return): the phase

@@ -1,15 +1,18 @@
 // Steady response of the forced periodic lattice to Fourier forcing modes, order by order
 // in the forcing amplitude (lbm_ws_lattice_response: first order, as mode coefficients;
-// lbm_ws_lattice_waves: first and second order, as population waves).  Host code: the
-// collision's first and second derivatives about rest are taken by central differences
-// of the library's own step on one-node periodic lattices, where the pull streaming maps
-// every population onto itself, so one step is one collision.  Each wave of the response
-// is then one Q x Q complex solve.
+// lbm_ws_lattice_waves: up to third order, as population waves).  Host code driving the
+// library's own step: the collision's derivatives about rest are central differences of
+// that step, and every wave of the response is one Q x Q complex solve.
+//
+// All collision evaluations of one stage run together as one step of an n x 1 x 1
+// periodic lattice with a per-node acceleration field: there the pull streaming moves
+// population i from node p to node p + e_ix (mod n) and leaves the other axes alone, so
+// the state after the step holds C(f_p, g_p)_i at node p + e_ix.
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <complex>
 #include <map>
-#include <tuple>
 #include <vector>
 
 #include "lbm.h"
@@ -23,6 +26,7 @@ using cvec = std::vector<cplx>;
 using rvec = std::vector<double>;
 using gvec = std::array<double, 3>;
 using gcvec = std::array<cplx, 3>;
+using kvec = std::array<int, 3>;
 
 // Gaussian elimination with partial pivoting on an n x n row-major system; x overwrites b.
 bool solve_complex(int n, std::vector<cplx> &A, std::vector<cplx> &b) {
@@ -50,140 +54,231 @@ bool solve_complex(int n, std::vector<cplx> &A, std::vector<cplx> &b) {
   return true;
 }
 
-// The collision of one node, C(f, g), as the library computes it: one step of a one-node
-// periodic binary64 lattice of uniform acceleration g (a context per distinct g, made on
-// first use and kept until destruction).
-class NodeCollision {
- public:
-  explicit NodeCollision(const lbm_params &q) : q_(q) {}
-  ~NodeCollision() {
-    for (auto &kv : ctx_) lbm_free(kv.second);
-  }
-  NodeCollision(const NodeCollision &) = delete;
-  NodeCollision &operator=(const NodeCollision &) = delete;
+// A direction of the expansion in (populations, acceleration).
+struct Dir {
+  cvec f;
+  gcvec g{};
+};
+struct RDir {
+  rvec f;
+  gvec g{};
+};
 
-  // Rest populations (the start of a context of zero acceleration).
-  int rest(rvec &f0) {
-    lbm_ctx *c = nullptr;
-    const int rc = context({0.0, 0.0, 0.0}, &c);
-    if (rc) return rc;
-    f0.assign(lbm::ops_for(q_.lattice).Q, 0.0);
-    return lbm_get_populations(c, 1, nullptr, f0.data());
+Dir conj(const Dir &d) {
+  Dir c = d;
+  for (auto &v : c.f) v = std::conj(v);
+  for (auto &v : c.g) v = std::conj(v);
+  return c;
+}
+Dir scaled(const Dir &d, cplx s) {
+  Dir c = d;
+  for (auto &v : c.f) v *= s;
+  for (auto &v : c.g) v *= s;
+  return c;
+}
+RDir part(const Dir &d, bool imag) {
+  RDir r;
+  r.f.resize(d.f.size());
+  for (size_t i = 0; i < d.f.size(); ++i) r.f[i] = imag ? d.f[i].imag() : d.f[i].real();
+  for (int a = 0; a < 3; ++a) r.g[a] = imag ? d.g[a].imag() : d.g[a].real();
+  return r;
+}
+double max_abs(const RDir &r) {
+  double m = 0;
+  for (double v : r.f) m = std::max(m, std::abs(v));
+  for (double v : r.g) m = std::max(m, std::abs(v));
+  return m;
+}
+
+// Collision evaluation points, run together (see the file comment).
+class CollisionBatch {
+ public:
+  CollisionBatch(const lbm_params &q, int Q, const int *E) : q_(q), Q_(Q), E_(E) {}
+  int size() const { return n_; }
+  int add(const rvec &f, const gvec &g) {
+    f_.insert(f_.end(), f.begin(), f.end());
+    for (int a = 0; a < 3; ++a) g_.push_back(g[a]);
+    return n_++;
   }
-  int operator()(const rvec &f, const gvec &g, rvec &out) {
+  // out: n x Q, point-major
+  int run(rvec &out) const {
+    out.assign((size_t)n_ * Q_, 0.0);
+    if (n_ == 0) return LBM_OK;
+    const int n = n_;
+    rvec gplanes((size_t)3 * n), pop((size_t)Q_ * n), next((size_t)Q_ * n);
+    for (int p = 0; p < n; ++p) {
+      for (int a = 0; a < 3; ++a) gplanes[(size_t)a * n + p] = g_[(size_t)3 * p + a];
+      for (int i = 0; i < Q_; ++i) pop[(size_t)i * n + p] = f_[(size_t)p * Q_ + i];
+    }
+    lbm_params q = q_;
+    q.nx = n;
+    q.ny = q.nz = 1;
+    q.g_kind = LBM_G_FIELD;
+    q.g_data = gplanes.data();
     lbm_ctx *c = nullptr;
-    int rc = context(g, &c);
+    int rc = lbm_init(&q, nullptr, nullptr, nullptr, &c);
     if (rc) return rc;
-    out.assign(f.size(), 0.0);
     const double one = 1.0;
-    rc = lbm_set_populations(c, f.data());
+    rc = lbm_set_populations(c, pop.data());
     if (!rc) rc = lbm_step(c, 1, &one);
-    if (!rc) rc = lbm_get_populations(c, 1, nullptr, out.data());
-    return rc;
+    if (!rc) rc = lbm_get_populations(c, n, nullptr, next.data());
+    lbm_free(c);
+    if (rc) return rc;
+    for (int p = 0; p < n; ++p)
+      for (int i = 0; i < Q_; ++i) {
+        const int dst = ((p + E_[3 * i]) % n + n) % n;
+        out[(size_t)p * Q_ + i] = next[(size_t)i * n + dst];
+      }
+    return LBM_OK;
   }
 
  private:
-  int context(const gvec &g, lbm_ctx **out) {
-    const auto key = std::make_tuple(g[0], g[1], g[2]);
-    auto it = ctx_.find(key);
-    if (it != ctx_.end()) {
-      *out = it->second;
-      return LBM_OK;
-    }
-    lbm_params q = q_;
-    for (int a = 0; a < 3; ++a) q.g_uniform[a] = g[a];
-    lbm_ctx *c = nullptr;
-    const int rc = lbm_init(&q, nullptr, nullptr, nullptr, &c);
-    if (rc) return rc;
-    ctx_[key] = c;
-    *out = c;
-    return LBM_OK;
-  }
   lbm_params q_;
-  std::map<std::tuple<double, double, double>, lbm_ctx *> ctx_;
+  int Q_;
+  const int *E_;
+  int n_ = 0;
+  rvec f_, g_;
 };
 
-// The collision expanded about rest: J = dC/d f-bar (Q x Q), G = dC/dg (Q x 3), and the
-// second derivative along two directions; and the steady periodic waves they drive.
+// The collision expanded about rest: J = dC/d f-bar (Q x Q) and G = dC/dg (Q x 3) by
+// central differences, the second and third derivatives along directions by mixed
+// central differences (planned into a batch, then read out), and the steady periodic
+// waves they drive.
 class Expansion {
  public:
   explicit Expansion(const lbm_params &q)
-      : C_(q), Q(lbm::ops_for(q.lattice).Q), D(lbm::ops_for(q.lattice).D),
+      : q_(q), Q(lbm::ops_for(q.lattice).Q), D(lbm::ops_for(q.lattice).D),
         E(lbm::ops_for(q.lattice).E) {}
 
+  CollisionBatch batch() const { return CollisionBatch(q_, Q, E); }
+
   int build() {
-    int rc = C_.rest(f0_);
+    // rest: the start of a one-node context of zero acceleration
+    lbm_ctx *c = nullptr;
+    int rc = lbm_init(&q_, nullptr, nullptr, nullptr, &c);
+    if (rc) return rc;
+    f0_.assign(Q, 0.0);
+    rc = lbm_get_populations(c, 1, nullptr, f0_.data());
+    lbm_free(c);
     if (rc) return rc;
     const double h = 1e-6;
+    CollisionBatch B = batch();
+    rvec f;
     const gvec zero = {0, 0, 0};
+    for (int col = 0; col < Q; ++col)
+      for (double s : {1.0, -1.0}) {
+        f = f0_;
+        f[col] += s * h;
+        B.add(f, zero);
+      }
+    for (int a = 0; a < D; ++a)
+      for (double s : {1.0, -1.0}) {
+        gvec g = zero;
+        g[a] = s * h;
+        B.add(f0_, g);
+      }
+    rvec out;
+    if ((rc = B.run(out))) return rc;
     J_.assign((size_t)Q * Q, 0.0);
     G_.assign((size_t)Q * 3, 0.0);
-    rvec fp, fm, cp, cm;
-    for (int col = 0; col < Q; ++col) {
-      fp = f0_;
-      fm = f0_;
-      fp[col] += h;
-      fm[col] -= h;
-      if ((rc = C_(fp, zero, cp)) || (rc = C_(fm, zero, cm))) return rc;
-      for (int i = 0; i < Q; ++i) J_[(size_t)i * Q + col] = (cp[i] - cm[i]) / (2 * h);
-    }
-    for (int a = 0; a < D; ++a) {
-      gvec gp = {0, 0, 0}, gm = {0, 0, 0};
-      gp[a] = h;
-      gm[a] = -h;
-      if ((rc = C_(f0_, gp, cp)) || (rc = C_(f0_, gm, cm))) return rc;
-      for (int i = 0; i < Q; ++i) G_[(size_t)i * 3 + a] = (cp[i] - cm[i]) / (2 * h);
-    }
+    for (int col = 0; col < Q; ++col)
+      for (int i = 0; i < Q; ++i)
+        J_[(size_t)i * Q + col] =
+            (out[(size_t)(2 * col) * Q + i] - out[(size_t)(2 * col + 1) * Q + i]) / (2 * h);
+    for (int a = 0; a < D; ++a)
+      for (int i = 0; i < Q; ++i)
+        G_[(size_t)i * 3 + a] = (out[(size_t)(2 * Q + 2 * a) * Q + i] -
+                                 out[(size_t)(2 * Q + 2 * a + 1) * Q + i]) /
+                                (2 * h);
     return LBM_OK;
   }
 
-  // Mixed second derivative of C along the real directions (a, ga) and (b, gb).
-  int d2(const rvec &a, const gvec &ga, const rvec &b, const gvec &gb, rvec &out) {
-    const double h = 1e-4;
-    const double sa[4] = {1, 1, -1, -1}, sb[4] = {1, -1, 1, -1};
-    rvec f(Q), c[4];
-    for (int t = 0; t < 4; ++t) {
-      gvec g;
-      for (int i = 0; i < Q; ++i) f[i] = f0_[i] + h * (sa[t] * a[i] + sb[t] * b[i]);
-      for (int k = 0; k < 3; ++k) g[k] = h * (sa[t] * ga[k] + sb[t] * gb[k]);
-      const int rc = C_(f, g, c[t]);
-      if (rc) return rc;
+  // A real mixed derivative of order m (2 or 3) along m real directions, planned as the
+  // 2^m points f0 + h sum_k s_k x_k / |x_k| (s_k = +-1) and read out as
+  // sum s_1..s_m C / (2^m h^m) times the directions' scales.  A zero direction makes it 0.
+  struct RealJob {
+    int base = -1;
+    double scale = 0;
+    int m = 0;
+  };
+  RealJob plan_real(CollisionBatch &B, const RDir *const *x, int m) const {
+    RealJob j;
+    j.m = m;
+    double norm[3];
+    for (int k = 0; k < m; ++k) {
+      norm[k] = max_abs(*x[k]);
+      if (norm[k] == 0) return j;
     }
-    out.assign(Q, 0.0);
-    for (int i = 0; i < Q; ++i)
-      out[i] = ((c[0][i] - c[1][i]) - (c[2][i] - c[3][i])) / (4 * h * h);
-    return LBM_OK;
+    const double h = m == 2 ? 1e-4 : 5e-4;
+    rvec f(Q);
+    for (int s = 0; s < (1 << m); ++s) {
+      gvec g = {0, 0, 0};
+      for (int i = 0; i < Q; ++i) f[i] = f0_[i];
+      for (int k = 0; k < m; ++k) {
+        const double c = ((s >> k) & 1 ? -h : h) / norm[k];
+        for (int i = 0; i < Q; ++i) f[i] += c * x[k]->f[i];
+        for (int a = 0; a < 3; ++a) g[a] += c * x[k]->g[a];
+      }
+      const int id = B.add(f, g);
+      if (s == 0) j.base = id;
+    }
+    double sc = 1.0;
+    for (int k = 0; k < m; ++k) sc *= norm[k] / (2 * h);
+    j.scale = sc;
+    return j;
+  }
+  void read_real(const RealJob &j, const rvec &out, double sign, cvec &acc, bool imag) const {
+    if (j.base < 0) return;
+    for (int s = 0; s < (1 << j.m); ++s) {
+      int par = 0;
+      for (int k = 0; k < j.m; ++k) par ^= (s >> k) & 1;
+      const double w = (par ? -1.0 : 1.0) * sign * j.scale;
+      for (int i = 0; i < Q; ++i) {
+        const double v = w * out[(size_t)(j.base + s) * Q + i];
+        acc[i] += imag ? cplx(0.0, v) : cplx(v, 0.0);
+      }
+    }
   }
 
-  // Its bilinear extension to complex directions (no conjugation).
-  int d2c(const cvec &a, const gcvec &ga, const cvec &b, const gcvec &gb, cvec &out) {
-    rvec ar(Q), ai(Q), br(Q), bi(Q), rr, ii, ri, ir;
-    gvec gar, gai, gbr, gbi;
-    for (int i = 0; i < Q; ++i) {
-      ar[i] = a[i].real();
-      ai[i] = a[i].imag();
-      br[i] = b[i].real();
-      bi[i] = b[i].imag();
+  // The multilinear extension to complex directions (no conjugation): each direction
+  // splits into real and imaginary parts; a term with k imaginary parts carries i^k.
+  struct ComplexJob {
+    std::vector<RealJob> jobs;
+    std::vector<int> ipow;  // k of each job
+  };
+  ComplexJob plan_complex(CollisionBatch &B, const Dir *const *d, int m) const {
+    ComplexJob cj;
+    RDir parts[3][2];
+    for (int k = 0; k < m; ++k) {
+      parts[k][0] = part(*d[k], false);
+      parts[k][1] = part(*d[k], true);
     }
-    for (int k = 0; k < 3; ++k) {
-      gar[k] = ga[k].real();
-      gai[k] = ga[k].imag();
-      gbr[k] = gb[k].real();
-      gbi[k] = gb[k].imag();
+    for (int s = 0; s < (1 << m); ++s) {
+      const RDir *x[3];
+      int k_im = 0;
+      for (int k = 0; k < m; ++k) {
+        const int im = (s >> k) & 1;
+        x[k] = &parts[k][im];
+        k_im += im;
+      }
+      cj.jobs.push_back(plan_real(B, x, m));
+      cj.ipow.push_back(k_im);
     }
-    int rc;
-    if ((rc = d2(ar, gar, br, gbr, rr)) || (rc = d2(ai, gai, bi, gbi, ii)) ||
-        (rc = d2(ar, gar, bi, gbi, ri)) || (rc = d2(ai, gai, br, gbr, ir)))
-      return rc;
-    out.assign(Q, cplx(0.0));
-    for (int i = 0; i < Q; ++i) out[i] = cplx(rr[i] - ii[i], ri[i] + ir[i]);
-    return LBM_OK;
+    return cj;
+  }
+  cvec read_complex(const ComplexJob &cj, const rvec &out) const {
+    cvec acc(Q, cplx(0.0));
+    for (size_t t = 0; t < cj.jobs.size(); ++t) {
+      const int k = cj.ipow[t] & 3;  // i^k: 1, i, -1, -i
+      read_real(cj.jobs[t], out, (k == 2 || k == 3) ? -1.0 : 1.0, acc, k & 1);
+    }
+    return acc;
   }
 
   // The steady wave f at the integer wavevector k (period box) under the per-step source
   // s added after the collision: f = S (J f + s), S = diag(exp(-i kappa . e_i)),
   // kappa = 2 pi k / box (the pull moves node x - e_i's value to x).
-  bool steady(const double k[3], int box, const cvec &s, cvec &f) const {
+  bool steady(const kvec &k, int box, const cvec &s, cvec &f) const {
     const double two_pi = 2.0 * std::acos(-1.0);
     std::vector<cplx> A((size_t)Q * Q);
     f.assign(Q, cplx(0.0));
@@ -230,9 +325,13 @@ class Expansion {
     return solve_complex(Q, A, f);
   }
 
+  bool solve_wave(const kvec &k, int box, const cvec &s, cvec &f) const {
+    return (k[0] == 0 && k[1] == 0 && k[2] == 0) ? steady_mean(s, f) : steady(k, box, s, f);
+  }
+
   // First-order wave of the unit forcing g = p sin(theta) = Re[(-i p) e^{i theta}]: the
   // source is G (-i p).
-  bool first(const double k[3], const double p[3], int box, cvec &f) const {
+  bool first(const kvec &k, const double p[3], int box, cvec &f) const {
     cvec s(Q, cplx(0.0));
     for (int i = 0; i < Q; ++i)
       for (int a = 0; a < 3; ++a) s[i] += G_[(size_t)i * 3 + a] * cplx(0.0, -p[a]);
@@ -240,7 +339,7 @@ class Expansion {
   }
 
  private:
-  NodeCollision C_;
+  lbm_params q_;
   rvec f0_, J_, G_;
 
  public:
@@ -272,12 +371,29 @@ int check_problem(const lbm_params *params, const lbm_ws_problem *p, int box) {
   const bool two_d = params->lattice == LBM_D2Q9;
   for (int j = 0; j < p->nmodes; ++j) {
     const double *k = p->k[j];
+    for (int a = 0; a < 3; ++a)
+      if (!(std::abs(k[a]) <= 1e6) || k[a] != std::nearbyint(k[a]))
+        return set_error(LBM_EINVAL, "mode %d: k must be integers", j);
     if (k[0] == 0 && k[1] == 0 && k[2] == 0)
       return set_error(LBM_EINVAL, "mode %d has k = 0", j);
     if (two_d && (k[2] != 0 || p->p[j][2] != 0))
       return set_error(LBM_EINVAL, "mode %d: a D2Q9 mode must lie in the x-y plane", j);
   }
   return LBM_OK;
+}
+
+kvec kint(const double k[3]) {
+  return {(int)std::lround(k[0]), (int)std::lround(k[1]), (int)std::lround(k[2])};
+}
+kvec add(const kvec &a, const kvec &b, int sb) {
+  return {a[0] + sb * b[0], a[1] + sb * b[1], a[2] + sb * b[2]};
+}
+// A wave Re[X e^{i k.x}] equals Re[conj(X) e^{-i k.x}]: the canonical wavevector has its
+// first nonzero component positive.
+bool flip(const kvec &k) {
+  for (int a = 0; a < 3; ++a)
+    if (k[a] != 0) return k[a] < 0;
+  return false;
 }
 
 }  // namespace
@@ -298,7 +414,7 @@ extern "C" int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_pr
     const double *pol = p->p[j];
     const double K = two_pi * std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]) / box;
     cvec f;
-    if (!X.first(k, pol, box, f))
+    if (!X.first(kint(k), pol, box, f))
       return set_error(LBM_EINVAL, "mode %d: the linearised step is singular", j);
     // density and physical velocity u = j/rho + g/2 to first order about rest
     cplx rho = 0, u[3] = {0, 0, 0};
@@ -328,9 +444,9 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
   if (!k_out || !phase_out || !amp_out || !count) return set_error(LBM_EINVAL, "NULL argument");
   int rc = check_problem(params, p, box);
   if (rc) return rc;
-  if (order != 1 && order != 2) return set_error(LBM_EINVAL, "order = %d must be 1 or 2", order);
+  if (order < 1 || order > 3) return set_error(LBM_EINVAL, "order = %d must be 1, 2 or 3", order);
   const int n = p->nmodes;
-  const int need = order == 1 ? n : n + n * (n + 1);
+  const int need = lbm_ws_max_waves(n, order);
   if (max_waves < need)
     return set_error(LBM_EINVAL, "max_waves = %d is below %d", (int)max_waves, need);
   const lbm_params q = one_node_params(*params);
@@ -338,53 +454,154 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
   if ((rc = X.build())) return rc;
   const int Q = X.Q;
   int w = 0;
-  auto emit = [&](const double k[3], double phase, const cvec &amp, double scale) {
-    for (int a = 0; a < 3; ++a) k_out[3 * w + a] = (int32_t)std::lround(k[a]);
+  auto emit = [&](const kvec &k, double phase, const cvec &amp, cplx scale) {
+    for (int a = 0; a < 3; ++a) k_out[3 * w + a] = k[a];
     phase_out[w] = phase;
     for (int i = 0; i < Q; ++i) {
-      amp_out[((size_t)w * Q + i) * 2] = scale * amp[i].real();
-      amp_out[((size_t)w * Q + i) * 2 + 1] = scale * amp[i].imag();
+      const cplx v = scale * amp[i];
+      amp_out[((size_t)w * Q + i) * 2] = v.real();
+      amp_out[((size_t)w * Q + i) * 2 + 1] = v.imag();
     }
     ++w;
   };
-  // first order: each mode's own wave; the direction of the expansion is (f1, -i p)
-  std::vector<cvec> f1(n);
-  std::vector<gcvec> g1(n);
+  // First order: each mode's own wave.  a_j = amp_j e^{i phase_j} (f_j, -i p_j) is the
+  // mode's direction of the expansion in (populations, g) with its phase folded in, so
+  // the first-order state is sum_j Re[a_j e^{i kappa_j . x}].
+  std::vector<Dir> a1(n);
+  std::vector<kvec> k1(n);
   for (int j = 0; j < n; ++j) {
-    if (!X.first(p->k[j], p->p[j], box, f1[j]))
+    k1[j] = kint(p->k[j]);
+    cvec f;
+    if (!X.first(k1[j], p->p[j], box, f))
       return set_error(LBM_EINVAL, "mode %d: the linearised step is singular", j);
-    for (int a = 0; a < 3; ++a) g1[j][a] = cplx(0.0, -p->p[j][a]);
-    emit(p->k[j], p->phase[j], f1[j], p->amp[j]);
+    emit(k1[j], p->phase[j], f, p->amp[j]);
+    Dir d;
+    d.f = f;
+    for (int a = 0; a < 3; ++a) d.g[a] = cplx(0.0, -p->p[j][a]);
+    a1[j] = scaled(d, std::polar(p->amp[j], p->phase[j]));
   }
-  // second order: the collision's second derivative on two first-order waves drives the
-  // waves theta_i + theta_j and theta_i - theta_j (i <= j).  With
-  // Re[a e^{i alpha}] Re[b e^{i beta}] = (Re[a b e^{i(alpha+beta)}] +
-  // Re[a conj(b) e^{i(alpha-beta)}]) / 2 and the Taylor factor 1/2, the source of a sum
-  // wave is a_i a_j D2(z_i, z_j) / 2 and that of a difference wave
-  // a_i a_j D2(z_i, conj z_j) / 2, each 1/4 instead when i = j (the orderings (i, j) and
+  if (order == 1) {
+    *count = w;
+    return LBM_OK;
+  }
+  struct Item {
+    kvec k;
+    double c;
+    Expansion::ComplexJob job;
+  };
+  // Second order: the Taylor term D2(delta, delta) / 2 of the collision with
+  // delta = sum_j Re[a_j e^{i theta_j}].  By Re[a e^{i alpha}] Re[b e^{i beta}] =
+  // (Re[a b e^{i(alpha+beta)}] + Re[a conj(b) e^{i(alpha-beta)}]) / 2, each pair i <= j
+  // drives the wave k_i + k_j with source D2(a_i, a_j) / 2 and the wave k_i - k_j with
+  // source D2(a_i, conj a_j) / 2, each 1/4 instead when i = j (the orderings (i, j) and
   // (j, i) coincide).  A wave of zero wavevector (the mean part, always present for
   // i = j) is the steady mean.
-  if (order == 2)
+  struct Wave {
+    kvec k;
+    cvec f;  // population amplitude, phase folded in
+  };
+  std::vector<Wave> w2;
+  {
+    CollisionBatch B = X.batch();
+    std::vector<Item> items;
+    std::vector<Dir> ac(n);
+    for (int j = 0; j < n; ++j) ac[j] = conj(a1[j]);
     for (int i = 0; i < n; ++i)
       for (int j = i; j < n; ++j)
         for (int sgn : {1, -1}) {
-          double kq[3];
-          for (int a = 0; a < 3; ++a) kq[a] = p->k[i][a] + sgn * p->k[j][a];
-          const bool mean = kq[0] == 0 && kq[1] == 0 && kq[2] == 0;
-          cvec zb = f1[j];
-          gcvec gb = g1[j];
-          if (sgn < 0) {
-            for (auto &v : zb) v = std::conj(v);
-            for (auto &v : gb) v = std::conj(v);
-          }
-          cvec src, f2;
-          if ((rc = X.d2c(f1[i], g1[i], zb, gb, src))) return rc;
-          if (!(mean ? X.steady_mean(src, f2) : X.steady(kq, box, src, f2)))
-            return set_error(LBM_EINVAL, "wave of modes (%d, %d): the linearised step is singular",
-                             i, j);
-          const double scale = p->amp[i] * p->amp[j] * (i == j ? 0.25 : 0.5);
-          emit(kq, p->phase[i] + sgn * p->phase[j], f2, scale);
+          const Dir *d[2] = {&a1[i], sgn > 0 ? &a1[j] : &ac[j]};
+          items.push_back({add(k1[i], k1[j], sgn), i == j ? 0.25 : 0.5,
+                           X.plan_complex(B, d, 2)});
         }
+    rvec out;
+    if ((rc = B.run(out))) return rc;
+    for (const Item &it : items) {
+      cvec src = X.read_complex(it.job, out), f2;
+      for (auto &v : src) v *= it.c;
+      if (!X.solve_wave(it.k, box, src, f2))
+        return set_error(LBM_EINVAL, "a second-order wave: the linearised step is singular");
+      emit(it.k, 0.0, f2, 1.0);
+      w2.push_back({it.k, f2});
+    }
+  }
+  if (order == 2) {
+    *count = w;
+    return LBM_OK;
+  }
+  // Third order: the cross term D2(delta1, delta2) of the second-order Taylor term (the
+  // first-order directions a_j against the second-order population waves b_w, which
+  // carry no acceleration) and the cubic term D3(delta1, delta1, delta1) / 6.
+  //   cross: each (j, w) drives k_j + q_w with D2(a_j, b_w) / 2 and k_j - q_w with
+  //     D2(a_j, conj b_w) / 2;
+  //   cubic: with delta1 = sum over the 2n signed components c of (a_c e^{i k_c . x}) / 2
+  //     (a_c = a_j or conj a_j, k_c = +-k_j), the term is
+  //     sum over ordered triples D3(a_c1, a_c2, a_c3) e^{i (k_c1 + k_c2 + k_c3) . x} / 48;
+  //     an unordered triple M with m orderings and its conjugate M* (every sign flipped,
+  //     never equal to M) together give Re[m D3(...) / 24 e^{i k_M . x}].
+  // Sources at the same wavevector are summed (a wave at -k as the conjugate at k) and
+  // solved once per wavevector.
+  {
+    CollisionBatch B = X.batch();
+    std::vector<Item> items;
+    std::vector<Dir> b2(w2.size()), b2c(w2.size());
+    for (size_t v = 0; v < w2.size(); ++v) {
+      b2[v].f = w2[v].f;
+      b2c[v] = conj(b2[v]);
+    }
+    for (int j = 0; j < n; ++j)
+      for (size_t v = 0; v < w2.size(); ++v)
+        for (int sgn : {1, -1}) {
+          const Dir *d[2] = {&a1[j], sgn > 0 ? &b2[v] : &b2c[v]};
+          items.push_back({add(k1[j], w2[v].k, sgn), 0.5, X.plan_complex(B, d, 2)});
+        }
+    std::vector<Dir> comp(2 * n);  // signed component c = 2 j + (sign < 0)
+    for (int j = 0; j < n; ++j) {
+      comp[2 * j] = a1[j];
+      comp[2 * j + 1] = conj(a1[j]);
+    }
+    const kvec zero = {0, 0, 0};
+    auto ck = [&](int c) { return (c & 1) ? add(zero, k1[c >> 1], -1) : k1[c >> 1]; };
+    for (int c1 = 0; c1 < 2 * n; ++c1)
+      for (int c2 = c1; c2 < 2 * n; ++c2)
+        for (int c3 = c2; c3 < 2 * n; ++c3) {
+          const std::array<int, 3> m = {c1, c2, c3};
+          std::array<int, 3> mc = {c1 ^ 1, c2 ^ 1, c3 ^ 1};
+          std::sort(mc.begin(), mc.end());
+          if (!(m < mc)) continue;  // one of each conjugate pair
+          const int orderings = (c1 == c2 && c2 == c3) ? 1 : (c1 == c2 || c2 == c3) ? 3 : 6;
+          const Dir *d[3] = {&comp[c1], &comp[c2], &comp[c3]};
+          items.push_back({add(add(ck(c1), ck(c2), 1), ck(c3), 1), orderings / 24.0,
+                           X.plan_complex(B, d, 3)});
+        }
+    rvec out;
+    if ((rc = B.run(out))) return rc;
+    std::map<kvec, cvec> src;
+    for (const Item &it : items) {
+      const cvec s = X.read_complex(it.job, out);
+      kvec k = it.k;
+      const bool fl = flip(k);
+      if (fl) k = {-k[0], -k[1], -k[2]};
+      cvec &acc = src[k];
+      if (acc.empty()) acc.assign(Q, cplx(0.0));
+      for (int i = 0; i < Q; ++i) acc[i] += it.c * (fl ? std::conj(s[i]) : s[i]);
+    }
+    for (const auto &kv : src) {
+      cvec f3;
+      if (!X.solve_wave(kv.first, box, kv.second, f3))
+        return set_error(LBM_EINVAL, "a third-order wave: the linearised step is singular");
+      emit(kv.first, 0.0, f3, 1.0);
+    }
+  }
   *count = w;
   return LBM_OK;
+}
+
+extern "C" int32_t lbm_ws_max_waves(int32_t nmodes, int32_t order) {
+  if (nmodes < 1 || nmodes > 8 || order < 1 || order > 3) return 0;
+  const int32_t n = nmodes;
+  int32_t c = n;                     // first order
+  if (order >= 2) c += n * (n + 1);  // a sum and a difference per pair i <= j
+  if (order >= 3)                    // at most one wavevector per planned item
+    c += 2 * n * n * (n + 1) + (2 * n) * (2 * n + 1) * (2 * n + 2) / 6;
+  return c;
 }

@@ -103,6 +103,11 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise OSError(f"{LIB_PATH} is not built; run python -m paper_2212_07494_amd.build")
+        # torch first: liblbm binds libamdhip64 by soname, so whichever copy of the HIP
+        # runtime is loaded first serves both; loaded before torch's own copy, the
+        # system one leaves torch without a device.  torch supplies device memory and
+        # streams here, so its runtime is the one to share.
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (args, res) in EXPORTS.items():
             fn = getattr(lib, name)
@@ -591,6 +596,7 @@ EXPORTS_NN = {
     "lbm_ws_lattice_waves": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)],
                              C.c_int),
+    "lbm_ws_max_waves": ([C.c_int32, C.c_int32], C.c_int32),
     "lbm_upsample_periodic": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "lbm_ws_compose": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
@@ -734,15 +740,17 @@ def lbm_ws_lattice_response(problem, box, lattice="D3Q27", collision="smrt", tau
 
 def lbm_ws_lattice_waves(problem, box, order=2, lattice="D3Q27", collision="smrt", tau3=1.0,
                          rho0=1.0, **rates):
-    """The steady state of the problem's forced periodic lattice to first or second order
-    in the forcing, as waves for lbm_set_waves: k (n, 3) int32, phase (n,), amp (n, Q)
+    """The steady state of the problem's forced periodic lattice to order 1, 2 or 3 in
+    the forcing, as waves for lbm_set_waves: k (n, 3) int32, phase (n,), amp (n, Q)
     complex; rates as for lbm_ws_lattice_response."""
     s = ws_problem_struct(problem)
     params, keep = make_params(lattice, collision, "f64", (1, 1, 1),
                                tau=(problem["tau2"], tau3, 1.0), rho0=rho0, **rates)
     Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}[lattice.upper()]
     nm = int(s.nmodes)
-    cap = nm + nm * (nm + 1)
+    cap = int(load().lbm_ws_max_waves(nm, int(order)))
+    if cap == 0:
+        raise LBMError(LBM_EINVAL, f"nmodes = {nm} or order = {order} out of range")
     k = np.zeros((cap, 3), np.int32)
     ph = np.zeros(cap, np.float64)
     amp = np.zeros((cap, Q, 2), np.float64)

@@ -93,7 +93,7 @@ class WarmStart:
     FLAGS = L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM | L.RESET_NONEQ
 
     def __init__(self, box=128, widths=WIDTHS, seed=0, max_rows=4096, stream=None,
-                 base_order=BASE_ORDER, flags=None, linear=False, waves=False):
+                 base_order=BASE_ORDER, flags=None, linear=False, waves=False, waves_order=3):
         import torch
         self.torch = torch
         self.box = box
@@ -105,6 +105,7 @@ class WarmStart:
         # analytic base; the network's coefficients then correct each mode's own wave
         # relative to that start (correction_waves)
         self.waves = waves
+        self.waves_order = waves_order
         self.velset = L.lbm_lattice_info("D3Q27") if waves else None
         self.widths = list(widths)
         self.stream = stream
@@ -144,9 +145,9 @@ class WarmStart:
         return L.lbm_ws_lattice_response(problem, self.box, tau3=TAU3)
 
     def lattice_waves(self, problem):
-        """The problem's steady lattice state to second order in the forcing, as
+        """The problem's steady lattice state to order waves_order in the forcing, as
         population waves (k, phase, complex amplitudes)."""
-        return L.lbm_ws_lattice_waves(problem, self.box, order=2, tau3=TAU3)
+        return L.lbm_ws_lattice_waves(problem, self.box, order=self.waves_order, tau3=TAU3)
 
     def correction_waves(self, problem, coef):
         """Each mode's correction (coef: nmodes x 8, the network's output in units of
@@ -340,6 +341,7 @@ class WarmStart:
         with open(path + ".json", "w") as fh:
             json.dump(dict(widths=self.widths, box=self.box, base_order=self.base_order,
                            flags=self.flags, linear=self.linear, waves=self.waves,
+                           waves_order=self.waves_order,
                            scale=self.scale.tolist()), fh)
 
     def load(self, path):
@@ -351,6 +353,7 @@ class WarmStart:
         self.flags = meta["flags"]
         self.linear = bool(meta.get("linear", False))
         self.waves = bool(meta.get("waves", False))
+        self.waves_order = int(meta.get("waves_order", 3))
         self.velset = L.lbm_lattice_info("D3Q27") if self.waves else None
         self.set_scale(meta["scale"])
         self.net.set_params(np.load(path + ".npy", allow_pickle=False))

@@ -121,6 +121,41 @@ def test_second_order_waves_are_the_steady_state_to_third_order(lat, coll):
     assert e2a < 0.05 * e1a and e1a < 0.05 * da, errs
 
 
+@pytest.mark.parametrize("lat,coll", [("D3Q27", "smrt"), ("D2Q9", "bgk")])
+def test_third_order_waves_are_the_steady_state_to_fourth_order(lat, coll):
+    """Order 3 (cross and cubic terms): its error against the converged lattice falls
+    16-fold per halving of the forcing, and is far below order 2's."""
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    box = 16
+    shape = (box, box, 1) if lat == "D2Q9" else (box, box, box)
+    errs = {}
+    for scale in (2.5, 1.25):
+        prob = _problem(lat, scale)
+        k3, ph3, A3 = L.lbm_ws_lattice_waves(prob, box, order=3, lattice=lat, collision=coll)
+        k2, ph2, A2 = L.lbm_ws_lattice_waves(prob, box, order=2, lattice=lat, collision=coll)
+        assert len(k2) < len(k3) <= L.load().lbm_ws_max_waves(2, 3)
+        g = inputs.fourier_force(shape, prob["modes"])
+        with L.Lattice(lat, coll, "f64", shape, (0, 0, 0), (0.8, 1.0, 1.0), g_field=g) as lt:
+            lt.set_waves(k2, ph2, A2)
+            f2 = lt.populations()
+            lt.set_waves(k3, ph3, A3)
+            f3 = lt.populations()
+            lt.step(6000)
+            prev = lt.populations()
+            lt.step(500)
+            fss = lt.populations()
+        e2 = np.abs(fss - f2).max()
+        e3 = np.abs(fss - f3).max()
+        assert np.abs(fss - prev).max() < 1e-2 * e3, (np.abs(fss - prev).max(), e3)
+        errs[scale] = (e2, e3)
+    (e2a, e3a), (e2b, e3b) = errs[2.5], errs[1.25]
+    print(lat, coll, errs)
+    assert 6.5 < e2a / e2b < 9.5, errs
+    assert 12.0 < e3a / e3b < 20.0, errs
+    assert e3a < 0.1 * e2a, errs
+
+
 def test_lattice_waves_first_order_matches_lattice_response():
     """Order 1 of lbm_ws_lattice_waves carries the same linear response that
     lbm_ws_lattice_response reports as mode coefficients: relative to the Stokes amplitude
