@@ -13,6 +13,10 @@ selected by the steps to steady state they give on validation problems.  The con
 lattice-Boltzmann solution decides the prediction's error; the plain start (rest, rho0)
 remains the fallback.
 
+With waves=True the start is instead the lattice's own steady state expanded to order
+1-3 in the forcing amplitude (lbm_ws_lattice_waves), set directly as populations
+(lbm_set_waves), with the network's per-mode output added as equilibrium waves.
+
 torch supplies device buffers and the stream only.
 
 CLI:  python -m paper_2212_07494_amd.warmstart --box 128 --train 80 --val 12 --test 16 --out <dir>
