@@ -257,14 +257,20 @@ def lbm_set_populations(ctx, f):
     _check(load().lbm_set_populations(ctx, _ptr(arr)))
 
 
-def lbm_set_waves(ctx, k, phase, amp):
-    """State w_i rho0 + sum_w Re[amp[w, i] exp(i theta_w)] (lbm_set_waves); k: (n, 3)
-    integers, phase: (n,), amp: (n, Q) complex."""
-    k = np.ascontiguousarray(np.asarray(k).reshape(-1, 3), dtype=np.int32)
+def lbm_set_waves(ctx, Q, k, phase, amp):
+    """State w_i rho0 + sum_w Re[amp[w, i] exp(i theta_w)] (lbm_set_waves) on a context
+    of Q populations; k: (n, 3) integers, phase: (n,), amp: (n, Q) complex."""
+    k = np.asarray(k)
+    if k.ndim != 2 or k.shape[1] != 3 or not np.all(k == np.round(k)):
+        raise ValueError(f"k must be an (n, 3) integer array, got shape {k.shape}")
+    k = np.ascontiguousarray(k, dtype=np.int32)
     n = k.shape[0]
     ph = np.ascontiguousarray(np.asarray(phase, np.float64).reshape(n))
     a = np.asarray(amp, np.complex128)
-    a = a.reshape(n, -1) if n else np.zeros((0, 1), np.complex128)
+    if n and a.shape != (n, Q):
+        raise ValueError(f"amp must have shape ({n}, {Q}), got {a.shape}")
+    if not n:
+        a = np.zeros((0, Q), np.complex128)
     ri = np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))
     _check(load().lbm_set_waves(ctx, n, _ptr(k), _ptr(ph), _ptr(ri)))
 
@@ -376,7 +382,7 @@ class Lattice:
         lbm_set_populations(self.ctx, f)
 
     def set_waves(self, k, phase, amp):
-        lbm_set_waves(self.ctx, k, phase, amp)
+        lbm_set_waves(self.ctx, self.Q, k, phase, amp)
 
     @property
     def time(self):

@@ -201,3 +201,17 @@ def test_set_waves_rejects_invalid_context():
     from paper_2212_07494_amd import lbm
     lib = lbm.load()
     assert lib.lbm_set_waves(None, 0, None, None, None) == lbm.LBM_ESTATE
+
+
+def test_set_waves_binding_checks_shapes():
+    """The binding rejects arrays whose shapes would make the library read past them."""
+    from paper_2212_07494_amd import lbm
+    k = np.zeros((2, 3), np.int32)
+    with pytest.raises(ValueError):
+        lbm.lbm_set_waves(None, 19, k, np.zeros(2), np.zeros((2, 9), complex))
+    with pytest.raises(ValueError):
+        lbm.lbm_set_waves(None, 19, np.zeros((2, 2), np.int32), np.zeros(2),
+                          np.zeros((2, 19), complex))
+    with pytest.raises(ValueError):
+        lbm.lbm_set_waves(None, 19, np.full((2, 3), 0.5), np.zeros(2),
+                          np.zeros((2, 19), complex))
