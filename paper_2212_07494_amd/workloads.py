@@ -32,22 +32,25 @@ def _time(torch, stream, fn, reps):
     return e0.elapsed_time(e1) / reps  # ms
 
 
-def single(torch, stream, name, storage, steps, warmup, collision="smrt"):
+def single(torch, stream, name, storage, steps, warmup, collision="smrt", **options):
+    """One lattice workload; options (force_order, max_order, tau_bulk, tau_31) go to the
+    lattice as in lbm.Lattice and are echoed in the record."""
     if name == "d3q19":
         w = inputs.taylor_green_3d(n=256)
         lat = L.Lattice(w.lattice, collision, storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
-                        g_profile=w.g_profile, stream=stream)
+                        g_profile=w.g_profile, stream=stream, **options)
         desc = f"D3Q19 {collision.upper()} 256^3 periodic, Taylor-Green + sin force"
     elif name == "d3q27":
         p = inputs.warmstart_problem(2022, box=128)
         shape = (128, 128, 128)
         lat = L.Lattice("D3Q27", collision, storage, shape, (0, 0, 0), (p["tau2"], 1.0, 1.0),
-                        g_field=inputs.fourier_force(shape, p["modes"]), stream=stream)
+                        g_field=inputs.fourier_force(shape, p["modes"]), stream=stream,
+                        **options)
         desc = f"D3Q27 {collision.upper()} 128^3 periodic, 4 Fourier forcing modes"
     elif name == "d2q9":
         w = inputs.kolmogorov_box(L=1024)
         lat = L.Lattice(w.lattice, collision, storage, w.shape, w.walls, w.tau, rho=w.rho, u=w.u,
-                        g_profile=w.g_profile, stream=stream)
+                        g_profile=w.g_profile, stream=stream, **options)
         desc = f"D2Q9 {collision.upper()} 1024^2 periodic Kolmogorov flow"
     else:
         raise ValueError(name)
@@ -57,8 +60,8 @@ def single(torch, stream, name, storage, steps, warmup, collision="smrt"):
         ms = _time(torch, stream, lambda: lat.step(steps), 1) / steps
         N, Q = lat.N, lat.Q
     S = L.STORAGE_BYTES[storage]
-    return {"workload": desc, "storage": storage, "nodes": N, "steps": steps,
-            "ms_per_step": round(ms, 5), "MLUPS": round(N / ms / 1e3, 1),
+    return {"workload": desc, "storage": storage, "options": options, "nodes": N,
+            "steps": steps, "ms_per_step": round(ms, 5), "MLUPS": round(N / ms / 1e3, 1),
             "GBps": round(2 * Q * S * N / ms / 1e6, 1),
             "launch": {"block": list(tuning[:2]), "memory_variant": tuning[2]}}
 
@@ -125,7 +128,16 @@ def main():
                     help="collision of the single-lattice workloads")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--force-order", type=int, default=None, choices=[1, 3],
+                    help="SMRT force content (3: with the third-order term)")
+    ap.add_argument("--max-order", type=int, default=None, choices=[4, 6],
+                    help="SMRT on D3Q27: carry orders 5-6 (6)")
+    ap.add_argument("--tau-bulk", type=float, default=None, help="SMRT bulk rate (tau-hat)")
+    ap.add_argument("--tau-31", type=float, default=None, help="SMRT third-order trace rate")
     args = ap.parse_args()
+    options = {k: v for k, v in (("force_order", args.force_order),
+                                 ("max_order", args.max_order), ("tau_bulk", args.tau_bulk),
+                                 ("tau_31", args.tau_31)) if v is not None}
     import torch
     L.load()
     stream = torch.cuda.Stream()
@@ -135,7 +147,7 @@ def main():
         rec = womersley(torch, stream, args.storage)
     else:
         rec = single(torch, stream, args.workload, args.storage, args.steps, args.warmup,
-                     args.collision)
+                     args.collision, **options)
     print(json.dumps(rec), flush=True)
 
 
