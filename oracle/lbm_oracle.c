@@ -31,8 +31,10 @@
  * over x, y, z.  Constants are exact rationals rounded once.  The SMRT and RMRT
  * projection, central shift, back-shift and reconstruction accumulate each term
  * with one fused multiply-add (fmar); in the shifts the binomial coefficient (a
- * power of two on these lattices, so exactly) scales u^l first.  Nothing else is
- * fused.  Compiled with
+ * power of two on these lattices, so exactly) scales u^l first.  The SMRT projection
+ * and reconstruction are folded over the opposite-velocity pairs of the population order
+ * (project_folded, reconstruct_folded); the RMRT ones run over the populations in index
+ * order.  Nothing else is fused.  Compiled with
  * -ffp-contract=off, no fast-math.
  */
 #include <math.h>
@@ -262,15 +264,82 @@ static void make_plan(const oracle_lattice *L, smrt_plan *S) {
   }
 }
 
+/* The population order pairs each velocity with its opposite, (e, -e) at i = 2p-1, 2p
+ * after the rest population i = 0, and H_m(-e) = (-1)^|m| H_m(e).  So a raw moment of
+ * even order is a sum over the pair sums f_{2p-1} + f_{2p} and one of odd order over the
+ * pair differences (the rest population enters only even moments), and the same split
+ * holds for the rows of the inverse transform.  The collisions that use it check the
+ * tables once: both relations must hold exactly. */
+static void check_pair_symmetry(const oracle_lattice *L) {
+  const int NM = L->NM, Q = L->Q;
+  for (int k = 0; k < NM; ++k) {
+    const real sg = (mabs(L->mi + 3 * k) % 2) ? (real)-1 : (real)1;
+    if (sg < 0 && (L->H[k * Q] != 0 || L->Minv[k] != 0)) abort();
+    for (int i = 1; i + 1 < Q; i += 2)
+      if (L->H[k * Q + i + 1] != sg * L->H[k * Q + i] ||
+          L->Minv[(i + 1) * NM + k] != sg * L->Minv[i * NM + k])
+        abort();
+  }
+}
+
+/* Raw moment k of f folded over the pairs: the rest population, then pair p = 1, 2, ...
+ * with its sum s_p (even order) or difference a_p (odd order), each term one fma from
+ * -0.0, zero coefficients skipped. */
+static real project_folded(const oracle_lattice *L, int k, const real *f, const real *s,
+                           const real *a) {
+  const int Q = L->Q;
+  const int odd = mabs(L->mi + 3 * k) % 2;
+  real A = -0.0;
+  if (L->H[k * Q] != 0) A = fmar(L->H[k * Q], f[0], A);
+  for (int p = 1; 2 * p < Q; ++p) {
+    real h = L->H[k * Q + 2 * p - 1];
+    if (h != 0) A = fmar(h, odd ? a[p] : s[p], A);
+  }
+  return A;
+}
+
+/* f + Minv dA folded over the pairs: the rest population sums its row over k = 1..NM-1;
+ * each pair sums its first member's row separately over the even-order and the odd-order
+ * moments (E, O, each from -0.0 in k order, one fma a term, zeros skipped) and takes
+ * f_{2p-1} + (E + O), f_{2p} + (E - O). */
+static void reconstruct_folded(const oracle_lattice *L, const real *f, const real *dA,
+                               real *out) {
+  const int Q = L->Q, NM = L->NM;
+  real acc = -0.0;
+  for (int k = 1; k < NM; ++k) {
+    real c = L->Minv[k];
+    if (c != 0) acc = fmar(c, dA[k], acc);
+  }
+  out[0] = f[0] + acc;
+  for (int p = 1; 2 * p < Q; ++p) {
+    const int i = 2 * p - 1;
+    real ev = -0.0, od = -0.0;
+    for (int k = 1; k < NM; ++k) {
+      real c = L->Minv[i * NM + k];
+      if (c == 0) continue;
+      if (mabs(L->mi + 3 * k) % 2)
+        od = fmar(c, dA[k], od);
+      else
+        ev = fmar(c, dA[k], ev);
+    }
+    out[i] = f[i] + (ev + od);
+    out[i + 1] = f[i + 1] + (ev - od);
+  }
+}
+
 static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const smrt_plan *S,
                          const real *f, const real g[3], real *out) {
   macro_t M;
   macroscopic(L, P, f, g, &M);
   const int NM = L->NM;
-  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ], D2[MAXQ], D3[MAXQ];
+  real U[MAXQ], E[MAXQ], N[MAXQ], Pc[MAXQ], D2[MAXQ], D3[MAXQ], ps[MAXQ], pa[MAXQ];
   for (int k = 0; k < NM; ++k) {
     U[k] = upow(L->mi + 3 * k, M.u);
     E[k] = M.rho * U[k];
+  }
+  for (int p = 1; 2 * p < L->Q; ++p) {
+    ps[p] = f[2 * p - 1] + f[2 * p];
+    pa[p] = f[2 * p - 1] - f[2 * p];
   }
   /* non-equilibrium raw moments */
   for (int k = 0; k < NM; ++k) {
@@ -281,12 +350,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       int a = m[0] ? 0 : (m[1] ? 1 : 2);
       N[k] = (real)-0.5 * M.F[a];
     } else if (n == 2 || n == 3) {
-      real A = -0.0;
-      for (int i = 0; i < L->Q; ++i) {
-        real h = L->H[k * L->Q + i];
-        if (h != 0) A = fmar(h, f[i], A);
-      }
-      N[k] = A - E[k];
+      N[k] = project_folded(L, k, f, ps, pa) - E[k];
     }
   }
   /* shift to the moving frame, relax */
@@ -376,11 +440,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
     /* pre-collision raw moment of order >= 4 (orders 2, 3 are already in N) */
     real Nk = N[k];
     if (n >= 4) {
-      real A = -0.0;
-      for (int i = 0; i < L->Q; ++i) {
-        real h = L->H[k * L->Q + i];
-        if (h != 0) A = fmar(h, f[i], A);
-      }
+      real A = project_folded(L, k, f, ps, pa);
       if (n > 4 && P->max_order < n) { /* orders above 4 are not carried: a*_m = 0 */
         dA[k] = -A;
         continue;
@@ -399,14 +459,7 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
     dA[k] = R - Nk;
   }
   /* eq:evolution: f-bar + Omega + F, the increment reconstructed from dA */
-  for (int i = 0; i < L->Q; ++i) {
-    real acc = -0.0;
-    for (int k = 1; k < NM; ++k) {
-      real c = L->Minv[i * NM + k];
-      if (c != 0) acc = fmar(c, dA[k], acc);
-    }
-    out[i] = f[i] + acc;
-  }
+  reconstruct_folded(L, f, dA, out);
 }
 
 /* ---- raw-moment MRT (the appendix: eq:RHS_a in its explicit form, eq:bbd1) ------- */
@@ -492,6 +545,7 @@ void oracle_collide_node(const oracle_lattice *L, const oracle_params *P, const 
                          const real *g, real *out) {
   smrt_plan S;
   make_plan(L, &S);
+  check_pair_symmetry(L);
   collide(L, P, &S, f, g, out);
 }
 
@@ -580,6 +634,7 @@ void oracle_step(const oracle_lattice *L, const oracle_params *P, const real *f,
   const int dims[3] = {nx, ny, nz};
   smrt_plan S;
   make_plan(L, &S);
+  check_pair_symmetry(L);
 #pragma omp parallel for schedule(static)
   for (int z = 0; z < nz; ++z) {
     for (int y = 0; y < ny; ++y) {

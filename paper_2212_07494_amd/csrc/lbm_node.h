@@ -177,6 +177,25 @@ constexpr int trace_partner3(int k) {
   return -1;
 }
 
+// The population order pairs each velocity with its opposite, (e, -e) at i = 2p-1, 2p
+// after the rest population, and H_m(-e) = (-1)^|m| H_m(e): an even-order moment is a sum
+// over the pair sums, an odd-order one over the pair differences (the rest population
+// enters only even moments), and the rows of the inverse transform split the same way.
+// Whether L's tables in type T obey this exactly (required by the folded transforms).
+template <class L, class T>
+constexpr bool pair_symmetric() {
+  for (int k = 0; k < L::NM; ++k) {
+    const T sg = (L::ORD[k] % 2) ? T(-1) : T(1);
+    if (sg < T(0) && (Tab<L, T>::h(k, 0) != T(0) || Tab<L, T>::minv(0, k) != T(0)))
+      return false;
+    for (int i = 1; i + 1 < L::Q; i += 2)
+      if (Tab<L, T>::h(k, i + 1) != sg * Tab<L, T>::h(k, i) ||
+          Tab<L, T>::minv(i + 1, k) != sg * Tab<L, T>::minv(i, k))
+        return false;
+  }
+  return true;
+}
+
 // Index of the multi-index MI[k] - e_a in L's canonical list (-1 if absent).
 template <class L>
 constexpr int sub_index(int k, int a) {
@@ -265,12 +284,21 @@ template <class L, bool HI56, class T>
 __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)[3],
                                              const SMRTCoef<T> &c) {
   constexpr int NM = L::NM;
+  constexpr int NP = (L::Q - 1) / 2;  // opposite-velocity pairs
+  static_assert(pair_symmetric<L, T>());
   const Macro<T> M = macroscopic<L>(d, shift, g);
   T U[NM], E[NM], N[NM], P[NM], dA[NM], C2[NM];
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     U[k] = upow<L, k>(M.u);
     E[k] = M.rho * U[k];
+  });
+  // pair sums and differences, p = 1..NP (index 0 unused)
+  T ps[NP + 1], pa[NP + 1];
+  static_for<NP>([&](auto Pp) {
+    constexpr int p = decltype(Pp)::value + 1;
+    ps[p] = d[2 * p - 1] + d[2 * p];
+    pa[p] = d[2 * p - 1] - d[2 * p];
   });
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
@@ -279,11 +307,15 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
       N[k] = T(-0.5) * M.F[a];
     } else if constexpr (n >= 2) {
+      // folded projection: the rest population, then each pair's sum (even n) or
+      // difference (odd n)
       T acc = T(-0.0);
-      static_for<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr T h = Tab<L, T>::h(k, i);
-        if constexpr (h != T(0)) acc = fmadd(h, d[i], acc);
+      constexpr T h0 = Tab<L, T>::h(k, 0);
+      if constexpr (h0 != T(0)) acc = fmadd(h0, d[0], acc);
+      static_for<NP>([&](auto Pp) {
+        constexpr int p = decltype(Pp)::value + 1;
+        constexpr T h = Tab<L, T>::h(k, 2 * p - 1);
+        if constexpr (h != T(0)) acc = fmadd(h, (n % 2) ? pa[p] : ps[p], acc);
       });
       // orders 2..4: non-equilibrium part; above 4: the raw moment itself
       if constexpr (n <= 4)
@@ -379,15 +411,33 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       dA[k] = R - N[k];
     }
   });
-  static_for<L::Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
+  // folded reconstruction: the rest population sums its row; each pair sums its first
+  // member's row over the even- and the odd-order moments apart (E, O) and takes
+  // f_{2p-1} + (E + O), f_{2p} + (E - O)
+  {
     T acc = T(-0.0);
     static_for<NM>([&](auto K) {
       constexpr int k = decltype(K)::value;
-      constexpr T cf = Tab<L, T>::minv(i, k);
+      constexpr T cf = Tab<L, T>::minv(0, k);
       if constexpr (k > 0 && cf != T(0)) acc = fmadd(cf, dA[k], acc);
     });
-    d[i] = d[i] + acc;
+    d[0] = d[0] + acc;
+  }
+  static_for<NP>([&](auto Pp) {
+    constexpr int i = 2 * decltype(Pp)::value + 1;
+    T ev = T(-0.0), od = T(-0.0);
+    static_for<NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr T cf = Tab<L, T>::minv(i, k);
+      if constexpr (k > 0 && cf != T(0)) {
+        if constexpr (L::ORD[k] % 2)
+          od = fmadd(cf, dA[k], od);
+        else
+          ev = fmadd(cf, dA[k], ev);
+      }
+    });
+    d[i] = d[i] + (ev + od);
+    d[i + 1] = d[i + 1] + (ev - od);
   });
 }
 
