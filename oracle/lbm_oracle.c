@@ -31,10 +31,10 @@
  * over x, y, z.  Constants are exact rationals rounded once.  The SMRT and RMRT
  * projection, central shift, back-shift and reconstruction accumulate each term
  * with one fused multiply-add (fmar); in the shifts the binomial coefficient (a
- * power of two on these lattices, so exactly) scales u^l first.  The SMRT projection
- * and reconstruction are folded over the opposite-velocity pairs of the population order
- * (project_folded, reconstruct_folded); the RMRT ones run over the populations in index
- * order.  Nothing else is fused.  Compiled with
+ * power of two on these lattices, so exactly) scales u^l first.  The SMRT and RMRT
+ * projections and reconstructions are folded over the opposite-velocity pairs of the
+ * population order (project_folded, reconstruct_folded).  Nothing else is fused.
+ * Compiled with
  * -ffp-contract=off, no fast-math.
  */
 #include <math.h>
@@ -478,8 +478,12 @@ static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const 
   macro_t M;
   macroscopic(L, P, f, g, &M);
   const int NM = L->NM;
-  real U[MAXQ], dA[MAXQ];
+  real U[MAXQ], dA[MAXQ], ps[MAXQ], pa[MAXQ];
   for (int k = 0; k < NM; ++k) U[k] = upow(L->mi + 3 * k, M.u);
+  for (int p = 1; 2 * p < L->Q; ++p) {
+    ps[p] = f[2 * p - 1] + f[2 * p];
+    pa[p] = f[2 * p - 1] - f[2 * p];
+  }
   for (int k = 0; k < NM; ++k) {
     const int32_t *m = L->mi + 3 * k;
     int n = mabs(m);
@@ -492,11 +496,7 @@ static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const 
       dA[k] = M.F[a];
       continue;
     }
-    real A = -0.0;
-    for (int i = 0; i < L->Q; ++i) {
-      real h = L->H[k * L->Q + i];
-      if (h != 0) A = fmar(h, f[i], A);
-    }
+    real A = project_folded(L, k, f, ps, pa);
     if (n > 4) {
       dA[k] = -A;
       continue;
@@ -521,14 +521,7 @@ static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const 
     }
     dA[k] = t - N;
   }
-  for (int i = 0; i < L->Q; ++i) {
-    real acc = -0.0;
-    for (int k = 1; k < NM; ++k) {
-      real c = L->Minv[i * NM + k];
-      if (c != 0) acc = fmar(c, dA[k], acc);
-    }
-    out[i] = f[i] + acc;
-  }
+  reconstruct_folded(L, f, dA, out);
 }
 
 static void collide(const oracle_lattice *L, const oracle_params *P, const smrt_plan *S,

@@ -196,6 +196,69 @@ constexpr bool pair_symmetric() {
   return true;
 }
 
+// The populations folded over their pairs, p = 1..NP (index 0 unused): sums s_p =
+// d_{2p-1} + d_{2p} and differences a_p = d_{2p-1} - d_{2p}.
+template <class L, class T>
+struct PairFold {
+  static constexpr int NP = (L::Q - 1) / 2;
+  T s[NP + 1], a[NP + 1];
+  __device__ __forceinline__ explicit PairFold(const T (&d)[L::Q]) {
+    static_assert(pair_symmetric<L, T>());
+    static_for<NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value + 1;
+      s[p] = d[2 * p - 1] + d[2 * p];
+      a[p] = d[2 * p - 1] - d[2 * p];
+    });
+  }
+  // Raw moment k (order >= 1): from -0.0, the rest population, then each pair's sum (even
+  // order) or difference (odd order), one fma a nonzero term.
+  template <int k>
+  __device__ __forceinline__ T project(const T (&d)[L::Q]) const {
+    constexpr bool odd = L::ORD[k] % 2;
+    T acc = T(-0.0);
+    constexpr T h0 = Tab<L, T>::h(k, 0);
+    if constexpr (h0 != T(0)) acc = fmadd(h0, d[0], acc);
+    static_for<NP>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value + 1;
+      constexpr T h = Tab<L, T>::h(k, 2 * p - 1);
+      if constexpr (h != T(0)) acc = fmadd(h, odd ? a[p] : s[p], acc);
+    });
+    return acc;
+  }
+};
+
+// d += M^-1 dA folded over the pairs: the rest population sums its row over k >= 1; each
+// pair sums its first member's row over the even- and the odd-order moments apart (E, O,
+// each from -0.0 in k order, one fma a nonzero term) and takes d_{2p-1} + (E + O),
+// d_{2p} + (E - O).
+template <class L, class T>
+__device__ __forceinline__ void reconstruct_folded(T (&d)[L::Q], const T (&dA)[L::NM]) {
+  static_assert(pair_symmetric<L, T>());
+  T acc = T(-0.0);
+  static_for<L::NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr T cf = Tab<L, T>::minv(0, k);
+    if constexpr (k > 0 && cf != T(0)) acc = fmadd(cf, dA[k], acc);
+  });
+  d[0] = d[0] + acc;
+  static_for<(L::Q - 1) / 2>([&](auto Pp) {
+    constexpr int i = 2 * decltype(Pp)::value + 1;
+    T ev = T(-0.0), od = T(-0.0);
+    static_for<L::NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr T cf = Tab<L, T>::minv(i, k);
+      if constexpr (k > 0 && cf != T(0)) {
+        if constexpr (L::ORD[k] % 2)
+          od = fmadd(cf, dA[k], od);
+        else
+          ev = fmadd(cf, dA[k], ev);
+      }
+    });
+    d[i] = d[i] + (ev + od);
+    d[i + 1] = d[i + 1] + (ev - od);
+  });
+}
+
 // Index of the multi-index MI[k] - e_a in L's canonical list (-1 if absent).
 template <class L>
 constexpr int sub_index(int k, int a) {
@@ -284,8 +347,6 @@ template <class L, bool HI56, class T>
 __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)[3],
                                              const SMRTCoef<T> &c) {
   constexpr int NM = L::NM;
-  constexpr int NP = (L::Q - 1) / 2;  // opposite-velocity pairs
-  static_assert(pair_symmetric<L, T>());
   const Macro<T> M = macroscopic<L>(d, shift, g);
   T U[NM], E[NM], N[NM], P[NM], dA[NM], C2[NM];
   static_for<NM>([&](auto K) {
@@ -293,13 +354,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
     U[k] = upow<L, k>(M.u);
     E[k] = M.rho * U[k];
   });
-  // pair sums and differences, p = 1..NP (index 0 unused)
-  T ps[NP + 1], pa[NP + 1];
-  static_for<NP>([&](auto Pp) {
-    constexpr int p = decltype(Pp)::value + 1;
-    ps[p] = d[2 * p - 1] + d[2 * p];
-    pa[p] = d[2 * p - 1] - d[2 * p];
-  });
+  const PairFold<L, T> pf(d);
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int n = L::ORD[k];
@@ -307,16 +362,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
       N[k] = T(-0.5) * M.F[a];
     } else if constexpr (n >= 2) {
-      // folded projection: the rest population, then each pair's sum (even n) or
-      // difference (odd n)
-      T acc = T(-0.0);
-      constexpr T h0 = Tab<L, T>::h(k, 0);
-      if constexpr (h0 != T(0)) acc = fmadd(h0, d[0], acc);
-      static_for<NP>([&](auto Pp) {
-        constexpr int p = decltype(Pp)::value + 1;
-        constexpr T h = Tab<L, T>::h(k, 2 * p - 1);
-        if constexpr (h != T(0)) acc = fmadd(h, (n % 2) ? pa[p] : ps[p], acc);
-      });
+      const T acc = pf.template project<k>(d);
       // orders 2..4: non-equilibrium part; above 4: the raw moment itself
       if constexpr (n <= 4)
         N[k] = acc - E[k];
@@ -411,34 +457,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       dA[k] = R - N[k];
     }
   });
-  // folded reconstruction: the rest population sums its row; each pair sums its first
-  // member's row over the even- and the odd-order moments apart (E, O) and takes
-  // f_{2p-1} + (E + O), f_{2p} + (E - O)
-  {
-    T acc = T(-0.0);
-    static_for<NM>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      constexpr T cf = Tab<L, T>::minv(0, k);
-      if constexpr (k > 0 && cf != T(0)) acc = fmadd(cf, dA[k], acc);
-    });
-    d[0] = d[0] + acc;
-  }
-  static_for<NP>([&](auto Pp) {
-    constexpr int i = 2 * decltype(Pp)::value + 1;
-    T ev = T(-0.0), od = T(-0.0);
-    static_for<NM>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      constexpr T cf = Tab<L, T>::minv(i, k);
-      if constexpr (k > 0 && cf != T(0)) {
-        if constexpr (L::ORD[k] % 2)
-          od = fmadd(cf, dA[k], od);
-        else
-          ev = fmadd(cf, dA[k], ev);
-      }
-    });
-    d[i] = d[i] + (ev + od);
-    d[i + 1] = d[i + 1] + (ev - od);
-  });
+  reconstruct_folded<L>(d, dA);
 }
 
 // Raw-moment MRT with force (the paper's appendix, eq:RHS_a in its explicit form): every
@@ -464,6 +483,7 @@ __device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)
     constexpr int k = decltype(K)::value;
     U[k] = upow<L, k>(M.u);
   });
+  const PairFold<L, T> pf(d);
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int n = L::ORD[k];
@@ -473,12 +493,7 @@ __device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
       dA[k] = M.F[a];
     } else {
-      T acc = T(-0.0);
-      static_for<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr T h = Tab<L, T>::h(k, i);
-        if constexpr (h != T(0)) acc = fmadd(h, d[i], acc);
-      });
+      const T acc = pf.template project<k>(d);
       if constexpr (n > 4) {
         dA[k] = -acc;
       } else {
@@ -503,16 +518,7 @@ __device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)
       }
     }
   });
-  static_for<L::Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    T acc = T(-0.0);
-    static_for<NM>([&](auto K) {
-      constexpr int k = decltype(K)::value;
-      constexpr T cf = Tab<L, T>::minv(i, k);
-      if constexpr (k > 0 && cf != T(0)) acc = fmadd(cf, dA[k], acc);
-    });
-    d[i] = d[i] + acc;
-  });
+  reconstruct_folded<L>(d, dA);
 }
 
 // Initial stored state f-bar = f_eq - F_i/2 (eq:newf with Omega = 0): density and
