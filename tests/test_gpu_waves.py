@@ -122,7 +122,8 @@ def _problem(lat, scale):
     return dict(tau2=0.8, modes=modes)
 
 
-@pytest.mark.parametrize("lat,coll", [("D3Q27", "smrt"), ("D2Q9", "bgk"), ("D3Q19", "smrt")])
+@pytest.mark.parametrize("lat,coll", [("D3Q27", "smrt"), ("D2Q9", "bgk"), ("D3Q19", "smrt"),
+                                      ("D3Q27", "rmrt")])
 def test_second_order_waves_are_the_steady_state_to_third_order(lat, coll):
     from paper_2212_07494_amd import lbm as L
     L.load()
@@ -157,7 +158,8 @@ def test_second_order_waves_are_the_steady_state_to_third_order(lat, coll):
     assert e2a < 0.05 * e1a and e1a < 0.05 * da, errs
 
 
-@pytest.mark.parametrize("lat,coll", [("D3Q27", "smrt"), ("D2Q9", "bgk")])
+@pytest.mark.parametrize("lat,coll", [("D3Q27", "smrt"), ("D2Q9", "bgk"), ("D3Q19", "smrt"),
+                                      ("D3Q19", "rmrt")])
 def test_third_order_waves_are_the_steady_state_to_fourth_order(lat, coll):
     """Order 3 (cross and cubic terms): its error against the converged lattice falls
     16-fold per halving of the forcing, and is far below order 2's."""
