@@ -189,7 +189,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU step "
+        print("bench.py runs on one GPU only: it measures the single-GPU step "
               "(--gpus 1); multi-GPU runs are not supported.", file=sys.stderr)
         sys.exit(2)
 

@@ -21,11 +21,12 @@ from tests.helpers import gpu_available
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# Directory that collects the measured errors as JSON lines (precision.jsonl), if set.
+OUT = os.environ.get("LBM_RECORD_DIR", "")
 
 
 def _record(name, data):
-    if os.path.isdir(OUT):
+    if OUT and os.path.isdir(OUT):
         path = os.path.join(OUT, "precision.jsonl")
         with open(path, "a") as fh:
             fh.write(json.dumps({"case": name, **data}) + "\n")
