@@ -106,8 +106,9 @@ def time_to_steady(torch, L, nprob, box=128, seed=2022, tol=1e-8, check_every=20
     """Steps and wall time to a per-step velocity residual below tol from the plain start
     and from the warm start, on nprob seeded problems of the warm-start family (D3Q27
     SMRT, FP64 storage, four Fourier forcing modes).  The warm start is the lattice's own
-    steady state to third order in the forcing (lbm_ws_lattice_waves), set as
-    populations on the device (lbm_set_waves); its wall time includes computing and
+    steady state to third order in the forcing (fourth where the series converges slowly,
+    warmstart.AUTO_ORDER4) (lbm_ws_lattice_waves), set as populations on the device
+    (lbm_set_waves); its wall time includes computing and
     loading the start.  No network correction is applied here (the network's own gain is
     measured by the warm-start tests).  Both runs check the residual every check_every
     steps, which is the resolution of the step counts.  The errors at stop (plain_err,
@@ -144,8 +145,9 @@ def time_to_steady(torch, L, nprob, box=128, seed=2022, tol=1e-8, check_every=20
         m = len(v) // 2
         return round(v[m] if len(v) % 2 else 0.5 * (v[m - 1] + v[m]), 4)
     return {"workload": f"D3Q27 SMRT FP64, {box}^3 periodic, 4 seeded Fourier modes, "
-                        f"resid < {tol:g}", "start": "the lattice's steady state to third order in the forcing, as population "
-                     "waves (exact lattice response of orders 1-3)", "check_every": check_every,
+                        f"resid < {tol:g}", "start": "the lattice's steady state to third order in the forcing (fourth where the "
+                     "series converges slowly), as population waves (exact lattice response)",
+            "check_every": check_every,
             "error_reference": f"converged to a per-step residual below {ref_tol:g}",
             "problems": rows, "median_steps_ratio": med("warm_steps", "plain_steps"),
             "median_plain_err": float(np.median([r["plain_err"] for r in rows])),

@@ -132,7 +132,7 @@ int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_problem *p, i
                             double *coef);
 
 /* The steady state of the forced periodic lattice expanded in the forcing amplitude to
- * order 1, 2 or 3 about rest, as population waves for lbm_set_waves (the state is
+ * order 1 to 4 about rest, as population waves for lbm_set_waves (the state is
  * w_i rho0 + sum_w Re[A_wi exp(i theta_w)]).  C(f, g) below is the collision of one node
  * as this library's step computes it, and a_j = amp_j e^{i phase_j} (f_j, -i p_j) the
  * direction of mode j in (populations, g).
@@ -146,6 +146,10 @@ int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_problem *p, i
  *     triple of signed modes, m D3(a_c1, a_c2, a_c3) / 24 at k_c1 + k_c2 + k_c3 (m its
  *     orderings, a_c = a_j or conj a_j for k_c = +-k_j; each triple counted once with its
  *     all-flipped conjugate).  Sources at one wavevector are summed, one wave each.
+ *   Order 4 adds the waves of D2(delta1, delta3) + D2(delta2, delta2) / 2 +
+ *     D3(delta1, delta1, delta2) / 2 + D4(delta1, delta1, delta1, delta1) / 24, delta_n the
+ *     order-n field written as its conjugate-closed components (k, b/2), (-k, conj b/2),
+ *     tuples within one delta taken as multisets times their orderings.
  * A wave of zero wavevector (a mean part) solves (I - J) f = s with the mean's mass and
  * momentum held at zero.  Waves of order 2 and 3 carry their phase in A (phase 0).  J, G
  * and the derivatives D2, D3 along directions are central differences of the library's
@@ -156,14 +160,14 @@ int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_problem *p, i
  * k_out max_waves x 3, phase_out max_waves, amp_out max_waves x Q x 2 ((re, im) of A_wi
  * at 2 (w Q + i)), count = the waves written; max_waves must be at least
  * lbm_ws_max_waves(nmodes, order).  Uses the device (small contexts).  Errors: those of
- * lbm_ws_lattice_response, and LBM_EINVAL for an order outside 1..3, max_waves below the
+ * lbm_ws_lattice_response, and LBM_EINVAL for an order outside 1..4, max_waves below the
  * bound, a non-integer k or a NULL output. */
 int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_problem *p, int32_t box,
                          int32_t order, int32_t max_waves, int32_t *k_out, double *phase_out,
                          double *amp_out, int32_t *count);
 
-/* The number of waves lbm_ws_lattice_waves may write for nmodes modes (1..8) to order
- * 1..3 (0 for arguments outside those ranges). */
+/* An upper bound on the waves lbm_ws_lattice_waves writes for nmodes modes (1..8) to
+ * order 1..4 (0 for arguments outside those ranges). */
 int32_t lbm_ws_max_waves(int32_t nmodes, int32_t order);
 
 #define LBM_WS_MODE_FEATURES 13

@@ -1,6 +1,6 @@
 // Steady response of the forced periodic lattice to Fourier forcing modes, order by order
 // in the forcing amplitude (lbm_ws_lattice_response: first order, as mode coefficients;
-// lbm_ws_lattice_waves: up to third order, as population waves).  Host code driving the
+// lbm_ws_lattice_waves: up to fourth order, as population waves).  Host code driving the
 // library's own step: the collision's derivatives about rest are central differences of
 // that step, and every wave of the response is one Q x Q complex solve.
 //
@@ -193,7 +193,7 @@ class Expansion {
     return LBM_OK;
   }
 
-  // A real mixed derivative of order m (2 or 3) along m real directions, planned as the
+  // A real mixed derivative of order m (2 to 4) along m real directions, planned as the
   // 2^m points f0 + h sum_k s_k x_k / |x_k| (s_k = +-1) and read out as
   // sum s_1..s_m C / (2^m h^m) times the directions' scales.  A zero direction makes it 0.
   struct RealJob {
@@ -204,12 +204,12 @@ class Expansion {
   RealJob plan_real(CollisionBatch &B, const RDir *const *x, int m) const {
     RealJob j;
     j.m = m;
-    double norm[3];
+    double norm[4];
     for (int k = 0; k < m; ++k) {
       norm[k] = max_abs(*x[k]);
       if (norm[k] == 0) return j;
     }
-    const double h = m == 2 ? 1e-4 : 5e-4;
+    const double h = m == 2 ? 1e-4 : (m == 3 ? 5e-4 : 2e-3);
     rvec f(Q);
     for (int s = 0; s < (1 << m); ++s) {
       gvec g = {0, 0, 0};
@@ -248,13 +248,13 @@ class Expansion {
   };
   ComplexJob plan_complex(CollisionBatch &B, const Dir *const *d, int m) const {
     ComplexJob cj;
-    RDir parts[3][2];
+    RDir parts[4][2];
     for (int k = 0; k < m; ++k) {
       parts[k][0] = part(*d[k], false);
       parts[k][1] = part(*d[k], true);
     }
     for (int s = 0; s < (1 << m); ++s) {
-      const RDir *x[3];
+      const RDir *x[4];
       int k_im = 0;
       for (int k = 0; k < m; ++k) {
         const int im = (s >> k) & 1;
@@ -444,7 +444,7 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
   if (!k_out || !phase_out || !amp_out || !count) return set_error(LBM_EINVAL, "NULL argument");
   int rc = check_problem(params, p, box);
   if (rc) return rc;
-  if (order < 1 || order > 3) return set_error(LBM_EINVAL, "order = %d must be 1, 2 or 3", order);
+  if (order < 1 || order > 4) return set_error(LBM_EINVAL, "order = %d must be 1 to 4", order);
   const int n = p->nmodes;
   const int need = lbm_ws_max_waves(n, order);
   if (max_waves < need)
@@ -455,6 +455,7 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
   const int Q = X.Q;
   int w = 0;
   auto emit = [&](const kvec &k, double phase, const cvec &amp, cplx scale) {
+    if (w >= max_waves) return;  // cannot happen: max_waves covers the bound
     for (int a = 0; a < 3; ++a) k_out[3 * w + a] = k[a];
     phase_out[w] = phase;
     for (int i = 0; i < Q; ++i) {
@@ -500,7 +501,8 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
     kvec k;
     cvec f;  // population amplitude, phase folded in
   };
-  std::vector<Wave> w2;
+  std::vector<Wave> w2, w3;
+  const kvec zero_k = {0, 0, 0};
   {
     CollisionBatch B = X.batch();
     std::vector<Item> items;
@@ -559,8 +561,7 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
       comp[2 * j] = a1[j];
       comp[2 * j + 1] = conj(a1[j]);
     }
-    const kvec zero = {0, 0, 0};
-    auto ck = [&](int c) { return (c & 1) ? add(zero, k1[c >> 1], -1) : k1[c >> 1]; };
+    auto ck = [&](int c) { return (c & 1) ? add(zero_k, k1[c >> 1], -1) : k1[c >> 1]; };
     for (int c1 = 0; c1 < 2 * n; ++c1)
       for (int c2 = c1; c2 < 2 * n; ++c2)
         for (int c3 = c2; c3 < 2 * n; ++c3) {
@@ -590,6 +591,100 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
       if (!X.solve_wave(kv.first, box, kv.second, f3))
         return set_error(LBM_EINVAL, "a third-order wave: the linearised step is singular");
       emit(kv.first, 0.0, f3, 1.0);
+      w3.push_back({kv.first, f3});
+    }
+  }
+  if (order == 3) {
+    *count = w;
+    return LBM_OK;
+  }
+  // Fourth order: D2(delta1, delta3) + D2(delta2, delta2) / 2 + D3(delta1, delta1, delta2) / 2
+  // + D4(delta1, delta1, delta1, delta1) / 24 (the fourth-order part of the Taylor series
+  // of the collision).  Each delta_n is written as its conjugate-closed components
+  // c = (k_c, v_c): (k, b / 2) and (-k, conj b / 2) for a wave Re[b e^{i k.x}], so a
+  // multilinear term is a sum over tuples of components of D(v_c1, ...) e^{i (k_c1 + ...).x}.
+  // Tuples drawn from one delta are taken as unordered multisets times their number of
+  // orderings (the derivatives are symmetric).  The total at -k is the conjugate of that
+  // at k, so only tuples whose wavevector is canonical or zero are evaluated; a canonical
+  // k then carries 2 X_k and the mean X_0.
+  {
+    struct Comp {
+      kvec k;
+      Dir v;
+    };
+    auto comps = [&](const std::vector<Wave> &ws, std::vector<Comp> &out) {
+      for (const Wave &wv : ws) {
+        Dir d;
+        d.f = wv.f;
+        out.push_back({wv.k, scaled(d, 0.5)});
+        out.push_back({add(zero_k, wv.k, -1), scaled(conj(d), 0.5)});
+      }
+    };
+    std::vector<Comp> c1, c2, c3;
+    for (int j = 0; j < n; ++j) {
+      c1.push_back({k1[j], scaled(a1[j], 0.5)});
+      c1.push_back({add(zero_k, k1[j], -1), scaled(conj(a1[j]), 0.5)});
+    }
+    comps(w2, c2);
+    comps(w3, c3);
+    CollisionBatch B = X.batch();
+    std::vector<Item> items;
+    auto plan = [&](std::initializer_list<const Comp *> cs, double coef) {
+      kvec k = zero_k;
+      const Dir *d[4];
+      int m = 0;
+      for (const Comp *c : cs) {
+        k = add(k, c->k, 1);
+        d[m++] = &c->v;
+      }
+      if (flip(k)) return;
+      items.push_back({k, coef, X.plan_complex(B, d, m)});
+    };
+    auto orderings = [](std::initializer_list<int> idx) {
+      // m! / prod(multiplicity!) for a sorted multiset of at most four indices
+      std::vector<int> v(idx);
+      int fact[5] = {1, 1, 2, 6, 24}, den = 1, run = 1;
+      for (size_t t = 1; t <= v.size(); ++t) {
+        if (t < v.size() && v[t] == v[t - 1]) {
+          ++run;
+        } else {
+          den *= fact[run];
+          run = 1;
+        }
+      }
+      return fact[v.size()] / den;
+    };
+    for (const Comp &a : c1)
+      for (const Comp &b : c3) plan({&a, &b}, 1.0);
+    for (size_t i = 0; i < c2.size(); ++i)
+      for (size_t j = i; j < c2.size(); ++j)
+        plan({&c2[i], &c2[j]}, 0.5 * orderings({(int)i, (int)j}));
+    for (size_t i = 0; i < c1.size(); ++i)
+      for (size_t j = i; j < c1.size(); ++j)
+        for (const Comp &c : c2) plan({&c1[i], &c1[j], &c}, 0.5 * orderings({(int)i, (int)j}));
+    for (size_t i = 0; i < c1.size(); ++i)
+      for (size_t j = i; j < c1.size(); ++j)
+        for (size_t k = j; k < c1.size(); ++k)
+          for (size_t l = k; l < c1.size(); ++l)
+            plan({&c1[i], &c1[j], &c1[k], &c1[l]},
+                 orderings({(int)i, (int)j, (int)k, (int)l}) / 24.0);
+    rvec out;
+    if ((rc = B.run(out))) return rc;
+    std::map<kvec, cvec> src;
+    for (const Item &it : items) {
+      const cvec s4 = X.read_complex(it.job, out);
+      cvec &acc = src[it.k];
+      if (acc.empty()) acc.assign(Q, cplx(0.0));
+      for (int i = 0; i < Q; ++i) acc[i] += it.c * s4[i];
+    }
+    for (auto &kv : src) {
+      const bool mean = kv.first == zero_k;
+      if (!mean)
+        for (auto &v : kv.second) v *= 2.0;
+      cvec f4;
+      if (!X.solve_wave(kv.first, box, kv.second, f4))
+        return set_error(LBM_EINVAL, "a fourth-order wave: the linearised step is singular");
+      emit(kv.first, 0.0, f4, 1.0);
     }
   }
   *count = w;
@@ -597,11 +692,20 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
 }
 
 extern "C" int32_t lbm_ws_max_waves(int32_t nmodes, int32_t order) {
-  if (nmodes < 1 || nmodes > 8 || order < 1 || order > 3) return 0;
-  const int32_t n = nmodes;
-  int32_t c = n;                     // first order
-  if (order >= 2) c += n * (n + 1);  // a sum and a difference per pair i <= j
-  if (order >= 3)                    // at most one wavevector per planned item
-    c += 2 * n * n * (n + 1) + (2 * n) * (2 * n + 1) * (2 * n + 2) / 6;
-  return c;
+  if (nmodes < 1 || nmodes > 8 || order < 1 || order > 4) return 0;
+  const int64_t n = nmodes;
+  auto multisets = [](int64_t m, int64_t r) {  // C(m + r - 1, r)
+    int64_t c = 1;
+    for (int64_t t = 1; t <= r; ++t) c = c * (m + t - 1) / t;
+    return c;
+  };
+  const int64_t n2 = n * (n + 1);                                  // second order
+  const int64_t n3 = 2 * n * n2 + multisets(2 * n, 3);             // third order
+  int64_t c = n;                                                   // first order
+  if (order >= 2) c += n2;  // a sum and a difference per pair i <= j
+  if (order >= 3) c += n3;  // at most one wavevector per planned item
+  if (order >= 4)
+    c += 2 * n * 2 * n3 + multisets(2 * n2, 2) + multisets(2 * n, 2) * 2 * n2 +
+         multisets(2 * n, 4);
+  return (int32_t)c;
 }

@@ -746,9 +746,9 @@ def lbm_ws_lattice_response(problem, box, lattice="D3Q27", collision="smrt", tau
 
 def lbm_ws_lattice_waves(problem, box, order=2, lattice="D3Q27", collision="smrt", tau3=1.0,
                          rho0=1.0, **rates):
-    """The steady state of the problem's forced periodic lattice to order 1, 2 or 3 in
-    the forcing, as waves for lbm_set_waves: k (n, 3) int32, phase (n,), amp (n, Q)
-    complex; rates as for lbm_ws_lattice_response."""
+    """The steady state of the problem's forced periodic lattice to order 1 to 4 in the
+    forcing, as waves for lbm_set_waves: k (n, 3) int32, phase (n,), amp (n, Q) complex;
+    rates as for lbm_ws_lattice_response."""
     s = ws_problem_struct(problem)
     params, keep = make_params(lattice, collision, "f64", (1, 1, 1),
                                tau=(problem["tau2"], tau3, 1.0), rho0=rho0, **rates)

@@ -38,6 +38,23 @@ WIDTHS = [L.WS_MODE_FEATURES, 576, 576, 576, 576, 8]  # 1.00M parameters
 TAU3 = 1.0
 BASE_ORDER = 2
 NMODES = 4
+# Waves start, order "auto": the fourth order is added when a3^2 / (a2 a1) exceeds this,
+# a_n the norm of the order-n wave amplitudes (the expansion's ratio applied once more,
+# relative to the first order).  Measured at 128^3: below about 1e-6 the third-order start
+# is steady within 20-60 steps; above about 3e-6 it needs hundreds to thousands, which the
+# fourth order (about 45 ms more) cuts to 20-560.
+AUTO_ORDER4 = 3e-6
+
+
+def series_ratio(nmodes, amp):
+    """a3^2 / (a2 a1) for third-order waves (lbm_ws_lattice_waves order 3 with nmodes
+    modes: nmodes first-order waves, then nmodes (nmodes + 1) second-order ones, then the
+    third order), a_n the root-sum-square of the order-n amplitudes."""
+    n = nmodes
+    n2 = n + n * (n + 1)
+    a1, a2, a3 = (float(np.sqrt((np.abs(amp[lo:hi]) ** 2).sum()))
+                  for lo, hi in ((0, n), (n, n2), (n2, len(amp))))
+    return a3 * a3 / (a2 * a1) if a2 > 0 and a1 > 0 else 0.0
 
 
 def domain_of(problem, box):
@@ -97,7 +114,8 @@ class WarmStart:
     FLAGS = L.RESET_FILTER | L.RESET_MASS | L.RESET_MOMENTUM | L.RESET_NONEQ
 
     def __init__(self, box=128, widths=WIDTHS, seed=0, max_rows=4096, stream=None,
-                 base_order=BASE_ORDER, flags=None, linear=False, waves=False, waves_order=3):
+                 base_order=BASE_ORDER, flags=None, linear=False, waves=False,
+                 waves_order="auto"):
         import torch
         self.torch = torch
         self.box = box
@@ -149,9 +167,16 @@ class WarmStart:
         return L.lbm_ws_lattice_response(problem, self.box, tau3=TAU3)
 
     def lattice_waves(self, problem):
-        """The problem's steady lattice state to order waves_order in the forcing, as
-        population waves (k, phase, complex amplitudes)."""
-        return L.lbm_ws_lattice_waves(problem, self.box, order=self.waves_order, tau3=TAU3)
+        """The problem's steady lattice state to order waves_order in the forcing (1 to 4;
+        "auto": 3, or 4 where the series converges slowly, AUTO_ORDER4), as population
+        waves (k, phase, complex amplitudes)."""
+        if self.waves_order != "auto":
+            return L.lbm_ws_lattice_waves(problem, self.box, order=int(self.waves_order),
+                                          tau3=TAU3)
+        k, ph, A = L.lbm_ws_lattice_waves(problem, self.box, order=3, tau3=TAU3)
+        if series_ratio(len(problem["modes"]), A) > AUTO_ORDER4:
+            return L.lbm_ws_lattice_waves(problem, self.box, order=4, tau3=TAU3)
+        return k, ph, A
 
     def correction_waves(self, problem, coef):
         """Each mode's correction (coef: nmodes x 8, the network's output in units of
@@ -357,7 +382,7 @@ class WarmStart:
         self.flags = meta["flags"]
         self.linear = bool(meta.get("linear", False))
         self.waves = bool(meta.get("waves", False))
-        self.waves_order = int(meta.get("waves_order", 3))
+        self.waves_order = meta.get("waves_order", "auto")
         self.velset = L.lbm_lattice_info("D3Q27") if self.waves else None
         self.set_scale(meta["scale"])
         self.net.set_params(np.load(path + ".npy", allow_pickle=False))

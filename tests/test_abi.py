@@ -173,12 +173,15 @@ def test_lattice_waves_rejects_bad_arguments():
     amp = np.zeros((8, 27, 2))
     n = C.c_int32()
     args = (k.ctypes.data, ph.ctypes.data, amp.ctypes.data, C.byref(n))
-    assert lib.lbm_ws_lattice_waves(C.byref(params), C.byref(prob), 32, 4, 8,
+    assert lib.lbm_ws_lattice_waves(C.byref(params), C.byref(prob), 32, 5, 8,
                                     *args) == lbm.LBM_EINVAL
     assert b"order" in lib.lbm_last_error()
     # the bound: n, n + n (n + 1), plus 2 n^2 (n + 1) + C(2n + 2, 3) at order 3
     assert [lib.lbm_ws_max_waves(2, o) for o in (1, 2, 3)] == [2, 8, 8 + 24 + 20]
-    assert lib.lbm_ws_max_waves(0, 1) == 0 and lib.lbm_ws_max_waves(4, 4) == 0
+    assert lib.lbm_ws_max_waves(0, 1) == 0 and lib.lbm_ws_max_waves(4, 5) == 0
+    # order 4 adds 2n * 2 n3 + C(2 n2 + 1, 2) + C(2n + 1, 2) * 2 n2 + C(2n + 3, 4) for
+    # n2 = n (n + 1) second-order and n3 = 2 n n2 + C(2n + 2, 3) third-order waves
+    assert lib.lbm_ws_max_waves(2, 4) == 52 + 4 * 2 * 44 + 78 + 10 * 12 + 35
     frac = lbm.ws_problem_struct(dict(tau2=0.8, modes=[dict(k=[0.5, 0, 0], p=[0, 1, 0],
                                                              amp=1e-6, phase=0.0)]))
     assert lib.lbm_ws_lattice_waves(C.byref(params), C.byref(frac), 32, 1, 8,

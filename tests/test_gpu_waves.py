@@ -194,6 +194,41 @@ def test_third_order_waves_are_the_steady_state_to_fourth_order(lat, coll):
     assert e3a < 0.1 * e2a, errs
 
 
+@pytest.mark.parametrize("lat,coll", [("D3Q27", "smrt"), ("D2Q9", "bgk")])
+def test_fourth_order_waves_are_the_steady_state_to_fifth_order(lat, coll):
+    """Order 4 (D2 of orders 1 and 3, of 2 and 2, D3 of 1, 1, 2 and D4 of order 1): its
+    error against the converged lattice falls 32-fold per halving of the forcing."""
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    box = 16
+    shape = (box, box, 1) if lat == "D2Q9" else (box, box, box)
+    errs = {}
+    for scale in (2.5, 1.25):
+        prob = _problem(lat, scale)
+        k3, ph3, A3 = L.lbm_ws_lattice_waves(prob, box, order=3, lattice=lat, collision=coll)
+        k4, ph4, A4 = L.lbm_ws_lattice_waves(prob, box, order=4, lattice=lat, collision=coll)
+        assert len(k3) < len(k4) <= L.load().lbm_ws_max_waves(2, 4)
+        g = inputs.fourier_force(shape, prob["modes"])
+        with L.Lattice(lat, coll, "f64", shape, (0, 0, 0), (0.8, 1.0, 1.0), g_field=g) as lt:
+            lt.set_waves(k3, ph3, A3)
+            f3 = lt.populations()
+            lt.set_waves(k4, ph4, A4)
+            f4 = lt.populations()
+            lt.step(6000)
+            prev = lt.populations()
+            lt.step(500)
+            fss = lt.populations()
+        e3 = np.abs(fss - f3).max()
+        e4 = np.abs(fss - f4).max()
+        assert np.abs(fss - prev).max() < 1e-2 * e4, (np.abs(fss - prev).max(), e4)
+        errs[scale] = (e3, e4)
+    (e3a, e4a), (e3b, e4b) = errs[2.5], errs[1.25]
+    print(lat, coll, errs)
+    assert 12.0 < e3a / e3b < 20.0, errs
+    assert 24.0 < e4a / e4b < 40.0, errs
+    assert e4a < 0.1 * e3a, errs
+
+
 def test_lattice_waves_first_order_matches_lattice_response():
     """Order 1 of lbm_ws_lattice_waves carries the same linear response that
     lbm_ws_lattice_response reports as mode coefficients: relative to the Stokes amplitude
