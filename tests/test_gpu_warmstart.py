@@ -243,3 +243,26 @@ def test_waves_targets_recover_a_correction():
         assert np.abs(t - c).max() < 0.05 * np.abs(c).max(), (t, c)
     finally:
         ws.close()
+
+
+def test_waves_order_follows_the_series_ratio():
+    """waves_order="auto" keeps order 3 where the series converges fast and adds the fourth
+    order where it converges slowly (128^3 problems of the family: seed 3022 typical,
+    seeds 3028 and 3044 slow)."""
+    from paper_2212_07494_amd import lbm as L
+    from paper_2212_07494_amd import warmstart as W
+    L.load()
+    ws = W.WarmStart(box=128, seed=1, waves=True)
+    try:
+        n = W.NMODES
+        n3 = len(L.lbm_ws_lattice_waves(inputs.warmstart_problem(3022, box=128), 128,
+                                        order=3, tau3=W.TAU3)[0])
+        for seed, fourth in ((3022, False), (3028, True), (3044, True)):
+            p = inputs.warmstart_problem(seed, box=128)
+            k3, _, A3 = L.lbm_ws_lattice_waves(p, 128, order=3, tau3=W.TAU3)
+            assert (W.series_ratio(n, A3) > W.AUTO_ORDER4) == fourth, seed
+            k, _, _ = ws.lattice_waves(p)
+            assert (len(k) > len(k3)) == fourth, (seed, len(k), len(k3))
+        assert n3 == n + n * (n + 1) + 48
+    finally:
+        ws.close()
