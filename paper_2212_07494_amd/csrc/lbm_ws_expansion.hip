@@ -13,6 +13,7 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <memory>
 #include <vector>
 
 #include "lbm.h"
@@ -90,46 +91,45 @@ double max_abs(const RDir &r) {
   return m;
 }
 
-// Collision evaluation points, run together (see the file comment).
+// Collision evaluation points, run together (see the file comment).  The points are kept
+// population-major as they are added, which is the layout lbm_set_populations takes.
 class CollisionBatch {
  public:
-  CollisionBatch(const lbm_params &q, int Q, const int *E) : q_(q), Q_(Q), E_(E) {}
+  CollisionBatch(const lbm_params &q, int Q, const int *E)
+      : q_(q), Q_(Q), E_(E), f_(Q), g_(3) {}
   int size() const { return n_; }
   int add(const rvec &f, const gvec &g) {
-    f_.insert(f_.end(), f.begin(), f.end());
-    for (int a = 0; a < 3; ++a) g_.push_back(g[a]);
+    for (int i = 0; i < Q_; ++i) f_[i].push_back(f[i]);
+    for (int a = 0; a < 3; ++a) g_[a].push_back(g[a]);
     return n_++;
   }
-  // out: n x Q, point-major
-  int run(rvec &out) const {
-    out.assign((size_t)n_ * Q_, 0.0);
+  int run() {
     if (n_ == 0) return LBM_OK;
-    const int n = n_;
-    rvec gplanes((size_t)3 * n), pop((size_t)Q_ * n), next((size_t)Q_ * n);
-    for (int p = 0; p < n; ++p) {
-      for (int a = 0; a < 3; ++a) gplanes[(size_t)a * n + p] = g_[(size_t)3 * p + a];
-      for (int i = 0; i < Q_; ++i) pop[(size_t)i * n + p] = f_[(size_t)p * Q_ + i];
-    }
+    const size_t n = (size_t)n_;
+    std::unique_ptr<double[]> gplanes(new double[3 * n]), pop(new double[Q_ * n]);
+    for (int a = 0; a < 3; ++a) std::copy(g_[a].begin(), g_[a].end(), gplanes.get() + a * n);
+    for (int i = 0; i < Q_; ++i) std::copy(f_[i].begin(), f_[i].end(), pop.get() + i * n);
+    next_.reset(new double[Q_ * n]);
     lbm_params q = q_;
-    q.nx = n;
+    q.nx = n_;
     q.ny = q.nz = 1;
     q.g_kind = LBM_G_FIELD;
-    q.g_data = gplanes.data();
+    q.g_data = gplanes.get();
     lbm_ctx *c = nullptr;
     int rc = lbm_init(&q, nullptr, nullptr, nullptr, &c);
     if (rc) return rc;
     const double one = 1.0;
-    rc = lbm_set_populations(c, pop.data());
+    rc = lbm_set_populations(c, pop.get());
     if (!rc) rc = lbm_step(c, 1, &one);
-    if (!rc) rc = lbm_get_populations(c, n, nullptr, next.data());
+    if (!rc) rc = lbm_get_populations(c, n_, nullptr, next_.get());
     lbm_free(c);
-    if (rc) return rc;
-    for (int p = 0; p < n; ++p)
-      for (int i = 0; i < Q_; ++i) {
-        const int dst = ((p + E_[3 * i]) % n + n) % n;
-        out[(size_t)p * Q_ + i] = next[(size_t)i * n + dst];
-      }
-    return LBM_OK;
+    return rc;
+  }
+  // After run(): C(f_p, g_p)_i, which the step left at node p + e_ix.
+  double value(int p, int i) const {
+    int dst = p + E_[3 * i];
+    dst = dst < 0 ? dst + n_ : (dst >= n_ ? dst - n_ : dst);
+    return next_[(size_t)i * n_ + dst];
   }
 
  private:
@@ -137,7 +137,8 @@ class CollisionBatch {
   int Q_;
   const int *E_;
   int n_ = 0;
-  rvec f_, g_;
+  std::vector<rvec> f_, g_;
+  std::unique_ptr<double[]> next_;
 };
 
 // The collision expanded about rest: J = dC/d f-bar (Q x Q) and G = dC/dg (Q x 3) by
@@ -177,19 +178,16 @@ class Expansion {
         g[a] = s * h;
         B.add(f0_, g);
       }
-    rvec out;
-    if ((rc = B.run(out))) return rc;
+    if ((rc = B.run())) return rc;
     J_.assign((size_t)Q * Q, 0.0);
     G_.assign((size_t)Q * 3, 0.0);
     for (int col = 0; col < Q; ++col)
       for (int i = 0; i < Q; ++i)
-        J_[(size_t)i * Q + col] =
-            (out[(size_t)(2 * col) * Q + i] - out[(size_t)(2 * col + 1) * Q + i]) / (2 * h);
+        J_[(size_t)i * Q + col] = (B.value(2 * col, i) - B.value(2 * col + 1, i)) / (2 * h);
     for (int a = 0; a < D; ++a)
       for (int i = 0; i < Q; ++i)
-        G_[(size_t)i * 3 + a] = (out[(size_t)(2 * Q + 2 * a) * Q + i] -
-                                 out[(size_t)(2 * Q + 2 * a + 1) * Q + i]) /
-                                (2 * h);
+        G_[(size_t)i * 3 + a] =
+            (B.value(2 * Q + 2 * a, i) - B.value(2 * Q + 2 * a + 1, i)) / (2 * h);
     return LBM_OK;
   }
 
@@ -227,14 +225,15 @@ class Expansion {
     j.scale = sc;
     return j;
   }
-  void read_real(const RealJob &j, const rvec &out, double sign, cvec &acc, bool imag) const {
+  void read_real(const RealJob &j, const CollisionBatch &B, double sign, cvec &acc,
+                 bool imag) const {
     if (j.base < 0) return;
     for (int s = 0; s < (1 << j.m); ++s) {
       int par = 0;
       for (int k = 0; k < j.m; ++k) par ^= (s >> k) & 1;
       const double w = (par ? -1.0 : 1.0) * sign * j.scale;
       for (int i = 0; i < Q; ++i) {
-        const double v = w * out[(size_t)(j.base + s) * Q + i];
+        const double v = w * B.value(j.base + s, i);
         acc[i] += imag ? cplx(0.0, v) : cplx(v, 0.0);
       }
     }
@@ -266,11 +265,11 @@ class Expansion {
     }
     return cj;
   }
-  cvec read_complex(const ComplexJob &cj, const rvec &out) const {
+  cvec read_complex(const ComplexJob &cj, const CollisionBatch &B) const {
     cvec acc(Q, cplx(0.0));
     for (size_t t = 0; t < cj.jobs.size(); ++t) {
       const int k = cj.ipow[t] & 3;  // i^k: 1, i, -1, -i
-      read_real(cj.jobs[t], out, (k == 2 || k == 3) ? -1.0 : 1.0, acc, k & 1);
+      read_real(cj.jobs[t], B, (k == 2 || k == 3) ? -1.0 : 1.0, acc, k & 1);
     }
     return acc;
   }
@@ -515,10 +514,9 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
           items.push_back({add(k1[i], k1[j], sgn), i == j ? 0.25 : 0.5,
                            X.plan_complex(B, d, 2)});
         }
-    rvec out;
-    if ((rc = B.run(out))) return rc;
+    if ((rc = B.run())) return rc;
     for (const Item &it : items) {
-      cvec src = X.read_complex(it.job, out), f2;
+      cvec src = X.read_complex(it.job, B), f2;
       for (auto &v : src) v *= it.c;
       if (!X.solve_wave(it.k, box, src, f2))
         return set_error(LBM_EINVAL, "a second-order wave: the linearised step is singular");
@@ -574,11 +572,10 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
           items.push_back({add(add(ck(c1), ck(c2), 1), ck(c3), 1), orderings / 24.0,
                            X.plan_complex(B, d, 3)});
         }
-    rvec out;
-    if ((rc = B.run(out))) return rc;
+    if ((rc = B.run())) return rc;
     std::map<kvec, cvec> src;
     for (const Item &it : items) {
-      const cvec s = X.read_complex(it.job, out);
+      const cvec s = X.read_complex(it.job, B);
       kvec k = it.k;
       const bool fl = flip(k);
       if (fl) k = {-k[0], -k[1], -k[2]};
@@ -668,11 +665,10 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
           for (size_t l = k; l < c1.size(); ++l)
             plan({&c1[i], &c1[j], &c1[k], &c1[l]},
                  orderings({(int)i, (int)j, (int)k, (int)l}) / 24.0);
-    rvec out;
-    if ((rc = B.run(out))) return rc;
+    if ((rc = B.run())) return rc;
     std::map<kvec, cvec> src;
     for (const Item &it : items) {
-      const cvec s4 = X.read_complex(it.job, out);
+      const cvec s4 = X.read_complex(it.job, B);
       cvec &acc = src[it.k];
       if (acc.empty()) acc.assign(Q, cplx(0.0));
       for (int i = 0; i < Q; ++i) acc[i] += it.c * s4[i];

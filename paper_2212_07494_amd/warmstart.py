@@ -42,7 +42,7 @@ NMODES = 4
 # a_n the norm of the order-n wave amplitudes (the expansion's ratio applied once more,
 # relative to the first order).  Measured at 128^3: below about 1e-6 the third-order start
 # is steady within 20-60 steps; above about 3e-6 it needs hundreds to thousands, which the
-# fourth order (about 45 ms more) cuts to 20-560.
+# fourth order (about 26 ms more on the host) cuts to 20-560.
 AUTO_ORDER4 = 3e-6
 
 
