@@ -51,7 +51,7 @@ def _lib(kind: str):
             _build.build(force=False)
         L = C.CDLL(path)
         vp = C.c_void_p
-        real = C.c_double if kind == "f64" else C.c_float
+        real = C.c_float if kind == "f32" else C.c_double
         L.oracle_step.argtypes = [vp, vp, vp, vp, vp, real]
         L.oracle_run.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64]
         L.oracle_init.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -61,6 +61,7 @@ def _lib(kind: str):
         L.oracle_bgk_terms.argtypes = [vp, real, vp, vp, vp, vp]
         L.oracle_round_half.argtypes = [C.c_float]
         L.oracle_round_half.restype = C.c_float
+        L.oracle_is_plain.restype = C.c_int
         _LIBS[kind] = L
     return _LIBS[kind]
 
@@ -84,6 +85,9 @@ class Oracle:
     tau4) -- BGK uses tau2 only, SMRT and RMRT require tau4 == 1 (order 4 is trimmed);
     shift: constant s removed from stored populations (f-bar_i - w_i s);
     real: 'f64' (reference) or 'f32' (emulation); store16: round stores to binary16;
+    plain: use the PLAIN build (FP64 only): the textbook operation order (plain sums over
+    all populations, plain inverse-transform rows, no fused multiply-add) instead of the
+    operation-order twin the library is compared with bit for bit;
     force_order: 1, or 3 for SMRT's third-order force content; solid: N flags of solid
     nodes (halfway bounce-back against them; not stepped; zero moments) or None;
     tau_bulk: SMRT rate of the trace of order 2 (0 = tau2); tau_31: SMRT rate of the trace
@@ -95,7 +99,7 @@ class Oracle:
     def __init__(self, lattice: str, collision: str, shape, walls=(0, 0, 0), tau=(0.8, 0.8, 1.0),
                  shift: float = 0.0, real: str = "f64", store16: bool = False,
                  force_order: int = 1, solid=None, tau_bulk: float = 0.0,
-                 tau_31: float = 0.0, max_order: int = 4):
+                 tau_31: float = 0.0, max_order: int = 4, plain: bool = False):
         self.lattice = lattice
         self.collision = collision.lower()
         nx, ny, nz = (tuple(shape) + (1, 1))[:3]
@@ -149,7 +153,10 @@ class Oracle:
             if self.solid.size != self.N:
                 raise ValueError("solid needs one flag per node")
             self._p.solid = self.solid.ctypes.data
-        self._l = _lib(real)
+        if plain and real != "f64":
+            raise ValueError("the plain build is binary64")
+        self.plain = bool(plain)
+        self._l = _lib("plain" if plain else real)
         self._lref = C.byref(self._lat)
         self._pref = C.byref(self._p)
 

@@ -7,9 +7,19 @@
  * library: its lattice tables are produced by oracle/lattice.py in exact
  * rational arithmetic and passed in already rounded.
  *
- * Built twice: with REAL = double (the reference, FP64) and with REAL = float
- * (an emulation of the library's reduced-precision modes: FP32 arithmetic in
- * the same order, stores rounded to binary32 or binary16).
+ * Built three times: with REAL = double (FP64), with REAL = float (an emulation of
+ * the library's reduced-precision modes: FP32 arithmetic in the same order, stores
+ * rounded to binary32 or binary16), and with REAL = double and PLAIN defined.
+ *
+ * Two operation orders.  The default build ("operation-order twin") fixes the rounding
+ * order described below, which the HIP library follows too, so the two can be compared
+ * bit for bit.  The PLAIN build is the textbook form of the same step: every moment a
+ * sum over all populations in index order, sum_i f_i H_m(e_i) (eq:dft); the Hermite
+ * shifts as plain sums of C(m,l) u^l N_{m-l}; the increment of each population as a
+ * plain row of the inverse transform, sum_m Minv_im (a*_m - a_m); no fused multiply-add
+ * and no folding over opposite velocities.  In real arithmetic both builds compute the
+ * same map; in floating point they differ by rounding only, which bounds how far any
+ * implementation of this fixed order may sit from the plain definition.
  *
  * Paper: X. Li, W. Duan, X. Shan, "Second-order force scheme for lattice
  * Boltzmann method" (arXiv 2212.07494).  Each function cites the passage it
@@ -51,8 +61,12 @@ typedef REAL real;
  * collision accumulates its moment transforms with it (the paper fixes no rounding
  * order; one rounding per term is the more accurate choice). */
 static inline real fmar(real a, real b, real c) {
+#ifdef PLAIN
+  return a * b + c; /* two roundings (the build never contracts) */
+#else
   return sizeof(real) == sizeof(float) ? (real)fmaf((float)a, (float)b, (float)c)
                                        : (real)fma((double)a, (double)b, (double)c);
+#endif
 }
 
 #define MAXQ 27
@@ -206,16 +220,57 @@ static real bgk_force(const oracle_lattice *L, int i, const real u[3], const rea
   return L->w[i] * G;
 }
 
+/* The change of the populations over a BGK collision, Omega_i + F_i =
+ * (1 - omega/2) F_i - omega (f_i - f_eq_i), has mass 0 and momentum F in exact
+ * arithmetic (the equilibrium carries rho and rho u, the force term 0 and F).  Formed
+ * population by population in floating point, those two moments pass through the
+ * rounded weights (in binary32, sum_i 3 fl(w_i) e_ix^2 != 1), which biases the momentum
+ * by about omega rho u times the weights' rounding at every step.  As for the MRT
+ * collisions, the post-collision state is formed as eq:evolution writes it, f-bar plus
+ * the change, and the change's conserved moments are set to their exact values through
+ * the inverse transform's columns of orders 0 and 1: each population gains
+ * Minv_i0 (0 - sum_j c_j) + sum_a Minv_i,e_a (F_a - sum_j c_j e_ja).  In exact arithmetic
+ * the correction is zero. */
 static void collide_bgk(const oracle_lattice *L, const oracle_params *P, const real *f,
                         const real g[3], real *out) {
   macro_t M;
   macroscopic(L, P, f, g, &M);
-  for (int i = 0; i < L->Q; ++i) {
+  const int Q = L->Q, NM = L->NM;
+  real c[MAXQ];
+  for (int i = 0; i < Q; ++i) {
     real eu;
     real Pi = bgk_P(L, i, M.u, &eu);
     real feq = L->w[i] * (M.drho + M.rho * Pi);
     real Fi = bgk_force(L, i, M.u, M.F, eu);
-    out[i] = (f[i] - P->omega * (f[i] - feq)) + P->hforce * Fi;
+    c[i] = P->hforce * Fi - P->omega * (f[i] - feq);
+  }
+  /* the change's moments of orders 0 and 1 against their exact values: r[k] per
+   * multi-index k of order <= 1 (canonical order puts them first) */
+  real r[4];
+  int nk = 0;
+  for (int k = 0; k < NM && mabs(L->mi + 3 * k) <= 1; ++k, ++nk) {
+    const int32_t *m = L->mi + 3 * k;
+    real s = -0.0;
+    if (mabs(m) == 0) {
+      for (int i = 0; i < Q; ++i) s = s + c[i];
+      r[k] = -s;
+    } else {
+      const int a = m[0] ? 0 : (m[1] ? 1 : 2);
+      for (int i = 0; i < Q; ++i) {
+        const int ea = L->e[3 * i + a];
+        if (ea == 1) s = s + c[i];
+        if (ea == -1) s = s + (-c[i]);
+      }
+      r[k] = M.F[a] - s;
+    }
+  }
+  for (int i = 0; i < Q; ++i) {
+    real corr = -0.0;
+    for (int k = 0; k < nk; ++k) {
+      const real cf = L->Minv[i * NM + k];
+      if (cf != 0) corr = corr + cf * r[k];
+    }
+    out[i] = f[i] + (c[i] + corr);
   }
 }
 
@@ -271,6 +326,10 @@ static void make_plan(const oracle_lattice *L, smrt_plan *S) {
  * holds for the rows of the inverse transform.  The collisions that use it check the
  * tables once: both relations must hold exactly. */
 static void check_pair_symmetry(const oracle_lattice *L) {
+#ifdef PLAIN
+  (void)L; /* the plain transforms do not fold */
+  return;
+#endif
   const int NM = L->NM, Q = L->Q;
   for (int k = 0; k < NM; ++k) {
     const real sg = (mabs(L->mi + 3 * k) % 2) ? (real)-1 : (real)1;
@@ -288,6 +347,14 @@ static void check_pair_symmetry(const oracle_lattice *L) {
 static real project_folded(const oracle_lattice *L, int k, const real *f, const real *s,
                            const real *a) {
   const int Q = L->Q;
+#ifdef PLAIN
+  /* eq:dft as written: sum over every population in index order */
+  (void)s;
+  (void)a;
+  real P = -0.0;
+  for (int i = 0; i < Q; ++i) P = P + L->H[k * Q + i] * f[i];
+  return P;
+#endif
   const int odd = mabs(L->mi + 3 * k) % 2;
   real A = -0.0;
   if (L->H[k * Q] != 0) A = fmar(L->H[k * Q], f[0], A);
@@ -305,6 +372,15 @@ static real project_folded(const oracle_lattice *L, int k, const real *f, const 
 static void reconstruct_folded(const oracle_lattice *L, const real *f, const real *dA,
                                real *out) {
   const int Q = L->Q, NM = L->NM;
+#ifdef PLAIN
+  /* each population plus its row of the inverse transform applied to the changes */
+  for (int i = 0; i < Q; ++i) {
+    real r = -0.0;
+    for (int k = 0; k < NM; ++k) r = r + L->Minv[i * NM + k] * dA[k];
+    out[i] = f[i] + r;
+  }
+  return;
+#endif
   real acc = -0.0;
   for (int k = 1; k < NM; ++k) {
     real c = L->Minv[k];
@@ -716,3 +792,12 @@ void oracle_bgk_terms(const oracle_lattice *L, real rho, const real *u, const re
 }
 
 int oracle_real_size(void) { return (int)sizeof(real); }
+
+/* 1 for the PLAIN build (textbook operation order), 0 for the operation-order twin. */
+int oracle_is_plain(void) {
+#ifdef PLAIN
+  return 1;
+#else
+  return 0;
+#endif
+}

@@ -62,6 +62,7 @@ struct Tab<L, float> {
 template <class T>
 struct Macro {
   T drho, rho;
+  T j[3];  // sum_i f-bar_i e_i = rho u-bar
   T u[3], F[3];
 };
 
@@ -86,10 +87,12 @@ __device__ __forceinline__ Macro<T> macroscopic(const T (&d)[L::Q], T shift, con
       if constexpr (ea == 1) j = j + d[i];
       if constexpr (ea == -1) j = j + (-d[i]);
     });
+    M.j[a] = j;
     M.u[a] = j / M.rho + T(0.5) * g[a];
     M.F[a] = M.rho * g[a];
   });
   if constexpr (L::D == 2) {
+    M.j[2] = T(0);
     M.u[2] = T(0);
     M.F[2] = T(0);
   }
@@ -270,8 +273,9 @@ constexpr int sub_index(int k, int a) {
   return -1;
 }
 
-// BGK with the second-order force term (Sec. II.B, eq:explict_eq):
-//   f*_i = f_i - omega (f_i - f_eq_i) + (1 - omega/2) F_i
+// BGK with the second-order force term (Sec. II.B, eq:explict_eq), formed as
+// eq:evolution writes it, f-bar plus the change:
+//   f*_i = f_i + [(1 - omega/2) F_i - omega (f_i - f_eq_i)] + (conserved-moment fix-up)
 //   f_eq_i = w_i (rho + rho P_i),  P_i = (3 e.u + 4.5 (e.u)^2) - 1.5 u.u
 //   F_i   = w_i (3 (e.F - u.F) + 9 (e.F)(e.u))
 // (the truncated Hermite equilibrium and the second-order force, c_s^2 = 1/3).  In
@@ -280,6 +284,7 @@ template <class L, class T>
 __device__ __forceinline__ void collide_bgk(T (&d)[L::Q], T shift, const T (&g)[3],
                                             const BGKCoef<T> &c) {
   const Macro<T> M = macroscopic<L>(d, shift, g);
+  T ch[L::Q];  // the change Omega_i + F_i of each population
   T usq = T(-0.0), uF = T(-0.0);
   static_for<L::D>([&](auto A) {
     constexpr int a = decltype(A)::value;
@@ -309,7 +314,40 @@ __device__ __forceinline__ void collide_bgk(T (&d)[L::Q], T shift, const T (&g)[
     const T feq = wi * (M.drho + M.rho * P);
     const T G = T(3) * (eF - uF) + T(9) * (eF * eu);
     const T Fi = wi * G;
-    d[i] = (d[i] - c.omega * (d[i] - feq)) + c.hforce * Fi;
+    ch[i] = c.hforce * Fi - c.omega * (d[i] - feq);
+  });
+  // The change's moments of orders 0 and 1 set to their exact values, 0 and F, through
+  // the inverse transform's columns k = 0 (mass) and k = 1..D (momentum, the canonical
+  // order puts e_x, e_y, e_z there): without this, binary32 weights bias the momentum
+  // by about omega rho u per step (sum_i 3 fl(w_i) e_ix^2 != 1).  Zero in exact
+  // arithmetic.
+  T r[1 + L::D];
+  {
+    T s = T(-0.0);
+    static_for<L::Q>([&](auto I) { s = s + ch[decltype(I)::value]; });
+    r[0] = -s;
+  }
+  static_for<L::D>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    static_assert(L::ORD[1 + a] == 1 && L::MI[1 + a][a] == 1);
+    T s = T(-0.0);
+    static_for<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int ea = L::E[i][a];
+      if constexpr (ea == 1) s = s + ch[i];
+      if constexpr (ea == -1) s = s + (-ch[i]);
+    });
+    r[1 + a] = M.F[a] - s;
+  });
+  static_for<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    T corr = T(-0.0);
+    static_for<1 + L::D>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr T cf = Tab<L, T>::minv(i, k);
+      if constexpr (cf != T(0)) corr = corr + cf * r[k];
+    });
+    d[i] = d[i] + (ch[i] + corr);
   });
 }
 

@@ -62,7 +62,8 @@ def test_small_box_against_fp64_oracle():
 
 def test_full_config_precision():
     """The 256^3 D3Q19 SMRT + force configuration for its full 5,000 steps: FP32-shifted
-    against FP64 (the FP64 path is bit-identical to the FP64 oracle) within 1e-5."""
+    against FP64 (the FP64 path is bit-identical to the FP64 oracle) within 1e-5,
+    unshifted FP32 within 1e-3 and FP16-shifted within 5e-2."""
     w = inputs.taylor_green_3d(n=256)
     steps = w.steps
     _, u64 = _run_gpu(w, "f64", steps)
@@ -78,3 +79,6 @@ def test_full_config_precision():
     _record("D3Q19 SMRT 256^3 x 5000 vs FP64", res)
     assert res["f32s"] <= 1e-5
     assert res["f32"] <= 1e-3
+    # binary16 deviations lose force increments below half an ulp: gated at the stated
+    # bound (measured 3.4e-2), not at 1e-5
+    assert res["f16s"] <= 5e-2
