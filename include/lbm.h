@@ -20,8 +20,9 @@
  *              fluid node and the next) on both faces of an axis, or periodic.
  *
  * Conventions for every entry point
- *   - Returns LBM_OK (0) or a negative lbm_status; never aborts or throws.  After a
- *     failure lbm_last_error() returns a thread-local message.
+ *   - Returns LBM_OK (0), a negative lbm_status (an error) or the positive warning
+ *     LBM_WMACH; never aborts or throws.  After a failure or warning lbm_last_error()
+ *     returns a thread-local message.
  *   - Node index n = (z * ny + y) * nx + x (x fastest); N = nx * ny * nz (nz = 1 in 2-D).
  *   - Host arrays passed in are read during the call only; the caller keeps them.
  *     Output arrays are caller-allocated host memory.
@@ -48,6 +49,8 @@ extern "C" {
 
 typedef enum {
   LBM_OK = 0,
+  LBM_WMACH = 1,       /* warning, the call did its work: a monitor record showed
+                          max |u| > mach_limit c_s (see lbm_params.mach_limit) */
   LBM_EINVAL = -1,     /* invalid argument or parameter combination */
   LBM_ENOMEM = -2,     /* device or host allocation failed */
   LBM_EDEVICE = -3,    /* a HIP call failed; message in lbm_last_error() */
@@ -137,16 +140,25 @@ typedef struct {
    * D3Q27 only): orders 5 and 6 are carried as rho u^m plus the back-shift of the
    * relaxed central moments, their own central parts trimmed to zero like order 4. */
   int32_t max_order;
+  /* Mach guard: if > 0, a monitor record whose max |u| exceeds mach_limit c_s (c_s^2 =
+   * 1/3) makes the call that reads it return the warning LBM_WMACH (the low-Mach
+   * expansion behind the truncated equilibrium loses accuracy there).  0 = off. */
+  double mach_limit;
+  /* Debug pass: 1 = before every step, fill the buffer the step writes with NaN, so a
+   * value that the next step pulls but this step did not write shows up as NaN in the
+   * results (every slot a step pulls is written by the step before it).  0 = off. */
+  int32_t debug_poison;
 } lbm_params;
 
 /* Monitor record (binary64, summed on the device in a fixed order).
- *   mass = sum rho, mom = sum rho u (physical u of eq:half_F), umax = max |u|,
+ *   mass = sum rho, mom = sum rho u (physical u of eq:half_F), j = sum_x sum_i f-bar_i e_i
+ *   (= sum rho u-bar: the stored first moment, mom - sum F/2), umax = max |u|,
  *   resid = sqrt(sum |u(t) - u(t-1)|^2 / sum |u(t)|^2) over the nodes,
  *   nonfinite = number of nodes whose rho or u is NaN or Inf.
  * step is the time t the fields belong to (-1: never computed). */
 typedef struct {
   int64_t step;
-  double mass, mom[3], umax, resid;
+  double mass, mom[3], j[3], umax, resid;
   int64_t nonfinite;
 } lbm_monitors;
 
@@ -165,19 +177,30 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init,
              void *hip_stream, lbm_ctx **out);
 
 /* Advance n >= 0 steps.  g_scale: NULL (s(t) = 1) or n host doubles, the factor s(t)
- * of g(x) for each step.  Enqueues work only (no synchronisation).  If monitor_every
- * is K > 0 the monitors are refreshed after every step whose time is a multiple of K. */
+ * of g(x) for each step.  Enqueues work only (no synchronisation).
+ * Monitors in the step: if monitor_every is K > 0, after every step whose time t is a
+ * multiple of K the monitor record of time t is computed on the device (with the
+ * residual against time t - 1, whose velocity is recorded one step earlier; K = 1
+ * compares every step) and copied to host memory without blocking.  lbm_step and every
+ * call that synchronises the stream read the latest such record once it is complete:
+ *   - non-finite nodes: the call returns LBM_ENONFINITE, lbm_step refuses to advance
+ *     (the state is kept for inspection) until the state is replaced (lbm_set_populations,
+ *     lbm_set_waves, lbm_reset_fields, lbm_load);
+ *   - max |u| above the Mach limit: LBM_WMACH (warning; the call did its work).
+ * lbm_monitors_get at such a time t returns that record as computed in the step. */
 int lbm_step(lbm_ctx *c, int64_t n, const double *g_scale);
 
 /* Density and physical velocity u = j/rho + g s/2 (eq:half_F) of the current state,
  * evaluated with acceleration g(x) * g_scale.  rho: N doubles or NULL; u: D x N doubles
- * (component planes) or NULL.  Synchronises the stream. */
+ * (component planes) or NULL.  Synchronises the stream.  May return LBM_ENONFINITE or
+ * LBM_WMACH from an in-step monitor record (see lbm_step); the outputs are written. */
 int lbm_moments(lbm_ctx *c, double g_scale, double *rho, double *u);
 
-/* Refresh and return the monitor record of the current state (force scale of the last
- * step, 1 before any step); resid compares with the state one step earlier when that
- * was recorded, else 0.  Returns LBM_ENONFINITE if any node is not finite.
- * Synchronises the stream. */
+/* Return the monitor record of the current time t: the one computed in lbm_step at t
+ * if monitor_every made one, else a fresh one (force scale of the last step, 1 before
+ * any step).  resid compares with the state one step earlier when that was recorded,
+ * else 0.  Returns LBM_ENONFINITE if any node is not finite, LBM_WMACH if max |u|
+ * exceeds the Mach limit (the record is filled either way).  Synchronises the stream. */
 int lbm_monitors_get(lbm_ctx *c, lbm_monitors *mon);
 
 /* Pre-collision populations f-bar_i(x, t) of the current state, values as stored
@@ -201,7 +224,7 @@ int lbm_set_populations(lbm_ctx *c, const double *f);
  * amp: nwaves x Q x 2 binary64, the (re, im) pairs of A_wi at 2 (w Q + i).  nwaves = 0
  * gives the rest state.  Resets the time to 0, like lbm_set_populations; values at solid
  * nodes are unspecified.  Errors: LBM_EINVAL (nwaves outside 0..LBM_MAX_WAVES, a NULL
- * array with nwaves > 0, a non-finite amplitude or phase), LBM_ESTATE, LBM_EHIP. */
+ * array with nwaves > 0, a non-finite amplitude or phase), LBM_ESTATE, LBM_EDEVICE. */
 #define LBM_MAX_WAVES 4096
 int lbm_set_waves(lbm_ctx *c, int32_t nwaves, const int32_t *k, const double *phase,
                   const double *amp);

@@ -79,6 +79,20 @@ int lbm_batch_run(lbm_batch *b, int64_t max_steps, double tol, int32_t check_eve
                   int32_t stall_checks, int64_t *steps_out, double *resid_out,
                   int32_t *status_out);
 
+/* The batched step of the problem statement (eq:dv per domain, advanced by eq:evolution):
+ * step every domain until its residual (as in lbm_batch_run) is below tol, it reaches its
+ * round-off floor, or max_steps steps were taken; the same as lbm_batch_run with
+ * check_every = LBM_BATCH_CHECK_EVERY and stall_checks = LBM_BATCH_STALL_CHECKS.
+ * steps_out, resid_out: ndom entries each, or NULL.  The per-domain outcome is read with
+ * lbm_batch_status.  Errors as lbm_batch_run. */
+#define LBM_BATCH_CHECK_EVERY 100
+#define LBM_BATCH_STALL_CHECKS 10
+int lbm_batch_step(lbm_batch *b, int64_t max_steps, double tol, int64_t *steps_out,
+                   double *resid_out);
+
+/* Per-domain lbm_domain_status after the last run (ndom entries).  Synchronises. */
+int lbm_batch_status(lbm_batch *b, int32_t *status_out);
+
 /* Density and physical velocity of domain dom (as lbm_moments, force scale 1). */
 int lbm_batch_moments(lbm_batch *b, int32_t dom, double *rho, double *u);
 

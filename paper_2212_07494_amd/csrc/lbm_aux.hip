@@ -8,8 +8,8 @@
 namespace lbm {
 namespace {
 
-constexpr int kSlots = 8;   // mass, mom x/y/z, sum |du|^2, sum |u|^2, max |u|, non-finite
-constexpr int kUmax = 6;
+constexpr int kSlots = MON_SLOTS;  // the monitor record's slots (lbm_internal.h)
+constexpr int kUmax = MON_UMAX;
 
 // Sum the per-block partials in a fixed order (one block of 256 threads): thread k
 // folds blocks k, k + 256, ... in turn, then a fixed binary tree combines the threads.
@@ -68,6 +68,16 @@ __global__ void copy_four(const float4 *__restrict__ src, float4 *__restrict__ d
     const int64_t i = base + (int64_t)k * blockDim.x;
     if (i < n) dst[i] = v[k];
   }
+}
+
+// Every byte of a buffer set to 0xff: a quiet NaN in binary16, binary32 and binary64 alike
+// (the debug pass that poisons the buffer a step is about to write).  16 bytes a thread,
+// then the tail byte by byte.
+__global__ void fill_ff_kernel(uint4 *__restrict__ p, int64_t n16, unsigned char *__restrict__ tail,
+                               int ntail) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) p[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+  if (i < ntail) tail[i] = 0xff;
 }
 
 // Per-domain convergence decision after a compare pass (one thread per domain).
@@ -131,6 +141,17 @@ hipError_t decide_domains(const int *tile_begin, const int *tile_end, const doub
 hipError_t add_domain_steps(const int *active, void *state, int ndom, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(add_steps_kernel, dim3((ndom + 255) / 256), dim3(256), 0, s, active,
                      static_cast<DomState *>(state), ndom, n);
+  return hipGetLastError();
+}
+
+hipError_t fill_nan(void *p, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  const int ntail = (int)(bytes % 16);
+  const int64_t n = n16 > ntail ? n16 : ntail;
+  if (n == 0) return hipSuccess;
+  unsigned char *tail = static_cast<unsigned char *>(p) + (size_t)n16 * 16;
+  hipLaunchKernelGGL(fill_ff_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     static_cast<uint4 *>(p), n16, tail, ntail);
   return hipGetLastError();
 }
 

@@ -536,6 +536,23 @@ int lbm_batch_run(lbm_batch *b, int64_t max_steps, double tol, int32_t check_eve
   return LBM_OK;
 }
 
+int lbm_batch_step(lbm_batch *b, int64_t max_steps, double tol, int64_t *steps_out,
+                   double *resid_out) {
+  return lbm_batch_run(b, max_steps, tol, LBM_BATCH_CHECK_EVERY, LBM_BATCH_STALL_CHECKS,
+                       steps_out, resid_out, nullptr);
+}
+
+int lbm_batch_status(lbm_batch *b, int32_t *status_out) {
+  if (!valid(b)) return set_error(LBM_ESTATE, "invalid batch");
+  if (!status_out) return set_error(LBM_EINVAL, "status_out is NULL");
+  std::vector<lbm::DomState> st(b->ndom);
+  HIP_TRY(hipMemcpyAsync(st.data(), b->state_d, st.size() * sizeof(lbm::DomState),
+                         hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int d = 0; d < b->ndom; ++d) status_out[d] = st[d].status;
+  return LBM_OK;
+}
+
 int lbm_batch_moments(lbm_batch *b, int32_t dom, double *rho, double *u) {
   if (!valid(b)) return set_error(LBM_ESTATE, "invalid batch");
   if (dom < 0 || dom >= b->ndom) return set_error(LBM_EINVAL, "domain %d out of range", dom);

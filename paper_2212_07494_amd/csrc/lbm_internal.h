@@ -9,6 +9,14 @@
 
 namespace lbm {
 
+// Slots of a monitor record (binary64), per block partial and after finalisation: mass,
+// momentum of the physical velocity sum rho u (x, y, z), sum j = sum f-bar e (x, y, z),
+// sum |u(t) - u(t-1)|^2, sum |u|^2, max |u|, non-finite node count.
+enum {
+  MON_MASS = 0, MON_MX, MON_MY, MON_MZ, MON_JX, MON_JY, MON_JZ, MON_DU2, MON_U2, MON_UMAX,
+  MON_BAD, MON_SLOTS
+};
+
 // Solid mask word: bit i = the pull source of population i is solid; this bit = the
 // node itself is solid.
 constexpr uint32_t SOLID_NODE = 1u << 31;

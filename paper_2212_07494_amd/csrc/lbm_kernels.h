@@ -362,9 +362,7 @@ __global__ void __launch_bounds__(256) waves_kernel(S *__restrict__ f, Geom geo,
 }
 
 // ---- monitors -------------------------------------------------------------------------
-// Slots of a block partial (binary64): mass, mom x/y/z, sum |du|^2, sum |u|^2, max |u|,
-// non-finite count.
-enum { MON_MASS = 0, MON_MX, MON_MY, MON_MZ, MON_DU2, MON_U2, MON_UMAX, MON_BAD, MON_SLOTS };
+// Block partials use the monitor slots of lbm_internal.h (MON_*).
 enum { MOM_WRITE = 1, MOM_RECORD = 2, MOM_COMPARE = 4 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -391,7 +389,8 @@ __global__ void __launch_bounds__(256) moments_kernel(StepArgs<T> a, double *rho
   const int node = (z * a.geo.ny + y) * a.geo.nx + x;
   const uint32_t sm = inside ? node_mask(a.geo, node) : 0u;
   const bool live = inside && !(sm & SOLID_NODE);
-  double v[MON_SLOTS] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double v[MON_SLOTS];
+  for (int s = 0; s < MON_SLOTS; ++s) v[s] = 0.0;
   if (inside && !live && (mode & MOM_WRITE)) {  // solid node: no fluid
     if (rho_out) rho_out[node] = 0.0;
     if (u_out)
@@ -419,6 +418,7 @@ __global__ void __launch_bounds__(256) moments_kernel(StepArgs<T> a, double *rho
       const double uc = double(M.u[c]);
       u2 += uc * uc;
       v[MON_MX + c] = r * uc;
+      v[MON_JX + c] = double(M.j[c]);
       if (mode & MOM_COMPARE) {
         const double dd = uc - double(uprev[(int64_t)c * N + node]);
         du2 += dd * dd;

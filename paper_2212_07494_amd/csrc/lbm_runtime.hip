@@ -101,8 +101,21 @@ struct lbm_ctx {
   void *uprev = nullptr;
   int64_t uprev_time = -2;
   double *partials = nullptr;
-  int64_t nblocks = 0;
+  int64_t nblocks = 0, nblocks_cap = 0;  // blocks of the current grid; partials' capacity
   double *mon_dev = nullptr;
+  // In-step monitor checks (monitor_every > 0): the device record of time dev_step (-1:
+  // none) and its mode; the latest check's copy in pinned host memory (mon_host) with the
+  // event that completes it, read once without blocking (check_pending); a non-finite
+  // record stops the stepping until the state is replaced.
+  int64_t dev_step = -1;
+  int dev_mode = 0;
+  double *mon_host = nullptr;
+  hipEvent_t mon_ev = nullptr;
+  bool check_pending = false;
+  int64_t check_step = -1;
+  int check_mode = 0;
+  bool nonfinite_seen = false;
+  int64_t nonfinite_step = -1;
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
   size_t bytes = 0;
@@ -244,6 +257,10 @@ int validate(const lbm_params *p) {
   if (p->g_kind != LBM_G_UNIFORM && !p->g_data)
     return fail(LBM_EINVAL, "g_data is NULL for a profile or field force");
   if (p->monitor_every < 0) return fail(LBM_EINVAL, "monitor_every must be >= 0");
+  if (!(p->mach_limit >= 0) || !std::isfinite(p->mach_limit))
+    return fail(LBM_EINVAL, "mach_limit = %g must be >= 0 (0 = off)", p->mach_limit);
+  if (p->debug_poison != 0 && p->debug_poison != 1)
+    return fail(LBM_EINVAL, "debug_poison must be 0 or 1");
   if (p->allocator && (!p->allocator->alloc || !p->allocator->free))
     return fail(LBM_EINVAL, "allocator needs both alloc and free");
   return LBM_OK;
@@ -267,15 +284,18 @@ void release(lbm_ctx *c) {
   c->dfree(c->partials);
   c->dfree(c->mon_dev);
   c->dfree(c->scratch);
+  if (c->mon_host) (void)hipHostFree(c->mon_host);
+  if (c->mon_ev) (void)hipEventDestroy(c->mon_ev);
   c->magic = 0;
   delete c;
 }
 
 }  // namespace
 
-// Monitor finalisation and the stream-copy probe (lbm_aux.hip).
+// Monitor finalisation, the NaN fill and the stream-copy probe (lbm_aux.hip).
 namespace lbm {
 hipError_t finalize_monitors(const double *partials, int64_t nb, double *out, hipStream_t s);
+hipError_t fill_nan(void *p, size_t bytes, hipStream_t s);
 hipError_t copy_probe(const void *src, void *dst, size_t bytes, int reps, int block,
                       int variant, hipStream_t s);
 }  // namespace lbm
@@ -287,6 +307,83 @@ int refresh_monitors(lbm_ctx *c, int mode) {
   HIP_TRY(c->ops->moments(d, nullptr, nullptr, c->uprev, mode, c->partials, c->stream));
   HIP_TRY(lbm::finalize_monitors(c->partials, c->nblocks, c->mon_dev, c->stream));
   return LBM_OK;
+}
+
+// A monitor record from the finalised slots h (lbm_internal.h MON_*) of time t; the
+// residual exists only if the pass compared with a recorded previous step (mode 4).
+lbm_monitors record_of(const double *h, int64_t t, int mode) {
+  lbm_monitors m{};
+  m.step = t;
+  m.mass = h[lbm::MON_MASS];
+  for (int a = 0; a < 3; ++a) {
+    m.mom[a] = h[lbm::MON_MX + a];
+    m.j[a] = h[lbm::MON_JX + a];
+  }
+  m.resid = (mode == 4 && h[lbm::MON_U2] > 0) ? std::sqrt(h[lbm::MON_DU2] / h[lbm::MON_U2]) : 0.0;
+  m.umax = h[lbm::MON_UMAX];
+  m.nonfinite = (int64_t)h[lbm::MON_BAD];
+  return m;
+}
+
+// What a monitor record reports: LBM_ENONFINITE (sticky until the state is replaced),
+// the warning LBM_WMACH, or LBM_OK.
+int judge_record(lbm_ctx *c, const lbm_monitors &m) {
+  if (m.nonfinite) {
+    c->nonfinite_seen = true;
+    c->nonfinite_step = m.step;
+    return fail(LBM_ENONFINITE, "%lld nodes are not finite at step %lld",
+                (long long)m.nonfinite, (long long)m.step);
+  }
+  const double cs = std::sqrt(1.0 / 3.0);
+  if (c->p.mach_limit > 0 && m.umax > c->p.mach_limit * cs)
+    return fail(LBM_WMACH, "max |u| = %g at step %lld exceeds the Mach limit %g c_s", m.umax,
+                (long long)m.step, c->p.mach_limit);
+  return LBM_OK;
+}
+
+// The in-step check at the current time t (a multiple of monitor_every): the record of
+// time t on the device, compared with t - 1 when that was recorded, and its copy to the
+// pinned host record behind an event.
+int in_step_check(lbm_ctx *c) {
+  const int mode = (c->uprev_time == c->t - 1) ? 4 : 2;
+  int rc = refresh_monitors(c, mode);
+  if (rc) return rc;
+  c->uprev_time = c->t;
+  c->dev_step = c->t;
+  c->dev_mode = mode;
+  HIP_TRY(hipMemcpyAsync(c->mon_host, c->mon_dev, lbm::MON_SLOTS * sizeof(double),
+                         hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipEventRecord(c->mon_ev, c->stream));
+  c->check_pending = true;
+  c->check_step = c->t;
+  c->check_mode = mode;
+  return LBM_OK;
+}
+
+// Read the latest in-step record once it is complete (wait: block until it is).  A
+// non-finite state seen before keeps returning LBM_ENONFINITE.
+int poll_checks(lbm_ctx *c, bool wait) {
+  if (c->nonfinite_seen)
+    return fail(LBM_ENONFINITE, "the state had non-finite nodes at step %lld",
+                (long long)c->nonfinite_step);
+  if (!c->check_pending) return LBM_OK;
+  const hipError_t e = wait ? hipEventSynchronize(c->mon_ev) : hipEventQuery(c->mon_ev);
+  if (e == hipErrorNotReady) return LBM_OK;
+  if (e != hipSuccess)
+    return fail(LBM_EDEVICE, "monitor check: %s", hipGetErrorString(e));
+  c->check_pending = false;
+  const lbm_monitors m = record_of(c->mon_host, c->check_step, c->check_mode);
+  c->mon = m;
+  return judge_record(c, m);
+}
+
+// The state was replaced: no record, residual or non-finite verdict carries over.
+void state_replaced(lbm_ctx *c) {
+  c->uprev_time = -2;
+  c->dev_step = -1;
+  c->check_pending = false;
+  c->nonfinite_seen = false;
+  c->mon.step = -1;
 }
 
 }  // namespace
@@ -456,6 +553,7 @@ int lbm_lattice_info(int32_t lattice, int32_t *D, int32_t *Q, int32_t *e, double
 const char *lbm_strerror(int status) {
   switch (status) {
     case LBM_OK: return "ok";
+    case LBM_WMACH: return "warning: max |u| exceeds the Mach limit";
     case LBM_EINVAL: return "invalid argument";
     case LBM_ENOMEM: return "out of memory";
     case LBM_EDEVICE: return "device error";
@@ -505,6 +603,7 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   block_shape(p->nx, c->bx, c->by);
   const dim3 grid((p->nx + c->bx - 1) / c->bx, (p->ny + c->by - 1) / c->by, p->nz);
   c->nblocks = (int64_t)grid.x * grid.y * grid.z;
+  c->nblocks_cap = c->nblocks;
 
   const size_t pop_bytes = (size_t)c->Q * (size_t)c->N * storage_bytes(p->storage);
   const size_t ab = arith_bytes(p->storage);
@@ -551,11 +650,25 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
       (rc = c->dalloc(&c->gtab, gconv.size())) ||
       (p->solid && (rc = c->dalloc((void **)&c->smask, (size_t)c->N * sizeof(uint32_t)))) ||
       (rc = c->dalloc(&c->uprev, 3 * (size_t)c->N * ab)) ||
-      (rc = c->dalloc((void **)&c->partials, (size_t)c->nblocks * 8 * sizeof(double))) ||
-      (rc = c->dalloc((void **)&c->mon_dev, 8 * sizeof(double)))) {
+      (rc = c->dalloc((void **)&c->partials,
+                      (size_t)c->nblocks * lbm::MON_SLOTS * sizeof(double))) ||
+      (rc = c->dalloc((void **)&c->mon_dev, lbm::MON_SLOTS * sizeof(double)))) {
     std::string msg = g_last_error;
     release(c);
     return fail(rc, "%s", msg.c_str());
+  }
+  if (p->monitor_every > 0) {
+    if (hipHostMalloc((void **)&c->mon_host, lbm::MON_SLOTS * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+      c->mon_host = nullptr;
+      release(c);
+      return fail(LBM_ENOMEM, "pinned host memory for the monitor record");
+    }
+    if (hipEventCreateWithFlags(&c->mon_ev, hipEventDisableTiming) != hipSuccess) {
+      c->mon_ev = nullptr;
+      release(c);
+      return fail(LBM_EDEVICE, "creating the monitor event failed");
+    }
   }
   auto bail = [&](int code) {
     std::string msg = g_last_error;
@@ -605,55 +718,63 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
 int lbm_step(lbm_ctx *c, int64_t n, const double *g_scale) {
   if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
+  if (g_scale)
+    for (int64_t s = 0; s < n; ++s)
+      if (!std::isfinite(g_scale[s]))
+        return fail(LBM_EINVAL, "g_scale[%lld] is not finite", (long long)s);
+  // a completed in-step record: a non-finite state stops here, a Mach warning is
+  // returned after the steps are enqueued
+  const int seen = poll_checks(c, false);
+  if (seen < 0) return seen;
   const int K = c->p.monitor_every;
+  const size_t pop_bytes = (size_t)c->Q * c->N * storage_bytes(c->p.storage);
   for (int64_t s = 0; s < n; ++s) {
     const double sc = g_scale ? g_scale[s] : 1.0;
-    if (!std::isfinite(sc)) return fail(LBM_EINVAL, "g_scale[%lld] is not finite", (long long)s);
+    if (c->p.debug_poison) HIP_TRY(lbm::fill_nan(c->buf[c->cur ^ 1], pop_bytes, c->stream));
     lbm::LaunchDesc d = c->desc(sc);
     HIP_TRY(c->ops->step(d, c->stream));
     c->cur ^= 1;
     c->t += 1;
     c->last_scale = sc;
     if (K > 0) {
-      if ((c->t + 1) % K == 0) {
+      if (c->t % K == 0) {
+        int rc = in_step_check(c);
+        if (rc) return rc;
+      } else if ((c->t + 1) % K == 0) {
+        // the velocity of the step before a check, for its residual
         int rc = refresh_monitors(c, 2 /* record */);
         if (rc) return rc;
         c->uprev_time = c->t;
-      } else if (c->t % K == 0) {
-        const int mode = (c->uprev_time == c->t - 1) ? 4 : 2;
-        int rc = refresh_monitors(c, mode);
-        if (rc) return rc;
-        c->uprev_time = c->t;
-        c->mon.step = c->t;
       }
     }
   }
-  return LBM_OK;
+  return seen;
 }
 
 int lbm_monitors_get(lbm_ctx *c, lbm_monitors *mon) {
   if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
   if (!mon) return fail(LBM_EINVAL, "mon is NULL");
-  const int mode = (c->uprev_time == c->t - 1) ? 4 : 2;
-  int rc = refresh_monitors(c, mode);
-  if (rc) return rc;
-  c->uprev_time = c->t;
-  double h[8];
+  int mode;
+  if (c->dev_step == c->t) {
+    // the in-step check of this time holds the record (refreshing it now would compare
+    // the state with itself)
+    mode = c->dev_mode;
+  } else {
+    mode = (c->uprev_time == c->t - 1) ? 4 : 2;
+    int rc = refresh_monitors(c, mode);
+    if (rc) return rc;
+    c->uprev_time = c->t;
+    c->dev_step = c->t;
+    c->dev_mode = mode;
+  }
+  double h[lbm::MON_SLOTS];
   HIP_TRY(hipMemcpyAsync(h, c->mon_dev, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  lbm_monitors m{};
-  m.step = c->t;
-  m.mass = h[0];
-  m.mom[0] = h[1];
-  m.mom[1] = h[2];
-  m.mom[2] = h[3];
-  m.resid = (mode == 4 && h[5] > 0) ? std::sqrt(h[4] / h[5]) : 0.0;
-  m.umax = h[6];
-  m.nonfinite = (int64_t)h[7];
+  c->check_pending = false;  // this record is the latest
+  const lbm_monitors m = record_of(h, c->t, mode);
   c->mon = m;
   *mon = m;
-  if (m.nonfinite) return fail(LBM_ENONFINITE, "%lld nodes are not finite", (long long)m.nonfinite);
-  return LBM_OK;
+  return judge_record(c, m);
 }
 
 int lbm_moments(lbm_ctx *c, double g_scale, double *rho, double *u) {
@@ -669,7 +790,7 @@ int lbm_moments(lbm_ctx *c, double g_scale, double *rho, double *u) {
   if (rho) HIP_TRY(hipMemcpyAsync(rho, rho_d, fld, hipMemcpyDeviceToHost, c->stream));
   if (u) HIP_TRY(hipMemcpyAsync(u, u_d, fld * c->D, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return poll_checks(c, true);
 }
 
 int lbm_get_populations(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double *out) {
@@ -694,7 +815,7 @@ int lbm_get_populations(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double
   HIP_TRY(c->ops->gather(d, idx_d, nnodes, out_d, c->stream));
   HIP_TRY(hipMemcpyAsync(out, out_d, outb, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return poll_checks(c, true);
 }
 
 int lbm_set_populations(lbm_ctx *c, const double *f) {
@@ -710,7 +831,7 @@ int lbm_set_populations(lbm_ctx *c, const double *f) {
   // the host array may be released once this returns
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->t = 0;
-  c->uprev_time = -2;
+  state_replaced(c);
   return LBM_OK;
 }
 
@@ -745,7 +866,7 @@ int lbm_set_waves(lbm_ctx *c, int32_t nwaves, const int32_t *k, const double *ph
   // the host arrays may be released once this returns
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->t = 0;
-  c->uprev_time = -2;
+  state_replaced(c);
   return LBM_OK;
 }
 
@@ -812,8 +933,7 @@ int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t layout, double
   d.fout = c->buf[0];
   HIP_TRY(c->ops->init(d, rho_d, u_d, c->p.rho0, noneq ? P : nullptr, c->stream));
   c->t = 0;
-  c->uprev_time = -2;
-  c->mon.step = -1;
+  state_replaced(c);
   return LBM_OK;
 }
 
@@ -944,8 +1064,7 @@ int lbm_load(lbm_ctx *c, const char *path) {
   HIP_TRY(hipStreamSynchronize(c->stream));  // host is released on return
   c->cur = 0;
   c->t = h.t;
-  c->uprev_time = -2;
-  c->mon.step = -1;
+  state_replaced(c);
   return LBM_OK;
 }
 
@@ -976,19 +1095,23 @@ int lbm_set_tuning(lbm_ctx *c, const lbm_tuning *t) {
   if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
   if (!tuning_ok(t)) return fail(LBM_EINVAL, "invalid tuning");
   if (t->by > 65535) return fail(LBM_EINVAL, "invalid tuning");
+  // the monitor partials are sized by the block grid: a larger buffer is allocated
+  // before anything changes, so a failure leaves the context as it was
+  const int64_t nb = (int64_t)((c->p.nx + t->bx - 1) / t->bx) * ((c->p.ny + t->by - 1) / t->by) *
+                     c->p.nz;
+  if (nb > c->nblocks_cap) {
+    double *grown = nullptr;
+    int rc = c->dalloc((void **)&grown, (size_t)nb * lbm::MON_SLOTS * sizeof(double));
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));  // the stream may still read the old one
+    c->dfree(c->partials);
+    c->bytes -= (size_t)c->nblocks_cap * lbm::MON_SLOTS * sizeof(double);
+    c->partials = grown;
+    c->nblocks_cap = nb;
+  }
   c->bx = t->bx;
   c->by = t->by;
   c->variant = t->variant;
-  // the monitor partials are sized by the block grid
-  const int64_t nb = (int64_t)((c->p.nx + c->bx - 1) / c->bx) * ((c->p.ny + c->by - 1) / c->by) *
-                     c->p.nz;
-  if (nb > c->nblocks) {
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    c->dfree(c->partials);
-    c->partials = nullptr;
-    int rc = c->dalloc((void **)&c->partials, (size_t)nb * 8 * sizeof(double));
-    if (rc) return rc;
-  }
   c->nblocks = nb;
   return LBM_OK;
 }

@@ -357,6 +357,8 @@ lbm_params one_node_params(const lbm_params &params) {
   q.g_data = nullptr;
   q.solid = nullptr;
   q.monitor_every = 0;
+  q.mach_limit = 0.0;
+  q.debug_poison = 0;
   if (q.rho0 == 0) q.rho0 = 1.0;
   return q;
 }

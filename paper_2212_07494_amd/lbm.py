@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_WMACH = 1  # warning: the call did its work, but max |u| exceeded the Mach limit
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
 COLLISIONS = {"bgk": 0, "smrt": 1, "rmrt": 2}
 STORAGES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3}
@@ -31,6 +32,10 @@ class LBMError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"lbm status {status}: {message}")
         self.status = status
+
+
+class MachWarning(UserWarning):
+    """A monitor record showed max |u| above the lattice's Mach limit (LBM_WMACH)."""
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -49,7 +54,8 @@ class lbm_params(C.Structure):
                 ("g_data", C.c_void_p), ("monitor_every", C.c_int32),
                 ("allocator", C.POINTER(lbm_allocator)), ("force_order", C.c_int32),
                 ("solid", C.c_void_p), ("tau_bulk", C.c_double), ("tau_31", C.c_double),
-                ("max_order", C.c_int32)]
+                ("max_order", C.c_int32), ("mach_limit", C.c_double),
+                ("debug_poison", C.c_int32)]
 
 
 class lbm_tuning(C.Structure):
@@ -61,11 +67,12 @@ class lbm_tuning(C.Structure):
 
 class lbm_monitors(C.Structure):
     _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("mom", C.c_double * 3),
-                ("umax", C.c_double), ("resid", C.c_double), ("nonfinite", C.c_int64)]
+                ("j", C.c_double * 3), ("umax", C.c_double), ("resid", C.c_double),
+                ("nonfinite", C.c_int64)]
 
     def as_dict(self):
-        return dict(step=self.step, mass=self.mass, mom=list(self.mom), umax=self.umax,
-                    resid=self.resid, nonfinite=self.nonfinite)
+        return dict(step=self.step, mass=self.mass, mom=list(self.mom), j=list(self.j),
+                    umax=self.umax, resid=self.resid, nonfinite=self.nonfinite)
 
 
 EXPORTS = {
@@ -118,7 +125,11 @@ def load():
 
 
 def _check(rc: int):
-    if rc != LBM_OK:
+    if rc == LBM_WMACH:
+        import warnings
+        warnings.warn(load().lbm_last_error().decode(errors="replace"), MachWarning,
+                      stacklevel=3)
+    elif rc != LBM_OK:
         msg = load().lbm_last_error().decode(errors="replace")
         raise LBMError(rc, msg)
 
@@ -164,11 +175,13 @@ class TorchAllocator:
 def make_params(lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1), bc=(0, 0, 0),
                 tau=(0.8, 0.8, 1.0), rho0=1.0, g=None, g_profile=None, g_field=None,
                 monitor_every=0, allocator=None, force_order=1, solid=None, tau_bulk=0.0,
-                tau_31=0.0, max_order=4):
+                tau_31=0.0, max_order=4, mach_limit=0.0, debug_poison=False):
     """Fill an lbm_params.  g: uniform (3,) acceleration; g_profile: (axis, (3, n) table);
     g_field: (3, N) array; force_order 1 or 3 (SMRT third-order force content); solid: N
-    flags (nonzero = solid node) or None.  Returned together with the arrays it points to
-    (keep both)."""
+    flags (nonzero = solid node) or None; mach_limit: warn (MachWarning) when a monitor
+    record has max |u| above mach_limit c_s (0 = off); debug_poison: fill the buffer each
+    step writes with NaN first.  Returned together with the arrays it points to (keep
+    both)."""
     nx, ny, nz = (tuple(shape) + (1, 1))[:3]
     p = lbm_params()
     p.lattice = LATTICES[lattice]
@@ -198,6 +211,8 @@ def make_params(lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1),
     p.tau_bulk = float(tau_bulk)
     p.tau_31 = float(tau_31)
     p.max_order = int(max_order)
+    p.mach_limit = float(mach_limit)
+    p.debug_poison = int(bool(debug_poison))
     if solid is not None:
         mask = np.ascontiguousarray(np.asarray(solid).ravel() != 0, dtype=np.uint8)
         if mask.size != nx * ny * nz:
@@ -234,9 +249,11 @@ def lbm_moments(ctx, N: int, D: int, g_scale: float = 1.0):
 
 
 def lbm_monitors_get(ctx) -> lbm_monitors:
+    """The monitor record; a non-finite state is reported in it (nonfinite > 0), not
+    raised."""
     m = lbm_monitors()
     rc = load().lbm_monitors_get(ctx, C.byref(m))
-    if rc not in (LBM_OK, LBM_ENONFINITE):
+    if rc != LBM_ENONFINITE:
         _check(rc)
     return m
 
@@ -333,7 +350,8 @@ class Lattice:
     def __init__(self, lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1),
                  walls=(0, 0, 0), tau=(0.8, 0.8, 1.0), rho0=1.0, rho=None, u=None, g=None,
                  g_profile=None, g_field=None, monitor_every=0, stream=None, allocator=None,
-                 force_order=1, solid=None, tau_bulk=0.0, tau_31=0.0, max_order=4):
+                 force_order=1, solid=None, tau_bulk=0.0, tau_31=0.0, max_order=4,
+                 mach_limit=0.0, debug_poison=False):
         self.lattice = lattice
         self.Q = QOF[lattice]
         self.D = 2 if lattice == "D2Q9" else 3
@@ -344,7 +362,7 @@ class Lattice:
         self._params, self._keep = make_params(lattice, collision, storage, self.shape, walls, tau,
                                                rho0, g, g_profile, g_field, monitor_every,
                                                allocator, force_order, solid, tau_bulk,
-                                               tau_31, max_order)
+                                               tau_31, max_order, mach_limit, debug_poison)
         if u is not None:
             u = np.asarray(u, dtype=np.float64)[: self.D]
         self.ctx = lbm_init(self._params, rho, u, stream)
@@ -430,6 +448,8 @@ EXPORTS_BATCH = {
     "lbm_batch_advance": ([C.c_void_p, C.c_int64], C.c_int),
     "lbm_batch_run": ([C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
                        C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_batch_step": ([C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_batch_status": ([C.c_void_p, C.c_void_p], C.c_int),
     "lbm_batch_moments": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_batch_get_populations": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
     "lbm_batch_set_populations": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
@@ -508,6 +528,20 @@ class Batch:
         _check(load().lbm_batch_run(self.ctx, int(max_steps), float(tol), int(check_every),
                                     int(stall_checks), _ptr(steps), _ptr(resid), _ptr(status)))
         return steps, resid, status
+
+    def step(self, max_steps, tol):
+        """lbm_batch_step: every domain to resid < tol (or its floor, or max_steps);
+        returns steps, resid and the per-domain status (lbm_batch_status)."""
+        steps = np.zeros(self.ndom, np.int64)
+        resid = np.zeros(self.ndom)
+        _check(load().lbm_batch_step(self.ctx, int(max_steps), float(tol), _ptr(steps),
+                                     _ptr(resid)))
+        return steps, resid, self.status()
+
+    def status(self):
+        st = np.zeros(self.ndom, np.int32)
+        _check(load().lbm_batch_status(self.ctx, _ptr(st)))
+        return st
 
     def N(self, d):
         nx, ny, nz = self.shapes[d]

@@ -57,6 +57,9 @@ def test_version_and_strerror():
     (dict(lattice="D3Q27", shape=(8, 8, 8), collision="smrt", max_order=5), "4 (default) or 6"),
     (dict(lattice="D3Q19", shape=(8, 8, 8), collision="smrt", max_order=6), "SMRT on D3Q27"),
     (dict(lattice="D3Q27", shape=(8, 8, 8), max_order=6), "SMRT on D3Q27"),
+    (dict(mach_limit=-0.1), "mach_limit"),
+    (dict(mach_limit=float("nan")), "mach_limit"),
+    (dict(rho0=float("nan")), "rho0"),
 ])
 def test_invalid_parameters_rejected(change, fragment):
     from paper_2212_07494_amd import lbm
@@ -101,6 +104,28 @@ def test_batch_rejects_invalid_domains():
     lib = lbm.load()
     assert lib.lbm_batch_advance(None, 1) == lbm.LBM_ESTATE
     assert lib.lbm_batch_free(None) == lbm.LBM_ESTATE
+    # the boundary's batched step and the status read, through ctypes
+    steps = np.zeros(4, np.int64)
+    resid = np.zeros(4)
+    assert lib.lbm_batch_step(None, 100, 1e-8, steps.ctypes.data, resid.ctypes.data) == \
+        lbm.LBM_ESTATE
+    assert lib.lbm_batch_status(None, None) == lbm.LBM_ESTATE
+
+
+def test_status_codes_and_warning():
+    """The warning code is positive and named; the monitor record carries J."""
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    assert lbm.LBM_WMACH > 0
+    assert b"Mach" in lib.lbm_strerror(lbm.LBM_WMACH)
+    assert lib.lbm_strerror(lbm.LBM_ENONFINITE) == b"non-finite value in the state"
+    names = [f[0] for f in lbm.lbm_monitors._fields_]
+    assert names == ["step", "mass", "mom", "j", "umax", "resid", "nonfinite"]
+    # lbm_monitors as declared in the header: field order
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    decl = re.search(r"typedef struct \{\s*int64_t step;\s*double (.*?);\s*int64_t nonfinite;",
+                     text, flags=re.S)
+    assert decl and decl.group(1).replace(" ", "") == "mass,mom[3],j[3],umax,resid"
 
 
 def test_generated_tables_are_current():
