@@ -209,6 +209,17 @@ int lbm_monitors_get(lbm_ctx *c, lbm_monitors *mon);
  *   out  : Q x nnodes doubles, population-major.  Synchronises the stream. */
 int lbm_get_populations(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lbm_get_populations staging through a
+ * fixed device array of LBM_NOALLOC_SCRATCH_BYTES instead of memory it allocates on
+ * demand.  Same arguments and results as lbm_get_populations, for nnodes with
+ * (Q + 1) * 8 * nnodes <= LBM_NOALLOC_SCRATCH_BYTES (Q * 8 * N with nodes NULL); larger
+ * requests fail with LBM_EINVAL.  Calls no allocating routine.  Every context on a
+ * device shares that device's array (set up by lbm_init, kept until the process ends):
+ * calls that overlap on one device race; calls on one stream, or synchronised, do not. */
+#define LBM_NOALLOC_SCRATCH_BYTES (4 << 20)
+int lbm_get_populations_noalloc(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double *out);
+
 /* Replace the state by the given pre-collision populations (Q x N doubles, as stored,
  * population-major), rounded to the storage type (nearest-even). */
 int lbm_set_populations(lbm_ctx *c, const double *f);

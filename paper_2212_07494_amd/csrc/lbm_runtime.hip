@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -82,8 +83,45 @@ void block_shape(int nx, int &bx, int &by) {
 
 }  // namespace
 
+// Staging memory of lbm_get_populations_noalloc, which allocates nothing: node indices and
+// gathered values.  Each device holds its own copy for the life of the process.  In host
+// code this name is not a device address: its address on each device is taken once, with
+// that device current, by noalloc_scratch_setup (called from lbm_init), and only that
+// address is passed to kernels and copies.
+static __device__ __align__(256) unsigned char lbm_noalloc_scratch[LBM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+// The device address of lbm_noalloc_scratch on the current device, kept per device.
+int noalloc_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(LBM_EDEVICE, "device %d beyond the library's table of %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return LBM_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(lbm_noalloc_scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(LBM_EDEVICE, "hipGetSymbolAddress of the no-alloc scratch: %s",
+                hipGetErrorString(e));
+  g_noalloc_ptr[device] = ptr;
+  return LBM_OK;
+}
+
+void *noalloc_scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  return g_noalloc_ptr[device];
+}
+
+}  // namespace
+
 struct lbm_ctx {
   uint32_t magic = kMagic;
+  int device = 0;  // the device current at lbm_init
   lbm_params p{};
   const lbm::LatticeOps *ops = nullptr;
   int D = 0, Q = 0;
@@ -571,8 +609,12 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   *out = nullptr;
   int rc = validate(p);
   if (rc) return rc;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(LBM_EDEVICE, "no current HIP device");
+  if ((rc = noalloc_scratch_setup(device))) return rc;
   lbm_ctx *c = new (std::nothrow) lbm_ctx();
   if (!c) return fail(LBM_ENOMEM, "host allocation of the context failed");
+  c->device = device;
   c->p = *p;
   c->p.g_data = nullptr;
   if (p->allocator) c->alloc = *p->allocator;
@@ -810,6 +852,37 @@ int lbm_get_populations(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double
   double *out_d = static_cast<double *>(c->scratch);
   int64_t *idx_d = nodes ? reinterpret_cast<int64_t *>(static_cast<char *>(c->scratch) + outb)
                          : nullptr;
+  if (nodes) HIP_TRY(hipMemcpyAsync(idx_d, nodes, idxb, hipMemcpyHostToDevice, c->stream));
+  lbm::LaunchDesc d = c->desc(1.0);
+  HIP_TRY(c->ops->gather(d, idx_d, nnodes, out_d, c->stream));
+  HIP_TRY(hipMemcpyAsync(out, out_d, outb, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return poll_checks(c, true);
+}
+
+int lbm_get_populations_noalloc(lbm_ctx *c, int64_t nnodes, const int64_t *nodes, double *out) {
+  if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  if (!nodes && nnodes != c->N) return fail(LBM_EINVAL, "nodes NULL requires nnodes == N");
+  if (nnodes < 0) return fail(LBM_EINVAL, "negative node count");
+  if (nnodes == 0) return LBM_OK;
+  const size_t outb = (size_t)c->Q * (size_t)nnodes * sizeof(double);
+  const size_t idxb = nodes ? (size_t)nnodes * sizeof(int64_t) : 0;
+  if ((uint64_t)nnodes > (uint64_t)LBM_NOALLOC_SCRATCH_BYTES / sizeof(double) ||
+      outb + idxb > (size_t)LBM_NOALLOC_SCRATCH_BYTES)
+    return fail(LBM_EINVAL,
+                "%lld nodes need %zu bytes of staging, beyond the %d bytes of the no-alloc "
+                "scratch (at most %lld nodes of this lattice)",
+                (long long)nnodes, outb + idxb, LBM_NOALLOC_SCRATCH_BYTES,
+                (long long)(LBM_NOALLOC_SCRATCH_BYTES / ((c->Q + 1) * sizeof(double))));
+  if (nodes)
+    for (int64_t j = 0; j < nnodes; ++j)
+      if (nodes[j] < 0 || nodes[j] >= c->N)
+        return fail(LBM_EINVAL, "node index %lld out of range", (long long)nodes[j]);
+  char *base = static_cast<char *>(noalloc_scratch_of(c->device));
+  if (!base) return fail(LBM_ESTATE, "no-alloc scratch not set up on device %d", c->device);
+  double *out_d = reinterpret_cast<double *>(base);
+  int64_t *idx_d = nodes ? reinterpret_cast<int64_t *>(base + outb) : nullptr;
   if (nodes) HIP_TRY(hipMemcpyAsync(idx_d, nodes, idxb, hipMemcpyHostToDevice, c->stream));
   lbm::LaunchDesc d = c->desc(1.0);
   HIP_TRY(c->ops->gather(d, idx_d, nnodes, out_d, c->stream));

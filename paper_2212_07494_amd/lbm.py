@@ -85,6 +85,7 @@ EXPORTS = {
     "lbm_monitors_get": ([C.c_void_p, C.POINTER(lbm_monitors)], C.c_int),
     "lbm_get_populations": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_set_populations": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lbm_get_populations_noalloc": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_set_waves": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_lattice_info": ([C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p,
                           C.c_void_p], C.c_int),
@@ -266,6 +267,19 @@ def lbm_get_populations(ctx, Q: int, N: int, nodes=None):
     idx = np.ascontiguousarray(nodes, dtype=np.int64)
     out = np.empty((Q, idx.size))
     _check(load().lbm_get_populations(ctx, idx.size, _ptr(idx), _ptr(out)))
+    return out
+
+
+def lbm_get_populations_noalloc(ctx, Q: int, N: int, nodes=None):
+    """lbm_get_populations staged through the library's fixed device array (no device
+    allocation; bounded size, see LBM_NOALLOC_SCRATCH_BYTES)."""
+    if nodes is None:
+        out = np.empty((Q, N))
+        _check(load().lbm_get_populations_noalloc(ctx, N, None, _ptr(out)))
+        return out
+    idx = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.empty((Q, idx.size))
+    _check(load().lbm_get_populations_noalloc(ctx, idx.size, _ptr(idx), _ptr(out)))
     return out
 
 
