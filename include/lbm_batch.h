@@ -52,7 +52,7 @@ typedef struct {
 typedef enum {
   LBM_DOM_RUNNING = 0,   /* still stepping (max_steps reached first) */
   LBM_DOM_CONVERGED = 1, /* resid < tol at a check */
-  LBM_DOM_FLOOR = 2,     /* resid stopped decreasing for `stall_checks` checks: round-off floor */
+  LBM_DOM_FLOOR = 2,     /* resid stopped decreasing and is noise: round-off floor (below) */
   LBM_DOM_NONFINITE = 3  /* NaN/Inf seen; the domain was stopped */
 } lbm_domain_status;
 
@@ -70,8 +70,12 @@ int lbm_batch_advance(lbm_batch *b, int64_t n);
 /* Step until every domain has converged (resid < tol), hit its round-off floor, or
  * max_steps steps were taken.  resid is the per-domain relative per-step change of the
  * physical velocity, sqrt(sum |u(t) - u(t-1)|^2 / sum |u(t)|^2), checked every
- * check_every steps (even, >= 2); a domain whose resid has not dropped below 0.99 of its
- * best value for stall_checks consecutive checks is stopped as LBM_DOM_FLOOR.  Each
+ * check_every steps (even, >= 2).  A domain is stopped as LBM_DOM_FLOOR when for
+ * stall_checks consecutive checks its resid has not dropped below 0.99 of its best value
+ * and its change is noise rather than a drift: over a window of stall_checks checks, the
+ * change of the velocity divided by the window's steps is below 3% of the last
+ * step's change (a state still converging, however slowly, drifts steadily and is not
+ * stopped; round-off noise does not accumulate over the window).  Each
  * check_every steps with the monitor pass run as one replay of a captured HIP graph.
  * Outputs (ndom entries each, any may be NULL): steps taken, last resid, status.
  * Synchronises the stream once per replay. */

@@ -80,6 +80,9 @@ __global__ void fill_ff_kernel(uint4 *__restrict__ p, int64_t n16, unsigned char
   if (i < ntail) tail[i] = 0xff;
 }
 
+// Below this window coherence a stalled residual counts as the round-off floor.
+constexpr double kFloorCoherence = 0.03;
+
 // Per-domain convergence decision after a compare pass (one thread per domain).
 __global__ void decide_kernel(const int *__restrict__ tile_begin, const int *__restrict__ tile_end,
                               const double *__restrict__ partials, DomState *__restrict__ st,
@@ -87,16 +90,29 @@ __global__ void decide_kernel(const int *__restrict__ tile_begin, const int *__r
                               double tol, int stall_checks, int steps) {
   const int d = blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= ndom || !active[d]) return;
-  double du2 = 0.0, u2 = 0.0, bad = 0.0;
+  double du2 = 0.0, u2 = 0.0, bad = 0.0, duk2 = 0.0;
   for (int t = tile_begin[d]; t < tile_end[d]; ++t) {
-    du2 += partials[(int64_t)t * 3 + 0];
-    u2 += partials[(int64_t)t * 3 + 1];
-    bad += partials[(int64_t)t * 3 + 2];
+    du2 += partials[(int64_t)t * BATCH_PARTIALS + BP_DU2];
+    u2 += partials[(int64_t)t * BATCH_PARTIALS + BP_U2];
+    bad += partials[(int64_t)t * BATCH_PARTIALS + BP_BAD];
+    duk2 += partials[(int64_t)t * BATCH_PARTIALS + BP_DUK2];
   }
   DomState s = st[d];
   s.steps += steps;
   const double r = u2 > 0.0 ? sqrt(du2 / u2) : (du2 > 0.0 ? INFINITY : 0.0);
   s.resid = r;
+  // Coherence over a window of stall_checks checks: the drift per step since the window
+  // started against the change of the last step.  A state still converging, however
+  // slowly, drifts steadily (coherence near 1); at the round-off floor the per-step
+  // changes are noise, which the long window does not accumulate (coherence near 0).
+  // The monitor pass of a check that starts a window stored the window's first velocity.
+  const bool window_end = s.nchk % stall_checks == 0;  // this check also starts the next
+  if (window_end) {
+    const int64_t gap = s.win_steps >= 0 ? s.steps - s.win_steps : 0;
+    if (gap > 0) s.coherence = du2 > 0.0 ? sqrt(duk2 / du2) / (double)gap : 0.0;
+    s.win_steps = s.steps;
+  }
+  s.nchk += 1;
   int stop = 0;
   if (bad > 0.0 || !isfinite(r)) {
     s.status = 3;
@@ -108,7 +124,8 @@ __global__ void decide_kernel(const int *__restrict__ tile_begin, const int *__r
     if (r < 0.99 * s.best) {
       s.best = r;
       s.stall = 0;
-    } else if (++s.stall >= stall_checks) {
+    } else if (++s.stall >= stall_checks && window_end && s.coherence < kFloorCoherence) {
+      // no progress for a whole window, and its change is noise, not a drift
       s.status = 2;
       stop = 1;
     }

@@ -18,7 +18,8 @@
 namespace lbm {
 
 struct BatchDom {
-  int64_t base;   // population offset (elements) of plane 0
+  int64_t base;   // population offset (elements) of plane 0, on a 128-byte boundary
+  int64_t ps;     // plane stride: nx ny rounded up to 128 bytes
   int64_t ubase;  // offset of the recorded-velocity planes
   int64_t goff;   // offset of the force table / field in the table buffer
   int nx, ny, nz, N;
@@ -74,12 +75,31 @@ __device__ __forceinline__ void batch_force(const T *__restrict__ gbuf, const Ba
   }
 }
 
+// The tiles a persistent workgroup walks.  Workgroups are dispatched to the chip's
+// XCDs round-robin (workgroup b on XCD b mod kXcds) and each XCD has its own L2, while
+// neighbouring tiles share cache lines through their +-1 pulls: so each XCD takes one
+// contiguous part of the tile table (equal counts), which its own workgroups walk in turn.
+// A grid that is not a multiple of kXcds falls back to a plain stride over the table.
+constexpr int kXcds = 8;
+struct TileWalk {
+  int t, end, stride;
+};
+__device__ __forceinline__ TileWalk tile_walk(int ntiles) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (G % kXcds) return {b, ntiles, G};
+  const int x = b % kXcds;
+  const int lo = (int)((int64_t)ntiles * x / kXcds);
+  const int hi = (int)((int64_t)ntiles * (x + 1) / kXcds);
+  return {lo + b / kXcds, hi, G / kXcds};
+}
+
 __device__ __forceinline__ Geom batch_geom(const BatchDom &dm) {
   Geom geo;
   geo.nx = dm.nx;
   geo.ny = dm.ny;
   geo.nz = dm.nz;
   geo.N = dm.N;
+  geo.ps = dm.ps;
   for (int a = 0; a < 3; ++a) geo.wall[a] = dm.wall[a];
   geo.smask = nullptr;  // batched domains have no solid nodes
   return geo;
@@ -90,7 +110,8 @@ __global__ void __launch_bounds__(256)
     batch_step_kernel(const S *__restrict__ fin, S *__restrict__ fout, const T *__restrict__ gbuf,
                       const BatchDom *__restrict__ doms, const BatchTile *__restrict__ tiles,
                       const int *__restrict__ active, int ntiles, T shift) {
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.stride) {
+    const int t = w.t;
     const BatchTile tile = tiles[t];
     if (!active[tile.dom]) continue;
     const BatchDom dm = doms[tile.dom];
@@ -108,22 +129,27 @@ __global__ void __launch_bounds__(256)
 }
 
 // Residual monitor over the tiles of active domains: physical u(t) of the current state
-// (pulled), compared with the recorded u (mode 4) and/or recorded (modes 2 and 4).
-// Writes per tile: sum |u - u_rec|^2, sum |u|^2, non-finite count.
+// (pulled), compared with the recorded u (mode 4) and/or recorded (modes 2 and 4).  At a
+// check (mode 4) u(t) is also compared with uchk, the velocity at the start of the
+// domain's coherence window; at a check that starts a window (every `window` checks)
+// uchk takes u(t).  Writes per tile the BATCH_PARTIALS slots (lbm_internal.h).
 template <class L, class S, class T>
 __global__ void __launch_bounds__(256)
     batch_monitor_kernel(const S *__restrict__ f, const T *__restrict__ gbuf,
                          const BatchDom *__restrict__ doms, const BatchTile *__restrict__ tiles,
                          const int *__restrict__ active, int ntiles, T shift,
-                         T *__restrict__ urec, int mode, double *__restrict__ partials) {
-  __shared__ double red[4][3];
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+                         T *__restrict__ urec, T *__restrict__ uchk,
+                         const DomState *__restrict__ st, int window, int mode,
+                         double *__restrict__ partials) {
+  __shared__ double red[4][BATCH_PARTIALS];
+  for (TileWalk w = tile_walk(ntiles); w.t < w.end; w.t += w.stride) {
+    const int t = w.t;
     const BatchTile tile = tiles[t];
     if (!active[tile.dom]) continue;
     const BatchDom dm = doms[tile.dom];
     int x = 0, y = 0;
     const int z = tile.z;
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[BATCH_PARTIALS] = {0.0, 0.0, 0.0, 0.0};
     if (tile_xy(tile, dm, x, y)) {
       const Geom geo = batch_geom(dm);
       const int node = (z * dm.ny + y) * dm.nx + x;
@@ -137,26 +163,33 @@ __global__ void __launch_bounds__(256)
       batch_force<T>(gbuf, dm, x, y, z, node, L::D, g);
       const Macro<T> M = macroscopic<L>(d, shift, g);
       T *ur = urec + dm.ubase;
+      T *uk = uchk + dm.ubase;
+      const bool starts = st[tile.dom].nchk % window == 0;
       for (int c = 0; c < L::D; ++c) {
+        const int64_t o = (int64_t)c * dm.N + node;
         const double uc = double(M.u[c]);
-        v[1] += uc * uc;
+        v[BP_U2] += uc * uc;
         if (mode & MOM_COMPARE) {
-          const double dd = uc - double(ur[(int64_t)c * dm.N + node]);
-          v[0] += dd * dd;
+          const double dd = uc - double(ur[o]);
+          v[BP_DU2] += dd * dd;
+          const double dk = uc - double(uk[o]);
+          v[BP_DUK2] += dk * dk;
+          if (starts) uk[o] = M.u[c];
         }
-        ur[(int64_t)c * dm.N + node] = M.u[c];
+        ur[o] = M.u[c];
       }
-      v[2] = (isfinite(v[1]) && isfinite(double(M.rho))) ? 0.0 : 1.0;
+      v[BP_BAD] = (isfinite(v[BP_U2]) && isfinite(double(M.rho))) ? 0.0 : 1.0;
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < BATCH_PARTIALS; ++s) {
       const double r = wave_sum(v[s]);
       if (lane == 0) red[wave][s] = r;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < BATCH_PARTIALS) {
       const int s = threadIdx.x;
-      partials[(int64_t)t * 3 + s] = ((red[0][s] + red[1][s]) + red[2][s]) + red[3][s];
+      partials[(int64_t)t * BATCH_PARTIALS + s] =
+          ((red[0][s] + red[1][s]) + red[2][s]) + red[3][s];
     }
     __syncthreads();
   }

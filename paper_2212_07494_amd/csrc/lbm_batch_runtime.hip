@@ -64,11 +64,12 @@ struct lbm_batch {
   hipStream_t cap = nullptr;  // private stream the check interval is captured on
   int ndom = 0;
   int64_t nodes = 0;
+  int64_t pop_elems = 0;  // elements of one population buffer (planes padded to lines)
   std::vector<lbm::BatchDom> dom;
   std::vector<int> gk;  // per domain: 1 if full field
   void *buf[2] = {nullptr, nullptr};
   int cur = 0;
-  void *gbuf = nullptr, *urec = nullptr;
+  void *gbuf = nullptr, *urec = nullptr, *uchk = nullptr;
   void *doms_d = nullptr, *tiles_d = nullptr;
   int *tile_begin_d = nullptr, *tile_end_d = nullptr;
   int ntiles = 0, max_tiles = 0;
@@ -132,6 +133,7 @@ struct lbm_batch {
     L.geo.ny = m.ny;
     L.geo.nz = m.nz;
     L.geo.N = m.N;
+    L.geo.ps = m.ps;
     for (int a = 0; a < 3; ++a) L.geo.wall[a] = m.wall[a];
     L.gtab = static_cast<const char *>(gbuf) + (size_t)m.goff * ab;
     L.g_axis = m.gaxis == 3 ? -1 : m.gaxis;
@@ -159,6 +161,9 @@ struct lbm_batch {
     b.grid = tune.blocks_per_cu * ncu;
     b.shift = shift;
     b.urec = urec;
+    b.uchk = uchk;
+    b.state = state_d;
+    b.window = 1;  // set by the monitor passes of a check interval
     b.partials = partials;
     return b;
   }
@@ -259,7 +264,7 @@ void release(lbm_batch *b) {
   (void)hipStreamSynchronize(b->stream);
   b->drop_graph();
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  void *ptrs[] = {b->buf[0], b->buf[1], b->gbuf,     b->urec,         b->doms_d,
+  void *ptrs[] = {b->buf[0], b->buf[1], b->gbuf,     b->urec,         b->uchk,  b->doms_d,
                   b->tiles_d, b->tile_begin_d, b->tile_end_d, b->partials, b->active_d,
                   b->n_active_d, b->state_d, b->scratch};
   for (void *p : ptrs)
@@ -277,6 +282,9 @@ int reset_states(lbm_batch *b) {
     s.best = std::numeric_limits<double>::infinity();
     s.status = LBM_DOM_RUNNING;
     s.stall = 0;
+    s.nchk = 0;
+    s.win_steps = -1;
+    s.coherence = 1.0;
   }
   int n = b->ndom;
   HIP_TRY(hipMemcpyAsync(b->active_d, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -296,6 +304,7 @@ int enqueue_interval(lbm_batch *b, int K, double tol, int stall, hipStream_t s) 
     if (k == K - 1) {
       lbm::BatchLaunch m = b->launch(from);
       m.mode = 2;
+      m.window = stall;
       HIP_TRY(b->ops->batch_monitor(m, s));
     }
     HIP_TRY(b->ops->batch_step(b->launch(from), s));
@@ -303,6 +312,7 @@ int enqueue_interval(lbm_batch *b, int K, double tol, int stall, hipStream_t s) 
   }
   lbm::BatchLaunch m = b->launch(from);
   m.mode = 4;
+  m.window = stall;
   HIP_TRY(b->ops->batch_monitor(m, s));
   HIP_TRY(lbm::decide_domains(b->tile_begin_d, b->tile_end_d, b->partials, b->state_d,
                               b->active_d, b->n_active_d, b->ndom, tol, stall, K, s));
@@ -359,9 +369,14 @@ int lbm_batch_init(const lbm_domain *domains, int32_t ndom, int32_t lattice, int
     m.nz = s.nz;
     m.N = s.nx * s.ny * s.nz;
     for (int a = 0; a < 3; ++a) m.wall[a] = s.bc[a] == LBM_WALLS;
+    // every population plane on a 128-byte boundary: a plane stride of whole cache lines
+    // and a domain base on a line, so no line is shared by two planes or two domains
+    const int64_t line = 128 / (int64_t)storage_bytes(storage);
+    m.ps = ((int64_t)m.nx * m.ny + line - 1) / line * line;
+    base = (base + line - 1) / line * line;
     m.base = base;
     m.ubase = ubase;
-    base += (int64_t)b->Q * m.N;
+    base += (int64_t)b->Q * m.nz * m.ps;
     ubase += (int64_t)b->D * m.N;
     m.goff = (int64_t)gh.size();
     if (s.g_kind == LBM_G_UNIFORM) {
@@ -393,6 +408,7 @@ int lbm_batch_init(const lbm_domain *domains, int32_t ndom, int32_t lattice, int
       return set_error(LBM_EINVAL, "non-finite acceleration value");
     }
   b->nodes = ubase / b->D;
+  b->pop_elems = base;
   std::vector<unsigned char> gconv(gh.size() * ab);
   for (size_t k = 0; k < gh.size(); ++k) {
     if (ab == 8)
@@ -410,11 +426,13 @@ int lbm_batch_init(const lbm_domain *domains, int32_t ndom, int32_t lattice, int
   int rc;
   if ((rc = b->dalloc(&b->buf[0], pop)) || (rc = b->dalloc(&b->buf[1], pop)) ||
       (rc = b->dalloc(&b->gbuf, gconv.size())) || (rc = b->dalloc(&b->urec, (size_t)ubase * ab)) ||
+      (rc = b->dalloc(&b->uchk, (size_t)ubase * ab)) ||
       (rc = b->dalloc(&b->doms_d, ndom * sizeof(lbm::BatchDom))) ||
       (rc = b->dalloc(&b->tiles_d, (size_t)b->max_tiles * sizeof(lbm::BatchTile))) ||
       (rc = b->dalloc((void **)&b->tile_begin_d, ndom * sizeof(int))) ||
       (rc = b->dalloc((void **)&b->tile_end_d, ndom * sizeof(int))) ||
-      (rc = b->dalloc((void **)&b->partials, (size_t)b->max_tiles * 3 * sizeof(double))) ||
+      (rc = b->dalloc((void **)&b->partials,
+                      (size_t)b->max_tiles * lbm::BATCH_PARTIALS * sizeof(double))) ||
       (rc = b->dalloc((void **)&b->active_d, ndom * sizeof(int))) ||
       (rc = b->dalloc((void **)&b->n_active_d, sizeof(int))) ||
       (rc = b->dalloc((void **)&b->state_d, ndom * sizeof(lbm::DomState)))) {
@@ -605,6 +623,9 @@ int lbm_batch_set_populations(lbm_batch *b, int32_t dom, const double *f) {
   st[dom].best = std::numeric_limits<double>::infinity();
   st[dom].status = LBM_DOM_RUNNING;
   st[dom].stall = 0;
+  st[dom].nchk = 0;
+  st[dom].win_steps = -1;
+  st[dom].coherence = 1.0;
   int n = 0;
   for (int a : act) n += a != 0;
   HIP_TRY(hipMemcpyAsync(b->active_d, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -636,7 +657,7 @@ int lbm_batch_get_tuning(const lbm_batch *b, lbm_batch_tuning *t) {
 int lbm_batch_autotune(lbm_batch *b, int32_t steps, lbm_batch_tuning *best, double *best_ms) {
   if (!valid(b)) return set_error(LBM_ESTATE, "invalid batch");
   if (steps < 1) return set_error(LBM_EINVAL, "steps must be >= 1");
-  const size_t pop = (size_t)b->Q * b->nodes * storage_bytes(b->storage);
+  const size_t pop = (size_t)b->pop_elems * storage_bytes(b->storage);
   int rc = b->need_scratch(pop);
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(b->scratch, b->buf[b->cur], pop, hipMemcpyDeviceToDevice, b->stream));

@@ -23,6 +23,7 @@ constexpr uint32_t SOLID_NODE = 1u << 31;
 
 struct GeomDesc {
   int nx, ny, nz, N;
+  int64_t ps;  // plane stride (elements between population planes), >= nx ny
   int wall[3];
   const uint32_t *smask;  // device, per-node solid mask words (NULL: no solid nodes)
 };
@@ -61,10 +62,17 @@ struct BatchLaunch {
   int ntiles;
   int grid;           // persistent workgroups
   double shift;
-  void *urec;         // monitor: recorded velocities
+  void *urec;         // monitor: recorded velocities (the step before a check)
+  void *uchk;         // monitor: velocities at the start of the coherence window
+  const void *state;  // monitor: per-domain DomState (which checks start a window)
+  int window;         // monitor: checks per coherence window
   int mode;           // monitor: 2 record, 4 compare + record
-  double *partials;   // monitor: 3 per tile
+  double *partials;   // monitor: BATCH_PARTIALS per tile
 };
+
+// Per-tile slots of the batched monitor: sum |u(t) - u(t-1)|^2, sum |u|^2, non-finite
+// count, sum |u(t) - u(start of the coherence window)|^2.
+enum { BP_DU2 = 0, BP_U2, BP_BAD, BP_DUK2, BATCH_PARTIALS };
 
 struct LatticeOps {
   int D, Q;
@@ -97,6 +105,9 @@ struct DomState {
   int64_t steps;
   double resid, best;
   int status, stall;
+  int nchk;           // checks since the state was set
+  int64_t win_steps;  // steps at the start of the current coherence window (-1: none)
+  double coherence;   // last full window: drift per step over it / the last step's change
 };
 
 // lbm_aux.hip

@@ -27,6 +27,7 @@ enum { GK_PROFILE = 0, GK_FIELD = 1 };
 
 struct Geom {
   int nx, ny, nz, N;
+  int64_t ps;  // plane stride: elements from one population plane to the next (>= nx ny)
   int wall[3];
   // Solid nodes (NULL: none): per node, bit i = the pull source of population i is solid,
   // bit 31 = the node itself is solid.
@@ -75,20 +76,22 @@ __device__ __forceinline__ void store_v(S *p, T v) {
 }
 
 // Storage slot of population i at node (x, y, z).  Layout: one slab per z layer holding
-// the layer's Q planes back to back, slot = (z Q + i) nx ny + y nx + x.  Compared with Q
+// the layer's Q planes back to back, slot = (z Q + i) ps + y nx + x, with the plane stride
+// ps = nx ny for a single lattice and nx ny rounded up to 128 bytes in the batched
+// engine (so every plane of every domain starts on a cache line).  Compared with Q
 // planes of the whole grid it keeps every access of a workgroup (its layer and the two
 // beside it) inside 3 Q nx ny contiguous values (a probe of the access pattern alone
 // streamed 5% faster this way).
 template <class L>
 __device__ __forceinline__ int64_t pop_slot(int i, int x, int y, int z, const Geom &G) {
-  return ((int64_t)z * L::Q + i) * ((int64_t)G.nx * G.ny) + (y * G.nx + x);
+  return ((int64_t)z * L::Q + i) * G.ps + (y * G.nx + x);
 }
 
 // Start of population i's plane in layer z.  z comes from blockIdx.z, so the address is
 // the same across the workgroup and lives in scalar registers.
 template <class L, class S>
 __device__ __forceinline__ S *plane_ptr(S *f, int i, int z, const Geom &G) {
-  return f + ((int64_t)z * L::Q + i) * ((int64_t)G.nx * G.ny);
+  return f + ((int64_t)z * L::Q + i) * G.ps;
 }
 
 // Element o of a plane through a 32-bit byte offset (the scalar-base + vector-offset
@@ -106,7 +109,7 @@ __device__ __forceinline__ S *at_offset(S *plane, uint32_t o) {
 template <class S>
 __device__ __forceinline__ bool fast_block(const Geom &G, int x0, int x1, int y0, int y1,
                                            int z) {
-  if (G.smask != nullptr || (uint64_t)G.nx * G.ny * sizeof(S) >= (1ull << 32)) return false;
+  if (G.smask != nullptr || (uint64_t)G.ps * sizeof(S) >= (1ull << 32)) return false;
   if (G.wall[0] && (x0 == 0 || x1 >= G.nx - 1)) return false;
   if (G.wall[1] && (y0 == 0 || y1 >= G.ny - 1)) return false;
   if (G.wall[2] && (z == 0 || z >= G.nz - 1)) return false;

@@ -18,6 +18,7 @@ inline StepArgs<T> make_args(const LaunchDesc &d) {
   a.geo.ny = d.geo.ny;
   a.geo.nz = d.geo.nz;
   a.geo.N = d.geo.N;
+  a.geo.ps = d.geo.ps;
   for (int c = 0; c < 3; ++c) a.geo.wall[c] = d.geo.wall[c];
   a.geo.smask = d.geo.smask;
   a.force.tab = static_cast<const T *>(d.gtab);
@@ -40,6 +41,7 @@ inline Geom geom_of(const LaunchDesc &d) {
   g.ny = d.geo.ny;
   g.nz = d.geo.nz;
   g.N = d.geo.N;
+  g.ps = d.geo.ps;
   for (int c = 0; c < 3; ++c) g.wall[c] = d.geo.wall[c];
   g.smask = d.geo.smask;
   return g;
@@ -206,7 +208,8 @@ struct Ops {
                          static_cast<const S *>(b.fin), static_cast<const T *>(b.gbuf),
                          static_cast<const BatchDom *>(b.doms),
                          static_cast<const BatchTile *>(b.tiles), b.active, b.ntiles, T(b.shift),
-                         static_cast<T *>(b.urec), b.mode, b.partials);
+                         static_cast<T *>(b.urec), static_cast<T *>(b.uchk),
+                         static_cast<const DomState *>(b.state), b.window, b.mode, b.partials);
       return hipGetLastError();
     });
   }

@@ -211,6 +211,7 @@ struct lbm_ctx {
     d.geo.ny = p.ny;
     d.geo.nz = p.nz;
     d.geo.N = (int)N;
+    d.geo.ps = (int64_t)p.nx * p.ny;
     for (int a = 0; a < 3; ++a) d.geo.wall[a] = p.bc[a] == LBM_WALLS;
     d.geo.smask = smask;
     d.gtab = gtab;
