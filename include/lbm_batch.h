@@ -109,8 +109,8 @@ int lbm_batch_set_populations(lbm_batch *b, int32_t dom, const double *f);
 /* Launch configuration: tile policy (tile_bx 64, 128, 256: tiles of that width and
  * 256/tile_bx rows; 0: per domain the smallest of those covering nx; 1: linear tiles
  * of 256 consecutive nodes of a layer, every lane busy whatever the width), persistent
- * workgroups per compute unit (1..32) and the memory variant of lbm_tuning.  Results do
- * not depend on it. */
+ * workgroups per compute unit (1..32; 0: one workgroup per tile instead of a persistent
+ * grid) and the memory variant of lbm_tuning.  Results do not depend on it. */
 typedef struct {
   int32_t tile_bx;
   int32_t blocks_per_cu;

@@ -158,7 +158,9 @@ struct lbm_batch {
     b.tiles = tiles_d;
     b.active = active_d;
     b.ntiles = ntiles;
-    b.grid = tune.blocks_per_cu * ncu;
+    // blocks_per_cu 0: one workgroup per tile (a multiple of the XCD count, so the
+    // XCD-contiguous tile walk applies); else a persistent grid walking the table
+    b.grid = tune.blocks_per_cu ? tune.blocks_per_cu * ncu : (ntiles + 7) / 8 * 8;
     b.shift = shift;
     b.urec = urec;
     b.uchk = uchk;
@@ -641,7 +643,7 @@ int lbm_batch_set_tuning(lbm_batch *b, const lbm_batch_tuning *t) {
   if (!valid(b)) return set_error(LBM_ESTATE, "invalid batch");
   if (!t || !(t->tile_bx == 0 || t->tile_bx == kLinearTiles || t->tile_bx == 64 ||
               t->tile_bx == 128 || t->tile_bx == 256) ||
-      t->blocks_per_cu < 1 || t->blocks_per_cu > 32 || t->variant < 0 || t->variant > 2)
+      t->blocks_per_cu < 0 || t->blocks_per_cu > 32 || t->variant < 0 || t->variant > 2)
     return set_error(LBM_EINVAL, "invalid batch tuning");
   b->tune = *t;
   return build_tiles(b);
@@ -670,7 +672,7 @@ int lbm_batch_autotune(lbm_batch *b, int32_t steps, lbm_batch_tuning *best, doub
   HIP_TRY(hipEventCreate(&e1));
   int status = LBM_OK;
   for (int tbx : {0, kLinearTiles, 64, 128, 256}) {
-    for (int bpc : {2, 4, 8, 16}) {
+    for (int bpc : {0, 2, 4, 8, 16}) {
       for (int v = 0; v < 3 && !status; ++v) {
         lbm_batch_tuning t{tbx, bpc, v};
         if ((status = lbm_batch_set_tuning(b, &t))) break;

@@ -239,11 +239,18 @@ def mlp_init_params(widths, seed: int) -> np.ndarray:
 
 
 def warmstart_problem(seed: int, box: int = 128, tau_range=(0.55, 1.2), kmax=4,
-                      amp_range=(1e-7, 1e-5), umax=0.05, remax=0.5, nmodes=4):
+                      amp_range=(1e-7, 1e-5), umax=0.05, remax=0.5, nmodes=4,
+                      family="narrow"):
     """One seeded warm-start problem on a periodic box^3: tau2 uniform in tau_range and
-    nmodes Fourier forcing modes (fourier_modes), redrawn until the summed Stokes
-    amplitude U = sum_j amp_j / (nu K_j^2) (K_j = 2 pi |k_j| / box) is at most umax and
-    the Reynolds number U / (nu K_min) at most remax.  Returns dict(tau2, modes, U)."""
+    nmodes Fourier forcing modes (fourier_modes), redrawn until the draw is accepted.
+
+    family "narrow": the summed Stokes amplitude U = sum_j amp_j / (nu K_j^2)
+    (K_j = 2 pi |k_j| / box) is at most umax and the Reynolds number U / (nu K_min) at
+    most remax.  family "wide": each mode on its own has a Stokes amplitude
+    U_j = amp_j / (nu K_j^2) of at most 0.1 and a Reynolds number
+    Re_j = amp_j / (nu^2 K_j^3) of at most 1 (the bounds per mode of the configuration's
+    sampling; some such problems have no steady state).  Returns dict(tau2, modes, U,
+    Re) with U the summed Stokes amplitude and Re the largest Re_j."""
     rng = np.random.default_rng(seed)
     while True:
         tau2 = float(rng.uniform(*tau_range))
@@ -251,6 +258,12 @@ def warmstart_problem(seed: int, box: int = 128, tau_range=(0.55, 1.2), kmax=4,
                               amp_range=amp_range)
         nu = (tau2 - 0.5) / 3
         Ks = [2 * math.pi * float(np.linalg.norm(m["k"])) / box for m in modes]
-        U = sum(m["amp"] / (nu * K * K) for m, K in zip(modes, Ks))
-        if U <= umax and U / (nu * min(Ks)) <= remax:
-            return dict(tau2=tau2, modes=modes, U=U)
+        Uj = [m["amp"] / (nu * K * K) for m, K in zip(modes, Ks)]
+        Rej = [m["amp"] / (nu * nu * K ** 3) for m, K in zip(modes, Ks)]
+        U = sum(Uj)
+        if family == "wide":
+            ok = max(Uj) <= 0.1 and max(Rej) <= 1.0
+        else:
+            ok = U <= umax and U / (nu * min(Ks)) <= remax
+        if ok:
+            return dict(tau2=tau2, modes=modes, U=U, Re=max(Rej))

@@ -106,7 +106,7 @@ def test_launch_configurations_identical():
         ref.advance(5)
         want = [ref.populations(d) for d in range(len(doms))]
     for tbx in (0, 1, 64, 256):
-        for bpc in (1, 8):
+        for bpc in (0, 1, 8):
             for v in (0, 2):
                 with L.Batch(doms, "D2Q9", "smrt", "f32s") as b:
                     b.tune(tbx, bpc, v)
