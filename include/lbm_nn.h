@@ -166,6 +166,33 @@ int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_problem *p, int3
                          int32_t order, int32_t max_waves, int32_t *k_out, double *phase_out,
                          double *amp_out, int32_t *count);
 
+/* lbm_ws_lattice_waves with the boundaries of the orders: order_end[n - 1] (4 entries) is
+ * the number of waves of orders 1..n, so order n's waves are [order_end[n - 2],
+ * order_end[n - 1]) (from 0 for n = 1); entries beyond `order` equal the count. */
+int lbm_ws_lattice_waves_ordered(const lbm_params *params, const lbm_ws_problem *p,
+                                 int32_t box, int32_t order, int32_t max_waves, int32_t *k_out,
+                                 double *phase_out, double *amp_out, int32_t *count,
+                                 int32_t *order_end);
+
+/* The learned resummation of the expansion.  The steady state is approximated by
+ * sum_n c_n W_n, W_n the order-n waves of lbm_ws_lattice_waves_ordered (order 4), with
+ * c_n = 1 + sigma y_n, where sigma = a_3 / sqrt(a_2 a_1) (a_n the root-sum-square of the
+ * order-n amplitudes: the expansion's ratio, which vanishes as the series converges) and
+ * y (4 values) is the network's output.
+ * lbm_ws_resum_features writes the network's LBM_WS_RESUM_FEATURES inputs and sigma from
+ * a problem (nmodes 4) and its order-4 waves (amp: nwaves x Q x 2, order_end as above):
+ * tau2 - 1/2; log10 sigma; log10 (a_2/a_1), (a_3/a_1), (a_4/a_1); log10 of the summed
+ * Stokes amplitude U = sum_j s_j (s_j = amp_j / (nu K_j^2), K_j = 2 pi |k_j| / box) and of
+ * the largest Reynolds number Re_j = amp_j / (nu^2 K_j^3); then per mode, by decreasing
+ * s_j: s_j / U, K_j, log10 Re_j.  Host only.  Errors: LBM_EINVAL (NULL, nmodes != 4, an
+ * order without waves). */
+#define LBM_WS_RESUM_FEATURES 19
+int lbm_ws_resum_features(const lbm_ws_problem *p, int32_t box, int32_t Q, const double *amp,
+                          const int32_t *order_end, float *feat, double *sigma);
+
+/* amp (waves x Q x 2, in place) of each order n scaled by c[n - 1] (4 entries).  Host. */
+int lbm_ws_scale_orders(double *amp, int32_t Q, const int32_t *order_end, const double *c);
+
 /* An upper bound on the waves lbm_ws_lattice_waves writes for nmodes modes (1..8) to
  * order 1..4 (0 for arguments outside those ranges). */
 int32_t lbm_ws_max_waves(int32_t nmodes, int32_t order);
@@ -177,26 +204,6 @@ int32_t lbm_ws_max_waves(int32_t nmodes, int32_t order);
  * response depends on (the lattice sees a wave through its values on the links). */
 int lbm_ws_mode_features(const lbm_ws_problem *p, int32_t box, float *out_dev,
                          void *hip_stream);
-
-/* Solenoidal composition of the network's output on count stacked periodic n^3 grids
- * (rows n^3 per grid, x fastest, 4 channels): out = base + (curl psi, r) where psi is
- * channels 0..2 of y, r channel 3, and the curl takes central differences of unit grid
- * spacing, so the velocity correction has zero discrete divergence.  base may be NULL;
- * then the map is linear and its own adjoint (the transpose of the central difference is
- * its negative), which is how a loss gradient on out is taken back to y.  out must not
- * alias y. */
-int lbm_ws_compose(const float *y_dev, const float *base_dev, int32_t n, int32_t count,
-                   float *out_dev, void *hip_stream);
-
-/* Periodic trilinear upsampling of nchan fields on an nc^3 grid (x fastest) to nf^3 (nf
- * a multiple of nc): fine point x takes the coarse grid at x nc/nf.  Input channel-major
- * planes (point_major_in == 0) or point-major rows of nchan values (the network's
- * output); output channel-major planes, plus addend (point-major nf^3 x nchan rows,
- * device; may be NULL).  With an even ratio nf/nc the interpolation has zero transfer
- * at the fine grid's wavenumber pi. */
-int lbm_upsample_periodic(const float *coarse_dev, int32_t nc, int32_t nchan,
-                          int32_t point_major_in, const float *addend_dev, float *fine_dev,
-                          int32_t nf, void *hip_stream);
 
 /* Restart lattice c from device fields (N nodes, D velocity components):
  *   layout 0: planes rho (N), then u (D x N) (U and R unused);

@@ -634,60 +634,6 @@ __global__ void features_kernel(ModeDev m0, ModeDev m1, ModeDev m2, ModeDev m3, 
   b[3] = rb * inv_rho_scale;
 }
 
-// out = base + (curl of y's channels 0..2, y's channel 3) on count stacked periodic n^3
-// grids (x fastest), curl by central differences of unit spacing.  Without base this is
-// its own adjoint (the central difference is antisymmetric, so the curl is symmetric).
-__global__ void compose_kernel(const float *__restrict__ y, const float *__restrict__ base, int n,
-                               int64_t total, float *__restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int64_t N = (int64_t)n * n * n;
-  const int64_t g0 = idx / N * N, r = idx - g0;
-  const int x = (int)(r % n), yy = (int)((r / n) % n), z = (int)(r / ((int64_t)n * n));
-  auto at = [&](int i, int j, int k, int ch) {
-    return y[(g0 + ((int64_t)k * n + j) * n + i) * 4 + ch];
-  };
-  const int xp = (x + 1) % n, xm = (x + n - 1) % n;
-  const int yp = (yy + 1) % n, ym = (yy + n - 1) % n;
-  const int zp = (z + 1) % n, zm = (z + n - 1) % n;
-  // d_b psi_c = (psi_c(+e_b) - psi_c(-e_b)) / 2
-  const float dy_pz = 0.5f * (at(x, yp, z, 2) - at(x, ym, z, 2));
-  const float dz_py = 0.5f * (at(x, yy, zp, 1) - at(x, yy, zm, 1));
-  const float dz_px = 0.5f * (at(x, yy, zp, 0) - at(x, yy, zm, 0));
-  const float dx_pz = 0.5f * (at(xp, yy, z, 2) - at(xm, yy, z, 2));
-  const float dx_py = 0.5f * (at(xp, yy, z, 1) - at(xm, yy, z, 1));
-  const float dy_px = 0.5f * (at(x, yp, z, 0) - at(x, ym, z, 0));
-  float v[4] = {dy_pz - dz_py, dz_px - dx_pz, dx_py - dy_px, y[idx * 4 + 3]};
-  if (base)
-    for (int c = 0; c < 4; ++c) v[c] += base[idx * 4 + c];
-  for (int c = 0; c < 4; ++c) out[idx * 4 + c] = v[c];
-}
-
-__global__ void upsample_kernel(const float *__restrict__ c, int nc, int nch, int pm,
-                                const float *__restrict__ addend, float *__restrict__ f, int nf) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t Nf = (int64_t)nf * nf * nf;
-  if (idx >= Nf) return;
-  const int x = (int)(idx % nf), y = (int)((idx / nf) % nf), z = (int)(idx / ((int64_t)nf * nf));
-  const float r = (float)nc / (float)nf;
-  const float fx = x * r, fy = y * r, fz = z * r;
-  const int x0 = (int)fx, y0 = (int)fy, z0 = (int)fz;
-  const float ax = fx - x0, ay = fy - y0, az = fz - z0;
-  const int x1 = (x0 + 1) % nc, y1 = (y0 + 1) % nc, z1 = (z0 + 1) % nc;
-  const int64_t Nc = (int64_t)nc * nc * nc;
-  for (int ch = 0; ch < nch; ++ch) {
-    auto at = [&](int i, int j, int k) {
-      const int64_t q = ((int64_t)k * nc + j) * nc + i;
-      return pm ? c[q * nch + ch] : c[ch * Nc + q];
-    };
-    const float v = (1 - az) * ((1 - ay) * ((1 - ax) * at(x0, y0, z0) + ax * at(x1, y0, z0)) +
-                                ay * ((1 - ax) * at(x0, y1, z0) + ax * at(x1, y1, z0))) +
-                    az * ((1 - ay) * ((1 - ax) * at(x0, y0, z1) + ax * at(x1, y0, z1)) +
-                          ay * ((1 - ax) * at(x0, y1, z1) + ax * at(x1, y1, z1)));
-    f[ch * Nf + idx] = addend ? v + addend[idx * nch + ch] : v;
-  }
-}
-
 }  // namespace
 
 extern "C" {
@@ -762,32 +708,6 @@ int lbm_ws_mode_features(const lbm_ws_problem *p, int32_t box, float *out_dev,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   HIP_TRY(hipMemcpyAsync(out_dev, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));  // h is released on return
-  return LBM_OK;
-}
-
-int lbm_upsample_periodic(const float *coarse_dev, int32_t nc, int32_t nchan,
-                          int32_t point_major_in, const float *addend_dev, float *fine_dev,
-                          int32_t nf, void *hip_stream) {
-  if (!coarse_dev || !fine_dev) return set_error(LBM_EINVAL, "NULL argument");
-  if (nc < 1 || nf < nc || nf % nc || nchan < 1 || nf > 2048)
-    return set_error(LBM_EINVAL, "invalid sizes");
-  const int64_t N = (int64_t)nf * nf * nf;
-  hipLaunchKernelGGL(upsample_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
-                     static_cast<hipStream_t>(hip_stream), coarse_dev, nc, nchan,
-                     point_major_in ? 1 : 0, addend_dev, fine_dev, nf);
-  HIP_TRY(hipGetLastError());
-  return LBM_OK;
-}
-
-int lbm_ws_compose(const float *y_dev, const float *base_dev, int32_t n, int32_t count,
-                   float *out_dev, void *hip_stream) {
-  if (!y_dev || !out_dev) return set_error(LBM_EINVAL, "NULL argument");
-  if (n < 1 || n > 1024 || count < 1) return set_error(LBM_EINVAL, "invalid sizes");
-  if (y_dev == out_dev) return set_error(LBM_EINVAL, "out must not alias y");
-  const int64_t total = (int64_t)n * n * n * count;
-  hipLaunchKernelGGL(compose_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                     static_cast<hipStream_t>(hip_stream), y_dev, base_dev, n, total, out_dev);
-  HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
 

@@ -437,10 +437,13 @@ extern "C" int lbm_ws_lattice_response(const lbm_params *params, const lbm_ws_pr
   return LBM_OK;
 }
 
-extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_problem *p,
-                                    int32_t box, int32_t order, int32_t max_waves,
-                                    int32_t *k_out, double *phase_out, double *amp_out,
-                                    int32_t *count) {
+namespace {
+
+// The waves of orders 1..order, emitted order by order; ends (may be NULL) receives after
+// each order n the number of waves written so far (ends[n - 1]).
+int lattice_waves(const lbm_params *params, const lbm_ws_problem *p, int32_t box,
+                  int32_t order, int32_t max_waves, int32_t *k_out, double *phase_out,
+                  double *amp_out, int32_t *count, int32_t *ends) {
   using lbm::set_error;
   if (!k_out || !phase_out || !amp_out || !count) return set_error(LBM_EINVAL, "NULL argument");
   int rc = check_problem(params, p, box);
@@ -482,6 +485,7 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
     for (int a = 0; a < 3; ++a) d.g[a] = cplx(0.0, -p->p[j][a]);
     a1[j] = scaled(d, std::polar(p->amp[j], p->phase[j]));
   }
+  if (ends) ends[0] = w;
   if (order == 1) {
     *count = w;
     return LBM_OK;
@@ -526,6 +530,7 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
       w2.push_back({it.k, f2});
     }
   }
+  if (ends) ends[1] = w;
   if (order == 2) {
     *count = w;
     return LBM_OK;
@@ -593,6 +598,7 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
       w3.push_back({kv.first, f3});
     }
   }
+  if (ends) ends[2] = w;
   if (order == 3) {
     *count = w;
     return LBM_OK;
@@ -685,7 +691,104 @@ extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_probl
       emit(kv.first, 0.0, f4, 1.0);
     }
   }
+  if (ends) ends[3] = w;
   *count = w;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" int lbm_ws_lattice_waves(const lbm_params *params, const lbm_ws_problem *p,
+                                    int32_t box, int32_t order, int32_t max_waves,
+                                    int32_t *k_out, double *phase_out, double *amp_out,
+                                    int32_t *count) {
+  return lattice_waves(params, p, box, order, max_waves, k_out, phase_out, amp_out, count,
+                       nullptr);
+}
+
+extern "C" int lbm_ws_lattice_waves_ordered(const lbm_params *params, const lbm_ws_problem *p,
+                                            int32_t box, int32_t order, int32_t max_waves,
+                                            int32_t *k_out, double *phase_out,
+                                            double *amp_out, int32_t *count,
+                                            int32_t *order_end) {
+  if (!order_end) return lbm::set_error(LBM_EINVAL, "order_end is NULL");
+  for (int n = 0; n < 4; ++n) order_end[n] = 0;
+  int rc = lattice_waves(params, p, box, order, max_waves, k_out, phase_out, amp_out, count,
+                         order_end);
+  if (rc) return rc;
+  for (int n = order; n < 4; ++n) order_end[n] = *count;
+  return LBM_OK;
+}
+
+extern "C" int lbm_ws_resum_features(const lbm_ws_problem *p, int32_t box, int32_t Q,
+                                     const double *amp, const int32_t *order_end,
+                                     float *feat, double *sigma) {
+  using lbm::set_error;
+  if (!p || !amp || !order_end || !feat || !sigma) return set_error(LBM_EINVAL, "NULL argument");
+  if (p->nmodes != 4) return set_error(LBM_EINVAL, "nmodes = %d: the features need 4", p->nmodes);
+  if (box < 1 || Q < 1) return set_error(LBM_EINVAL, "box and Q must be positive");
+  if (!(p->tau2 > 0.5)) return set_error(LBM_EINVAL, "tau2 must exceed 1/2");
+  // root-sum-square amplitude of each order's waves
+  double a[4];
+  int lo = 0;
+  for (int n = 0; n < 4; ++n) {
+    const int hi = order_end[n];
+    if (hi < lo) return set_error(LBM_EINVAL, "order_end must not decrease");
+    double s = 0.0;
+    for (int64_t j = (int64_t)lo * Q * 2; j < (int64_t)hi * Q * 2; ++j) s += amp[j] * amp[j];
+    a[n] = std::sqrt(s);
+    lo = hi;
+  }
+  if (!(a[0] > 0) || !(a[1] > 0) || !(a[2] > 0) || !(a[3] > 0))
+    return set_error(LBM_EINVAL, "the features need waves of all four orders");
+  // sigma^2 = a3^2 / (a2 a1): the series' ratio applied once more, relative to order 1
+  *sigma = a[2] / std::sqrt(a[1] * a[0]);
+  const double nu = (p->tau2 - 0.5) / 3.0;
+  struct M {
+    double s, K, Re;
+  };
+  M m[4];
+  double U = 0.0, Remax = 0.0;
+  for (int j = 0; j < 4; ++j) {
+    double kk = 0.0;
+    for (int c = 0; c < 3; ++c) kk += p->k[j][c] * p->k[j][c];
+    const double K = 2.0 * M_PI * std::sqrt(kk) / box;
+    m[j] = {p->amp[j] / (nu * K * K), K, p->amp[j] / (nu * nu * K * K * K)};
+    U += m[j].s;
+    Remax = std::max(Remax, m[j].Re);
+  }
+  // modes by decreasing Stokes amplitude (ties keep their order)
+  int ord[4] = {0, 1, 2, 3};
+  for (int i = 1; i < 4; ++i)
+    for (int j = i; j > 0 && m[ord[j]].s > m[ord[j - 1]].s; --j) std::swap(ord[j], ord[j - 1]);
+  int f = 0;
+  feat[f++] = (float)(p->tau2 - 0.5);
+  feat[f++] = (float)std::log10(*sigma);
+  feat[f++] = (float)std::log10(a[1] / a[0]);
+  feat[f++] = (float)std::log10(a[2] / a[0]);
+  feat[f++] = (float)std::log10(a[3] / a[0]);
+  feat[f++] = (float)std::log10(U);
+  feat[f++] = (float)std::log10(Remax);
+  for (int i = 0; i < 4; ++i) {
+    const M &q = m[ord[i]];
+    feat[f++] = (float)(q.s / U);
+    feat[f++] = (float)q.K;
+    feat[f++] = (float)std::log10(q.Re);
+  }
+  return f == LBM_WS_RESUM_FEATURES ? LBM_OK : set_error(LBM_EINVAL, "feature count");
+}
+
+extern "C" int lbm_ws_scale_orders(double *amp, int32_t Q, const int32_t *order_end,
+                                   const double *c) {
+  if (!amp || !order_end || !c || Q < 1) return lbm::set_error(LBM_EINVAL, "bad argument");
+  int lo = 0;
+  for (int n = 0; n < 4; ++n) {
+    const int hi = order_end[n];
+    if (hi < lo) return lbm::set_error(LBM_EINVAL, "order_end must not decrease");
+    if (!std::isfinite(c[n])) return lbm::set_error(LBM_EINVAL, "c[%d] is not finite", n);
+    for (int64_t j = (int64_t)lo * Q * 2; j < (int64_t)hi * Q * 2; ++j) amp[j] *= c[n];
+    lo = hi;
+  }
   return LBM_OK;
 }
 

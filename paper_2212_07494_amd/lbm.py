@@ -625,6 +625,7 @@ class lbm_ws_problem(C.Structure):
 
 
 WS_FEATURES = 46
+WS_RESUM_FEATURES = 19
 WS_MODE_FEATURES = 13
 RESET_MASS, RESET_MOMENTUM, RESET_FILTER, RESET_NONEQ = 1, 2, 4, 8
 
@@ -651,10 +652,12 @@ EXPORTS_NN = {
                               C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)],
                              C.c_int),
     "lbm_ws_max_waves": ([C.c_int32, C.c_int32], C.c_int32),
-    "lbm_upsample_periodic": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
-                               C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
-    "lbm_ws_compose": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p],
-                       C.c_int),
+    "lbm_ws_lattice_waves_ordered": ([C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                                      C.c_void_p], C.c_int),
+    "lbm_ws_resum_features": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "lbm_ws_scale_orders": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p], C.c_int),
     "lbm_mlp_set_output_scale": ([C.c_void_p, C.c_void_p], C.c_int),
     "lbm_mlp_loss_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                            C.POINTER(C.c_double)], C.c_int),
@@ -815,21 +818,54 @@ def lbm_ws_lattice_waves(problem, box, order=2, lattice="D3Q27", collision="smrt
     return k[:n].copy(), ph[:n].copy(), amp[:n, :, 0] + 1j * amp[:n, :, 1]
 
 
+def lbm_ws_lattice_waves_ordered(problem, box, order=4, lattice="D3Q27", collision="smrt",
+                                 tau3=1.0, rho0=1.0, **rates):
+    """lbm_ws_lattice_waves with the order boundaries: (k, phase, amp (n, Q, 2) binary64,
+    order_end (4,) int32); order n's waves are [order_end[n-2], order_end[n-1])."""
+    s = ws_problem_struct(problem)
+    params, keep = make_params(lattice, collision, "f64", (1, 1, 1),
+                               tau=(problem["tau2"], tau3, 1.0), rho0=rho0, **rates)
+    Q = QOF[lattice.upper()]
+    cap = int(load().lbm_ws_max_waves(int(s.nmodes), int(order)))
+    if cap == 0:
+        raise LBMError(LBM_EINVAL, f"nmodes = {int(s.nmodes)} or order = {order} out of range")
+    k = np.zeros((cap, 3), np.int32)
+    ph = np.zeros(cap, np.float64)
+    amp = np.zeros((cap, Q, 2), np.float64)
+    ends = np.zeros(4, np.int32)
+    count = C.c_int32()
+    _check(load().lbm_ws_lattice_waves_ordered(C.byref(params), C.byref(s), int(box), int(order),
+                                               cap, _ptr(k), _ptr(ph), _ptr(amp), C.byref(count),
+                                               _ptr(ends)))
+    n = count.value
+    return k[:n].copy(), ph[:n].copy(), np.ascontiguousarray(amp[:n]), ends
+
+
+def lbm_ws_resum_features(problem, box, amp, order_end):
+    """Network inputs (WS_RESUM_FEATURES float32) and sigma of a problem and its order-4
+    waves (amp: (n, Q, 2) binary64 as returned by lbm_ws_lattice_waves_ordered)."""
+    s = ws_problem_struct(problem)
+    a = np.ascontiguousarray(amp, np.float64)
+    ends = np.ascontiguousarray(order_end, np.int32)
+    feat = np.zeros(WS_RESUM_FEATURES, np.float32)
+    sigma = C.c_double()
+    _check(load().lbm_ws_resum_features(C.byref(s), int(box), int(a.shape[1]), _ptr(a),
+                                        _ptr(ends), _ptr(feat), C.byref(sigma)))
+    return feat, sigma.value
+
+
+def lbm_ws_scale_orders(amp, order_end, c):
+    """Scale each order's waves of amp ((n, Q, 2) binary64, in place) by c (4,)."""
+    if amp.dtype != np.float64 or not amp.flags.c_contiguous:
+        raise ValueError("amp must be a C-contiguous float64 array")
+    ends = np.ascontiguousarray(order_end, np.int32)
+    cc = np.ascontiguousarray(c, np.float64)
+    _check(load().lbm_ws_scale_orders(_ptr(amp), int(amp.shape[1]), _ptr(ends), _ptr(cc)))
+    return amp
+
+
 def _optr(t):
     return None if t is None else _dptr(t)
-
-
-def lbm_upsample_periodic(coarse, nc, nchan, fine, nf, point_major_in=False, addend=None,
-                          stream=None):
-    _check(load().lbm_upsample_periodic(_dptr(coarse), int(nc), int(nchan), int(bool(point_major_in)),
-                                        _optr(addend), _dptr(fine), int(nf), _stream_handle(stream)))
-
-
-def lbm_ws_compose(y, base, n, count, out, stream=None):
-    """out = base + (curl of y[:, :3], y[:, 3]) on count stacked periodic n^3 grids; with
-    base None the linear part, which is its own adjoint."""
-    _check(load().lbm_ws_compose(_dptr(y), _optr(base), int(n), int(count), _dptr(out),
-                                 _stream_handle(stream)))
 
 
 def lbm_reset_fields(ctx, fields, layout, U=1.0, R=None, flags=0):

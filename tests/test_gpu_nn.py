@@ -1,9 +1,11 @@
 """The warm-start network's GPU kernels against the FP64 reference (oracle/mlp.py).
 
 The reference with bf16=True rounds exactly the operands the GPU rounds, so forward
-outputs and gradients agree to FP32 accumulation error (checked at 1e-3 relative L2, with
-occasional one-ulp BF16 flips of re-rounded activations); against the unrounded FP64
-reference the agreement is at BF16 precision (reported, checked at 2e-2)."""
+outputs and gradients agree to FP32 accumulation error, apart from occasional one-ulp
+BF16 flips of re-rounded activations.  Checked element by element: every output and
+every gradient entry within 2e-2 of the RMS of its layer block (a wrong tile edge or
+row would be off by about the RMS), plus 1e-3 relative L2 over each array; against the
+unrounded FP64 reference the agreement is at BF16 precision (checked at 2e-2 L2)."""
 import math
 
 import numpy as np
@@ -19,6 +21,30 @@ pytestmark = [pytest.mark.gpu,
 
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def elementwise(a, b, blocks, bound=2e-2):
+    """Largest |a - b| over each block (slices of the flat arrays), in units of the RMS of
+    b over that block; asserts it is within bound."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    worst = 0.0
+    for sl in blocks:
+        rms = float(np.sqrt(np.mean(b[sl] ** 2))) or 1e-300
+        e = float(np.max(np.abs(a[sl] - b[sl]))) / rms
+        worst = max(worst, e)
+        assert e <= bound, (sl, e)
+    return worst
+
+
+def param_blocks(widths):
+    out, off = [], 0
+    for l in range(len(widths) - 1):
+        n, k = widths[l + 1], widths[l]
+        out.append(slice(off, off + n * k))
+        out.append(slice(off + n * k, off + n * k + n))
+        off += n * k + n
+    return out
 
 
 @pytest.mark.parametrize("widths,rows", [([64, 64], 64), ([34, 96], 1000), ([130, 70], 777),
@@ -55,6 +81,11 @@ def test_forward_and_gradients(widths, rows):
     assert rel(y, y_e) < 1e-3, rel(y, y_e)
     assert abs(loss - l_e) < 1e-3 * l_e
     assert rel(g, g_e) < 1e-3, rel(g, g_e)
+    # element by element: each output column, each weight matrix and bias vector
+    ey = elementwise(y, y_e, [slice(c, None, widths[-1]) for c in range(widths[-1])])
+    eg = elementwise(g, g_e, param_blocks(widths))
+    print(f"{widths} x {rows}: worst element error {ey:.1e} (outputs), {eg:.1e} (gradients) "
+          "of the block RMS")
     assert rel(y, y_f) < 2e-2 and rel(g, g_f) < 2e-2, (rel(y, y_f), rel(g, g_f))
 
 
@@ -119,7 +150,7 @@ def test_adam_step():
         net.close()
 
 
-def test_features_and_upsampling():
+def test_features():
     import torch
     from paper_2212_07494_amd import lbm as L
     L.load()
@@ -159,29 +190,6 @@ def test_features_and_upsampling():
     assert np.all(base[:, 3] == 0)
     assert np.allclose(x[:, 44], prob["tau2"] - 0.5, rtol=1e-6)
     assert np.allclose(x[:, 45], U / (nu * min(Ks)), rtol=1e-5)
-    # upsampling: a periodic field sampled on 8^3 and interpolated to 32^3
-    nc, nf = 8, 32
-    c = np.random.default_rng(1).standard_normal((2, nc ** 3)).astype(np.float32)
-    fd = torch.empty((2, nf ** 3), device="cuda")
-    L.lbm_upsample_periodic(torch.tensor(c, device="cuda"), nc, 2, fd, nf)
-    f = fd.cpu().numpy().reshape(2, nf, nf, nf)
-    fd2 = torch.empty((2, nf ** 3), device="cuda")
-    L.lbm_upsample_periodic(torch.tensor(np.ascontiguousarray(c.T), device="cuda"), nc, 2, fd2,
-                            nf, point_major_in=True)
-    assert np.array_equal(fd2.cpu().numpy(), fd.cpu().numpy())
-    cc = c.reshape(2, nc, nc, nc).astype(np.float64)
-    r = nc / nf
-    for (z, y, xx) in [(0, 0, 0), (5, 17, 31), (31, 2, 9), (12, 30, 30)]:
-        fx, fy, fz = xx * r, y * r, z * r
-        x0, y0, z0 = int(fx), int(fy), int(fz)
-        ax, ay, az = fx - x0, fy - y0, fz - z0
-        want = 0.0
-        for dz, wz in ((0, 1 - az), (1, az)):
-            for dy, wy in ((0, 1 - ay), (1, ay)):
-                for dx, wx in ((0, 1 - ax), (1, ax)):
-                    want = want + wz * wy * wx * cc[:, (z0 + dz) % nc, (y0 + dy) % nc, (x0 + dx) % nc]
-        assert np.allclose(f[:, z, y, xx], want, atol=1e-5)
-    assert np.allclose(f[:, ::4, ::4, ::4].reshape(2, -1), c, atol=1e-6)
 
 
 @pytest.mark.parametrize("layout", [0, 1, 2])
@@ -318,61 +326,3 @@ def test_output_scale_and_loss_grad():
     d = y - t
     want = 2 * w * d / d.size
     assert np.max(np.abs(dy.cpu().numpy() - want)) < 1e-6 * np.abs(want).max()
-
-
-def curl_np(psi, n):
-    """Central-difference curl on a periodic n^3 grid; psi (3, n, n, n) indexed [c, z, y, x]."""
-    def d(a, axis):   # axis 0 = x, 1 = y, 2 = z
-        ax = 3 - axis
-        return 0.5 * (np.roll(a, -1, ax - 1) - np.roll(a, 1, ax - 1))
-    px, py, pz = psi
-    return np.stack([d(pz, 1) - d(py, 2), d(px, 2) - d(pz, 0), d(py, 0) - d(px, 1)])
-
-
-def test_compose_curl_adjoint_and_divergence():
-    import torch
-    from paper_2212_07494_amd import lbm as L
-    L.load()
-    n, count = 6, 3
-    N = n ** 3
-    rng = np.random.default_rng(15)
-    y = rng.standard_normal((count * N, 4)).astype(np.float32)
-    b = rng.standard_normal((count * N, 4)).astype(np.float32)
-    v = rng.standard_normal((count * N, 4)).astype(np.float32)
-    yd, bd, vd = (torch.tensor(a, device="cuda") for a in (y, b, v))
-    out = torch.empty_like(yd)
-    L.lbm_ws_compose(yd, bd, n, count, out)
-    o = out.cpu().numpy().astype(np.float64)
-    for g in range(count):
-        rows = slice(g * N, (g + 1) * N)
-        psi = y[rows, :3].T.astype(np.float64).reshape(3, n, n, n)
-        want = curl_np(psi, n).reshape(3, N).T + b[rows, :3]
-        assert np.max(np.abs(o[rows, :3] - want)) < 1e-5
-        assert np.array_equal(o[rows, 3], (y[rows, 3] + b[rows, 3]).astype(np.float32))
-        # zero central-difference divergence of the velocity correction
-        c = (o[rows, :3] - b[rows, :3]).T.reshape(3, n, n, n)
-        div = sum(0.5 * (np.roll(c[a], -1, 2 - a) - np.roll(c[a], 1, 2 - a)) for a in range(3))
-        assert np.max(np.abs(div)) < 1e-5
-    # the linear part is its own adjoint: <A y, v> = <y, A v>
-    Ay = torch.empty_like(yd)
-    Av = torch.empty_like(yd)
-    L.lbm_ws_compose(yd, None, n, count, Ay)
-    L.lbm_ws_compose(vd, None, n, count, Av)
-    lhs = float(np.sum(Ay.cpu().numpy().astype(np.float64) * v))
-    rhs = float(np.sum(y.astype(np.float64) * Av.cpu().numpy()))
-    assert abs(lhs - rhs) < 1e-5 * (abs(lhs) + 1)
-
-
-def test_upsample_with_addend():
-    import torch
-    from paper_2212_07494_amd import lbm as L
-    L.load()
-    nc, nf, ch = 4, 8, 4
-    rng = np.random.default_rng(16)
-    c = torch.tensor(rng.standard_normal((nc ** 3, ch)).astype(np.float32), device="cuda")
-    a = torch.tensor(rng.standard_normal((nf ** 3, ch)).astype(np.float32), device="cuda")
-    f0 = torch.empty((ch, nf ** 3), device="cuda")
-    f1 = torch.empty((ch, nf ** 3), device="cuda")
-    L.lbm_upsample_periodic(c, nc, ch, f0, nf, point_major_in=True)
-    L.lbm_upsample_periodic(c, nc, ch, f1, nf, point_major_in=True, addend=a)
-    assert np.array_equal(f1.cpu().numpy(), f0.cpu().numpy() + a.cpu().numpy().T)
