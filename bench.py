@@ -86,19 +86,30 @@ def copy_roofline(torch, L, stream, nbytes=2 << 30, reps=10):
     return best
 
 
-def cpu_baseline(w, steps: int):
+def cpu_baseline(w, steps: int, steps_one_thread: int = 1):
     """The FP64 oracle as it stands, on the host cores, over `steps` steps of the
-    same 256^3 workload."""
+    same 256^3 workload; and on one thread over `steps_one_thread` steps."""
+    import oracle
     from oracle import Oracle
     o = Oracle(w.lattice, w.collision, w.shape, walls=w.walls, tau=w.tau)
-    f = o.init(w.rho, w.u, w.g)
+    f0 = o.init(w.rho, w.u, w.g)
+    cores = oracle.set_threads(0)
     t0 = time.perf_counter()
-    f = o.run(f, w.g, steps)
+    o.run(f0, w.g, steps)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": w.N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle, {steps} steps of the full {w.shape[0]}^3 D3Q19 SMRT workload "
-                      f"({dt:.1f} s)"}
+    rec = {"value": w.N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"FP64 oracle, {steps} steps of the full {w.shape[0]}^3 D3Q19 SMRT "
+                     f"workload ({dt:.1f} s)"}
+    if steps_one_thread > 0:
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        o.run(f0, w.g, steps_one_thread)
+        dt1 = time.perf_counter() - t0
+        oracle.set_threads(cores)
+        rec["one_thread"] = {"value": w.N * steps_one_thread / dt1 / 1e6, "unit": "MLUPS",
+                             "cores": 1, "sample": f"{steps_one_thread} step(s) of the same "
+                                                   f"workload ({dt1:.1f} s)"}
+    return rec
 
 
 def time_to_steady(torch, L, nprob, box=128, seed=2022, tol=1e-8, check_every=20,
@@ -157,6 +168,30 @@ def time_to_steady(torch, L, nprob, box=128, seed=2022, tol=1e-8, check_every=20
             "total_warm_s": round(sum(r["warm_s"] for r in rows), 3)}
 
 
+def time_to_steady_learned(nprob, tol=1e-8, check_every=20):
+    """The learned warm start (the committed resummation network) against the same
+    expansion without the network, on nprob held-out problems of the wide forcing family
+    whose series converges slowly enough to matter (ratio sigma >= 1e-3): D3Q27 SMRT
+    128^3, FP64 storage, steps and wall time (start computation included) to a per-step
+    residual below tol, and the plain start for scale."""
+    from paper_2212_07494_amd import resum as R
+    res = R.evaluate(R.WEIGHTS, nprob, tol=tol, check=check_every, log=lambda s: None)
+    rows = [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
+             if k in ("sigma", "Re", "plain", "waves", "learned", "plain_s", "waves_s",
+                      "learned_s")} for r in res["problems"]]
+    return {"workload": f"D3Q27 SMRT FP64, 128^3 periodic, 4 seeded Fourier modes of the wide "
+                        f"family, series ratio >= {R.SIGMA_MIN:g}, resid < {tol:g}",
+            "learned": "order-4 lattice expansion with per-order factors from the BF16 network "
+                       "(paper_2212_07494_amd/weights/resum)",
+            "without_network": "order-3 expansion, order 4 where the series converges slowly",
+            "check_every": check_every, "problems": rows, "totals": res["totals"],
+            "learned_over_without_network_total": round(res["learned_over_waves_total"], 4),
+            "learned_over_without_network_median": round(res["learned_over_waves_median"], 4),
+            "learned_over_plain_total": round(res["learned_over_plain_total"], 4),
+            "wall_learned_over_without_network": round(res["wall_learned_over_waves"], 4),
+            "wall_learned_over_plain": round(res["wall_learned_over_plain"], 4)}
+
+
 def precision_vs_f64(L, w, stream, t, rho_t, u_t):
     """Error of the timed run's fields against the same workload stepped t steps in FP64
     storage: relative L2 of u (E2, the paper's error norm) and max |rho difference|."""
@@ -188,6 +223,8 @@ def main():
                     help="skip the error of the timed run against FP64 storage")
     ap.add_argument("--ttss", type=int, default=6,
                     help="warm-start problems for the time-to-steady comparison (0: skip)")
+    ap.add_argument("--learned", type=int, default=12,
+                    help="held-out problems for the learned warm start's leg (0: skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -228,6 +265,13 @@ def main():
     bytes_launch = 2 * Q * S * w.N
     achieved = bytes_launch / (ms_step * 1e-3) / 1e9
     m = lat.monitors()
+    # one monitor pass (FP64 sums of the record, compared with the step before), outside
+    # the timed steps: a call at a new time runs the pass
+    lat.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.monitors()
+    mon_ms = (time.perf_counter() - t0) * 1e3
     t_run = lat.time
     fields = None if (args.no_precision or args.storage == "f64") else lat.moments()
     lat.close()
@@ -273,12 +317,17 @@ def main():
                                "f16s": "FP16-shifted"}[args.storage],
                    "nodes": w.N, "parallelism": "single GPU"},
         "roofline": roof,
-        "monitors": {"step": m.step, "mass": m.mass, "umax": m.umax, "nonfinite": m.nonfinite},
+        "monitors": {"step": m.step, "mass": m.mass, "umax": m.umax, "nonfinite": m.nonfinite,
+                     "monitor_every": 0, "note": "the timed steps run no monitor pass; one "
+                     "pass (read back included) takes monitor_pass_ms",
+                     "monitor_pass_ms": round(mon_ms, 3)},
         "precision": precision,
         "kernel_source_hash": khash,
     }
     if args.ttss > 0:
         rec["time_to_steady"] = time_to_steady(torch, L, args.ttss)
+    if args.learned > 0:
+        rec["time_to_steady_learned"] = time_to_steady_learned(args.learned)
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(rec), flush=True)

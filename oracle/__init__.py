@@ -62,12 +62,19 @@ def _lib(kind: str):
         L.oracle_round_half.argtypes = [C.c_float]
         L.oracle_round_half.restype = C.c_float
         L.oracle_is_plain.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = C.c_int
         _LIBS[kind] = L
     return _LIBS[kind]
 
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(n: int, real: str = "f64") -> int:
+    """Threads of the oracle's whole-lattice loops (n <= 0: leave); the count in effect."""
+    return int(_lib(real).oracle_set_threads(int(n)))
 
 
 def round_half(x: float) -> float:

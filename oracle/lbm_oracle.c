@@ -48,6 +48,7 @@
  * -ffp-contract=off, no fast-math.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -792,6 +793,13 @@ void oracle_bgk_terms(const oracle_lattice *L, real rho, const real *u, const re
 }
 
 int oracle_real_size(void) { return (int)sizeof(real); }
+
+/* Threads of the whole-lattice loops (the results do not depend on it); returns the
+ * count in effect. */
+int oracle_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
 
 /* 1 for the PLAIN build (textbook operation order), 0 for the operation-order twin. */
 int oracle_is_plain(void) {
