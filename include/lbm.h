@@ -177,7 +177,13 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init,
              void *hip_stream, lbm_ctx **out);
 
 /* Advance n >= 0 steps.  g_scale: NULL (s(t) = 1) or n host doubles, the factor s(t)
- * of g(x) for each step.  Enqueues work only (no synchronisation).
+ * of g(x) for each step.  Enqueues work only (no synchronisation), except as below.
+ * Small lattices (N <= 2^21 nodes), where launch overhead dominates: when n covers at
+ * least two chunks of 64 steps and neither monitor_every nor debug_poison is set, the
+ * chunks are replayed from a HIP graph captured once per buffer parity (the factors s(t)
+ * are then uploaded to the device and read there, the call synchronising the stream once
+ * for that upload); the remainder runs as single launches.  The results are identical
+ * to single launches.
  * Monitors in the step: if monitor_every is K > 0, after every step whose time t is a
  * multiple of K the monitor record of time t is computed on the device (with the
  * residual against time t - 1, whose velocity is recorded one step earlier; K = 1

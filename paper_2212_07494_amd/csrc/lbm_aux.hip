@@ -161,6 +161,16 @@ hipError_t add_domain_steps(const int *active, void *state, int ndom, int64_t n,
   return hipGetLastError();
 }
 
+// The force-factor counter of graph replays: *ctr = set ? add : *ctr + add.
+__global__ void counter_kernel(int64_t *ctr, int64_t add, int set) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = set ? add : *ctr + add;
+}
+
+hipError_t graph_counter(int64_t *ctr, int64_t add, int set, hipStream_t s) {
+  hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, s, ctr, add, set);
+  return hipGetLastError();
+}
+
 hipError_t fill_nan(void *p, size_t bytes, hipStream_t s) {
   const int64_t n16 = (int64_t)(bytes / 16);
   const int ntail = (int)(bytes % 16);

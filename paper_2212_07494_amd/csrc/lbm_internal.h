@@ -48,6 +48,11 @@ struct LaunchDesc {
   int bx, by;        // block shape (bx * by <= 256, bx a multiple of 64)
   int variant;       // memory-access variant of the step kernel (MEM_*)
   int fast_ok;       // 1: blocks that cannot bounce back may take the scalar-base path
+  // Force factor from device memory (steps replayed from a captured graph): when gs_dev
+  // is set, s(t) = gs_dev[*gs_ctr + gs_j] instead of gscale.
+  const double *gs_dev;
+  const int64_t *gs_ctr;
+  int gs_j;
 };
 
 // One launch of the batched engine's persistent kernels.

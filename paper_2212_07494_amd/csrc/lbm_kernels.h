@@ -44,6 +44,11 @@ struct ForceRef {
   int axis;      // profile: 0, 1, 2, or -1 (uniform, n = 1)
   int n;
   T scale;       // s(t)
+  // s(t) from device memory instead (graph replays): sdev[*sctr + sj], rounded to T as
+  // the host value would be
+  const double *sdev;
+  const int64_t *sctr;
+  int sj;
 };
 
 // Memory-access variants of the step (chosen at run time by the tuner):
@@ -158,11 +163,12 @@ __device__ __forceinline__ int64_t pull_slot(int x, int y, int z, const Geom &G,
 template <class T, int GK>
 __device__ __forceinline__ void load_force(const ForceRef<T> &F, int x, int y, int z, int node,
                                            int N, int D, T (&g)[3]) {
+  const T scale = F.sdev ? T(F.sdev[*F.sctr + F.sj]) : F.scale;
   if constexpr (GK == GK_FIELD) {
-    for (int a = 0; a < 3; ++a) g[a] = (a < D) ? F.tab[(int64_t)a * N + node] * F.scale : T(0);
+    for (int a = 0; a < 3; ++a) g[a] = (a < D) ? F.tab[(int64_t)a * N + node] * scale : T(0);
   } else {
     const int c = F.axis == 0 ? x : (F.axis == 1 ? y : (F.axis == 2 ? z : 0));
-    for (int a = 0; a < 3; ++a) g[a] = (a < D) ? F.tab[a * F.n + c] * F.scale : T(0);
+    for (int a = 0; a < 3; ++a) g[a] = (a < D) ? F.tab[a * F.n + c] * scale : T(0);
   }
 }
 

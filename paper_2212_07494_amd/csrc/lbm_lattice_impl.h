@@ -25,6 +25,9 @@ inline StepArgs<T> make_args(const LaunchDesc &d) {
   a.force.axis = d.g_axis;
   a.force.n = d.g_n;
   a.force.scale = T(d.gscale);
+  a.force.sdev = d.gs_dev;
+  a.force.sctr = d.gs_ctr;
+  a.force.sj = d.gs_j;
   a.shift = T(d.shift);
   a.c0 = T(d.c0);
   a.c1 = T(d.c1);

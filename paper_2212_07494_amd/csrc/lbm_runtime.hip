@@ -154,6 +154,22 @@ struct lbm_ctx {
   int check_mode = 0;
   bool nonfinite_seen = false;
   int64_t nonfinite_step = -1;
+  // Steps replayed from captured graphs (small lattices, where launches dominate): a
+  // chunk of kGraphChunk steps captured on a private stream, one graph per (buffer
+  // parity, device force factors or not); the factors are uploaded to gs_dev and read at
+  // the device counter gs_ctr, which each replay advances.
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  double *gs_dev = nullptr;
+  size_t gs_cap = 0;
+  int64_t *gs_ctr = nullptr;
+  void drop_graphs() {
+    for (auto &row : gexec)
+      for (auto &e : row) {
+        if (e) (void)hipGraphExecDestroy(e);
+        e = nullptr;
+      }
+  }
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
   size_t bytes = 0;
@@ -325,6 +341,10 @@ void release(lbm_ctx *c) {
   c->dfree(c->scratch);
   if (c->mon_host) (void)hipHostFree(c->mon_host);
   if (c->mon_ev) (void)hipEventDestroy(c->mon_ev);
+  c->drop_graphs();
+  c->dfree(c->gs_dev);
+  c->dfree(c->gs_ctr);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   c->magic = 0;
   delete c;
 }
@@ -335,6 +355,7 @@ void release(lbm_ctx *c) {
 namespace lbm {
 hipError_t finalize_monitors(const double *partials, int64_t nb, double *out, hipStream_t s);
 hipError_t fill_nan(void *p, size_t bytes, hipStream_t s);
+hipError_t graph_counter(int64_t *ctr, int64_t add, int set, hipStream_t s);
 hipError_t copy_probe(const void *src, void *dst, size_t bytes, int reps, int block,
                       int variant, hipStream_t s);
 }  // namespace lbm
@@ -758,6 +779,100 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   return LBM_OK;
 }
 
+namespace {
+
+constexpr int kGraphChunk = 64;             // steps per captured graph (even)
+constexpr int64_t kGraphMaxNodes = 1 << 21;  // larger lattices are not launch-bound
+
+// Whether n steps of c run as graph replays: a small lattice, at least two chunks, no
+// in-step monitors or poison pass.
+bool graph_steps(const lbm_ctx *c, int64_t n) {
+  return c->N <= kGraphMaxNodes && n >= 2 * kGraphChunk && c->p.monitor_every == 0 &&
+         !c->p.debug_poison;
+}
+
+// The graph of one chunk from the current buffer, with device force factors (scaled) or
+// s(t) = 1; captured once per (parity, scaled).
+int chunk_graph(lbm_ctx *c, bool scaled, hipGraphExec_t *out) {
+  hipGraphExec_t &e = c->gexec[c->cur][scaled];
+  if (e) {
+    *out = e;
+    return LBM_OK;
+  }
+  if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  if (!c->gs_ctr) {
+    int rc = c->dalloc((void **)&c->gs_ctr, sizeof(int64_t));
+    if (rc) return rc;
+  }
+  HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  int cur = c->cur;
+  for (int j = 0; j < kGraphChunk && err == hipSuccess; ++j) {
+    const int saved = c->cur;
+    c->cur = cur;
+    lbm::LaunchDesc d = c->desc(1.0);
+    c->cur = saved;
+    if (scaled) {
+      d.gs_dev = c->gs_dev;
+      d.gs_ctr = c->gs_ctr;
+      d.gs_j = j;
+    }
+    err = c->ops->step(d, c->cap);
+    cur ^= 1;
+  }
+  if (err == hipSuccess && scaled) err = lbm::graph_counter(c->gs_ctr, kGraphChunk, 0, c->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->cap, &g);
+  if (err == hipSuccess) err = ec;
+  if (err == hipSuccess) err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (err != hipSuccess) {
+    e = nullptr;
+    return fail(LBM_EDEVICE, "capturing the step graph: %s", hipGetErrorString(err));
+  }
+  *out = e;
+  return LBM_OK;
+}
+
+// n >= 2 kGraphChunk steps as graph replays plus the remainder launched one by one.
+int graph_run(lbm_ctx *c, int64_t n, const double *g_scale) {
+  const bool scaled = g_scale != nullptr;
+  if (scaled) {
+    const size_t need = (size_t)n * sizeof(double);
+    if (need > c->gs_cap) {
+      HIP_TRY(hipStreamSynchronize(c->stream));  // the old table may still be read
+      c->drop_graphs();                          // the graphs hold its address
+      c->dfree(c->gs_dev);
+      c->bytes -= c->gs_cap;
+      c->gs_dev = nullptr;
+      c->gs_cap = 0;
+      int rc = c->dalloc((void **)&c->gs_dev, need);
+      if (rc) return rc;
+      c->gs_cap = need;
+    }
+    HIP_TRY(hipMemcpyAsync(c->gs_dev, g_scale, need, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));  // the host array is the caller's again
+  }
+  hipGraphExec_t e = nullptr;
+  int rc = chunk_graph(c, scaled, &e);
+  if (rc) return rc;
+  if (scaled) HIP_TRY(lbm::graph_counter(c->gs_ctr, 0, 1, c->stream));
+  const int64_t reps = n / kGraphChunk;
+  for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(e, c->stream));
+  c->t += reps * kGraphChunk;  // kGraphChunk is even: the current buffer is unchanged
+  int64_t s = reps * kGraphChunk;
+  for (; s < n; ++s) {
+    const double sc = scaled ? g_scale[s] : 1.0;
+    HIP_TRY(c->ops->step(c->desc(sc), c->stream));
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  c->last_scale = scaled ? g_scale[n - 1] : 1.0;
+  return LBM_OK;
+}
+
+}  // namespace
+
 int lbm_step(lbm_ctx *c, int64_t n, const double *g_scale) {
   if (!valid(c)) return fail(LBM_ESTATE, "invalid context");
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
@@ -769,6 +884,10 @@ int lbm_step(lbm_ctx *c, int64_t n, const double *g_scale) {
   // returned after the steps are enqueued
   const int seen = poll_checks(c, false);
   if (seen < 0) return seen;
+  if (graph_steps(c, n)) {
+    const int rc = graph_run(c, n, g_scale);
+    return rc ? rc : seen;
+  }
   const int K = c->p.monitor_every;
   const size_t pop_bytes = (size_t)c->Q * c->N * storage_bytes(c->p.storage);
   for (int64_t s = 0; s < n; ++s) {
@@ -1183,6 +1302,10 @@ int lbm_set_tuning(lbm_ctx *c, const lbm_tuning *t) {
     c->partials = grown;
     c->nblocks_cap = nb;
   }
+  if (c->bx != t->bx || c->by != t->by || c->variant != t->variant) {
+    HIP_TRY(hipStreamSynchronize(c->stream));  // a replay may still be in flight
+    c->drop_graphs();
+  }
   c->bx = t->bx;
   c->by = t->by;
   c->variant = t->variant;
@@ -1205,6 +1328,9 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_tuning *best, double *best_ms) {
   const size_t pop_bytes = (size_t)c->Q * c->N * storage_bytes(c->p.storage);
   int rc = c->need_scratch(pop_bytes);
   if (rc) return rc;
+  // graphs hold a launch configuration: the trials change it
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->drop_graphs();
   // save the state; trials ping-pong between the two buffers
   HIP_TRY(hipMemcpyAsync(c->scratch, c->buf[c->cur], pop_bytes, hipMemcpyDeviceToDevice,
                          c->stream));
