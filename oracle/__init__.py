@@ -26,7 +26,8 @@ _LIBS: dict = {}
 class _Lattice(C.Structure):
     _fields_ = [("D", C.c_int32), ("Q", C.c_int32), ("NM", C.c_int32),
                 ("e", C.c_void_p), ("opp", C.c_void_p), ("mi", C.c_void_p),
-                ("w", C.c_void_p), ("H", C.c_void_p), ("Minv", C.c_void_p)]
+                ("w", C.c_void_p), ("H", C.c_void_p), ("Minv", C.c_void_p),
+                ("ics2", C.c_double)]
 
 
 def _params_struct(real_t):
@@ -85,8 +86,9 @@ def round_half(x: float) -> float:
 class Oracle:
     """Plain forced LB step on one periodic / walled box.
 
-    lattice: 'D2Q9' | 'D3Q19' | 'D3Q27'; collision: 'bgk' | 'smrt' | 'rmrt' (the raw-moment
-    MRT of the paper's appendix);
+    lattice: 'D2Q9' | 'D3Q19' | 'D3Q27' | 'D3Q39' (the high-order lattice: periodic boxes,
+    no solid nodes, no tau_31); collision: 'bgk' | 'smrt' | 'rmrt' (the raw-moment MRT of
+    the paper's appendix);
     shape (nx, ny, nz) (nz = 1 in 2-D); walls: per-axis flags (halfway bounce-back
     on both faces); tau: dict or tuple of tau-hat per Hermite order (tau2, tau3,
     tau4) -- BGK uses tau2 only, SMRT and RMRT require tau4 == 1 (order 4 is trimmed);
@@ -127,7 +129,10 @@ class Oracle:
         self._lat = _Lattice(self.L["D"], self.L["Q"], self.L["NM"],
                              self.L["e"].ctypes.data, self.L["opp"].ctypes.data,
                              self.L["mi"].ctypes.data, self.L["w"].ctypes.data,
-                             self.L["H"].ctypes.data, self.L["Minv"].ctypes.data)
+                             self.L["H"].ctypes.data, self.L["Minv"].ctypes.data,
+                             float(self.L["ics2"]))
+        if lattice in lat.HIGH_ORDER and (any(walls) or solid is not None or tau_31):
+            raise ValueError(f"{lattice} takes periodic boxes without solid nodes or tau_31")
         omega = 1.0 / tau2
         if force_order not in (1, 3) or (force_order == 3 and self.collision != "smrt"):
             raise ValueError("force_order is 1, or 3 with SMRT")

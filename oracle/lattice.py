@@ -6,21 +6,27 @@ with the HIP path, which derives its own copy of the same tables.
 
 What it defines (paper Sec. II.A, discrete Hermite transform, eq:dft):
 
-* the discrete velocities e_i of D2Q9, D3Q19 and D3Q27 in lattice units
+* the discrete velocities e_i of D2Q9, D3Q19 and D3Q27 (c_s^2 = 1/3) and of the
+  high-order lattice D3Q39 (c_s^2 = 2/3, exact to degree 7) in lattice units
   (Delta x = Delta t = 1), with their Gauss-Hermite weights w_i;
-* the lattice Hermite polynomials, written in lattice units so that no sqrt(3)
-  appears: per axis H0(e) = 1, H1(e) = e, H2(e) = e^2 - c_s^2 with c_s^2 = 1/3,
-  and for a multi-index m = (mx, my, mz) the product H_m(e) = prod_a H_{m_a}(e_a).
-  This is the paper's tensor Hermite polynomial of xi = e / c_s scaled by
-  c_s^|m| (one component of H^(n), n = |m|);
+* the lattice Hermite polynomials, written in lattice units so that no square root
+  appears: per axis H0(e) = 1, H1(e) = e, H2(e) = e^2 - c_s^2, H3(e) = e^3 - 3 c_s^2 e,
+  H4(e) = e^4 - 6 c_s^2 e^2 + 3 c_s^4, and for a multi-index m = (mx, my, mz) the
+  product H_m(e) = prod_a H_{m_a}(e_a).  This is the paper's tensor Hermite
+  polynomial of xi = e / c_s scaled by c_s^|m| (one component of H^(n), n = |m|);
 * the index set I of multi-indices each lattice represents, in a fixed
   canonical order (|m| ascending, then m descending lexicographically with x
   most significant);
 * the projection matrix M[m][i] = H_m(e_i) (the forward transform of eq:dft)
-  and its exact inverse.  On D2Q9 and D3Q27 the inverse equals the paper's
-  reconstruction w_i sum_m a_m H_m(e_i) / (m! c_s^(2|m|)) (second half of
+  and the reconstruction.  On D2Q9, D3Q19 and D3Q27 the index set has Q members and
+  the reconstruction is the exact inverse of M; on D2Q9 and D3Q27 it equals the
+  paper's reconstruction w_i sum_m a_m H_m(e_i) / (m! c_s^(2|m|)) (second half of
   eq:dft); on D3Q19 the basis is not orthogonal and the exact inverse is used
-  (reading documented with the oracle).
+  (reading documented with the oracle).  On D3Q39 the index set is every m with
+  |m| <= 4 (35 < Q = 39 moments) and the reconstruction is the paper's Hermite sum to
+  order 4 itself, which is not an inverse: the populations it builds carry exactly the
+  moments of orders 0 to 3 given to it (the quadrature is exact to degree 7), and
+  nothing that the 35 moments do not describe.
 
 Everything is computed in exact rational arithmetic (``fractions.Fraction``)
 and rounded once to the target float format when a table is handed to C.
@@ -35,9 +41,11 @@ from math import factorial
 
 import numpy as np
 
-CS2 = Fraction(1, 3)  # lattice speed of sound squared
+CS2 = Fraction(1, 3)  # lattice speed of sound squared of D2Q9, D3Q19, D3Q27
 
 LATTICES = ("D2Q9", "D3Q19", "D3Q27")
+HIGH_ORDER = ("D3Q39",)  # multi-speed lattices: periodic boxes only
+ALL_LATTICES = LATTICES + HIGH_ORDER
 
 # Population order shared with the library's storage layout: rest particle
 # first, then pairs (e, -e) so that the opposite of i is i+1 (i odd) or i-1.
@@ -53,10 +61,24 @@ _D3Q19 = [(0, 0, 0),
 _VEL["D3Q19"] = _D3Q19
 _VEL["D3Q27"] = _D3Q19 + [(1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
                           (1, -1, 1), (-1, 1, -1), (1, -1, -1), (-1, 1, 1)]
+# D3Q39: the rest particle, then per speed shell |e|^2 = 1, 3, 4, 8, 9 each velocity
+# followed by its opposite.
+_VEL["D3Q39"] = [(0, 0, 0)] + [
+    v for e in [(1, 0, 0), (0, 1, 0), (0, 0, 1),
+                (1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1),
+                (2, 0, 0), (0, 2, 0), (0, 0, 2),
+                (2, 2, 0), (2, -2, 0), (2, 0, 2), (2, 0, -2), (0, 2, 2), (0, 2, -2),
+                (3, 0, 0), (0, 3, 0), (0, 0, 3)]
+    for v in (e, tuple(-c for c in e))]
 
 
 def dim(lat: str) -> int:
     return 2 if lat == "D2Q9" else 3
+
+
+def cs2(lat: str) -> Fraction:
+    """Lattice speed of sound squared: sum_i w_i e_ix^2."""
+    return Fraction(2, 3) if lat == "D3Q39" else CS2
 
 
 def velocities(lat: str) -> list[tuple[int, int, int]]:
@@ -75,6 +97,8 @@ def weights(lat: str) -> list[Fraction]:
         "D3Q19": {0: Fraction(1, 3), 1: Fraction(1, 18), 2: Fraction(1, 36)},
         "D3Q27": {0: Fraction(8, 27), 1: Fraction(2, 27), 2: Fraction(1, 54),
                   3: Fraction(1, 216)},
+        "D3Q39": {0: Fraction(1, 12), 1: Fraction(1, 12), 3: Fraction(1, 27),
+                  4: Fraction(2, 135), 8: Fraction(1, 432), 9: Fraction(1, 1620)},
     }[lat]
     return [shell[sum(c * c for c in e)] for e in _VEL[lat]]
 
@@ -89,25 +113,32 @@ def index_set(lat: str) -> list[tuple[int, int, int]]:
         ms = [(a, b, 0) for a, b in product(range(3), repeat=2)]
     elif lat == "D3Q27":
         ms = list(product(range(3), repeat=3))
+    elif lat == "D3Q39":  # every order up to 4
+        ms = [m for m in product(range(5), repeat=3) if sum(m) <= 4]
     else:  # D3Q19: at most two non-zero components
         ms = [m for m in product(range(3), repeat=3) if sum(c > 0 for c in m) <= 2]
     return _canonical(ms)
 
 
-def hermite_1d(k: int, e: int) -> Fraction:
+def hermite_1d(k: int, e: int, c2: Fraction = CS2) -> Fraction:
+    """c^k He_k(e / c), c^2 = c2: the probabilists' Hermite polynomial in lattice units."""
     if k == 0:
         return Fraction(1)
     if k == 1:
         return Fraction(e)
     if k == 2:
-        return Fraction(e * e) - CS2
+        return Fraction(e * e) - c2
+    if k == 3:
+        return Fraction(e ** 3) - 3 * c2 * e
+    if k == 4:
+        return Fraction(e ** 4) - 6 * c2 * e * e + 3 * c2 * c2
     raise ValueError(k)
 
 
-def hermite(m, e) -> Fraction:
+def hermite(m, e, c2: Fraction = CS2) -> Fraction:
     p = Fraction(1)
     for ma, ea in zip(m, e):
-        p *= hermite_1d(ma, ea)
+        p *= hermite_1d(ma, ea, c2)
     return p
 
 
@@ -121,7 +152,7 @@ def mfact(m) -> int:
 @lru_cache(maxsize=None)
 def projection(lat: str) -> tuple[tuple[Fraction, ...], ...]:
     """M[m][i] = H_m(e_i): raw Hermite moments a_m = sum_i f_i H_m(e_i)."""
-    return tuple(tuple(hermite(m, e) for e in _VEL[lat]) for m in index_set(lat))
+    return tuple(tuple(hermite(m, e, cs2(lat)) for e in _VEL[lat]) for m in index_set(lat))
 
 
 def _inverse(A):
@@ -141,14 +172,20 @@ def _inverse(A):
 
 @lru_cache(maxsize=None)
 def reconstruction(lat: str) -> tuple[tuple[Fraction, ...], ...]:
-    """Exact inverse of the projection: Minv[i][m], so f = Minv a."""
+    """Reconstruction Minv[i][m], f = Minv a: the exact inverse of the projection where
+    the index set has Q members, the paper's Hermite sum (reconstruction_orthogonal)
+    on D3Q39."""
+    if lat in HIGH_ORDER:
+        return reconstruction_orthogonal(lat)
     return tuple(tuple(r) for r in _inverse([list(r) for r in projection(lat)]))
 
 
+@lru_cache(maxsize=None)
 def reconstruction_orthogonal(lat: str):
     """The paper's reconstruction coefficient w_i H_m(e_i) / (m! c_s^(2|m|))."""
     w = weights(lat)
-    return tuple(tuple(w[i] * hermite(m, e) / (mfact(m) * CS2 ** sum(m))
+    c2 = cs2(lat)
+    return tuple(tuple(w[i] * hermite(m, e, c2) / (mfact(m) * c2 ** sum(m))
                        for m in index_set(lat))
                  for i, e in enumerate(_VEL[lat]))
 
@@ -198,6 +235,7 @@ def tables(lat: str, real=np.float64) -> dict:
         "w": np.array([rnd(x) for x in weights(lat)], dtype=real),
         "H": np.array([[rnd(x) for x in row] for row in projection(lat)], dtype=real),
         "Minv": np.array([[rnd(x) for x in row] for row in reconstruction(lat)], dtype=real),
+        "ics2": real(rnd(1 / cs2(lat))),  # 3 or 3/2, exact in binary
     }
 
 

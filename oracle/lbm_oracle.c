@@ -23,8 +23,9 @@
  *
  * Paper: X. Li, W. Duan, X. Shan, "Second-order force scheme for lattice
  * Boltzmann method" (arXiv 2212.07494).  Each function cites the passage it
- * follows.  Lattice units, c_s^2 = 1/3; Hermite polynomials in lattice units
- * (H_m(e) = c_s^|m| times the paper's tensor Hermite polynomial of e/c_s).
+ * follows.  Lattice units; c_s^2 = 1/3 on D2Q9, D3Q19 and D3Q27, 2/3 on the
+ * high-order lattice D3Q39 (passed in as 1/c_s^2); Hermite polynomials in lattice
+ * units (H_m(e) = c_s^|m| times the paper's tensor Hermite polynomial of e/c_s).
  *
  * State.  The oracle holds the paper's stored variable f-bar(x, t) (the
  * pre-collision population after the change of variable eq:newf) and advances
@@ -40,8 +41,8 @@
  * is exactly zero.  Products of velocity components are formed left to right
  * over x, y, z.  Constants are exact rationals rounded once.  The SMRT and RMRT
  * projection, central shift, back-shift and reconstruction accumulate each term
- * with one fused multiply-add (fmar); in the shifts the binomial coefficient (a
- * power of two on these lattices, so exactly) scales u^l first.  The SMRT and RMRT
+ * with one fused multiply-add (fmar); in the shifts the binomial coefficient scales
+ * u^l first (exactly where it is a power of two, as on D2Q9, D3Q19 and D3Q27).  The SMRT and RMRT
  * projections and reconstructions are folded over the opposite-velocity pairs of the
  * population order (project_folded, reconstruct_folded).  Nothing else is fused.
  * Compiled with
@@ -70,7 +71,7 @@ static inline real fmar(real a, real b, real c) {
 #endif
 }
 
-#define MAXQ 27
+#define MAXQ 39
 
 typedef struct {
   int32_t D, Q, NM;
@@ -79,7 +80,10 @@ typedef struct {
   const int32_t *mi;   /* NM x 3 multi-indices, canonical order */
   const real *w;       /* Q weights */
   const real *H;       /* NM x Q: H_m(e_i) */
-  const real *Minv;    /* Q x NM: exact inverse of H */
+  const real *Minv;    /* Q x NM: the reconstruction, f = Minv a (exact inverse of H when
+                          NM == Q; the Hermite sum w_i H_m(e_i) / (m! c_s^(2|m|)) of
+                          the orders up to 4 when NM < Q) */
+  double ics2;         /* 1 / c_s^2 (3 or 3/2, exact in either precision) */
 } oracle_lattice;
 
 typedef struct {
@@ -153,7 +157,11 @@ static int find_index(const oracle_lattice *L, int a, int b, int c) {
   return -1;
 }
 
-static int binom(int n, int k) { return (k == 0 || k == n) ? 1 : n; /* n <= 2 */ }
+static int binom(int n, int k) {
+  int c = 1;
+  for (int j = 1; j <= k; ++j) c = c * (n - k + j) / j;
+  return c;
+}
 
 /* u^m = prod_a u_a^{m_a}, multiplied left to right over x, y, z starting from 1. */
 static real upow(const int32_t *m, const real u[3]) {
@@ -192,8 +200,9 @@ static void macroscopic(const oracle_lattice *L, const oracle_params *P, const r
 /* ---- BGK (Sec. II.B, eq:explict_eq) ------------------------------------------------ */
 /* Second-order truncated equilibrium evaluated at e_i (expansion after
  * eq:collision_BGK): w_i rho [1 + e.u/c_s^2 + ((e.u)^2 - c_s^2 u^2)/(2 c_s^4)], written
- * as w_i (rho + rho P_i) with P_i = (3 e.u + 4.5 (e.u)^2) - 1.5 u.u; in deviation
- * form the leading rho becomes drho (sum_i w_i s = s). */
+ * as w_i (rho + rho P_i) with P_i = (k e.u + (k^2/2) (e.u)^2) - (k/2) u.u, k = 1/c_s^2
+ * (3, 4.5, 1.5 for c_s^2 = 1/3); in deviation form the leading rho becomes drho
+ * (sum_i w_i s = s). */
 static real bgk_P(const oracle_lattice *L, int i, const real u[3], real *eu_out) {
   real eu = -0.0;
   for (int a = 0; a < 3; ++a) {
@@ -203,11 +212,13 @@ static real bgk_P(const oracle_lattice *L, int i, const real u[3], real *eu_out)
   real usq = -0.0;
   for (int a = 0; a < L->D; ++a) usq = usq + u[a] * u[a];
   *eu_out = eu;
-  return ((real)3 * eu + (real)4.5 * (eu * eu)) - (real)1.5 * usq;
+  const real k = (real)L->ics2;
+  return (k * eu + (real)(0.5 * L->ics2 * L->ics2) * (eu * eu)) - (real)(0.5 * L->ics2) * usq;
 }
 
 /* Force term truncated to second order (the familiar form below eq:Fr, evaluated at
- * e_i): F_i = w_i [ (e_i - u).F / c_s^2 + (e_i.F)(e_i.u) / c_s^4 ], F = rho g. */
+ * e_i): F_i = w_i [ (e_i - u).F / c_s^2 + (e_i.F)(e_i.u) / c_s^4 ], F = rho g (the
+ * factors 3 and 9 for c_s^2 = 1/3). */
 static real bgk_force(const oracle_lattice *L, int i, const real u[3], const real F[3],
                       real eu) {
   real eF = -0.0;
@@ -217,7 +228,7 @@ static real bgk_force(const oracle_lattice *L, int i, const real u[3], const rea
   }
   real uF = -0.0;
   for (int a = 0; a < L->D; ++a) uF = uF + u[a] * F[a];
-  real G = (real)3 * (eF - uF) + (real)9 * (eF * eu);
+  real G = (real)L->ics2 * (eF - uF) + (real)(L->ics2 * L->ics2) * (eF * eu);
   return L->w[i] * G;
 }
 
@@ -261,6 +272,7 @@ static void collide_bgk(const oracle_lattice *L, const oracle_params *P, const r
         const int ea = L->e[3 * i + a];
         if (ea == 1) s = s + c[i];
         if (ea == -1) s = s + (-c[i]);
+        if (ea > 1 || ea < -1) s = s + (real)ea * c[i];
       }
       r[k] = M.F[a] - s;
     }
@@ -404,6 +416,49 @@ static void reconstruct_folded(const oracle_lattice *L, const real *f, const rea
   }
 }
 
+/* The paper's reconstruction applied to the post-collision moments themselves (after
+ * eq:bbd1), f*_i = sum_m Minv_im a*_m, on a lattice whose index set is smaller than Q
+ * (D3Q39: the Hermite sum to order 4).  There the increment form f + Minv (a* - a) would
+ * keep whatever part of f the NM moments do not describe, which the paper's formula
+ * drops, so the state is rebuilt from a*; the quadrature being exact to degree 7, the
+ * moments of orders 0 to 3 of the result are exactly a* (mass a*_0 = d-rho in deviation
+ * form, Minv_i0 = w_i).  Folded over the pairs like reconstruct_folded: the rest
+ * population sums its row over every k from k = 0; each pair sums its first member's row
+ * over the even-order and the odd-order moments apart (from -0.0 in k order, one fma a
+ * nonzero term) and takes (E + O), (E - O). */
+static void reconstruct_full_folded(const oracle_lattice *L, const real *as, real *out) {
+  const int Q = L->Q, NM = L->NM;
+#ifdef PLAIN
+  /* each population as its plain row of the reconstruction */
+  for (int i = 0; i < Q; ++i) {
+    real r = -0.0;
+    for (int k = 0; k < NM; ++k) r = r + L->Minv[i * NM + k] * as[k];
+    out[i] = r;
+  }
+  return;
+#endif
+  real acc = -0.0;
+  for (int k = 0; k < NM; ++k) {
+    real c = L->Minv[k];
+    if (c != 0) acc = fmar(c, as[k], acc);
+  }
+  out[0] = acc;
+  for (int p = 1; 2 * p < Q; ++p) {
+    const int i = 2 * p - 1;
+    real ev = -0.0, od = -0.0;
+    for (int k = 0; k < NM; ++k) {
+      real c = L->Minv[i * NM + k];
+      if (c == 0) continue;
+      if (mabs(L->mi + 3 * k) % 2)
+        od = fmar(c, as[k], od);
+      else
+        ev = fmar(c, as[k], ev);
+    }
+    out[i] = ev + od;
+    out[i + 1] = ev - od;
+  }
+}
+
 static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const smrt_plan *S,
                          const real *f, const real g[3], real *out) {
   macro_t M;
@@ -500,26 +555,29 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       Pc[jc] = Pc[jc] + P->dq31 * s;
     }
   }
-  /* back to raw moments; the change of every moment over the collision */
+  /* back to raw moments; the change of every moment over the collision, or (full: the
+   * index set is smaller than Q) the post-collision moments a* themselves */
+  const int full = L->NM < L->Q;
   real dA[MAXQ];
   for (int k = 0; k < NM; ++k) {
     const int32_t *m = L->mi + 3 * k;
     int n = mabs(m);
     if (n == 0) { /* mass is unchanged */
-      dA[k] = 0;
+      dA[k] = full ? M.drho : 0;
       continue;
     }
     if (n == 1) { /* momentum gains F (a*^(1) = rho u + F/2 = j + F) */
       int a = m[0] ? 0 : (m[1] ? 1 : 2);
-      dA[k] = M.F[a];
+      dA[k] = full ? M.j[a] + M.F[a] : M.F[a];
       continue;
     }
-    /* pre-collision raw moment of order >= 4 (orders 2, 3 are already in N) */
+    /* pre-collision raw moment of order >= 4 (orders 2, 3 are already in N); a* of
+     * order 4 does not depend on it */
     real Nk = N[k];
-    if (n >= 4) {
+    if (n >= 4 && !(full && n == 4)) {
       real A = project_folded(L, k, f, ps, pa);
       if (n > 4 && P->max_order < n) { /* orders above 4 are not carried: a*_m = 0 */
-        dA[k] = -A;
+        dA[k] = full ? (real)0 : -A;
         continue;
       }
       /* carried orders: equilibrium plus the back-shift of the relaxed central moments,
@@ -532,11 +590,15 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       if (mabs(L->mi + 3 * km) > 3) continue; /* P = 0 at order 4 */
       R = fmar((real)S->cup[k][t] * U[S->kl[k][t]], Pc[km], R);
     }
-    /* a*_m - a_m = (rho u^m + R_m) - (rho u^m + N_m) */
-    dA[k] = R - Nk;
+    /* a*_m - a_m = (rho u^m + R_m) - (rho u^m + N_m); full: a*_m = rho u^m + R_m */
+    dA[k] = full ? E[k] + R : R - Nk;
   }
-  /* eq:evolution: f-bar + Omega + F, the increment reconstructed from dA */
-  reconstruct_folded(L, f, dA, out);
+  /* eq:evolution: f-bar + Omega + F, the increment reconstructed from dA; full: the
+   * post-collision state rebuilt from a* */
+  if (full)
+    reconstruct_full_folded(L, dA, out);
+  else
+    reconstruct_folded(L, f, dA, out);
 }
 
 /* ---- raw-moment MRT (the appendix: eq:RHS_a in its explicit form, eq:bbd1) ------- */
@@ -555,6 +617,7 @@ static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const 
   macro_t M;
   macroscopic(L, P, f, g, &M);
   const int NM = L->NM;
+  const int full = L->NM < L->Q; /* rebuild from a* (see reconstruct_full_folded) */
   real U[MAXQ], dA[MAXQ], ps[MAXQ], pa[MAXQ];
   for (int k = 0; k < NM; ++k) U[k] = upow(L->mi + 3 * k, M.u);
   for (int p = 1; 2 * p < L->Q; ++p) {
@@ -565,20 +628,22 @@ static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const 
     const int32_t *m = L->mi + 3 * k;
     int n = mabs(m);
     if (n == 0) {
-      dA[k] = 0;
+      dA[k] = full ? M.drho : 0;
       continue;
     }
     if (n == 1) {
       int a = m[0] ? 0 : (m[1] ? 1 : 2);
-      dA[k] = M.F[a];
+      dA[k] = full ? M.j[a] + M.F[a] : M.F[a];
       continue;
     }
-    real A = project_folded(L, k, f, ps, pa);
+    /* the pre-collision moment (a* of order 4 does not depend on it) */
+    real A = (full && n == 4) ? (real)0 : project_folded(L, k, f, ps, pa);
     if (n > 4) {
-      dA[k] = -A;
+      dA[k] = full ? (real)0 : -A;
       continue;
     }
-    real N = A - M.rho * U[k];
+    const real E = M.rho * U[k];
+    real N = A - E;
     real aF = -0.0;
     for (int a = 0; a < 3; ++a) {
       if (m[a] == 0) continue;
@@ -596,9 +661,12 @@ static void collide_rmrt(const oracle_lattice *L, const oracle_params *P, const 
     } else {
       t = (real)0.5 * aF;
     }
-    dA[k] = t - N;
+    dA[k] = full ? E + t : t - N;
   }
-  reconstruct_folded(L, f, dA, out);
+  if (full)
+    reconstruct_full_folded(L, dA, out);
+  else
+    reconstruct_folded(L, f, dA, out);
 }
 
 static void collide(const oracle_lattice *L, const oracle_params *P, const smrt_plan *S,
@@ -729,7 +797,7 @@ void oracle_step(const oracle_lattice *L, const oracle_params *P, const real *f,
               if (P->wall[a])
                 wall_hit = 1;
               else
-                d[a] = (d[a] + dims[a]) % dims[a];
+                d[a] = ((d[a] % dims[a]) + dims[a]) % dims[a];
             }
           }
           real v = store_value(P, out[i]);

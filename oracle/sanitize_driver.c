@@ -10,7 +10,8 @@
  * every result is finite; the sanitizers abort on the first error they find.
  *
  * Table file layout (native byte order): int32 D, Q, NM; int32 e[Q][3]; int32 opp[Q];
- * int32 mi[NM][3]; then in the build's real type w[Q], H[NM][Q], Minv[Q][NM].
+ * int32 mi[NM][3]; then in the build's real type w[Q], H[NM][Q], Minv[Q][NM]; then a
+ * double 1/c_s^2.
  */
 #include "lbm_oracle.c"
 
@@ -40,7 +41,7 @@ int main(int argc, char **argv) {
   int32_t hdr[3];
   if (!read_all_or_die(f, hdr, sizeof(hdr))) return 2;
   const int D = hdr[0], Q = hdr[1], NM = hdr[2];
-  if (Q < 1 || Q > MAXQ || NM != Q) return 2;
+  if (Q < 1 || Q > MAXQ || NM < 1 || NM > Q) return 2;
   int32_t *e = malloc(sizeof(int32_t) * 3 * Q), *opp = malloc(sizeof(int32_t) * Q),
           *mi = malloc(sizeof(int32_t) * 3 * NM);
   real *w = malloc(sizeof(real) * Q), *H = malloc(sizeof(real) * NM * Q),
@@ -49,8 +50,10 @@ int main(int argc, char **argv) {
       !read_all_or_die(f, mi, sizeof(int32_t) * 3 * NM) || !read_all_or_die(f, w, sizeof(real) * Q) ||
       !read_all_or_die(f, H, sizeof(real) * NM * Q) || !read_all_or_die(f, Minv, sizeof(real) * Q * NM))
     return 2;
+  double ics2 = 0;
+  if (!read_all_or_die(f, &ics2, sizeof(ics2))) return 2;
   fclose(f);
-  const oracle_lattice L = {D, Q, NM, e, opp, mi, w, H, Minv};
+  const oracle_lattice L = {D, Q, NM, e, opp, mi, w, H, Minv, ics2};
 
   const int nx = 7, ny = 5, nz = D == 2 ? 1 : 4;
   const int64_t N = (int64_t)nx * ny * nz;

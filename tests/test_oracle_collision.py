@@ -8,6 +8,11 @@
   (orders 0..4, theta = 1, order 4 by the recursion), a formulation independent of
   the oracle's multi-index Hermite shifts.
 * BGK post-collision moments equal those of eq:explict_eq in moment form.
+
+The high-order lattice D3Q39 (c_s^2 = 2/3) takes part wherever the statement holds on it;
+its post-collision state is the paper's Hermite sum to order 4, whose fourth-order
+moments on the 39 velocities are those of the sum (the product M R of the tables
+applied to the post-collision moments), not the moments themselves.
 """
 import itertools
 import math
@@ -19,6 +24,18 @@ from oracle import Oracle
 from oracle import lattice as lat
 
 CS2 = 1.0 / 3.0
+
+
+def _cs2(L):
+    return float(lat.cs2(L))
+
+
+def _as_lattice_moments(o, want):
+    """Moments the lattice returns for post-collision moments `want` (one per index):
+    themselves where the reconstruction inverts the projection, M R want on D3Q39."""
+    if o.L["NM"] == o.Q:
+        return np.asarray(want)
+    return (o.L["H"] @ o.L["Minv"]) @ np.asarray(want)
 
 
 def _setup(L, seed):
@@ -36,7 +53,7 @@ def _tol(terms):
     return 16 * np.finfo(np.float64).eps * np.sum(np.abs(terms))
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("seed", range(5))
 def test_bgk_force_moments(L, seed):
     rho, u, g = _setup(L, seed)
@@ -54,11 +71,11 @@ def test_bgk_force_moments(L, seed):
     assert abs(feq.sum() - rho) <= _tol(feq)
     assert np.allclose((feq[:, None] * e).sum(0), rho * u, rtol=0, atol=1e-15)
     D = lat.dim(L)
-    want2 = rho * (np.outer(u, u) + CS2 * np.diag([1.0] * D + [0.0] * (3 - D)))
+    want2 = rho * (np.outer(u, u) + _cs2(L) * np.diag([1.0] * D + [0.0] * (3 - D)))
     assert np.allclose(np.einsum("i,ia,ib->ab", feq, e, e), want2, rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt"])
 @pytest.mark.parametrize("shift", [0.0, 1.0])
 def test_init_recovers_rho_u(L, coll, shift):
@@ -106,10 +123,10 @@ def _sym_outer(*parts):
     return out
 
 
-def _lattice_hermite_tensors(e):
+def _lattice_hermite_tensors(e, c2):
     I = np.eye(3)
-    H2 = np.einsum("a,b->ab", e, e) - CS2 * I
-    H3 = np.einsum("a,b,c->abc", e, e, e) - CS2 * (
+    H2 = np.einsum("a,b->ab", e, e) - c2 * I
+    H3 = np.einsum("a,b,c->abc", e, e, e) - c2 * (
         np.einsum("a,bc->abc", e, I) + np.einsum("b,ac->abc", e, I) + np.einsum("c,ab->abc", e, I))
     return H2, H3
 
@@ -119,7 +136,7 @@ def _component(T, m):
     return T[idx] if idx else T
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("seed", range(4))
 def test_smrt_matches_bbd1_tensor_form(L, seed):
     rho0, u0, g = _setup(L, seed)
@@ -137,8 +154,9 @@ def test_smrt_matches_bbd1_tensor_form(L, seed):
     u = j / rho + g / 2
     F = rho * g
     w2, w3 = 1 / 0.62, 1 / 0.83
-    a2 = sum(fi * _lattice_hermite_tensors(e)[0] for fi, e in zip(f, E))
-    a3 = sum(fi * _lattice_hermite_tensors(e)[1] for fi, e in zip(f, E))
+    c2 = _cs2(L)
+    a2 = sum(fi * _lattice_hermite_tensors(e, c2)[0] for fi, e in zip(f, E))
+    a3 = sum(fi * _lattice_hermite_tensors(e, c2)[1] for fi, e in zip(f, E))
     # non-equilibrium parts (a_0^(n) = rho u^n at theta = 1)
     a2_1 = a2 - rho * _sym_outer(u, u) / 2  # sym_outer(u,u) = 2 uu
     a3_1 = a3 - rho * np.einsum("a,b,c->abc", u, u, u)
@@ -155,6 +173,7 @@ def test_smrt_matches_bbd1_tensor_form(L, seed):
     M = o.L["H"]
     mom = M @ out
     ms = [tuple(m) for m in o.L["mi"]]
+    wants = []
     for k, m in enumerate(ms):
         n = sum(m)
         if n == 0:
@@ -169,11 +188,14 @@ def test_smrt_matches_bbd1_tensor_form(L, seed):
             want = _component(rho * np.einsum("a,b,c,d->abcd", u, u, u, u) + a4_p, m)
         else:
             want = 0.0
-        assert abs(mom[k] - want) <= 1e-14 * max(1.0, abs(want)), (m, mom[k], want)
+        wants.append(want)
+    wants = _as_lattice_moments(o, wants)
+    for k, m in enumerate(ms):
+        assert abs(mom[k] - wants[k]) <= 1e-14 * max(1.0, abs(wants[k])), (m, mom[k], wants[k])
     assert D in (2, 3)
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 def test_bgk_post_collision_moments(L):
     """Moments of eq:explict_eq: mass kept, momentum j + F, second Hermite moment
     (1 - omega)(a2 - rho uu) + rho uu + (1 - omega/2)(F u + u F)."""
@@ -193,14 +215,14 @@ def test_bgk_post_collision_moments(L):
     assert np.allclose((out[:, None] * E).sum(0), j + F, rtol=0, atol=1e-16)
     D = lat.dim(L)
     I = np.diag([1.0] * D + [0.0] * (3 - D))
-    a2 = np.einsum("i,ia,ib->ab", f, E, E) - CS2 * rho * I
-    a2o = np.einsum("i,ia,ib->ab", out, E, E) - CS2 * rho * I
+    a2 = np.einsum("i,ia,ib->ab", f, E, E) - _cs2(L) * rho * I
+    a2o = np.einsum("i,ia,ib->ab", out, E, E) - _cs2(L) * rho * I
     uu = np.outer(u, u)
     want = (1 - om) * (a2 - rho * uu) + rho * uu + (1 - om / 2) * (np.outer(F, u) + np.outer(u, F))
     assert np.allclose(a2o, want, rtol=0, atol=2e-15)
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 def test_smrt_equal_rates_one_is_half_force(L):
     """SMRT with omega_2 = omega_3 = 1: every non-equilibrium moment is replaced by half
     the raw force moment, a*^(n) = rho u^n + a_F^(n)/2 for n = 1..4 (appendix, theta = 1)."""
@@ -214,10 +236,15 @@ def test_smrt_equal_rates_one_is_half_force(L):
     uu = (f[:, None] * E).sum(0) / r + g / 2
     F = r * g
     mom = o.L["H"] @ out
+    wants = []
     for k, m in enumerate(o.L["mi"]):
         m = tuple(m)
         n = sum(m)
-        if n == 0 or n > 4:
+        if n == 0:
+            wants.append(r)
+            continue
+        if n > 4:
+            wants.append(0.0)
             continue
         up = np.prod([uu[a] ** m[a] for a in range(3)])
         aF = 0.0
@@ -226,15 +253,20 @@ def test_smrt_equal_rates_one_is_half_force(L):
                 r_ = list(m)
                 r_[a] -= 1
                 aF += m[a] * np.prod([uu[b] ** r_[b] for b in range(3)]) * F[a]
-        assert math.isclose(mom[k], r * up + aF / 2, rel_tol=0, abs_tol=1e-15)
+        wants.append(r * up + aF / 2)
+    wants = _as_lattice_moments(o, wants)
+    for k, m in enumerate(o.L["mi"]):
+        if 0 < sum(m) <= 4:
+            assert math.isclose(mom[k], wants[k], rel_tol=0, abs_tol=1e-15), (m, mom[k], wants[k])
 
 
 # Number of independent Hermite moments of order 3 each velocity set resolves: D2Q9 has
 # xxy, xyy; D3Q19 the six with one repeated index; D3Q27 those and xyz.
-ORDER3 = {"D2Q9": 2, "D3Q19": 6, "D3Q27": 7}
+# D3Q39 carries all ten.
+ORDER3 = {"D2Q9": 2, "D3Q19": 6, "D3Q27": 7, "D3Q39": 10}
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("coll,tau2,tau3", [("bgk", 0.8, 1.0), ("smrt", 0.8, 1.0),
                                             ("smrt", 0.62, 0.7), ("smrt", 1.3, 2.5)])
 def test_linearised_collision_spectrum(L, coll, tau2, tau3):
@@ -278,7 +310,7 @@ def _collision_jacobian(o):
     return J
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("tau_b", [0.55, 0.9, 1.7])
 def test_bulk_rate_collision_spectrum(L, tau_b):
     """eq:domg per irreducible component at order 2: with its own rate for the trace,
@@ -388,7 +420,7 @@ def test_high_orders_on_d3q27(max_order, seed):
         assert max(abs(c) for _, c in raw.values()) > 1e-8, raw
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("tau_b", [0.0, 0.9, 1.7])
 def test_bulk_rate_sound_attenuation(L, tau_b):
     """Hydrodynamic limit of the linearised step at small wavenumber k (along x): the
@@ -403,9 +435,10 @@ def test_bulk_rate_sound_attenuation(L, tau_b):
     D = o.D
     J = _collision_jacobian(o)
     ex = np.array(lat.velocities(L))[:, 0]
-    cs = math.sqrt(CS2)
-    nu = CS2 * (tau2 - 0.5)
-    zeta = (2.0 / D) * CS2 * ((tau_b or tau2) - 0.5)
+    c2 = _cs2(L)
+    cs = math.sqrt(c2)
+    nu = c2 * (tau2 - 0.5)
+    zeta = (2.0 / D) * c2 * ((tau_b or tau2) - 0.5)
     gam = 0.5 * ((2 - 2.0 / D) * nu + zeta)
     errs = []
     for k in (2 * math.pi / 64, 2 * math.pi / 128):
@@ -417,7 +450,10 @@ def test_bulk_rate_sound_attenuation(L, tau_b):
         n_meas = -np.log(np.abs(shear)) / k ** 2
         assert np.max(np.abs(n_meas / nu - 1)) < 5e-4
         errs.append(np.max(np.abs(g_meas / gam - 1)))
-    assert errs[1] < 2e-4 and errs[1] < 0.3 * errs[0], errs
+    # second-order convergence to the hydrodynamic rate; D3Q39's O(k^2) coefficient is
+    # larger (measured 7.4e-4 at tau_bulk 1.7, k = 2 pi / 128)
+    bound = 2e-4 if L in lat.LATTICES else 1e-3
+    assert errs[1] < bound and errs[1] < 0.3 * errs[0], errs
 
 
 @pytest.mark.parametrize("L", lat.LATTICES)
@@ -443,7 +479,7 @@ def test_staggered_momentum_mode_never_decays(L, coll):
         assert np.max(np.abs(ut[1:])) < 1e-15
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("seed", range(3))
 def test_third_order_force_content(L, seed):
     """force_order 3 (eq:Frc at theta = 1, d_F^(3) = 3 g d^(2)): against force_order 1 the
@@ -469,7 +505,8 @@ def test_third_order_force_content(L, seed):
     j = e3.T @ f
     uu = j / r + g / 2
     F = r * g
-    A2 = np.einsum("i,ia,ib->ab", f, e3, e3) - r * np.eye(3) / 3 * (np.arange(3) < D)[:, None]
+    c2 = _cs2(L)
+    A2 = np.einsum("i,ia,ib->ab", f, e3, e3) - r * np.eye(3) * c2 * (np.arange(3) < D)[:, None]
     N2 = A2 - r * np.outer(uu, uu)
     N1 = -F / 2
     Dc = N2 - np.outer(uu, N1) - np.outer(N1, uu)
@@ -489,7 +526,7 @@ def test_third_order_force_content(L, seed):
         H = np.ones(o1.Q)
         for c in range(3):
             x = e3[:, c]
-            H *= {0: 1.0, 1: x, 2: x * x - 1 / 3, 3: x ** 3 - x}[int(m[c])]
+            H *= {0: 1.0, 1: x, 2: x * x - c2, 3: x ** 3 - 3 * c2 * x}[int(m[c])]
         got = float(diff @ H)
         assert abs(got - want) <= 1e-13 + 1e-9 * abs(want), (m, got, want)
         biggest = max(biggest, abs(want))
@@ -497,10 +534,14 @@ def test_third_order_force_content(L, seed):
     # mass, momentum and the second-order moments are untouched
     assert abs(diff.sum()) < 1e-16
     assert np.max(np.abs(e3.T @ diff)) < 1e-16
-    assert np.max(np.abs(np.einsum("i,ia,ib->ab", diff, e3, e3))) < 1e-16
+    # (D3Q39 rebuilds the whole state from its moments, so both outputs carry their own
+    # rounding: bound by the rounding of the second-moment sums instead)
+    tol2 = 1e-16 if o1.L["NM"] == o1.Q else 32 * np.finfo(float).eps * float(
+        np.max(np.einsum("i,ia,ib->ab", np.abs(f), np.abs(e3), np.abs(e3))))
+    assert np.max(np.abs(np.einsum("i,ia,ib->ab", diff, e3, e3))) < tol2
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("seed", range(3))
 def test_raw_moment_mrt_against_central(L, seed):
     """The appendix's raw-moment MRT (RMRT) against the central-moment SMRT on one node:

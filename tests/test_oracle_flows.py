@@ -13,7 +13,7 @@ from paper_2212_07494_amd import inputs
 
 # ---- P-U: uniform force in a periodic box ---------------------------------------------
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_uniform_force_momentum_balance(L, coll):
     """Periodic box, uniform g, any initial field: mass is conserved and the total
@@ -37,7 +37,7 @@ def test_uniform_force_momentum_balance(L, coll):
     assert np.allclose(dJ, steps * M0 * g, rtol=1e-9, atol=1e-16)
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_uniform_state_accelerates_exactly(L, coll):
     """A uniform state under uniform g stays uniform with u(t) = u0 + t g."""
@@ -57,7 +57,7 @@ def test_uniform_state_accelerates_exactly(L, coll):
     assert N > 1
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_equilibrium_is_fixed_point_without_force(L, coll):
     """Zero force: the equilibrium of a uniform moving state is a fixed point."""
@@ -221,7 +221,7 @@ def _rotate_scalar(s, shape):
     return np.rot90(s.reshape(nz, ny, nx), k=1, axes=(1, 2)).reshape(-1)
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_rotation_symmetry(L, coll):
     """Rotating the inputs by 90 degrees about z rotates the outputs (to round-off)."""

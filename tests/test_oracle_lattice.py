@@ -1,5 +1,6 @@
 """Pins of the oracle's lattice tables against the quadrature and Hermite facts they
-must satisfy (paper Sec. II.A: Gauss-Hermite quadrature and eq:dft)."""
+must satisfy (paper Sec. II.A: Gauss-Hermite quadrature and eq:dft), for the three
+degree-5 lattices and the degree-7 lattice D3Q39."""
 import json
 import os
 from fractions import Fraction
@@ -13,9 +14,9 @@ from oracle import lattice as lat
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 def test_weights_golden(L):
-    """Textbook weights of the three quadratures (tests/golden/lattice_weights.json)."""
+    """Textbook weights of the quadratures (tests/golden/lattice_weights.json)."""
     with open(os.path.join(GOLDEN, "lattice_weights.json")) as fh:
         gold = json.load(fh)["weights"][L]
     w = lat.weights(L)
@@ -45,6 +46,60 @@ def test_quadrature_isotropy(L):
         assert m4 == iso
     for idx in product(axes, repeat=5):
         assert sum(wi * np.prod([e[i] for i in idx]) for wi, e in zip(w, E)) == 0
+
+
+def _gauss_moment(m, c2):
+    """E[x^m] of the isotropic Gaussian of variance c2 per axis: prod_a (m_a - 1)!! c2^(m_a/2)
+    for even m_a, 0 if any m_a is odd."""
+    p = Fraction(1)
+    for k in m:
+        if k % 2:
+            return Fraction(0)
+        for j in range(k - 1, 0, -2):
+            p *= j
+        p *= c2 ** (k // 2)
+    return p
+
+
+DEGREE = {"D2Q9": 5, "D3Q19": 5, "D3Q27": 5, "D3Q39": 7}
+
+
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
+def test_quadrature_degree(L):
+    """Every weighted velocity moment sum_i w_i e^m equals the Gaussian's with variance
+    c_s^2 (1/3, or 2/3 on D3Q39) up to the lattice's degree (5, or 7 on D3Q39), and some
+    moment of the next even degree does not: the weights and c_s^2 are the unique solution
+    of these conditions on the velocity set."""
+    E = lat.velocities(L)
+    w = lat.weights(L)
+    D = lat.dim(L)
+    c2 = lat.cs2(L)
+    assert c2 == sum(wi * e[0] ** 2 for wi, e in zip(w, E))
+    for deg in range(DEGREE[L] + 2):
+        for m in product(range(deg + 1), repeat=D):
+            if sum(m) != deg:
+                continue
+            got = sum(wi * np.prod([e[a] ** m[a] for a in range(D)]) for wi, e in zip(w, E))
+            if deg <= DEGREE[L]:
+                assert got == _gauss_moment(m, c2), (m, got)
+    deg = DEGREE[L] + 1
+    assert any(sum(wi * e[0] ** deg for wi, e in zip(w, E)) != _gauss_moment((deg,), c2)
+               for _ in [0])
+
+
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
+def test_hermite_tables_against_numpy(L):
+    """H_m(e_i) = c_s^|m| prod_a He_{m_a}(e_ia / c_s) with numpy's probabilists' Hermite
+    series (numpy.polynomial.hermite_e), to rounding."""
+    from numpy.polynomial import hermite_e as He
+    c = float(lat.cs2(L)) ** 0.5
+    M = np.array([[float(x) for x in row] for row in lat.projection(L)])
+    E = np.array(lat.velocities(L), float)
+    for k, m in enumerate(lat.index_set(L)):
+        want = np.ones(len(E))
+        for a in range(3):
+            want *= He.hermeval(E[:, a] / c, [0] * m[a] + [1]) * c ** m[a]
+        assert np.max(np.abs(M[k] - want)) <= 1e-12 * max(1.0, np.max(np.abs(want))), m
 
 
 @pytest.mark.parametrize("L", lat.LATTICES)
@@ -86,7 +141,61 @@ def test_reconstruction_is_inverse(L):
         assert tuple(map(tuple, lat.reconstruction_orthogonal(L))) == Mi
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+def test_d3q39_hermite_orthogonality_to_degree_seven():
+    """D3Q39 carries every multi-index with |m| <= 4 (35 of them); sum_i w_i H_m H_m' =
+    delta m! c_s^(2|m|) whenever |m| + |m'| <= 7 (the quadrature's degree), and the
+    order-4 block is not orthogonal."""
+    L = "D3Q39"
+    w = lat.weights(L)
+    M = lat.projection(L)
+    ms = lat.index_set(L)
+    assert len(ms) == 35 and all(sum(m) <= 4 for m in ms) and len(set(ms)) == 35
+    c2 = lat.cs2(L)
+    off4 = 0
+    for a, ma in enumerate(ms):
+        for b, mb in enumerate(ms):
+            g = sum(w[i] * M[a][i] * M[b][i] for i in range(len(w)))
+            if sum(ma) + sum(mb) <= 7:
+                assert g == (lat.mfact(ma) * c2 ** sum(ma) if a == b else 0), (ma, mb)
+            elif g != (lat.mfact(ma) * c2 ** sum(ma) if a == b else 0):
+                off4 += 1
+    assert off4 > 0
+
+
+def test_d3q39_reconstruction_keeps_orders_to_three():
+    """The D3Q39 reconstruction is the paper's Hermite sum w_i H_m(e_i) / (m! c_s^(2|m|))
+    over |m| <= 4: projecting what it builds returns every moment of order <= 3 exactly
+    (the rows and the columns of M R of those orders are the identity), the order-4 block
+    is not the identity (degree 8 exceeds the quadrature), the rest column is w_i, and
+    nothing in the null space of M survives (R M kills it).  On the 39 velocities the 35
+    polynomials span 29 dimensions: the 20 of orders <= 3 and 9 of order 4 (six
+    fourth-order monomials alias lower ones, e.g. e_x^3 e_y = e_x e_y^3 on every
+    velocity), so the null space of M has dimension 10."""
+    L = "D3Q39"
+    M = lat.projection(L)
+    R = lat.reconstruction(L)
+    ms = lat.index_set(L)
+    assert R == lat.reconstruction_orthogonal(L)
+    Q, NM = len(lat.velocities(L)), len(ms)
+    MR = [[sum(M[a][i] * R[i][b] for i in range(Q)) for b in range(NM)] for a in range(NM)]
+    for a in range(NM):
+        for b in range(NM):
+            if sum(ms[a]) <= 3 or sum(ms[b]) <= 3:
+                assert MR[a][b] == (1 if a == b else 0), (ms[a], ms[b])
+    assert any(MR[a][b] != (1 if a == b else 0) for a in range(NM) for b in range(NM))
+    assert [r[0] for r in R] == lat.weights(L)
+    Mf = np.array([[float(x) for x in r] for r in M])
+    Rf = np.array([[float(x) for x in r] for r in R])
+    _, sv, vt = np.linalg.svd(Mf)
+    rank = int(np.sum(sv > 1e-10))
+    assert rank == 29
+    assert np.linalg.matrix_rank(Mf[[k for k, m in enumerate(ms) if sum(m) <= 3]]) == 20
+    null = vt[rank:]
+    assert null.shape == (Q - rank, Q) == (10, 39)
+    assert np.max(np.abs(Rf @ (Mf @ null.T))) < 1e-13
+
+
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 def test_opposites(L):
     E = lat.velocities(L)
     opp = lat.opposite(L)

@@ -22,6 +22,10 @@ output, and check the implicit rule in the continuous-time rates tau = tau-hat -
 * RMRT (the appendix, eq:RHS_a): the same in raw Hermite moments about rest, with the raw
   force moments a_F = sum_a m_a u^{m-e_a} F_a.
 
+On the high-order lattice D3Q39 (c_s^2 = 2/3, quadrature exact to degree 7) the moments of
+orders 0 to 3 are checked; its fourth-order moments are not all independent on the 39
+velocities, so the rule at order 4 is not a statement about them.
+
 Nowhere is the explicit factor 1 - omega/2 or the relation d = (1 - omega/2) d-bar typed
 in: they follow from the collision's own output.  A dropped term, a wrong rate or
 factor, or a sign error in any of the collisions fails these tests.  They run on both
@@ -35,8 +39,11 @@ import pytest
 from oracle import Oracle
 from oracle import lattice as lat
 
-CS2 = 1.0 / 3.0
 BUILDS = [False, True]  # plain?
+
+
+def _cs2(L):
+    return float(lat.cs2(L))
 
 
 def _velocities(L):
@@ -50,18 +57,23 @@ def _weights(L):
     return np.asarray(lat.tables(L, np.float64)["w"], float)
 
 
-def _hermite(x, n):
-    """One-dimensional lattice Hermite polynomial of degree n at c_s^2 = 1/3."""
-    return {0: np.ones_like(x), 1: x, 2: x * x - CS2, 3: x ** 3 - 3 * CS2 * x,
-            4: x ** 4 - 6 * CS2 * x * x + 3 * CS2 * CS2}[n]
+def _hermite(x, n, c2):
+    """One-dimensional lattice Hermite polynomial of degree n at c_s^2 = c2."""
+    return {0: np.ones_like(x), 1: x, 2: x * x - c2, 3: x ** 3 - 3 * c2 * x,
+            4: x ** 4 - 6 * c2 * x * x + 3 * c2 * c2}[n]
 
 
-def _moment(E, f, m, about):
+def _moment(E, f, m, about, c2):
     """sum_i f_i prod_a H_{m_a}(e_ia - about_a)."""
     h = np.ones(len(E))
     for a in range(3):
-        h = h * _hermite(E[:, a] - about[a], m[a])
+        h = h * _hermite(E[:, a] - about[a], m[a], c2)
     return float(h @ f)
+
+
+def _top_order(L):
+    """Highest Hermite order whose moments the lattice resolves exactly."""
+    return 3 if L in lat.HIGH_ORDER else 4
 
 
 def _index_set(L):
@@ -94,7 +106,7 @@ def _tol(*arrays):
 
 
 @pytest.mark.parametrize("plain", BUILDS)
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("seed", range(3))
 def test_bgk_is_the_trapezoid_rule(L, seed, plain):
     rho0, u0, g, rng = _state(L, seed)
@@ -104,9 +116,10 @@ def test_bgk_is_the_trapezoid_rule(L, seed, plain):
     fstar, f, rho, u = _mean_state(o, fbar, g)
     E, w = _velocities(L), _weights(L)
     eu = E @ u
-    feq = w * rho * (1 + eu / CS2 + (eu ** 2 - CS2 * (u @ u)) / (2 * CS2 ** 2))
+    c2 = _cs2(L)
+    feq = w * rho * (1 + eu / c2 + (eu ** 2 - c2 * (u @ u)) / (2 * c2 ** 2))
     F = rho * g
-    Fi = w * (((E - u) @ F) / CS2 + (E @ F) * eu / CS2 ** 2)
+    Fi = w * (((E - u) @ F) / c2 + (E @ F) * eu / c2 ** 2)
     tau = tau_hat - 0.5
     rhs = -(f - feq) / tau + Fi
     assert np.max(np.abs((fstar - fbar) - rhs)) <= _tol(fbar, fstar), (fstar - fbar, rhs)
@@ -124,12 +137,14 @@ SMRT_CASES = [
 
 
 @pytest.mark.parametrize("plain", BUILDS)
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("case", SMRT_CASES)
 def test_smrt_is_the_trapezoid_rule(L, case, plain):
     fo, tau2h, tau3h, taubh, tau31h = case
     if tau31h and L == "D2Q9":
         pytest.skip("D2Q9 carries no traceless third-order part")
+    if tau31h and L in lat.HIGH_ORDER:
+        pytest.skip("tau_31 is defined on the lattices that lack D_aaa")
     rho0, u0, g, rng = _state(L, 7 + fo)
     o = Oracle(L, "smrt", (1, 1, 1), tau=(tau2h, tau3h, 1.0), force_order=fo, tau_bulk=taubh,
                tau_31=tau31h, plain=plain)
@@ -139,7 +154,9 @@ def test_smrt_is_the_trapezoid_rule(L, case, plain):
     D = lat.dim(L)
     I = _index_set(L)
     tau = {2: tau2h - 0.5, 3: tau3h - 0.5, 4: 0.5}
-    cen = {m: (_moment(E, fbar, m, u), _moment(E, fstar, m, u), _moment(E, f, m, u)) for m in I}
+    c2 = _cs2(L)
+    cen = {m: (_moment(E, fbar, m, u, c2), _moment(E, fstar, m, u, c2), _moment(E, f, m, u, c2))
+           for m in I}
     tol = _tol(fbar, fstar)
     # orders 0 and 1: mass kept, momentum gains F; the first central moment of f is 0
     F = rho * g
@@ -151,7 +168,7 @@ def test_smrt_is_the_trapezoid_rule(L, case, plain):
     trace = sum(cen[m][2] for m in diag)
     for m in I:
         n = sum(m)
-        if n < 2 or n > 4:
+        if n < 2 or n > _top_order(L):
             continue
         before, after, mean = cen[m]
         if n == 2:
@@ -184,7 +201,7 @@ def test_smrt_is_the_trapezoid_rule(L, case, plain):
 
 
 @pytest.mark.parametrize("plain", BUILDS)
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("taus", [(0.7, 0.9), (0.58, 1.3)])
 def test_rmrt_is_the_trapezoid_rule(L, taus, plain):
     tau2h, tau3h = taus
@@ -197,9 +214,10 @@ def test_rmrt_is_the_trapezoid_rule(L, taus, plain):
     zero = np.zeros(3)
     tau = {2: tau2h - 0.5, 3: tau3h - 0.5, 4: 0.5}
     tol = _tol(fbar, fstar)
+    c2 = _cs2(L)
     for m in _index_set(L):
         n = sum(m)
-        if n < 2 or n > 4:
+        if n < 2 or n > _top_order(L):
             continue
         um = np.prod([u[a] ** m[a] for a in range(3)])
         aF = 0.0
@@ -208,20 +226,20 @@ def test_rmrt_is_the_trapezoid_rule(L, taus, plain):
                 ml = list(m)
                 ml[a] -= 1
                 aF += m[a] * np.prod([u[b] ** ml[b] for b in range(3)]) * F[a]
-        neq = _moment(E, f, m, zero) - rho * um
+        neq = _moment(E, f, m, zero, c2) - rho * um
         rhs = -neq / tau[n] + aF
-        got = _moment(E, fstar, m, zero) - _moment(E, fbar, m, zero)
+        got = _moment(E, fstar, m, zero, c2) - _moment(E, fbar, m, zero, c2)
         assert abs(got - rhs) <= tol, (m, got, rhs)
 
 
-@pytest.mark.parametrize("L", lat.LATTICES)
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 @pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
 def test_plain_and_twin_builds_agree_to_rounding(L, coll):
     """The operation-order twin and the plain build compute the same step: on a walled
-    lattice with a random state and force, after 1 and 40 steps they differ by rounding
-    only (bound 1e-14 max |f|; measured about 4e-16)."""
+    lattice (periodic for D3Q39) with a random state and force, after 1 and 40 steps they
+    differ by rounding only (bound 1e-14 max |f|; measured about 4e-16)."""
     shape = (12, 10, 1) if L == "D2Q9" else (8, 6, 5)
-    kw = dict(walls=(0, 1, 0), tau=(0.7, 0.9, 1.0))
+    kw = dict(walls=(0, 0, 0) if L in lat.HIGH_ORDER else (0, 1, 0), tau=(0.7, 0.9, 1.0))
     a = Oracle(L, coll, shape, **kw)
     b = Oracle(L, coll, shape, plain=True, **kw)
     rng = np.random.default_rng(3)

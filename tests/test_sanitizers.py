@@ -36,6 +36,7 @@ def _table_file(path, L, real):
             fh.write(np.ascontiguousarray(t[k], np.int32).tobytes())
         for k in ("w", "H", "Minv"):
             fh.write(np.ascontiguousarray(t[k], real).tobytes())
+        fh.write(np.array([t["ics2"]], np.float64).tobytes())
 
 
 @pytest.mark.parametrize("build", ["f64", "f32", "plain"])
@@ -49,7 +50,7 @@ def test_oracle_under_sanitizers(build, tmp_path):
     subprocess.run(["gcc", "-std=c11", "-fopenmp", "-ffp-contract=off", *SAN, *defs, src, "-o",
                     str(exe), "-lm"], check=True, capture_output=True, text=True)
     real = np.float32 if build == "f32" else np.float64
-    for L in lat.LATTICES:
+    for L in lat.ALL_LATTICES:
         tf = tmp_path / f"{L}_{build}.bin"
         _table_file(tf, L, real)
         r = subprocess.run([str(exe), str(tf)], capture_output=True, text=True, env=ENV,
