@@ -13,8 +13,10 @@
  *              SMRT  : relaxation of central Hermite moments per order (eq:domg,
  *                      eq:RHS), force entering through the first central moment only,
  *                      back-transform of eq:bbd1 to order 4, reconstruction with the
- *                      lattice's exact inverse Hermite transform (Sec. II.C).
- *   lattice    D2Q9, D3Q19, D3Q27 (lattice units, c_s^2 = 1/3).
+ *                      lattice's exact inverse Hermite transform (Sec. II.C), or on
+ *                      D3Q39 with the paper's Hermite sum to order 4 itself.
+ *   lattice    D2Q9, D3Q19, D3Q27 (lattice units, c_s^2 = 1/3, quadrature degree 5) and
+ *              the high-order lattice D3Q39 (c_s^2 = 2/3, degree 7; periodic boxes).
  *   force      g(x, t) = g(x) s(t): an acceleration; the force density is rho g.
  *   walls      halfway bounce-back (stationary no-slip wall midway between the last
  *              fluid node and the next) on both faces of an axis, or periodic.
@@ -36,6 +38,9 @@
  *   D2Q9 : (1,0) (-1,0) (0,1) (0,-1) (1,1) (-1,-1) (1,-1) (-1,1)
  *   D3Q19: +-x, +-y, +-z, +-(1,1,0), +-(1,-1,0), +-(1,0,1), +-(1,0,-1), +-(0,1,1), +-(0,1,-1)
  *   D3Q27: D3Q19 then +-(1,1,1), +-(1,1,-1), +-(1,-1,1), +-(1,-1,-1)
+ *   D3Q39: +-x, +-y, +-z, +-(1,1,1), +-(1,1,-1), +-(1,-1,1), +-(1,-1,-1), +-(2,0,0),
+ *          +-(0,2,0), +-(0,0,2), +-(2,2,0), +-(2,-2,0), +-(2,0,2), +-(2,0,-2), +-(0,2,2),
+ *          +-(0,2,-2), +-(3,0,0), +-(0,3,0), +-(0,0,3)
  */
 #ifndef LBM_H
 #define LBM_H
@@ -58,7 +63,15 @@ typedef enum {
   LBM_ESTATE = -5      /* NULL or wrong-kind context */
 } lbm_status;
 
-typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_lattice;
+/* LBM_D3Q39: the degree-7 quadrature of speed shells |e|^2 = 0, 1, 3, 4, 8, 9 with
+ * weights 1/12, 1/12, 1/27, 2/135, 1/432, 1/1620 and c_s^2 = 2/3 (viscosity
+ * (2/3)(tau[2] - 1/2)).  It carries every Hermite moment of order <= 4 (35 of them; on
+ * its 39 velocities they span 29 dimensions); SMRT and RMRT rebuild the post-collision
+ * populations from those moments with the Hermite sum to order 4 (the reconstruction
+ * after eq:bbd1), which keeps the moments of orders 0 to 3 exactly and drops what the
+ * moments do not describe.  Periodic boxes only, every extent >= 3, no solid nodes, no
+ * tau_31 (it carries D_aaa); not in the batched engine or the warm-start expansion. */
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2, LBM_D3Q39 = 3 } lbm_lattice;
 /* LBM_BGK: single relaxation time with the second-order force term (eq:explict_eq).
  * LBM_SMRT: central-moment relaxation per Hermite order with the force in the first
  * central moment (Sec. II.C).  LBM_RMRT: the raw-moment MRT of the paper's appendix
@@ -99,7 +112,7 @@ typedef struct {
   int32_t nx, ny, nz;  /* nz must be 1 for D2Q9 */
   int32_t bc[3];       /* lbm_bc per axis (both faces of the axis) */
   /* tau-hat per Hermite order n (tau-hat = tau + 1/2 of Sec. II.B, omega_n = 1/tau-hat_n,
-   * viscosity (tau[2] - 1/2)/3).  BGK uses tau[2] only.  SMRT and RMRT relax order 2 with
+   * viscosity c_s^2 (tau[2] - 1/2)).  BGK uses tau[2] only.  SMRT and RMRT relax order 2 with
    * tau[2] and order 3 with tau[3]; order 4 is trimmed, which is tau[4] == 1 (required).
    * tau[0], tau[1] are ignored (mass and momentum are conserved).  Each used value > 1/2. */
   double tau[5];
@@ -126,7 +139,7 @@ typedef struct {
    * stored at solid nodes are unspecified.  At least one node must be fluid. */
   const uint8_t *solid;
   /* SMRT only: relaxation time (tau-hat) of the trace of the second-order moment, the
-   * irreducible component S^(2,0) of eq:domg (bulk viscosity (2/D)(tau_bulk - 1/2)/3);
+   * irreducible component S^(2,0) of eq:domg (bulk viscosity (2/D) c_s^2 (tau_bulk - 1/2));
    * the traceless part keeps tau[2] (shear).  0 = tau[2] (one rate for order 2). */
   double tau_bulk;
   /* SMRT on D3Q19 / D3Q27 only: relaxation time of the third-order trace S^(3,1) of
@@ -171,7 +184,8 @@ typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
  *   u_init   : D x N doubles (component planes, D = 2 or 3), or NULL for rest.
  *   hip_stream: a hipStream_t (NULL = the default stream).
  * Errors: LBM_EINVAL (tau <= 1/2, SMRT with tau[4] != 1, nz != 1 on D2Q9, unknown
- * enum, non-positive size, node count >= 2^31, missing g_data, rho0 <= 0),
+ * enum, non-positive size, node count >= 2^31, missing g_data, rho0 <= 0, D3Q39 with
+ * walls, solid nodes, tau_31 or an extent below 3),
  * LBM_ENOMEM, LBM_EDEVICE.  On error *out is NULL. */
 int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init,
              void *hip_stream, lbm_ctx **out);

@@ -330,7 +330,8 @@ int lbm_batch_init(const lbm_domain *domains, int32_t ndom, int32_t lattice, int
   if (!out) return set_error(LBM_EINVAL, "out is NULL");
   *out = nullptr;
   if (!domains || ndom < 1) return set_error(LBM_EINVAL, "need at least one domain");
-  if (lattice < LBM_D2Q9 || lattice > LBM_D3Q27) return set_error(LBM_EINVAL, "unknown lattice");
+  if (lattice < LBM_D2Q9 || lattice > LBM_D3Q27)
+    return set_error(LBM_EINVAL, "unknown lattice (the batched engine covers D2Q9, D3Q19, D3Q27)");
   if (collision != LBM_BGK && collision != LBM_SMRT)
     return set_error(LBM_EINVAL, "unknown collision");
   if (storage < LBM_F64 || storage > LBM_F16_SHIFTED)

@@ -1,5 +1,5 @@
 // Internal interface between the C-ABI runtime (lbm_runtime.hip) and the per-lattice
-// kernel units (lbm_d2q9.hip, lbm_d3q19.hip, lbm_d3q27.hip), which are compiled
+// kernel units (lbm_d2q9.hip, lbm_d3q19.hip, lbm_d3q27.hip, lbm_d3q39.hip), which are compiled
 // separately so the heavily unrolled kernels build in parallel.
 #pragma once
 
@@ -124,12 +124,14 @@ hipError_t add_domain_steps(const int *active, void *state, int ndom, int64_t n,
 const LatticeOps &ops_d2q9();
 const LatticeOps &ops_d3q19();
 const LatticeOps &ops_d3q27();
+const LatticeOps &ops_d3q39();
 
-// Launcher table of an lbm_lattice value (0 D2Q9, 1 D3Q19, else D3Q27).
+// Launcher table of an lbm_lattice value (0 D2Q9, 1 D3Q19, 3 D3Q39, else D3Q27).
 inline const LatticeOps &ops_for(int lattice) {
   switch (lattice) {
     case 0: return ops_d2q9();
     case 1: return ops_d3q19();
+    case 3: return ops_d3q39();
     default: return ops_d3q27();
   }
 }

@@ -30,7 +30,8 @@ struct Geom {
   int64_t ps;  // plane stride: elements from one population plane to the next (>= nx ny)
   int wall[3];
   // Solid nodes (NULL: none): per node, bit i = the pull source of population i is solid,
-  // bit 31 = the node itself is solid.
+  // bit 31 = the node itself is solid.  Lattices of more than 31 populations (D3Q39) run
+  // without solid nodes.
   const uint32_t *smask;
 };
 
@@ -122,7 +123,7 @@ __device__ __forceinline__ bool fast_block(const Geom &G, int x0, int x1, int y0
 }
 
 // The pull of population i where no bounce-back can occur (fast_block): (i, x - e_i),
-// wrapped periodically.
+// wrapped periodically (one wrap: every extent is at least max |e_ia|).
 template <class L, int i, class S>
 __device__ __forceinline__ const S *pull_ptr_periodic(const S *f, int x, int y, int z,
                                                       const Geom &G) {
@@ -141,7 +142,8 @@ template <class L, int i>
 __device__ __forceinline__ int64_t pull_slot(int x, int y, int z, const Geom &G, uint32_t sm) {
   constexpr int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
   int xs = x - ex, ys = y - ey, zs = z - ez;
-  bool bounce = (sm >> i) & 1u;  // the source node is solid
+  bool bounce = false;
+  if constexpr (i < 31) bounce = (sm >> i) & 1u;  // the source node is solid
   if constexpr (ex != 0) {
     const bool o = (xs < 0) | (xs >= G.nx);
     bounce |= o & (G.wall[0] != 0);
@@ -271,16 +273,17 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<T> a, const double *
   init_node<L, T, COLL>(r, uu, g, a.shift, out);
   if (pi) {
     // A non-equilibrium second moment Pi (planes xx, yy, zz, xy, xz, yz): the Hermite
-    // term w_i (e_i e_i - I/3) : Pi / (2 c_s^4), which has no mass or momentum.
+    // term w_i (e_i e_i - c_s^2 I) : Pi / (2 c_s^4), which has no mass or momentum.
     T P[6];
     for (int c = 0; c < 6; ++c) P[c] = T(pi[(int64_t)c * N + node]);
+    const T c2 = T(L::CS2N) / T(L::CS2D);
     static_for<L::Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
       constexpr int ex = L::E[i][0], ey = L::E[i][1], ez = L::E[i][2];
-      const T q = ((T(ex * ex) - T(1) / T(3)) * P[0] + (T(ey * ey) - T(1) / T(3)) * P[1] +
-                   (T(ez * ez) - T(1) / T(3)) * P[2]) +
+      const T q = ((T(ex * ex) - c2) * P[0] + (T(ey * ey) - c2) * P[1] +
+                   (T(ez * ez) - c2) * P[2]) +
                   T(2) * ((T(ex * ey) * P[3] + T(ex * ez) * P[4]) + T(ey * ez) * P[5]);
-      out[i] = out[i] + Tab<L, T>::w(i) * (T(4.5) * q);
+      out[i] = out[i] + Tab<L, T>::w(i) * (T(0.5 * L::ICS2 * L::ICS2) * q);
     });
   }
   S *__restrict__ f = static_cast<S *>(a.fout);

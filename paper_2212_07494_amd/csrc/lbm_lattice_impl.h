@@ -1,5 +1,6 @@
 // Launchers of one lattice's kernels; included once per lattice unit with LBM_LAT set
-// to the lattice struct (D2Q9, D3Q19, D3Q27) and LBM_OPS to the exported table name.
+// to the lattice struct (D2Q9, D3Q19, D3Q27, D3Q39) and LBM_OPS to the exported table
+// name.  The batched engine is built for the lattices of at most 27 populations.
 #pragma once
 
 #include "lbm_batch_kernels.h"
@@ -121,7 +122,7 @@ struct Ops {
         for (int x = 0; x < nx; ++x) {
           const int64_t n = ((int64_t)z * ny + y) * nx + x;
           uint32_t w = solid[n] ? SOLID_NODE : 0u;
-          for (int i = 0; i < L::Q; ++i) {
+          for (int i = 0; i < L::Q && i < 31; ++i) {
             int c[3] = {x - L::E[i][0], y - L::E[i][1], z - L::E[i][2]};
             bool across_wall = false;
             for (int a = 0; a < 3; ++a) {
@@ -189,7 +190,8 @@ struct Ops {
     return hipGetLastError();
   }
   static hipError_t batch_step(const BatchLaunch &b, hipStream_t s) {
-    return with_types(b.storage, [&](auto *sp, auto *tp) -> hipError_t {
+    if constexpr (L::Q > 27) return hipErrorInvalidValue;
+    else return with_types(b.storage, [&](auto *sp, auto *tp) -> hipError_t {
       using S = std::remove_pointer_t<decltype(sp)>;
       using T = std::remove_pointer_t<decltype(tp)>;
       switch (b.variant + 3 * b.coll) {
@@ -204,7 +206,8 @@ struct Ops {
     });
   }
   static hipError_t batch_monitor(const BatchLaunch &b, hipStream_t s) {
-    return with_types(b.storage, [&](auto *sp, auto *tp) -> hipError_t {
+    if constexpr (L::Q > 27) return hipErrorInvalidValue;
+    else return with_types(b.storage, [&](auto *sp, auto *tp) -> hipError_t {
       using S = std::remove_pointer_t<decltype(sp)>;
       using T = std::remove_pointer_t<decltype(tp)>;
       hipLaunchKernelGGL((batch_monitor_kernel<L, S, T>), dim3(b.grid), dim3(256), 0, s,

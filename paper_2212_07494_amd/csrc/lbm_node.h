@@ -1,8 +1,9 @@
 // Per-node arithmetic of the forced lattice-Boltzmann step (device code, gfx950).
 //
 // Li, Duan & Shan, "Second-order force scheme for lattice Boltzmann method"
-// (arXiv 2212.07494).  Lattice units, c_s^2 = 1/3, Hermite polynomials written in
-// lattice units (H_m(e) = prod_a h_{m_a}(e_a), h_0 = 1, h_1 = e, h_2 = e^2 - 1/3).
+// (arXiv 2212.07494).  Lattice units; c_s^2 = 1/3 on D2Q9, D3Q19, D3Q27 and 2/3 on the
+// high-order lattice D3Q39 (L::CS2N / L::CS2D); Hermite polynomials written in lattice
+// units (H_m(e) = prod_a h_{m_a}(e_a), h_0 = 1, h_1 = e, h_2 = e^2 - c_s^2, ...).
 //
 // Everything here is templated on the lattice L (constants from lbm_tables.h) and the
 // arithmetic type T (double or float), and every loop runs over compile-time indices
@@ -86,6 +87,7 @@ __device__ __forceinline__ Macro<T> macroscopic(const T (&d)[L::Q], T shift, con
       constexpr int ea = L::E[i][a];
       if constexpr (ea == 1) j = j + d[i];
       if constexpr (ea == -1) j = j + (-d[i]);
+      if constexpr (ea > 1 || ea < -1) j = j + T(ea) * d[i];
     });
     M.j[a] = j;
     M.u[a] = j / M.rho + T(0.5) * g[a];
@@ -133,7 +135,9 @@ __device__ __forceinline__ float fmadd(float a, float b, float c) { return __bui
 __device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Whether c is +-2^n: then c u^l is exact, and c u^l N rounds once inside an fma.  The
-// shift coefficients C(m,l) are products of binomials C(m_a, l_a) with m_a <= 2.
+// shift coefficients C(m,l) are products of binomials C(m_a, l_a): powers of two where
+// m_a <= 2 (D2Q9, D3Q19, D3Q27); D3Q39's orders 3 and 4 along one axis bring 3 and 6,
+// for which the product c u^l is rounded first (the same expression in the oracle).
 constexpr bool pow2_coef(int c) {
   const int a = c < 0 ? -c : c;
   return a > 0 && (a & (a - 1)) == 0;
@@ -153,7 +157,7 @@ __device__ __forceinline__ T central(const T (&U)[L::NM], const T (&N)[L::NM]) {
   static_for<L::NT[K]>([&](auto Tt) {
     constexpr int t = decltype(Tt)::value;
     constexpr int kl = L::TL[K][t], km = L::TM[K][t];
-    static_assert(pow2_coef(L::CDN[K][t]));
+    static_assert(L::NM < L::Q || pow2_coef(L::CDN[K][t]));
     Dm = fmadd(T(L::CDN[K][t]) * U[kl], N[km], Dm);
   });
   return Dm;
@@ -262,6 +266,43 @@ __device__ __forceinline__ void reconstruct_folded(T (&d)[L::Q], const T (&dA)[L
   });
 }
 
+// The reconstruction applied to the post-collision moments themselves, d*_i = sum_k
+// MINV[i][k] a*_k, for a lattice whose index set is smaller than Q (D3Q39: MINV is the
+// paper's Hermite sum to order 4).  There the increment form d + MINV dA would keep the
+// part of d that no carried moment sees, which the paper's reconstruction drops; the
+// moments of orders 0 to 3 of the result are exactly a* (the quadrature is exact to
+// degree 7; a*_0 is the deviation mass, MINV[i][0] = w_i).  Folded over the pairs as in
+// reconstruct_folded: the rest population sums its row over every k from k = 0; each pair
+// sums its first member's row over the even- and the odd-order moments apart and takes
+// (E + O), (E - O).
+template <class L, class T>
+__device__ __forceinline__ void reconstruct_full_folded(T (&d)[L::Q], const T (&as)[L::NM]) {
+  static_assert(pair_symmetric<L, T>());
+  T acc = T(-0.0);
+  static_for<L::NM>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    constexpr T cf = Tab<L, T>::minv(0, k);
+    if constexpr (cf != T(0)) acc = fmadd(cf, as[k], acc);
+  });
+  d[0] = acc;
+  static_for<(L::Q - 1) / 2>([&](auto Pp) {
+    constexpr int i = 2 * decltype(Pp)::value + 1;
+    T ev = T(-0.0), od = T(-0.0);
+    static_for<L::NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr T cf = Tab<L, T>::minv(i, k);
+      if constexpr (cf != T(0)) {
+        if constexpr (L::ORD[k] % 2)
+          od = fmadd(cf, as[k], od);
+        else
+          ev = fmadd(cf, as[k], ev);
+      }
+    });
+    d[i] = ev + od;
+    d[i + 1] = ev - od;
+  });
+}
+
 // Index of the multi-index MI[k] - e_a in L's canonical list (-1 if absent).
 template <class L>
 constexpr int sub_index(int k, int a) {
@@ -276,10 +317,32 @@ constexpr int sub_index(int k, int a) {
 // BGK with the second-order force term (Sec. II.B, eq:explict_eq), formed as
 // eq:evolution writes it, f-bar plus the change:
 //   f*_i = f_i + [(1 - omega/2) F_i - omega (f_i - f_eq_i)] + (conserved-moment fix-up)
-//   f_eq_i = w_i (rho + rho P_i),  P_i = (3 e.u + 4.5 (e.u)^2) - 1.5 u.u
-//   F_i   = w_i (3 (e.F - u.F) + 9 (e.F)(e.u))
-// (the truncated Hermite equilibrium and the second-order force, c_s^2 = 1/3).  In
-// deviation form the leading rho of f_eq becomes d-rho.
+//   f_eq_i = w_i (rho + rho P_i),  P_i = (k e.u + (k^2/2) (e.u)^2) - (k/2) u.u
+//   F_i   = w_i (k (e.F - u.F) + k^2 (e.F)(e.u))
+// with k = 1/c_s^2 (3, 4.5, 1.5 and 9 at c_s^2 = 1/3): the truncated Hermite equilibrium
+// and the second-order force.  In deviation form the leading rho of f_eq becomes d-rho.
+template <class L, class T>
+struct BGKConst {
+  static constexpr T k1 = T(L::ICS2);                    // 1 / c_s^2
+  static constexpr T k2h = T(0.5 * L::ICS2 * L::ICS2);   // 1 / (2 c_s^4)
+  static constexpr T k1h = T(0.5 * L::ICS2);             // 1 / (2 c_s^2)
+  static constexpr T k2 = T(L::ICS2 * L::ICS2);          // 1 / c_s^4
+};
+
+// e_i . v, summed over the non-zero components in x, y, z order (multiples of v_a for
+// |e_ia| > 1).
+template <class L, int i, class T>
+__device__ __forceinline__ T edot(const T (&v)[3]) {
+  T s = T(-0.0);
+  static_for<3>([&](auto A) {
+    constexpr int a = decltype(A)::value;
+    constexpr int ea = L::E[i][a];
+    if constexpr (ea == 1) s = s + v[a];
+    if constexpr (ea == -1) s = s + (-v[a]);
+    if constexpr (ea > 1 || ea < -1) s = s + T(ea) * v[a];
+  });
+  return s;
+}
 template <class L, class T>
 __device__ __forceinline__ void collide_bgk(T (&d)[L::Q], T shift, const T (&g)[3],
                                             const BGKCoef<T> &c) {
@@ -294,25 +357,14 @@ __device__ __forceinline__ void collide_bgk(T (&d)[L::Q], T shift, const T (&g)[
     constexpr int a = decltype(A)::value;
     uF = uF + M.u[a] * M.F[a];
   });
+  using K = BGKConst<L, T>;
   static_for<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    T eu = T(-0.0), eF = T(-0.0);
-    static_for<3>([&](auto A) {
-      constexpr int a = decltype(A)::value;
-      constexpr int ea = L::E[i][a];
-      if constexpr (ea == 1) {
-        eu = eu + M.u[a];
-        eF = eF + M.F[a];
-      }
-      if constexpr (ea == -1) {
-        eu = eu + (-M.u[a]);
-        eF = eF + (-M.F[a]);
-      }
-    });
+    const T eu = edot<L, i>(M.u), eF = edot<L, i>(M.F);
     constexpr T wi = Tab<L, T>::w(i);
-    const T P = (T(3) * eu + T(4.5) * (eu * eu)) - T(1.5) * usq;
+    const T P = (K::k1 * eu + K::k2h * (eu * eu)) - K::k1h * usq;
     const T feq = wi * (M.drho + M.rho * P);
-    const T G = T(3) * (eF - uF) + T(9) * (eF * eu);
+    const T G = K::k1 * (eF - uF) + K::k2 * (eF * eu);
     const T Fi = wi * G;
     ch[i] = c.hforce * Fi - c.omega * (d[i] - feq);
   });
@@ -336,6 +388,7 @@ __device__ __forceinline__ void collide_bgk(T (&d)[L::Q], T shift, const T (&g)[
       constexpr int ea = L::E[i][a];
       if constexpr (ea == 1) s = s + ch[i];
       if constexpr (ea == -1) s = s + (-ch[i]);
+      if constexpr (ea > 1 || ea < -1) s = s + T(ea) * ch[i];
     });
     r[1 + a] = M.F[a] - s;
   });
@@ -381,10 +434,15 @@ __device__ __forceinline__ void reconstruct(const T (&a)[L::NM], T (&out)[L::Q])
 // so they carry no per-step bias.
 // HI56: carry the orders above 4 (D3Q27's 5 and 6) as rho u^m + R_m, their central parts
 // trimmed like order 4, instead of dropping them.
+// On a lattice whose index set is smaller than Q (D3Q39) the state is rebuilt from the
+// post-collision moments a*_0 = d-rho, a*_e = j + F, a*_m = rho u^m + R_m (|m| = 2..4)
+// by reconstruct_full_folded, and the order-4 moments are not projected (a* of order 4
+// does not depend on them).
 template <class L, bool HI56, class T>
 __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)[3],
                                              const SMRTCoef<T> &c) {
   constexpr int NM = L::NM;
+  constexpr bool FULL = L::NM < L::Q;
   const Macro<T> M = macroscopic<L>(d, shift, g);
   T U[NM], E[NM], N[NM], P[NM], dA[NM], C2[NM];
   static_for<NM>([&](auto K) {
@@ -400,12 +458,16 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
       N[k] = T(-0.5) * M.F[a];
     } else if constexpr (n >= 2) {
-      const T acc = pf.template project<k>(d);
-      // orders 2..4: non-equilibrium part; above 4: the raw moment itself
-      if constexpr (n <= 4)
-        N[k] = acc - E[k];
-      else
-        N[k] = acc;
+      if constexpr (FULL && n == 4) {
+        N[k] = T(0);  // not needed: a* of order 4 is rho u^m + R_m
+      } else {
+        const T acc = pf.template project<k>(d);
+        // orders 2..4: non-equilibrium part; above 4: the raw moment itself
+        if constexpr (n <= 4)
+          N[k] = acc - E[k];
+        else
+          N[k] = acc;
+      }
     } else {
       N[k] = T(0);
     }
@@ -466,10 +528,16 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
     constexpr int k = decltype(K)::value;
     constexpr int n = L::ORD[k];
     if constexpr (n == 0) {
-      dA[k] = T(0);
+      if constexpr (FULL)
+        dA[k] = M.drho;
+      else
+        dA[k] = T(0);
     } else if constexpr (n == 1) {
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
-      dA[k] = M.F[a];
+      if constexpr (FULL)
+        dA[k] = M.j[a] + M.F[a];
+      else
+        dA[k] = M.F[a];
     } else if constexpr (n > 4) {
       if constexpr (HI56) {
         // a*_m = rho u^m + R_m with the central parts of orders >= 4 trimmed
@@ -481,6 +549,8 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
           if constexpr (L::ORD[km] <= 3) R = fmadd(T(L::CUP[k][t]) * U[kl], P[km], R);
         });
         dA[k] = R - (N[k] - E[k]);
+      } else if constexpr (FULL) {
+        dA[k] = T(0);
       } else {
         dA[k] = -N[k];
       }
@@ -489,13 +559,19 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       static_for<L::NT[k]>([&](auto Tt) {
         constexpr int t = decltype(Tt)::value;
         constexpr int kl = L::TL[k][t], km = L::TM[k][t];
-        static_assert(pow2_coef(L::CUP[k][t]));
+        static_assert(FULL || pow2_coef(L::CUP[k][t]));
         if constexpr (L::ORD[km] <= 3) R = fmadd(T(L::CUP[k][t]) * U[kl], P[km], R);
       });
-      dA[k] = R - N[k];
+      if constexpr (FULL)
+        dA[k] = E[k] + R;
+      else
+        dA[k] = R - N[k];
     }
   });
-  reconstruct_folded<L>(d, dA);
+  if constexpr (FULL)
+    reconstruct_full_folded<L>(d, dA);
+  else
+    reconstruct_folded<L>(d, dA);
 }
 
 // Raw-moment MRT with force (the paper's appendix, eq:RHS_a in its explicit form): every
@@ -515,6 +591,7 @@ template <class L, class T>
 __device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)[3],
                                              const RMRTCoef<T> &c) {
   constexpr int NM = L::NM;
+  constexpr bool FULL = L::NM < L::Q;  // rebuild from a* (see collide_smrt)
   const Macro<T> M = macroscopic<L>(d, shift, g);
   T U[NM], dA[NM];
   static_for<NM>([&](auto K) {
@@ -526,16 +603,27 @@ __device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)
     constexpr int k = decltype(K)::value;
     constexpr int n = L::ORD[k];
     if constexpr (n == 0) {
-      dA[k] = T(0);
+      if constexpr (FULL)
+        dA[k] = M.drho;
+      else
+        dA[k] = T(0);
     } else if constexpr (n == 1) {
       constexpr int a = L::MI[k][0] ? 0 : (L::MI[k][1] ? 1 : 2);
-      dA[k] = M.F[a];
+      if constexpr (FULL)
+        dA[k] = M.j[a] + M.F[a];
+      else
+        dA[k] = M.F[a];
     } else {
-      const T acc = pf.template project<k>(d);
+      T acc = T(0);  // a* of order 4 does not depend on the pre-collision moment
+      if constexpr (!(FULL && n == 4)) acc = pf.template project<k>(d);
       if constexpr (n > 4) {
-        dA[k] = -acc;
+        if constexpr (FULL)
+          dA[k] = T(0);
+        else
+          dA[k] = -acc;
       } else {
-        const T Nk = acc - M.rho * U[k];
+        const T Ek = M.rho * U[k];
+        const T Nk = acc - Ek;
         T aF = T(-0.0);
         static_for<3>([&](auto A) {
           constexpr int a = decltype(A)::value;
@@ -552,11 +640,17 @@ __device__ __forceinline__ void collide_rmrt(T (&d)[L::Q], T shift, const T (&g)
         } else {
           t = T(0.5) * aF;
         }
-        dA[k] = t - Nk;
+        if constexpr (FULL)
+          dA[k] = Ek + t;
+        else
+          dA[k] = t - Nk;
       }
     }
   });
-  reconstruct_folded<L>(d, dA);
+  if constexpr (FULL)
+    reconstruct_full_folded<L>(d, dA);
+  else
+    reconstruct_folded<L>(d, dA);
 }
 
 // Initial stored state f-bar = f_eq - F_i/2 (eq:newf with Omega = 0): density and
@@ -582,25 +676,14 @@ __device__ __forceinline__ void init_node(T rho, const T (&u)[3], const T (&g)[3
       constexpr int a = decltype(A)::value;
       uF = uF + u[a] * F[a];
     });
+    using K = BGKConst<L, T>;
     static_for<L::Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      T eu = T(-0.0), eF = T(-0.0);
-      static_for<3>([&](auto A) {
-        constexpr int a = decltype(A)::value;
-        constexpr int ea = L::E[i][a];
-        if constexpr (ea == 1) {
-          eu = eu + u[a];
-          eF = eF + F[a];
-        }
-        if constexpr (ea == -1) {
-          eu = eu + (-u[a]);
-          eF = eF + (-F[a]);
-        }
-      });
+      const T eu = edot<L, i>(u), eF = edot<L, i>(F);
       constexpr T wi = Tab<L, T>::w(i);
-      const T P = (T(3) * eu + T(4.5) * (eu * eu)) - T(1.5) * usq;
+      const T P = (K::k1 * eu + K::k2h * (eu * eu)) - K::k1h * usq;
       const T feq = wi * (drho + rho * P);
-      const T G = T(3) * (eF - uF) + T(9) * (eF * eu);
+      const T G = K::k1 * (eF - uF) + K::k2 * (eF * eu);
       out[i] = feq - T(0.5) * (wi * G);
     });
   } else {

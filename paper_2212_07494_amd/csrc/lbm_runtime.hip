@@ -252,9 +252,12 @@ namespace {
 
 bool valid(const lbm_ctx *c) { return c && c->magic == kMagic; }
 
+// c_s^2 = num / 3 of a lattice: 1/3, or 2/3 on D3Q39.
+double cs2_num(int lattice) { return lattice == LBM_D3Q39 ? 2.0 : 1.0; }
+
 int validate(const lbm_params *p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
-  if (p->lattice < LBM_D2Q9 || p->lattice > LBM_D3Q27)
+  if (p->lattice < LBM_D2Q9 || p->lattice > LBM_D3Q39)
     return fail(LBM_EINVAL, "unknown lattice %d", p->lattice);
   if (p->collision != LBM_BGK && p->collision != LBM_SMRT && p->collision != LBM_RMRT)
     return fail(LBM_EINVAL, "unknown collision %d", p->collision);
@@ -263,6 +266,15 @@ int validate(const lbm_params *p) {
   if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0)
     return fail(LBM_EINVAL, "sizes must be positive (%d, %d, %d)", p->nx, p->ny, p->nz);
   if (p->lattice == LBM_D2Q9 && p->nz != 1) return fail(LBM_EINVAL, "D2Q9 needs nz == 1");
+  if (p->lattice == LBM_D3Q39) {
+    // links of up to three nodes: one periodic wrap needs every extent >= 3; no wall or
+    // solid-node rule is defined for populations that cross more than one node
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3)
+      return fail(LBM_EINVAL, "D3Q39 needs every extent >= 3 (%d, %d, %d)", p->nx, p->ny, p->nz);
+    if (p->bc[0] != LBM_PERIODIC || p->bc[1] != LBM_PERIODIC || p->bc[2] != LBM_PERIODIC)
+      return fail(LBM_EINVAL, "D3Q39 runs periodic boxes only (no wall rule for its long links)");
+    if (p->solid) return fail(LBM_EINVAL, "D3Q39 runs without solid nodes");
+  }
   if (p->ny > 65535 || p->nz > 65535) return fail(LBM_EINVAL, "ny and nz must be <= 65535");
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
   if (N >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "node count %lld >= 2^31", (long long)N);
@@ -298,6 +310,8 @@ int validate(const lbm_params *p) {
       return fail(LBM_EINVAL, "tau_31 needs the SMRT collision");
     if (p->lattice == LBM_D2Q9)
       return fail(LBM_EINVAL, "tau_31: D2Q9 carries no traceless third-order component");
+    if (p->lattice == LBM_D3Q39)
+      return fail(LBM_EINVAL, "tau_31 is defined on D3Q19/D3Q27 (D3Q39 carries D_aaa)");
     if (p->force_order == 3)
       return fail(LBM_EINVAL, "tau_31 is not combined with force_order 3");
     if (!(p->tau_31 > 0.5) || !std::isfinite(p->tau_31))
@@ -394,7 +408,7 @@ int judge_record(lbm_ctx *c, const lbm_monitors &m) {
     return fail(LBM_ENONFINITE, "%lld nodes are not finite at step %lld",
                 (long long)m.nonfinite, (long long)m.step);
   }
-  const double cs = std::sqrt(1.0 / 3.0);
+  const double cs = std::sqrt(cs2_num(c->p.lattice) / 3.0);
   if (c->p.mach_limit > 0 && m.umax > c->p.mach_limit * cs)
     return fail(LBM_WMACH, "max |u| = %g at step %lld exceeds the Mach limit %g c_s", m.umax,
                 (long long)m.step, c->p.mach_limit);
@@ -597,7 +611,7 @@ extern "C" {
 int lbm_version(void) { return 100; }
 
 int lbm_lattice_info(int32_t lattice, int32_t *D, int32_t *Q, int32_t *e, double *w) {
-  if (lattice < LBM_D2Q9 || lattice > LBM_D3Q27)
+  if (lattice < LBM_D2Q9 || lattice > LBM_D3Q39)
     return fail(LBM_EINVAL, "unknown lattice %d", (int)lattice);
   const lbm::LatticeOps &ops = lbm::ops_for(lattice);
   if (D) *D = ops.D;
@@ -1118,7 +1132,7 @@ int lbm_reset_fields(lbm_ctx *c, const float *fields_dev, int32_t layout, double
   if (noneq) {
     hipLaunchKernelGGL(strain_kernel, dim3(grid), dim3(256), 0, c->stream, rho_d, u_d, c->p.nx,
                        c->p.ny, c->p.nz, c->D, c->p.bc[0] == LBM_WALLS, c->p.bc[1] == LBM_WALLS,
-                       c->p.bc[2] == LBM_WALLS, -c->p.tau[2] / 3.0, P);
+                       c->p.bc[2] == LBM_WALLS, -(c->p.tau[2] * cs2_num(c->p.lattice)) / 3.0, P);
     HIP_TRY(hipGetLastError());
   }
   c->cur = 0;

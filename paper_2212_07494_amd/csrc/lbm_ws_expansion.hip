@@ -369,6 +369,8 @@ int check_problem(const lbm_params *params, const lbm_ws_problem *p, int box) {
   if (box < 1) return set_error(LBM_EINVAL, "box = %d must be positive", box);
   if (p->nmodes < 1 || p->nmodes > 8)
     return set_error(LBM_EINVAL, "nmodes = %d must be in 1..8", (int)p->nmodes);
+  if (params->lattice == LBM_D3Q39)
+    return set_error(LBM_EINVAL, "the expansion covers D2Q9, D3Q19 and D3Q27");
   const bool two_d = params->lattice == LBM_D2Q9;
   for (int j = 0; j < p->nmodes; ++j) {
     const double *k = p->k[j];

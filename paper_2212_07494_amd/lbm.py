@@ -19,11 +19,11 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_WMACH = 1  # warning: the call did its work, but max |u| exceeded the Mach limit
-LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
+LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2, "D3Q39": 3}
 COLLISIONS = {"bgk": 0, "smrt": 1, "rmrt": 2}
 STORAGES = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3}
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f32s": 4, "f16s": 2}
-QOF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+QOF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27, "D3Q39": 39}
 G_UNIFORM, G_PROFILE, G_FIELD = 0, 1, 2
 PERIODIC, WALLS = 0, 1
 

@@ -49,14 +49,14 @@ int main(void) {
   for (int s = -6; s <= 2; ++s) EXPECT(lbm_strerror(s) != NULL && strlen(lbm_strerror(s)) > 0);
   EXPECT(lbm_version() > 0);
   /* lattice tables (host only) */
-  for (int l = 0; l < 3; ++l) {
-    int32_t D = 0, Q = 0, e[27 * 3];
-    double w[27], sum = 0.0;
+  for (int l = 0; l < 4; ++l) {
+    int32_t D = 0, Q = 0, e[39 * 3];
+    double w[39], sum = 0.0;
     EXPECT(lbm_lattice_info(l, &D, &Q, e, w) == LBM_OK);
     for (int i = 0; i < Q; ++i) sum += w[i];
     EXPECT(fabs(sum - 1.0) < 1e-15 && (D == 2 || D == 3));
   }
-  EXPECT(lbm_lattice_info(3, NULL, NULL, NULL, NULL) == LBM_EINVAL);
+  EXPECT(lbm_lattice_info(4, NULL, NULL, NULL, NULL) == LBM_EINVAL);
 
   /* parameter validation: every one fails before any allocation */
   lbm_ctx *c = (lbm_ctx *)0x1;
@@ -74,6 +74,10 @@ int main(void) {
   p = base_params(); p.g_kind = LBM_G_FIELD; p.g_data = NULL;
   EXPECT(lbm_init(&p, NULL, NULL, NULL, &c) == LBM_EINVAL);
   p = base_params(); p.nx = 2048; p.ny = 2048; p.nz = 1024;
+  EXPECT(lbm_init(&p, NULL, NULL, NULL, &c) == LBM_EINVAL);
+  p = base_params(); p.lattice = LBM_D3Q39; p.nz = 2;
+  EXPECT(lbm_init(&p, NULL, NULL, NULL, &c) == LBM_EINVAL);
+  p = base_params(); p.lattice = LBM_D3Q39; p.bc[1] = LBM_WALLS;
   EXPECT(lbm_init(&p, NULL, NULL, NULL, &c) == LBM_EINVAL);
   EXPECT(lbm_init(NULL, NULL, NULL, NULL, &c) == LBM_EINVAL);
   EXPECT(lbm_init(&p, NULL, NULL, NULL, NULL) == LBM_EINVAL);

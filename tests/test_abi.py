@@ -60,6 +60,11 @@ def test_version_and_strerror():
     (dict(mach_limit=-0.1), "mach_limit"),
     (dict(mach_limit=float("nan")), "mach_limit"),
     (dict(rho0=float("nan")), "rho0"),
+    (dict(lattice="D3Q39", shape=(8, 8, 2)), "extent >= 3"),
+    (dict(lattice="D3Q39", shape=(8, 8, 8), bc=(0, 1, 0)), "periodic boxes only"),
+    (dict(lattice="D3Q39", shape=(8, 8, 8), solid=np.zeros(512, np.uint8)), "solid"),
+    (dict(lattice="D3Q39", shape=(8, 8, 8), collision="smrt", tau_31=0.7), "D_aaa"),
+    (dict(lattice="D3Q39", shape=(8, 8, 8), collision="smrt", max_order=6), "SMRT on D3Q27"),
 ])
 def test_invalid_parameters_rejected(change, fragment):
     from paper_2212_07494_amd import lbm
@@ -150,9 +155,10 @@ def test_library_constants_equal_oracle_rationals():
     spec = importlib.util.spec_from_file_location("gen_tables", path)
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
-    for name in olat.LATTICES:
+    for name in olat.ALL_LATTICES:
         vel, w, ms = mod.lattice(name)
-        _, minv = mod.reconstruction(vel, w, ms)
+        assert mod.sound_speed2(name) == olat.cs2(name)
+        _, minv = mod.reconstruction(vel, w, ms, mod.sound_speed2(name))
         assert vel == olat.velocities(name)
         assert w == olat.weights(name)
         assert ms == olat.index_set(name)
@@ -243,3 +249,31 @@ def test_set_waves_binding_checks_shapes():
     with pytest.raises(ValueError):
         lbm.lbm_set_waves(None, 19, np.full((2, 3), 0.5), np.zeros(2),
                           np.zeros((2, 19), complex))
+
+
+def test_lattice_info_matches_oracle_tables():
+    """lbm_lattice_info (host only) returns each lattice's velocities and weights in the
+    population order of the oracle's tables, D3Q39 included."""
+    from oracle import lattice as olat
+    from paper_2212_07494_amd import lbm
+    lib = lbm.load()
+    for name in olat.ALL_LATTICES:
+        D, Q = C.c_int32(), C.c_int32()
+        e = np.zeros(3 * 39, np.int32)
+        w = np.zeros(39)
+        assert lib.lbm_lattice_info(lbm.LATTICES[name], C.byref(D), C.byref(Q),
+                                    e.ctypes.data_as(C.c_void_p),
+                                    w.ctypes.data_as(C.c_void_p)) == 0
+        assert Q.value == len(olat.velocities(name)) == lbm.QOF[name]
+        assert D.value == olat.dim(name)
+        assert [tuple(v) for v in e[:3 * Q.value].reshape(-1, 3)] == olat.velocities(name)
+        assert list(w[:Q.value]) == [float(x) for x in olat.weights(name)]
+    assert lib.lbm_lattice_info(4, None, None, None, None) == lbm.LBM_EINVAL
+
+
+def test_warm_start_expansion_rejects_d3q39():
+    from paper_2212_07494_amd import lbm
+    prob = dict(tau2=0.8, modes=[dict(k=(1, 0, 0), p=(0, 1, 0), amp=1e-6, phase=0.0)] * 4)
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.lbm_ws_lattice_response(prob, 32, lattice="D3Q39")
+    assert "covers D2Q9, D3Q19 and D3Q27" in str(ei.value)

@@ -1,0 +1,193 @@
+"""The high-order lattice D3Q39 (c_s^2 = 2/3, quadrature degree 7) on the GPU.
+
+Bit-exact parity with the oracle's operation-order twin for every collision and storage
+mode (random state, force field or profile, per-step force scales, a periodic box with
+ragged tails), the third-order force content and the bulk rate, every launch
+configuration, initialisation and moments; the FP64 kernel within 1e-14 max |f| of the
+oracle's plain build; and an FP32-shifted Kolmogorov flow against the FP64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from oracle import lattice as olat
+from paper_2212_07494_amd import inputs
+from tests.helpers import exact_mismatch, gpu_available, oracle_for, to_storage
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
+
+LAT = "D3Q39"
+SHAPE = (67, 11, 7)
+PERIODIC = (0, 0, 0)
+TAU = {"bgk": (0.63, 0.63, 1.0), "smrt": (0.58, 0.87, 1.0), "rmrt": (0.58, 0.87, 1.0)}
+SCALES = [1.0, 0.5, -2.0]
+
+
+def lbm():
+    from paper_2212_07494_amd import lbm as L
+    L.load()
+    return L
+
+
+def _weights():
+    return np.array([float(x) for x in olat.weights(LAT)])
+
+
+def _state(storage, N, seed):
+    w = _weights()
+    f = inputs.random_state(len(w), N, seed, scale=0.05, weights=w)
+    if storage in ("f32s", "f16s"):
+        f = f - w[:, None]
+    return to_storage(f, storage)
+
+
+def _force(kind, seed, shape=SHAPE):
+    N = int(np.prod(shape))
+    rng = np.random.default_rng(seed)
+    if kind == "field":
+        g = rng.uniform(-1e-3, 1e-3, (3, N))
+        return dict(g_field=g), g
+    table = rng.uniform(-1e-3, 1e-3, (3, shape[1]))
+    return dict(g_profile=(1, table)), inputs.profile_field(shape, 1, table)
+
+
+def _oracle_steps(o, f0, g, scales):
+    fo = f0.astype(o.dtype)
+    for s in scales:
+        fo = o.step(fo, g, s)
+    return fo.astype(np.float64)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32s", "f16s"])
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
+def test_step_parity(coll, storage):
+    L = lbm()
+    N = int(np.prod(SHAPE))
+    for kind in ("field", "profile"):
+        kw, g = _force(kind, seed=7)
+        f0 = _state(storage, N, seed=11)
+        o = oracle_for(LAT, coll, storage, SHAPE, PERIODIC, TAU[coll])
+        want = _oracle_steps(o, f0, g, SCALES)
+        with L.Lattice(LAT, coll, storage, SHAPE, PERIODIC, TAU[coll], **kw) as gpu:
+            gpu.set_populations(f0)
+            assert exact_mismatch(gpu.populations(), f0) == 0
+            gpu.step(3, g_scale=SCALES)
+            got = gpu.populations()
+        bad = exact_mismatch(got, want)
+        assert bad == 0, (kind, bad, np.max(np.abs(got - want)))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32s", "f16s"])
+@pytest.mark.parametrize("opts", [dict(force_order=3), dict(tau_bulk=1.7)])
+def test_options_parity(opts, storage):
+    L = lbm()
+    N = int(np.prod(SHAPE))
+    kw, g = _force("field", seed=8)
+    f0 = _state(storage, N, seed=12)
+    o = oracle_for(LAT, "smrt", storage, SHAPE, PERIODIC, TAU["smrt"], **opts)
+    want = _oracle_steps(o, f0, g, SCALES)
+    with L.Lattice(LAT, "smrt", storage, SHAPE, PERIODIC, TAU["smrt"], **kw, **opts) as gpu:
+        gpu.set_populations(f0)
+        gpu.step(3, g_scale=SCALES)
+        got = gpu.populations()
+    assert exact_mismatch(got, want) == 0
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32s"])
+def test_all_launch_configurations(storage):
+    L = lbm()
+    shape = (70, 4, 3)
+    N = int(np.prod(shape))
+    _, g = _force("field", seed=4, shape=shape)
+    f0 = _state(storage, N, seed=3)
+    o = oracle_for(LAT, "smrt", storage, shape, PERIODIC, TAU["smrt"])
+    want = _oracle_steps(o, f0, g, [1.0, 1.0, 1.0])
+    with L.Lattice(LAT, "smrt", storage, shape, PERIODIC, TAU["smrt"], g_field=g) as gpu:
+        for bx in (64, 128, 256):
+            for by in (1, 2, 4):
+                if bx * by > 256:
+                    continue
+                for v in range(6):
+                    L.lbm_set_tuning(gpu.ctx, bx, by, v)
+                    gpu.set_populations(f0)
+                    gpu.step(3)
+                    assert exact_mismatch(gpu.populations(), want) == 0, (bx, by, v)
+
+
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32s", "f16s"])
+def test_init_and_moments_parity(coll, storage):
+    """lbm_init from (rho, u) fields under a force field places the oracle's initial state
+    (eq:newf with Omega = 0) bit for bit, lbm_moments returns the oracle's moments, and so
+    do four steps later."""
+    L = lbm()
+    shape = (19, 6, 5)
+    rho, u, _ = inputs.random_fields(shape, seed=5)
+    kw, g = _force("field", seed=9, shape=shape)
+    o = oracle_for(LAT, coll, storage, shape, PERIODIC, TAU[coll])
+    with L.Lattice(LAT, coll, storage, shape, PERIODIC, TAU[coll], rho=rho, u=u, **kw) as gpu:
+        fo = o.init(rho, u, g)
+        assert exact_mismatch(gpu.populations(), fo.astype(np.float64)) == 0
+        r_g, u_g = gpu.moments()
+        r_o, u_o = o.moments(fo, g)
+        assert exact_mismatch(r_g, r_o.astype(np.float64)) == 0
+        assert exact_mismatch(u_g, u_o.astype(np.float64)) == 0
+        gpu.step(4)
+        fo = o.run(fo, g, 4)
+        assert exact_mismatch(gpu.populations(), fo.astype(np.float64)) == 0
+        r_g, u_g = gpu.moments(g_scale=0.25)
+        r_o, u_o = o.moments(fo, g, 0.25)
+        assert exact_mismatch(u_g, u_o.astype(np.float64)) == 0
+
+
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
+@pytest.mark.parametrize("opts", [dict(), dict(force_order=3), dict(tau_bulk=1.3)])
+def test_fp64_kernel_matches_plain_definition(coll, opts):
+    if opts and coll != "smrt":
+        pytest.skip("the options are SMRT's")
+    L = lbm()
+    N = int(np.prod(SHAPE))
+    w = _weights()
+    f0 = inputs.random_state(len(w), N, 31, scale=0.05, weights=w)
+    g = np.random.default_rng(32).uniform(-1e-3, 1e-3, (3, N))
+    scales = np.linspace(1.0, -0.5, 5)
+    o = Oracle(LAT, coll, SHAPE, tau=TAU[coll], plain=True, **opts)
+    fo = f0.copy()
+    for s in scales:
+        fo = o.step(fo, g, s)
+    with L.Lattice(LAT, coll, "f64", SHAPE, PERIODIC, TAU[coll], g_field=g, **opts) as gpu:
+        gpu.set_populations(f0)
+        gpu.step(5, g_scale=scales)
+        got = gpu.populations()
+    rel = np.max(np.abs(got - fo)) / np.max(np.abs(fo))
+    print(f"D3Q39 {coll} {opts}: max |kernel - plain| / max |f| = {rel:.2e}")
+    assert rel <= 1e-14
+
+
+def test_kolmogorov_fp32_shifted_against_fp64_oracle():
+    """Kolmogorov flow (g_x = G sin(2 pi y / 32), 8 x 32 x 3, SMRT) for 2000 steps from
+    rest: the FP32-shifted velocity field equals the FP64 oracle's to 1e-5 (relative L2)
+    and the amplitude approaches G / (nu k^2) with nu = (2/3)(tau - 1/2)."""
+    L = lbm()
+    shape = (8, 32, 3)
+    N = int(np.prod(shape))
+    y = (np.arange(N) // shape[0]) % shape[1]
+    G, tau = 1e-5, 0.8
+    g = np.zeros((3, N))
+    g[0] = G * np.sin(2 * math.pi * y / shape[1])
+    steps = 2000
+    o = Oracle(LAT, "smrt", shape, tau=(tau, 1.0, 1.0))
+    fo = o.run(o.init(1.0, None, g), g, steps)
+    _, uo = o.moments(fo, g)
+    with L.Lattice(LAT, "smrt", "f32s", shape, PERIODIC, (tau, 1.0, 1.0), g_field=g) as gpu:
+        gpu.step(steps)
+        _, u = gpu.moments()
+    e2 = np.linalg.norm(u[0] - uo[0]) / np.linalg.norm(uo[0])
+    assert e2 < 1e-5, e2
+    nu, k = (2.0 / 3.0) * (tau - 0.5), 2 * math.pi / shape[1]
+    s = np.sin(2 * math.pi * y / shape[1])
+    amp = float(u[0] @ s / (s @ s))
+    assert 0.9 < amp / (G / (nu * k * k)) < 1.0

@@ -60,7 +60,7 @@ def test_oracle_under_sanitizers(build, tmp_path):
 
 
 RUNTIME_UNITS = ("lbm_runtime", "lbm_aux", "lbm_batch_runtime", "lbm_nn", "lbm_ws_expansion",
-                 "lbm_d2q9", "lbm_d3q19", "lbm_d3q27")
+                 "lbm_d2q9", "lbm_d3q19", "lbm_d3q27", "lbm_d3q39")
 
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
