@@ -1,16 +1,21 @@
 /*
- * lbm_nn.h -- the learned warm start: a small BF16 network and the kernels that turn
- * its output into an initial lattice state.
+ * lbm_nn.h -- the warm start of the steady forced lattice: the lattice's own steady state
+ * expanded in the forcing amplitude, a small BF16 network that resums that expansion,
+ * and the kernels that set the state.
  *
- * A multilayer perceptron evaluated per grid point maps features of the problem (the
- * relaxation time and the Fourier modes of the acceleration field, see
- * lbm_ws_features) to the steady velocity and density there.  Matrix products run on
- * the gfx950 matrix cores in BF16 with FP32 accumulation (hand-written kernels);
- * master weights, gradients and the Adam moments are FP32.  Hidden layers use the
- * tanh form of GELU, the output layer is linear.  The lattice is then started from
- * the predicted fields (lbm_reset_fields: force-corrected equilibrium of (rho, u), the
- * same state lbm_init builds), and the converged lattice-Boltzmann solution remains the
- * reference for the prediction's error.  The plain start (rest, rho0) stays the fallback.
+ * The start is the sum over orders n = 1..4 of the population waves W_n of the steady
+ * state's expansion about rest (lbm_ws_lattice_waves_ordered), each order scaled by a
+ * factor c_n = 1 + sigma y_n (lbm_ws_scale_orders), where sigma is the expansion's own
+ * ratio and y the output of a multilayer perceptron of problem-level inputs
+ * (lbm_ws_resum_features); the waves are synthesised on the device by lbm_set_waves.
+ * The network's matrix products run on the gfx950 matrix cores in BF16 with FP32
+ * accumulation (hand-written kernels); master weights, gradients and the Adam moments
+ * are FP32; hidden layers use the tanh form of GELU, the output layer is linear.  The
+ * converged lattice-Boltzmann solution stays the reference: the start only shortens the
+ * run to it, and the plain start (rest, rho0) is the fallback.  Earlier stages of the
+ * same pipeline remain available: per-point analytic base fields (lbm_ws_features),
+ * each mode's exact linear response (lbm_ws_lattice_response) and the consistent
+ * restart from (rho, u) fields (lbm_reset_fields).
  *
  * Device arrays (float*, row-major, one row per point) are caller-owned device memory;
  * host arrays are copied during the call.  Work is enqueued on the stream given at
