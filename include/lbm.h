@@ -195,9 +195,9 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init,
  * Small lattices (N <= 2^21 nodes), where launch overhead dominates: when n covers at
  * least two chunks of 64 steps and neither monitor_every nor debug_poison is set, the
  * chunks are replayed from a HIP graph captured once per buffer parity (the factors s(t)
- * are then uploaded to the device and read there, the call synchronising the stream once
- * for that upload); the remainder runs as single launches.  The results are identical
- * to single launches.
+ * are then staged in pinned host memory, uploaded asynchronously and read on the device;
+ * the call waits only for the previous call's upload to have completed); the remainder
+ * runs as single launches.  The results are identical to single launches.
  * Monitors in the step: if monitor_every is K > 0, after every step whose time t is a
  * multiple of K the monitor record of time t is computed on the device (with the
  * residual against time t - 1, whose velocity is recorded one step earlier; K = 1

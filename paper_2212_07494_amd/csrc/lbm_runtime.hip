@@ -163,6 +163,11 @@ struct lbm_ctx {
   double *gs_dev = nullptr;
   size_t gs_cap = 0;
   int64_t *gs_ctr = nullptr;
+  // pinned staging of the factors (the upload is asynchronous) and the event of the last
+  // upload, waited on before the staging buffer is written again
+  double *gs_host = nullptr;
+  size_t gs_host_cap = 0;
+  hipEvent_t gs_ev = nullptr;
   void drop_graphs() {
     for (auto &row : gexec)
       for (auto &e : row) {
@@ -358,6 +363,8 @@ void release(lbm_ctx *c) {
   c->drop_graphs();
   c->dfree(c->gs_dev);
   c->dfree(c->gs_ctr);
+  if (c->gs_host) (void)hipHostFree(c->gs_host);
+  if (c->gs_ev) (void)hipEventDestroy(c->gs_ev);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   c->magic = 0;
   delete c;
@@ -864,8 +871,24 @@ int graph_run(lbm_ctx *c, int64_t n, const double *g_scale) {
       if (rc) return rc;
       c->gs_cap = need;
     }
-    HIP_TRY(hipMemcpyAsync(c->gs_dev, g_scale, need, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));  // the host array is the caller's again
+    // stage the factors in pinned memory and upload them without blocking: the copy is
+    // ordered after the replays of earlier calls that read gs_dev, and the staging buffer
+    // is rewritten only after the previous upload from it has completed
+    if (!c->gs_ev) HIP_TRY(hipEventCreateWithFlags(&c->gs_ev, hipEventDisableTiming));
+    else HIP_TRY(hipEventSynchronize(c->gs_ev));
+    if (need > c->gs_host_cap) {
+      if (c->gs_host) HIP_TRY(hipHostFree(c->gs_host));
+      c->gs_host = nullptr;
+      c->gs_host_cap = 0;
+      if (hipHostMalloc((void **)&c->gs_host, need, hipHostMallocDefault) != hipSuccess) {
+        c->gs_host = nullptr;
+        return fail(LBM_ENOMEM, "pinned staging of %zu bytes of force factors", need);
+      }
+      c->gs_host_cap = need;
+    }
+    std::memcpy(c->gs_host, g_scale, need);
+    HIP_TRY(hipMemcpyAsync(c->gs_dev, c->gs_host, need, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipEventRecord(c->gs_ev, c->stream));
   }
   hipGraphExec_t e = nullptr;
   int rc = chunk_graph(c, scaled, &e);

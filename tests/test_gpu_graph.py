@@ -72,3 +72,26 @@ def test_graph_without_factors_field_force_and_retuning():
         assert exact_mismatch(a.populations(), b.populations()) == 0
         w = np.array([float(x) for x in olat.weights("D3Q19")])
         assert np.isfinite(a.populations()).all() and w.size == 19
+
+
+def test_graph_path_with_factors_does_not_block():
+    """With per-step force factors the graph path stages them in pinned memory and uploads
+    them asynchronously: the call returns while its 20,000 steps (tens of ms) are still
+    running, and a second call right after it (reusing the staging buffer) gives the same
+    result as one call of both halves."""
+    import torch
+    L = lbm()
+    s = np.cos(2 * math.pi * np.arange(40_000) / 1200)
+    stream = torch.cuda.Stream()
+    args = ("D2Q9", "smrt", "f64", (50, 200, 1), (0, 1, 0), (0.8, 1.0, 1.0))
+    with L.Lattice(*args, g=(-1e-4, 0.0, 0.0), stream=stream) as a, \
+            L.Lattice(*args, g=(-1e-4, 0.0, 0.0), stream=stream) as b:
+        a.step(128, s[:128])  # capture the graphs and stage the factors once
+        b.step(128, s[:128])
+        stream.synchronize()
+        a.step(20_000, s[128:20_128])
+        pending = not stream.query()
+        a.step(19_872, s[20_128:])
+        b.step(39_872, s[128:])
+        assert exact_mismatch(a.populations(), b.populations()) == 0
+        assert pending
