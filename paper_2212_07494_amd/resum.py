@@ -22,7 +22,7 @@ coefficients (density and momentum at every wavevector the waves occupy).  The n
 y = (c - 1) / sigma; the parameters are selected by the total steps to steady state on
 validation problems, checked from iteration 0 (the zero output, i.e. the plain
 expansion), so the kept network is never slower there than the start without it.  The
-converged lattice solution remains the judge of the start's error.
+converged lattice solution remains the reference for the start's error.
 
 Inference: waves (library, host), features (library, host), one forward pass (device),
 the scaling (library, host), synthesis on the device (lbm_set_waves).
