@@ -803,7 +803,7 @@ def lbm_ws_lattice_waves(problem, box, order=2, lattice="D3Q27", collision="smrt
     s = ws_problem_struct(problem)
     params, keep = make_params(lattice, collision, "f64", (1, 1, 1),
                                tau=(problem["tau2"], tau3, 1.0), rho0=rho0, **rates)
-    Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}[lattice.upper()]
+    Q = QOF[lattice.upper()]
     nm = int(s.nmodes)
     cap = int(load().lbm_ws_max_waves(nm, int(order)))
     if cap == 0:

@@ -274,6 +274,7 @@ def test_lattice_info_matches_oracle_tables():
 def test_warm_start_expansion_rejects_d3q39():
     from paper_2212_07494_amd import lbm
     prob = dict(tau2=0.8, modes=[dict(k=(1, 0, 0), p=(0, 1, 0), amp=1e-6, phase=0.0)] * 4)
-    with pytest.raises(lbm.LBMError) as ei:
-        lbm.lbm_ws_lattice_response(prob, 32, lattice="D3Q39")
-    assert "covers D2Q9, D3Q19 and D3Q27" in str(ei.value)
+    for call in (lbm.lbm_ws_lattice_response, lbm.lbm_ws_lattice_waves):
+        with pytest.raises(lbm.LBMError) as ei:
+            call(prob, 32, lattice="D3Q39")
+        assert "covers D2Q9, D3Q19 and D3Q27" in str(ei.value)
