@@ -281,11 +281,14 @@ int lbm_save(lbm_ctx *c, const char *path);
 int lbm_load(lbm_ctx *c, const char *path);
 
 /* Launch configuration of the step kernel: block shape bx x by (bx in {64, 128, 256},
- * bx * by <= 256) and variant 0..5: memory access variant % 3 (0 plain loads and
- * stores, 1 non-temporal stores, 2 non-temporal loads and stores); variants 3..5 also
- * let workgroups that cannot bounce back (no solid nodes, away from wall faces) address
- * each population plane through a scalar base and 32-bit offsets.  Results are
- * identical for every configuration; only the speed differs. */
+ * bx * by <= 256) and variant 0..11: memory access variant % 3 (0 plain loads and
+ * stores, 1 non-temporal stores, 2 non-temporal loads and stores); (variant / 3) odd
+ * also lets workgroups that cannot bounce back (no solid nodes, away from wall faces)
+ * address each population plane through a scalar base and 32-bit offsets; variant >= 6
+ * places the blocks XCD-contiguously (each of the chip's 8 XCDs, with its own L2, steps
+ * one contiguous stretch of the lattice, so the lines neighbouring blocks share stay in
+ * one L2) instead of in dispatch order.  Results are identical for every configuration;
+ * only the speed differs. */
 typedef struct {
   int32_t bx, by;
   int32_t variant;

@@ -80,7 +80,6 @@ __device__ __forceinline__ void batch_force(const T *__restrict__ gbuf, const Ba
 // neighbouring tiles share cache lines through their +-1 pulls: so each XCD takes one
 // contiguous part of the tile table (equal counts), which its own workgroups walk in turn.
 // A grid that is not a multiple of kXcds falls back to a plain stride over the table.
-constexpr int kXcds = 8;
 struct TileWalk {
   int t, end, stride;
 };

@@ -48,6 +48,7 @@ struct LaunchDesc {
   int bx, by;        // block shape (bx * by <= 256, bx a multiple of 64)
   int variant;       // memory-access variant of the step kernel (MEM_*)
   int fast_ok;       // 1: blocks that cannot bounce back may take the scalar-base path
+  int xcd;           // 1: XCD-contiguous block placement, 0: dispatch order
   // Force factor from device memory (steps replayed from a captured graph): when gs_dev
   // is set, s(t) = gs_dev[*gs_ctr + gs_j] instead of gscale.
   const double *gs_dev;

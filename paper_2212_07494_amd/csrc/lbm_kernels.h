@@ -25,6 +25,21 @@ namespace lbm {
 
 enum { GK_PROFILE = 0, GK_FIELD = 1 };
 
+// Workgroups are dispatched to the chip's XCDs round-robin (workgroup b on XCD b mod
+// kXcds), and each XCD has its own L2.
+constexpr int kXcds = 8;
+
+// XCD-contiguous placement of a grid's nb blocks: block b (in dispatch order) takes the
+// logical block start(XCD) + b / kXcds, so each XCD works through one contiguous stretch
+// of the lattice (whole row segments, rows and layers), and the lines that neighbouring
+// blocks share -- the x-shifted pulls across a block's edges, the rows and layers beside
+// it -- are fetched into one L2 rather than two.  The XCDs take nb / kXcds blocks each,
+// the first nb mod kXcds one more: a bijection of [0, nb) for any nb.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 struct Geom {
   int nx, ny, nz, N;
   int64_t ps;  // plane stride: elements from one population plane to the next (>= nx ny)
@@ -186,6 +201,7 @@ struct StepArgs {
   T c3;      // RMRT: h3; SMRT: (q_bulk - q2)/D (0 = one rate at order 2)
   T c4;      // SMRT: (q_31 - q3)/2 (0 = one rate at order 3)
   int fast_ok;  // 1: fast_block workgroups take the scalar-base path
+  int xcd;      // 1: XCD-contiguous block placement (xcd_block), 0: dispatch order
 };
 
 // One node of the fused step: pull the populations (periodic wrap or halfway
@@ -233,16 +249,26 @@ __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restri
 
 template <class L, int COLL, class S, class T, int GK, int MEM>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs<T> a) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
+  // the block's place in the lattice (uniform across the workgroup)
+  int bxi = blockIdx.x, byi = blockIdx.y, bzi = blockIdx.z;
+  if (a.xcd) {
+    const int64_t nxy = (int64_t)gridDim.x * gridDim.y;
+    const int64_t b = blockIdx.x + (int64_t)gridDim.x * blockIdx.y + nxy * blockIdx.z;
+    const int64_t t = xcd_block(b, nxy * gridDim.z);
+    bzi = (int)(t / nxy);
+    byi = (int)((t % nxy) / gridDim.x);
+    bxi = (int)(t % gridDim.x);
+  }
+  const int x = bxi * blockDim.x + threadIdx.x;
+  const int y = byi * blockDim.y + threadIdx.y;
+  const int z = bzi;
   if (x >= a.geo.nx || y >= a.geo.ny) return;
   const int node = (z * a.geo.ny + y) * a.geo.nx + x;
   const uint32_t sm = node_mask(a.geo, node);
   if (sm & SOLID_NODE) return;  // no fluid here: nothing pulls from its slots
   T g[3];
   load_force<T, GK>(a.force, x, y, z, node, a.geo.N, L::D, g);
-  const int x0 = blockIdx.x * blockDim.x, y0 = blockIdx.y * blockDim.y;
+  const int x0 = bxi * blockDim.x, y0 = byi * blockDim.y;
   const bool fast = a.fast_ok && fast_block<S>(a.geo, x0, x0 + (int)blockDim.x - 1, y0,
                                                y0 + (int)blockDim.y - 1, z);
   step_node<L, COLL, S, T, MEM>(static_cast<const S *>(a.fin), static_cast<S *>(a.fout), a.geo,

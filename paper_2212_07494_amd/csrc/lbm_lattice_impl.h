@@ -36,6 +36,7 @@ inline StepArgs<T> make_args(const LaunchDesc &d) {
   a.c3 = T(d.c3);
   a.c4 = T(d.c4);
   a.fast_ok = d.fast_ok;
+  a.xcd = d.xcd;
   return a;
 }
 

@@ -66,8 +66,9 @@ uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
   return h;
 }
 // Memory-access variants of the step (plain, non-temporal stores, non-temporal loads and
-// stores); a tuning variant v selects v % kMemVariants and, for v >= kMemVariants, the
-// scalar-base addressing path where no bounce-back can occur.
+// stores); a tuning variant v selects v % kMemVariants, for (v / kMemVariants) odd the
+// scalar-base addressing path where no bounce-back can occur, and for v >= 2 kMemVariants
+// the XCD-contiguous placement of the blocks.
 constexpr int kMemVariants = 3;
 constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
 size_t arith_bytes(int s) { return s == LBM_F64 ? 8 : 4; }
@@ -248,7 +249,8 @@ struct lbm_ctx {
     d.bx = bx;
     d.by = by;
     d.variant = variant % kMemVariants;
-    d.fast_ok = variant / kMemVariants;
+    d.fast_ok = (variant / kMemVariants) % 2;
+    d.xcd = variant / (2 * kMemVariants);
     return d;
   }
 };
@@ -1314,7 +1316,7 @@ int lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t reps, int32
 }
 
 namespace {
-constexpr int kVariants = 2 * kMemVariants;  // memory access x addressing path
+constexpr int kVariants = 4 * kMemVariants;  // memory access x addressing x placement
 bool tuning_ok(const lbm_tuning *t) {
   return t && (t->bx == 64 || t->bx == 128 || t->bx == 256) && t->by >= 1 &&
          t->bx * t->by <= 256 && t->variant >= 0 && t->variant < kVariants;

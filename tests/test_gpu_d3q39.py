@@ -110,7 +110,7 @@ def test_all_launch_configurations(storage):
             for by in (1, 2, 4):
                 if bx * by > 256:
                     continue
-                for v in range(6):
+                for v in range(12):
                     L.lbm_set_tuning(gpu.ctx, bx, by, v)
                     gpu.set_populations(f0)
                     gpu.step(3)

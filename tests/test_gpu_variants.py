@@ -1,6 +1,6 @@
 """Every launch configuration of the step (block shapes x memory variants x addressing
-paths) gives
-bit-identical results, equal to the oracle's: ragged rows, odd row lengths and x/y/z
+paths x block placements) gives bit-identical results, equal to the oracle's: ragged
+rows, odd row lengths, block counts that are not multiples of the XCD count and x/y/z
 walls are covered."""
 import numpy as np
 import pytest
@@ -47,13 +47,13 @@ def test_all_launch_configurations(lat, coll, storage):
                 for by in (1, 2, 4):
                     if bx * by > 256:
                         continue
-                    for v in range(6):
+                    for v in range(12):
                         L.lbm_set_tuning(gpu.ctx, bx, by, v)
                         gpu.set_populations(f0)
                         gpu.step(3)
                         bad = exact_mismatch(gpu.populations(), want)
                         assert bad == 0, (shape, walls, bx, by, v, bad)
             with pytest.raises(L.LBMError):
-                L.lbm_set_tuning(gpu.ctx, 64, 1, 6)
+                L.lbm_set_tuning(gpu.ctx, 64, 1, 12)
             with pytest.raises(L.LBMError):
                 L.lbm_set_tuning(gpu.ctx, 96, 1, 0)
