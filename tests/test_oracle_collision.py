@@ -223,6 +223,29 @@ def test_bgk_post_collision_moments(L):
 
 
 @pytest.mark.parametrize("L", lat.ALL_LATTICES)
+@pytest.mark.parametrize("coll", ["bgk", "smrt", "rmrt"])
+@pytest.mark.parametrize("plain", [False, True])
+def test_shifted_storage_is_a_change_of_variables(L, coll, plain):
+    """Storing d_i = f_i - w_i s is a change of variables, not a different scheme: since
+    sum_i w_i = 1 and sum_i w_i H_m(e_i) = 0 for m != 0, the deviations carry every
+    moment but the mass, so the collision of d with shift s is the collision of f,
+    less w_i s (to round-off), for any s, force and rates."""
+    rng = np.random.default_rng(41)
+    w = np.array([float(x) for x in lat.weights(L)])
+    D = lat.dim(L)
+    tau = (0.63, 0.63 if coll == "bgk" else 0.91, 1.0)
+    for s in (1.0, 0.97, 2.5):
+        f = w * (s + 0.05 * rng.uniform(-1, 1, w.size))
+        g = np.zeros(3)
+        g[:D] = rng.uniform(-1e-3, 1e-3, D)
+        o0 = Oracle(L, coll, (1, 1, 1), tau=tau, plain=plain)
+        os_ = Oracle(L, coll, (1, 1, 1), tau=tau, shift=s, plain=plain)
+        want = o0.collide_node(f, g) - w * s
+        got = os_.collide_node(f - w * s, g)
+        assert np.max(np.abs(got - want)) <= 1e-14 * s, (s, np.max(np.abs(got - want)))
+
+
+@pytest.mark.parametrize("L", lat.ALL_LATTICES)
 def test_smrt_equal_rates_one_is_half_force(L):
     """SMRT with omega_2 = omega_3 = 1: every non-equilibrium moment is replaced by half
     the raw force moment, a*^(n) = rho u^n + a_F^(n)/2 for n = 1..4 (appendix, theta = 1)."""
