@@ -109,7 +109,45 @@ def cpu_baseline(w, steps: int, steps_one_thread: int = 1):
         rec["one_thread"] = {"value": w.N * steps_one_thread / dt1 / 1e6, "unit": "MLUPS",
                              "cores": 1, "sample": f"{steps_one_thread} step(s) of the same "
                                                    f"workload ({dt1:.1f} s)"}
+    rec["other_workloads"] = cpu_other_workloads(cores)
     return rec
+
+
+def cpu_other_workloads(cores: int):
+    """The same oracle on short windows of the two other single-domain workloads: the
+    1024^2 D2Q9 SMRT Kolmogorov box and the 128^3 D3Q27 SMRT box with four Fourier
+    forcing modes, on `cores` threads and on one.  The oracle's threads split the z
+    axis, so the 2-D lattice runs on one thread either way."""
+    import oracle
+    from oracle import Oracle
+    from paper_2212_07494_amd import inputs
+    kol = inputs.kolmogorov_box(L=1024)
+    p = inputs.warmstart_problem(2022, box=128)
+    box = (128, 128, 128)
+    g5 = inputs.fourier_force(box, p["modes"])
+    cases = [("D2Q9 SMRT 1024^2 Kolmogorov, FP64",
+              Oracle(kol.lattice, kol.collision, kol.shape, walls=kol.walls, tau=kol.tau),
+              (kol.rho, kol.u, kol.g), kol.g, kol.N, 4, 1),
+             ("D3Q27 SMRT 128^3, 4 Fourier forcing modes, FP64",
+              Oracle("D3Q27", "smrt", box, tau=(p["tau2"], 1.0, 1.0)),
+              (1.0, None, g5), g5, 128 ** 3, 4, 1)]
+    out = []
+    for name, o, init, g, n, steps, steps1 in cases:
+        f0 = o.init(*init)
+        rates = {}
+        for threads, k in ((cores, steps), (1, steps1)):
+            oracle.set_threads(threads)
+            t0 = time.perf_counter()
+            o.run(f0, g, k)
+            dt = time.perf_counter() - t0
+            rates[threads] = (n * k / dt / 1e6, k, dt)
+        oracle.set_threads(cores)
+        (v, k, dt), (v1, k1, dt1) = rates[cores], rates[1]
+        out.append({"workload": name, "value": round(v, 3), "unit": "MLUPS", "cores": cores,
+                    "one_thread": round(v1, 3),
+                    "sample": f"{k} steps on {cores} threads ({dt:.1f} s), {k1} on one "
+                              f"({dt1:.1f} s)"})
+    return out
 
 
 def time_to_steady(torch, L, nprob, box=128, seed=2022, tol=1e-8, check_every=20,
