@@ -333,7 +333,9 @@ def main():
             "launch": {"block": [tuning[0], tuning[1]],
                        "memory_variant": ["plain", "nt-store", "nt-load+store"][tuning[2] % 3],
                        "addressing": "scalar-base" if (tuning[2] // 3) % 2 else "general",
-                       "placement": "xcd-contiguous" if tuning[2] >= 6 else "dispatch order"},
+                       "placement": ("xcd-contiguous" if tuning[2] % 12 >= 6
+                                     else "dispatch order"),
+                       "waves_per_simd_cap": [None, 5, 4, 3, 2][tuning[2] // 12]},
             "frac_of_copy": None if copy_gbps is None else round(achieved / copy_gbps, 4)}
     dtype = {"f64": "f64", "f32": "f32", "f32s": "f32", "f16s": "f32"}[args.storage]
     rec = {

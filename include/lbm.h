@@ -281,14 +281,17 @@ int lbm_save(lbm_ctx *c, const char *path);
 int lbm_load(lbm_ctx *c, const char *path);
 
 /* Launch configuration of the step kernel: block shape bx x by (bx in {64, 128, 256},
- * bx * by <= 256) and variant 0..11: memory access variant % 3 (0 plain loads and
- * stores, 1 non-temporal stores, 2 non-temporal loads and stores); (variant / 3) odd
- * also lets workgroups that cannot bounce back (no solid nodes, away from wall faces)
- * address each population plane through a scalar base and 32-bit offsets; variant >= 6
- * places the blocks XCD-contiguously (each of the chip's 8 XCDs, with its own L2, steps
- * one contiguous stretch of the lattice, so the lines neighbouring blocks share stay in
- * one L2) instead of in dispatch order.  Results are identical for every configuration;
- * only the speed differs. */
+ * bx * by <= 256) and variant 0..59, whose base b = variant % 12 selects the memory
+ * access b % 3 (0 plain loads and stores, 1 non-temporal stores, 2 non-temporal loads and
+ * stores); (b / 3) odd also lets workgroups that cannot bounce back (no solid nodes, away
+ * from wall faces) address each population plane through a scalar base and 32-bit
+ * offsets; b >= 6 places the blocks XCD-contiguously (each of the chip's 8 XCDs, with its
+ * own L2, steps one contiguous stretch of the lattice, so the lines neighbouring blocks
+ * share stay in one L2) instead of in dispatch order.  variant / 12 = 1, 2, 3, 4 holds the
+ * step's workgroups to at most 5, 4, 3, 2 waves per SIMD (each reserves LDS it does not
+ * use, so fewer fit on a CU; fewer concurrent streams of populations can use HBM better);
+ * 0 leaves as many as the kernel's registers allow, as does a cap the block shape cannot
+ * express.  Results are identical for every configuration; only the speed differs. */
 typedef struct {
   int32_t bx, by;
   int32_t variant;
@@ -297,8 +300,10 @@ typedef struct {
 int lbm_set_tuning(lbm_ctx *c, const lbm_tuning *t);
 int lbm_get_tuning(const lbm_ctx *c, lbm_tuning *t);
 
-/* Time every launch configuration for `steps` steps (>= 1) and keep the fastest.  The
- * state is saved before and restored after, so the simulation is unchanged.  best and
+/* Time every block shape with the variants 0..11 for `steps` steps (>= 1), then the
+ * fastest of those with each wave cap (variant + 12 k, k = 1..4), and keep the fastest
+ * of all.  The state is saved before and restored after, so the simulation is
+ * unchanged.  best and
  * best_ms (time per step of the winner) may be NULL.  Synchronises the stream and
  * temporarily needs one extra population buffer of device memory. */
 int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_tuning *best, double *best_ms);

@@ -49,6 +49,10 @@ struct LaunchDesc {
   int variant;       // memory-access variant of the step kernel (MEM_*)
   int fast_ok;       // 1: blocks that cannot bounce back may take the scalar-base path
   int xcd;           // 1: XCD-contiguous block placement, 0: dispatch order
+  // Dynamic LDS a workgroup of the step kernel reserves and never touches (0: none): it
+  // caps the workgroups resident on a CU, and so the waves per SIMD, below what the
+  // kernel's registers allow.
+  unsigned lds_pad;
   // Force factor from device memory (steps replayed from a captured graph): when gs_dev
   // is set, s(t) = gs_dev[*gs_ctr + gs_j] instead of gscale.
   const double *gs_dev;

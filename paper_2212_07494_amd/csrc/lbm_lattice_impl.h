@@ -68,8 +68,8 @@ template <class L>
 struct Ops {
   template <int COLL, class S, class T, int GK, int MEM>
   static hipError_t step_m(const LaunchDesc &d, hipStream_t s) {
-    hipLaunchKernelGGL((step_kernel<L, COLL, S, T, GK, MEM>), grid_of(d), dim3(d.bx, d.by), 0,
-                       s, make_args<T>(d));
+    hipLaunchKernelGGL((step_kernel<L, COLL, S, T, GK, MEM>), grid_of(d), dim3(d.bx, d.by),
+                       d.lds_pad, s, make_args<T>(d));
     return hipGetLastError();
   }
   template <int COLL, class S, class T, int GK>

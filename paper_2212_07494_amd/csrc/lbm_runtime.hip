@@ -3,6 +3,7 @@
 // The declarations and their contracts are in include/lbm.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -66,10 +67,33 @@ uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
   return h;
 }
 // Memory-access variants of the step (plain, non-temporal stores, non-temporal loads and
-// stores); a tuning variant v selects v % kMemVariants, for (v / kMemVariants) odd the
-// scalar-base addressing path where no bounce-back can occur, and for v >= 2 kMemVariants
-// the XCD-contiguous placement of the blocks.
+// stores); a tuning variant v has the base b = v % kBaseVariants, which selects
+// b % kMemVariants, for (b / kMemVariants) odd the scalar-base addressing path where no
+// bounce-back can occur, and for b >= 2 kMemVariants the XCD-contiguous placement of the
+// blocks; v / kBaseVariants indexes kWaveCaps, the waves per SIMD the step's workgroups
+// are held to (0: as many as the registers allow).
 constexpr int kMemVariants = 3;
+constexpr int kBaseVariants = 4 * kMemVariants;
+constexpr int kWaveCaps[] = {0, 5, 4, 3, 2};
+constexpr int kNumCaps = sizeof(kWaveCaps) / sizeof(kWaveCaps[0]);
+
+// Dynamic LDS bytes that leave room for at most (4 SIMDs x cap) / (waves of a block)
+// blocks of bx x by threads on a CU with lds_cu bytes of LDS, at most lds_block of them
+// to one block: a size strictly between lds_cu / (n + 1) and lds_cu / n, taken at the
+// middle of that interval on a 256-byte grid so that allocation granularity cannot move
+// it out; 0 where no cap is asked for or none is possible.
+unsigned lds_for_cap(int cap, int bx, int by, int lds_cu, int lds_block) {
+  if (cap <= 0 || lds_cu <= 0 || lds_block <= 0) return 0;
+  const int wpb = (bx * by + 63) / 64;
+  const int n = (4 * cap) / wpb;
+  if (n < 1) return 0;
+  const long lo = (long)lds_cu / (n + 1) + 1;
+  const long hi = std::min<long>((long)lds_cu / n, lds_block);
+  if (lo > hi) return 0;
+  long pad = ((lo + hi) / 2) & ~255L;
+  if (pad < lo) pad = hi;
+  return (unsigned)pad;
+}
 constexpr uint64_t kFnvBasis = 0xcbf29ce484222325ull;
 size_t arith_bytes(int s) { return s == LBM_F64 ? 8 : 4; }
 bool shifted(int s) { return s == LBM_F32_SHIFTED || s == LBM_F16_SHIFTED; }
@@ -183,6 +207,7 @@ struct lbm_ctx {
   double last_scale = 1.0;
   double c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, shift = 0;
   int bx = 64, by = 4, variant = 0;
+  int lds_cu = 0, lds_block = 0;  // LDS bytes of a CU and the most one workgroup may take
   lbm_monitors mon{};
 
   int dalloc(void **ptr, size_t n) {
@@ -248,9 +273,11 @@ struct lbm_ctx {
     d.c4 = c4;
     d.bx = bx;
     d.by = by;
-    d.variant = variant % kMemVariants;
-    d.fast_ok = (variant / kMemVariants) % 2;
-    d.xcd = variant / (2 * kMemVariants);
+    const int base = variant % kBaseVariants;
+    d.variant = base % kMemVariants;
+    d.fast_ok = (base / kMemVariants) % 2;
+    d.xcd = base / (2 * kMemVariants);
+    d.lds_pad = lds_for_cap(kWaveCaps[variant / kBaseVariants], bx, by, lds_cu, lds_block);
     return d;
   }
 };
@@ -660,6 +687,13 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
   lbm_ctx *c = new (std::nothrow) lbm_ctx();
   if (!c) return fail(LBM_ENOMEM, "host allocation of the context failed");
   c->device = device;
+  if (hipDeviceGetAttribute(&c->lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                            device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+          hipSuccess) {
+    c->lds_cu = 0;  // no occupancy caps
+    c->lds_block = 0;
+  }
   c->p = *p;
   c->p.g_data = nullptr;
   if (p->allocator) c->alloc = *p->allocator;
@@ -1316,7 +1350,8 @@ int lbm_copy_probe(const void *src, void *dst, size_t bytes, int32_t reps, int32
 }
 
 namespace {
-constexpr int kVariants = 4 * kMemVariants;  // memory access x addressing x placement
+// memory access x addressing x placement x wave cap
+constexpr int kVariants = kBaseVariants * kNumCaps;
 bool tuning_ok(const lbm_tuning *t) {
   return t && (t->bx == 64 || t->bx == 128 || t->bx == 256) && t->by >= 1 &&
          t->bx * t->by <= 256 && t->variant >= 0 && t->variant < kVariants;
@@ -1381,42 +1416,51 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_tuning *best, double *best_ms) {
   HIP_TRY(hipEventCreate(&e1));
   const int cur0 = c->cur;
   int status = LBM_OK;
+  // one timed trial of a launch configuration; false on a device error (status set)
+  auto trial = [&](int bx, int by, int v) -> bool {
+    c->bx = bx;
+    c->by = by;
+    c->variant = v;
+    // warm-up launch, then the timed ones
+    lbm::LaunchDesc d = c->desc(1.0);
+    hipError_t e = c->ops->step(d, c->stream);
+    c->cur ^= 1;
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int s = 0; s < steps && e == hipSuccess; ++s) {
+      d = c->desc(1.0);
+      e = c->ops->step(d, c->stream);
+      c->cur ^= 1;
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      status = fail(LBM_EDEVICE, "autotune trial failed: %s", hipGetErrorString(e));
+      return false;
+    }
+    ms /= steps;
+    if (win_ms < 0 || ms < win_ms) {
+      win_ms = ms;
+      win = {bx, by, v};
+    }
+    return true;
+  };
+  // block shapes x base variants, every workgroup resident that the registers allow ...
   for (int bx : {64, 128, 256}) {
     if (bx > 64 && bx >= 2 * c->p.nx) continue;  // mostly idle lanes
     for (int by : {1, 2, 4}) {
       if (bx * by > 256) continue;
-      for (int v = 0; v < kVariants; ++v) {
-        c->bx = bx;
-        c->by = by;
-        c->variant = v;
-        // warm-up launch, then the timed ones
-        lbm::LaunchDesc d = c->desc(1.0);
-        hipError_t e = c->ops->step(d, c->stream);
-        c->cur ^= 1;
-        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-        for (int s = 0; s < steps && e == hipSuccess; ++s) {
-          d = c->desc(1.0);
-          e = c->ops->step(d, c->stream);
-          c->cur ^= 1;
-        }
-        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-          status = fail(LBM_EDEVICE, "autotune trial failed: %s", hipGetErrorString(e));
-          break;
-        }
-        ms /= steps;
-        if (win_ms < 0 || ms < win_ms) {
-          win_ms = ms;
-          win = {bx, by, v};
-        }
-      }
+      for (int v = 0; v < kBaseVariants && !status; ++v) trial(bx, by, v);
       if (status) break;
     }
     if (status) break;
   }
+  // ... then the winner held to fewer waves per SIMD
+  const lbm_tuning stage1 = win;
+  for (int k = 1; k < kNumCaps && !status; ++k)
+    if (lds_for_cap(kWaveCaps[k], stage1.bx, stage1.by, c->lds_cu, c->lds_block))
+      trial(stage1.bx, stage1.by, stage1.variant % kBaseVariants + k * kBaseVariants);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // restore the state into the buffer it came from

@@ -110,7 +110,7 @@ def test_all_launch_configurations(storage):
             for by in (1, 2, 4):
                 if bx * by > 256:
                     continue
-                for v in range(12):
+                for v in list(range(12)) + [b + 12 * k for k in range(1, 5) for b in (2, 7)]:
                     L.lbm_set_tuning(gpu.ctx, bx, by, v)
                     gpu.set_populations(f0)
                     gpu.step(3)

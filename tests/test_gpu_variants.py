@@ -1,7 +1,7 @@
 """Every launch configuration of the step (block shapes x memory variants x addressing
-paths x block placements) gives bit-identical results, equal to the oracle's: ragged
-rows, odd row lengths, block counts that are not multiples of the XCD count and x/y/z
-walls are covered."""
+paths x block placements, and wave caps on a spread of those) gives bit-identical
+results, equal to the oracle's: ragged rows, odd row lengths, block counts that are not
+multiples of the XCD count and x/y/z walls are covered."""
 import numpy as np
 import pytest
 
@@ -18,6 +18,9 @@ CASES = {
     "D3Q27": [((70, 4, 3), (0, 0, 0)), ((70, 4, 3), (1, 0, 1)), ((65, 3, 3), (0, 1, 0))],
 }
 TAU = {"bgk": (0.61, 0.61, 1.0), "smrt": (0.57, 0.91, 1.0), "rmrt": (0.57, 0.91, 1.0)}
+# the 12 base variants, then each wave cap (variant // 12 = 1..4) on a spread of bases
+VARIANTS = list(range(12)) + [b + 12 * k for k in range(1, 5) for b in (0, 5, 8)]
+N_VARIANTS = 60
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32s", "f16s"])
@@ -47,13 +50,13 @@ def test_all_launch_configurations(lat, coll, storage):
                 for by in (1, 2, 4):
                     if bx * by > 256:
                         continue
-                    for v in range(12):
+                    for v in VARIANTS:
                         L.lbm_set_tuning(gpu.ctx, bx, by, v)
                         gpu.set_populations(f0)
                         gpu.step(3)
                         bad = exact_mismatch(gpu.populations(), want)
                         assert bad == 0, (shape, walls, bx, by, v, bad)
             with pytest.raises(L.LBMError):
-                L.lbm_set_tuning(gpu.ctx, 64, 1, 12)
+                L.lbm_set_tuning(gpu.ctx, 64, 1, N_VARIANTS)
             with pytest.raises(L.LBMError):
                 L.lbm_set_tuning(gpu.ctx, 96, 1, 0)
