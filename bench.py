@@ -47,9 +47,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_hash: str, storage: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel sources (else None)."""
+MEMORY_VARIANTS = ["plain", "nt-store", "nt-load+store"]
+
+
+def measured_traffic(kernel_hash: str, storage: str, memory_variant: str):
+    """HBM bytes per launch of the step with the given memory-access variant, from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel sources
+    and holds that variant (else None)."""
     path = os.path.join(ROOT, "profiles", f"step_d3q19_smrt_{storage}_256_counters.json")
     if not os.path.exists(path):
         return None
@@ -57,7 +61,7 @@ def measured_traffic(kernel_hash: str, storage: str):
         d = json.load(fh)
     if d.get("kernel_source_hash") != kernel_hash:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_by_memory_variant", {}).get(memory_variant)
 
 
 def copy_roofline(torch, L, stream, nbytes=2 << 30, reps=10):
@@ -323,7 +327,8 @@ def main():
 
     copy_gbps, copy_cfg = (None, None) if args.no_copy else copy_roofline(torch, L, stream)
     khash = kernel_source_hash()
-    traffic = measured_traffic(khash, args.storage) if args.n == 256 else None
+    mem = MEMORY_VARIANTS[tuning[2] % 3]
+    traffic = measured_traffic(khash, args.storage, mem) if args.n == 256 else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
@@ -331,7 +336,7 @@ def main():
             "measured_copy_GBps": None if copy_gbps is None else round(copy_gbps, 1),
             "copy_probe": copy_cfg,
             "launch": {"block": [tuning[0], tuning[1]],
-                       "memory_variant": ["plain", "nt-store", "nt-load+store"][tuning[2] % 3],
+                       "memory_variant": mem,
                        "addressing": "scalar-base" if (tuning[2] // 3) % 2 else "general",
                        "placement": ("xcd-contiguous" if tuning[2] % 12 >= 6
                                      else "dispatch order"),
