@@ -54,7 +54,9 @@ def test_womersley_graph_replays_equal_single_launches(storage):
 
 def test_graph_without_factors_field_force_and_retuning():
     """D3Q19 SMRT FP32-shifted 40 x 20 x 12 with a y-walled channel and a full force field,
-    s(t) = 1: 256 steps (four replays), a different launch configuration, 200 more."""
+    s(t) = 1: 256 steps (four replays), a different launch configuration, 200 more, then a
+    launch held to 4 waves per SIMD (its workgroups reserve LDS inside the graph), 200
+    more."""
     L = lbm()
     shape = (40, 20, 12)
     rng = np.random.default_rng(3)
@@ -67,6 +69,10 @@ def test_graph_without_factors_field_force_and_retuning():
         eager(b, 256, piece=64)
         assert exact_mismatch(a.populations(), b.populations()) == 0
         a.tune(64, 2, 4)
+        a.step(200)
+        eager(b, 200, piece=64)
+        assert exact_mismatch(a.populations(), b.populations()) == 0
+        a.tune(128, 2, 26)
         a.step(200)
         eager(b, 200, piece=64)
         assert exact_mismatch(a.populations(), b.populations()) == 0

@@ -276,14 +276,14 @@ def test_kolmogorov_full_size_sampled(storage):
         assert _sampled_step_parity(gpu, o, "D2Q9", w.shape, w.walls, g, nodes, storage) == 0
 
 
-@pytest.mark.parametrize("variant", [1, 5, 14])
+@pytest.mark.parametrize("variant", [1, 5, 13, 14])
 @pytest.mark.parametrize("storage", ["f64", "f32s", "f16s"])
 def test_taylor_green_256_sampled(storage, variant):
     """D3Q19 SMRT 256^3 Taylor-Green + sin(z) force (the benchmark workload), at the
-    launch configuration the tuner picks for it (256 x 1, non-temporal loads and stores,
-    general addressing, at most 5 waves per SIMD: variant 14), with non-temporal stores
-    only, and with the scalar-base addressing path: one step matches the oracle's
-    collision at sampled nodes exactly."""
+    launch configurations the tuner picks for it (256 x 1, general addressing, at most 5
+    waves per SIMD, with non-temporal stores or non-temporal loads and stores: variants 13
+    and 14), without the wave cap, and with the scalar-base addressing path: one step
+    matches the oracle's collision at sampled nodes exactly."""
     L = lbm()
     w = inputs.taylor_green_3d(n=256)
     o = oracle_for("D3Q19", "smrt", storage, w.shape, w.walls, w.tau)
