@@ -344,3 +344,42 @@ def test_monitors_match_oracle_sums():
     res = np.sqrt(((uu[:2] - u9[:2]) ** 2).sum() / (uu[:2] ** 2).sum())
     assert abs(m.resid - res) <= 1e-10 * res
     assert m.nonfinite == 0
+
+
+def test_buffers_beyond_4gib_sampled():
+    """D3Q19 SMRT 512^3 in FP32-shifted storage: 10.2 GB a population buffer, so slot
+    offsets pass 2^32 bytes (64-bit addressing) while each plane stays small enough for
+    the scalar-base path.  A smooth field varying along every axis, a z-profile force;
+    after two steps, one more step matches the oracle's collision at sampled nodes (the
+    first and last nodes of the lattice among them) exactly, at the tuned launch and
+    with the scalar-base addressing path."""
+    L = lbm()
+    n = 512
+    shape = (n, n, n)
+    k = 2 * np.pi / n
+    c = np.arange(n)
+    sx, cx = np.sin(k * c), np.cos(k * c)
+    u = np.empty((3, n, n, n))  # (component, z, y, x)
+    u[0] = 0.02 * sx[None, None, :] * cx[None, :, None] * cx[:, None, None]
+    u[1] = -0.02 * cx[None, None, :] * np.sin(2 * k * c)[None, :, None] * cx[:, None, None]
+    u[2] = 0.01 * np.cos(3 * k * c)[None, None, :] * sx[:, None, None]
+    u = u.reshape(3, -1)
+    rho = (1.0 + 1e-3 * cx[None, :, None] * np.sin(3 * k * c)[:, None, None]
+           * np.ones(n)[None, None, :]).reshape(-1)
+    table = np.zeros((3, n))
+    table[0] = 1e-6 * np.sin(k * c)
+    table[1] = 5e-7 * np.cos(2 * k * c)
+    tau = (0.56, 1.0, 1.0)
+    o = oracle_for("D3Q19", "smrt", "f32s", shape, (0, 0, 0), tau)
+    with L.Lattice("D3Q19", "smrt", "f32s", shape, (0, 0, 0), tau, rho=rho, u=u,
+                   g_profile=(2, table)) as gpu:
+        del rho, u
+        gpu.tune(256, 1, 13)
+        gpu.step(2)
+        nodes = _sample_nodes(shape, 300, 7)
+        z = nodes // (n * n)
+        g = np.zeros((3, n ** 3), o.dtype)  # only the sampled nodes' entries are read
+        g[:, nodes] = table[:, z].astype(o.dtype)
+        assert _sampled_step_parity(gpu, o, "D3Q19", shape, (0, 0, 0), g, nodes, "f32s") == 0
+        gpu.tune(256, 1, 5)
+        assert _sampled_step_parity(gpu, o, "D3Q19", shape, (0, 0, 0), g, nodes, "f32s") == 0
