@@ -125,11 +125,14 @@ typedef struct {
   const lbm_allocator *allocator; /* NULL: hipMalloc / hipFree */
   /* Force content of the SMRT collision (Sec. II.C): 1 (or 0) = first order only, the
    * paper's choice when the non-equilibrium parts are neglected (d_F^(n) = 0, n >= 2);
-   * 3 = also d_F^(3) = 3 g d^(2) (eq:Frc at theta = 1) with d^(2) the non-equilibrium
-   * central second moment of f = (1 - 1/(2 tau[2])) times that of the stored f-bar,
-   * added to the relaxed third-order central moments as (1 - 1/(2 tau[3])) d_F^(3),
-   * on the lattice's third-order index set.  The fourth-order force term stays out
-   * (order 4 is trimmed).  BGK: must be 0 or 1. */
+   * 3 = also d_F^(3) = 3 g d^(2) (eq:Frc at theta = 1), with d^(2) the non-equilibrium
+   * central second moment of f itself, the mean of the moments before and after the
+   * collision (eq:newf, eq:evolution; the trace at tau_bulk where that is set), added to
+   * the relaxed third-order central moments as (1 - 1/(2 tau[3])) d_F^(3), on the
+   * lattice's third-order index set; 4 = also the fourth-order term of eq:Frc,
+   * d_F^(4) = 4 g d^(3) with d^(3) likewise the mean of order 3, entering the trimmed
+   * order 4 with 1 - omega_4/2 = 1/2 (not on D3Q39, whose fourth-order moments are not
+   * independent on its 39 velocities, and not with max_order 6).  BGK and RMRT: 0 or 1. */
   int32_t force_order;
   /* Solid nodes: host array of N bytes (nonzero = solid), copied at init; NULL = none.
    * A fluid node whose pull source x - e_i is solid takes halfway bounce-back from its
@@ -146,7 +149,7 @@ typedef struct {
    * eq:domg, the vector sum_b D_abb of the central third moment; the lattices carry it as
    * D_abb + D_acc (b, c the other two axes; D_aaa is not carried).  The traceless rest
    * (the differences D_abb - D_acc and D_xyz) keeps tau[3].  0 = tau[3].  Not with
-   * force_order 3. */
+   * force_order 3 or 4. */
   double tau_31;
   /* Highest Hermite order carried after the collision.  0 or 4: raw moments above order
    * 4 are set to zero (the reconstruction sums to order 4, as the paper does).  6 (SMRT on

@@ -37,7 +37,7 @@ def _params_struct(real_t):
                     ("shift", real_t), ("omega", real_t), ("hforce", real_t),
                     ("q2", real_t), ("q3", real_t), ("fq3", real_t), ("h2", real_t),
                     ("h3", real_t), ("dqb", real_t), ("dq31", real_t), ("max_order", C.c_int32),
-                    ("solid", C.c_void_p)]
+                    ("fo4", C.c_int32), ("solid", C.c_void_p)]
     return _Params
 
 
@@ -97,7 +97,8 @@ class Oracle:
     plain: use the PLAIN build (FP64 only): the textbook operation order (plain sums over
     all populations, plain inverse-transform rows, no fused multiply-add) instead of the
     operation-order twin the library is compared with bit for bit;
-    force_order: 1, or 3 for SMRT's third-order force content; solid: N flags of solid
+    force_order: 1, or 3 for SMRT's third-order force content, or 4 for the third- and
+    fourth-order content (not on D3Q39, not with max_order 6); solid: N flags of solid
     nodes (halfway bounce-back against them; not stepped; zero moments) or None;
     tau_bulk: SMRT rate of the trace of order 2 (0 = tau2); tau_31: SMRT rate of the trace
     of order 3 on D3Q19/D3Q27 (0 = tau3); max_order: 4 (raw moments above order 4
@@ -134,22 +135,26 @@ class Oracle:
         if lattice in lat.HIGH_ORDER and (any(walls) or solid is not None or tau_31):
             raise ValueError(f"{lattice} takes periodic boxes without solid nodes or tau_31")
         omega = 1.0 / tau2
-        if force_order not in (1, 3) or (force_order == 3 and self.collision != "smrt"):
-            raise ValueError("force_order is 1, or 3 with SMRT")
-        fq3 = (1.0 - 0.5 / tau3) * (1.0 - 0.5 / tau2) if force_order == 3 else 0.0
+        if force_order not in (1, 3, 4) or (force_order > 1 and self.collision != "smrt"):
+            raise ValueError("force_order is 1, or 3 or 4 with SMRT")
+        if force_order == 4 and lattice in lat.HIGH_ORDER:
+            raise ValueError(f"{lattice} does not resolve the fourth-order moments independently")
+        fq3 = (1.0 - 0.5 / tau3) if force_order >= 3 else 0.0
         if tau_bulk and (self.collision != "smrt" or tau_bulk <= 0.5):
             raise ValueError("tau_bulk is for SMRT and must exceed 1/2")
         dim = 2 if self.lattice == "D2Q9" else 3
         dqb = (((1.0 - 1.0 / tau_bulk) - (1.0 - 1.0 / tau2)) / dim
                if tau_bulk and tau_bulk != tau2 else 0.0)
-        if tau_31 and (self.collision != "smrt" or lattice == "D2Q9" or force_order == 3
+        if tau_31 and (self.collision != "smrt" or lattice == "D2Q9" or force_order >= 3
                        or tau_31 <= 0.5):
-            raise ValueError("tau_31 is for SMRT on D3Q19/D3Q27, without force_order 3, "
+            raise ValueError("tau_31 is for SMRT on D3Q19/D3Q27, without force_order 3 or 4, "
                              "and must exceed 1/2")
         dq31 = ((1.0 - 1.0 / tau_31) - (1.0 - 1.0 / tau3)) / 2 if tau_31 and tau_31 != tau3 else 0.0
         if max_order not in (4, 6) or (max_order == 6 and (self.collision != "smrt"
                                                             or lattice != "D3Q27")):
             raise ValueError("max_order is 4, or 6 for SMRT on D3Q27")
+        if max_order == 6 and force_order == 4:
+            raise ValueError("force_order 4 is not combined with max_order 6")
         vals = dict(shift=shift, omega=omega, hforce=1.0 - 0.5 * omega,
                     q2=1.0 - 1.0 / tau2, q3=1.0 - 1.0 / tau3, fq3=fq3,
                     h2=1.0 - 0.5 / tau2, h3=1.0 - 0.5 / tau3, dqb=dqb, dq31=dq31)
@@ -158,7 +163,8 @@ class Oracle:
         self._p = P({"bgk": 0, "smrt": 1, "rmrt": 2}[self.collision], nx, ny, nz,
                     (C.c_int32 * 3)(*[int(bool(w)) for w in walls]), int(bool(store16)),
                     *[cast(vals[k]) for k in ("shift", "omega", "hforce", "q2", "q3", "fq3",
-                                              "h2", "h3", "dqb", "dq31")], int(max_order))
+                                              "h2", "h3", "dqb", "dq31")], int(max_order),
+                    int(force_order == 4))
         self.solid = None
         if solid is not None:
             self.solid = np.ascontiguousarray(np.asarray(solid).ravel() != 0, dtype=np.uint8)

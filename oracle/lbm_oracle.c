@@ -95,12 +95,13 @@ typedef struct {
   real omega;          /* BGK: 1 / tau-hat */
   real hforce;         /* BGK: 1 - omega / 2 */
   real q2, q3;         /* SMRT: 1 - omega_n, omega_n = 1 / tau-hat_n */
-  real fq3;            /* SMRT: (1 - omega_3/2)(1 - omega_2/2) for the third-order force
-                          content, 0 when it is neglected */
+  real fq3;            /* SMRT: 1 - omega_3/2, the factor of the third-order force
+                          content, 0 when the non-equilibrium force content is neglected */
   real h2, h3;         /* RMRT: 1 - omega_n / 2 */
   real dqb;            /* SMRT: (q_bulk - q2)/D for the trace of order 2 (0 = one rate) */
   real dq31;           /* SMRT: (q_31 - q3)/2 for the trace of order 3 (0 = one rate) */
   int32_t max_order;   /* SMRT: highest Hermite order carried after the collision, 4 or 6 */
+  int32_t fo4;         /* SMRT: 1 adds the fourth-order force content (with fq3 != 0) */
   const uint8_t *solid; /* N flags, nonzero = solid node (no fluid); NULL = none */
 } oracle_params;
 
@@ -500,21 +501,6 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       if (n == 2) D2[k] = D;
       if (n == 3) D3[k] = D;
       Pc[k] = (n == 2 ? P->q2 : P->q3) * D;
-      if (n == 3 && P->fq3 != 0) {
-        /* eq:Frc at theta = 1: d_F^(3) = 3 g d^(2), the symmetric product, per multi-index
-         * sum_a m_a g_a d_{m - e_a}; d^(2) of f is (1 - omega_2/2) times the central
-         * non-equilibrium second moment D of f-bar (its force part d_F^(2) vanishes), and
-         * the force enters the post-collision moment with (1 - omega_3/2) (eq:RHS).
-         * Canonical order puts every order-2 index before the order-3 ones. */
-        real s = -0.0;
-        for (int a = 0; a < 3; ++a) {
-          if (m[a] == 0) continue;
-          int j = find_index(L, m[0] - (a == 0), m[1] - (a == 1), m[2] - (a == 2));
-          if (j < 0) continue;
-          s = s + ((real)m[a] * g[a]) * D2[j];
-        }
-        Pc[k] = Pc[k] + P->fq3 * s;
-      }
     }
   }
   if (P->dqb != 0) {
@@ -555,6 +541,42 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
       Pc[jc] = Pc[jc] + P->dq31 * s;
     }
   }
+  /* Non-equilibrium force content (eq:Frc at theta = 1): d_F^(n) = n g d^(n-1), the
+   * symmetric product, per multi-index sum_a m_a g_a d^(n-1)_{m - e_a}, where d^(n-1) is
+   * the central non-equilibrium moment of f itself.  By eq:newf and eq:evolution f is the
+   * mean of the populations before and after the collision, so d^(n-1) = (D + P)/2 with D
+   * and P the pre- and post-collision central moments of order n - 1 (P with its own
+   * rates, the bulk rate included).  The content enters order n with (1 - omega_n/2)
+   * (eq:RHS): order 3 with fq3; order 4, trimmed (omega_4 = 1), with 1/2.  Canonical order
+   * puts every order before the next, so each order's P is final before it is used. */
+  if (P->fq3 != 0) {
+    for (int k = 0; k < NM; ++k) {
+      const int32_t *m = L->mi + 3 * k;
+      if (mabs(m) != 3) continue;
+      real s = -0.0;
+      for (int a = 0; a < 3; ++a) {
+        if (m[a] == 0) continue;
+        int j = find_index(L, m[0] - (a == 0), m[1] - (a == 1), m[2] - (a == 2));
+        if (j < 0) continue;
+        s = s + ((real)m[a] * g[a]) * ((real)0.5 * (D2[j] + Pc[j]));
+      }
+      Pc[k] = Pc[k] + P->fq3 * s;
+    }
+  }
+  if (P->fo4) {
+    for (int k = 0; k < NM; ++k) {
+      const int32_t *m = L->mi + 3 * k;
+      if (mabs(m) != 4) continue;
+      real s = -0.0;
+      for (int a = 0; a < 3; ++a) {
+        if (m[a] == 0) continue;
+        int j = find_index(L, m[0] - (a == 0), m[1] - (a == 1), m[2] - (a == 2));
+        if (j < 0) continue;
+        s = s + ((real)m[a] * g[a]) * ((real)0.5 * (D3[j] + Pc[j]));
+      }
+      Pc[k] = (real)0.5 * s;
+    }
+  }
   /* back to raw moments; the change of every moment over the collision, or (full: the
    * index set is smaller than Q) the post-collision moments a* themselves */
   const int full = L->NM < L->Q;
@@ -584,7 +606,8 @@ static void collide_smrt(const oracle_lattice *L, const oracle_params *P, const 
        * whose own parts at orders 4 and above are trimmed to zero */
       Nk = A - E[k];
     }
-    real R = (n <= 3) ? Pc[k] : (real)-0.0; /* l = 0 term; P_m = 0 for |m| = 4 */
+    /* l = 0 term; at order 4 P_m is 0 (trimmed) or the fourth-order force content */
+    real R = (n <= 3 || (n == 4 && P->fo4)) ? Pc[k] : (real)-0.0;
     for (int t = 0; t < S->n[k]; ++t) {
       int km = S->km[k][t];
       if (mabs(L->mi + 3 * km) > 3) continue; /* P = 0 at order 4 */

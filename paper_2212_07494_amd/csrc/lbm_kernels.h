@@ -226,10 +226,17 @@ __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restri
   if constexpr (COLL == 0) {
     collide_bgk<L>(d, shift, g, BGKCoef<T>{c0, c1});
   } else {
+    const SMRTCoef<T> sc{c0, c1, c2, c3, c4};
     if constexpr (COLL == 1)
-      collide_smrt<L, false>(d, shift, g, SMRTCoef<T>{c0, c1, c2, c3, c4});
+      collide_smrt<L, false, T, 0>(d, shift, g, sc);
     else if constexpr (COLL == 3)
-      collide_smrt<L, true>(d, shift, g, SMRTCoef<T>{c0, c1, c2, c3, c4});
+      collide_smrt<L, true, T, 0>(d, shift, g, sc);
+    else if constexpr (COLL == 4)
+      collide_smrt<L, false, T, 3>(d, shift, g, sc);
+    else if constexpr (COLL == 5)
+      collide_smrt<L, false, T, 4>(d, shift, g, sc);
+    else if constexpr (COLL == 6)
+      collide_smrt<L, true, T, 3>(d, shift, g, sc);
     else
       collide_rmrt<L>(d, shift, g, RMRTCoef<T>{c0, c1, c2, c3});
   }

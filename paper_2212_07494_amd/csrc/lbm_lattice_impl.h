@@ -92,6 +92,14 @@ struct Ops {
       if constexpr (L::ORD[L::NM - 1] > 4) {
         if (d.coll == 3)
           return d.gk ? step_t<3, S, T, GK_FIELD>(d, s) : step_t<3, S, T, GK_PROFILE>(d, s);
+        if (d.coll == 6)
+          return d.gk ? step_t<6, S, T, GK_FIELD>(d, s) : step_t<6, S, T, GK_PROFILE>(d, s);
+      }
+      if (d.coll == 4)
+        return d.gk ? step_t<4, S, T, GK_FIELD>(d, s) : step_t<4, S, T, GK_PROFILE>(d, s);
+      if constexpr (L::NM == L::Q) {
+        if (d.coll == 5)
+          return d.gk ? step_t<5, S, T, GK_FIELD>(d, s) : step_t<5, S, T, GK_PROFILE>(d, s);
       }
       return d.gk ? step_t<1, S, T, GK_FIELD>(d, s) : step_t<1, S, T, GK_PROFILE>(d, s);
     });

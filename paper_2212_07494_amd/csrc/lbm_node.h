@@ -119,8 +119,8 @@ struct BGKCoef {
 template <class T>
 struct SMRTCoef {
   T q2, q3;  // 1 - omega_n for orders 2 and 3
-  // Third-order force content with the non-equilibrium stress (0 = neglected, as in the
-  // paper's runs): (1 - omega_3/2)(1 - omega_2/2), see collide_smrt.
+  // Factor 1 - omega_3/2 of the third-order force content (read only by the collisions
+  // that carry it, see collide_smrt).
   T fq3;
   // Bulk rate: (q_bulk - q2) / D for the trace of the second-order moment (0 = one
   // rate for the whole order).
@@ -438,13 +438,19 @@ __device__ __forceinline__ void reconstruct(const T (&a)[L::NM], T (&out)[L::Q])
 // post-collision moments a*_0 = d-rho, a*_e = j + F, a*_m = rho u^m + R_m (|m| = 2..4)
 // by reconstruct_full_folded, and the order-4 moments are not projected (a* of order 4
 // does not depend on them).
-template <class L, bool HI56, class T>
+// FC: the non-equilibrium force content carried, 0 (none: d_F^(n) = 0 for n >= 2, the
+// paper's runs), 3 (d_F^(3)) or 4 (d_F^(3) and d_F^(4)); a compile-time choice, so the
+// step without it carries none of its code.
+template <class L, bool HI56, class T, int FC = 0>
 __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)[3],
                                              const SMRTCoef<T> &c) {
   constexpr int NM = L::NM;
   constexpr bool FULL = L::NM < L::Q;
+  constexpr bool FO4 = FC == 4;
+  static_assert(FC == 0 || FC == 3 || FC == 4);
+  static_assert(!FO4 || (!HI56 && !FULL));
   const Macro<T> M = macroscopic<L>(d, shift, g);
-  T U[NM], E[NM], N[NM], P[NM], dA[NM], C2[NM];
+  T U[NM], E[NM], N[NM], P[NM], dA[NM], C2[NM], C3[NM];
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     U[k] = upow<L, k>(M.u);
@@ -502,24 +508,37 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
     } else if constexpr (n == 2 || n == 3) {
       const T Dm = central<L, k>(U, N);
       if constexpr (n == 2) C2[k] = Dm;
+      if constexpr (n == 3 && FO4) C3[k] = Dm;
       P[k] = (n == 2 ? c.q2 : c.q3) * Dm;
       if constexpr (is_diag2<L>(k)) P[k] = P[k] + tb;
       if constexpr (trace_partner3<L>(k) >= 0) P[k] = P[k] + t3[k];
       if constexpr (n == 3) {
-        // Third-order force content (eq:Frc, d_F^(3) = 3 g d^(2)): the symmetric product
-        // sum_a m_a g_a d_{m - e_a} of the acceleration with the non-equilibrium central
-        // second moment of f, d^(2) = (1 - omega_2/2) of that of f-bar, relaxed as a
-        // force term by (1 - omega_3/2).
-        if (c.fq3 != T(0)) {
+        // Third-order force content (eq:Frc at theta = 1, d_F^(3) = 3 g d^(2)): the
+        // symmetric product sum_a m_a g_a d_{m - e_a} of the acceleration with the central
+        // non-equilibrium second moment of f itself, which eq:newf and eq:evolution make
+        // the mean (D + P)/2 of the moment before and after the collision (P final here:
+        // order 2 precedes order 3), relaxed as a force term by 1 - omega_3/2.
+        if constexpr (FC >= 3) {
           T sF = T(-0.0);
           static_for<3>([&](auto A) {
             constexpr int a = decltype(A)::value;
             constexpr int j = sub_index<L>(k, a);
-            if constexpr (j >= 0) sF = sF + (T(L::MI[k][a]) * g[a]) * C2[j];
+            if constexpr (j >= 0) sF = sF + (T(L::MI[k][a]) * g[a]) * (T(0.5) * (C2[j] + P[j]));
           });
           P[k] = P[k] + c.fq3 * sF;
         }
       }
+    } else if constexpr (FO4 && n == 4) {
+      // Fourth-order force content (eq:Frc, d_F^(4) = 4 g d^(3)), the same product with the
+      // central third moment of f, (D + P)/2 of order 3, entering the trimmed order 4
+      // (omega_4 = 1) with 1 - omega_4/2 = 1/2.
+      T s4 = T(-0.0);
+      static_for<3>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        constexpr int j = sub_index<L>(k, a);
+        if constexpr (j >= 0) s4 = s4 + (T(L::MI[k][a]) * g[a]) * (T(0.5) * (C3[j] + P[j]));
+      });
+      P[k] = T(0.5) * s4;
     } else {
       P[k] = T(0);
     }
@@ -555,7 +574,7 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
         dA[k] = -N[k];
       }
     } else {
-      T R = (n <= 3) ? P[k] : T(-0.0);
+      T R = (n <= 3 || (FO4 && n == 4)) ? P[k] : T(-0.0);
       static_for<L::NT[k]>([&](auto Tt) {
         constexpr int t = decltype(Tt)::value;
         constexpr int kl = L::TL[k][t], km = L::TM[k][t];

@@ -249,7 +249,13 @@ struct lbm_ctx {
   }
   lbm::LaunchDesc desc(double gscale) const {
     lbm::LaunchDesc d{};
-    d.coll = (p.collision == LBM_SMRT && p.max_order == 6) ? 3 : p.collision;
+    d.coll = p.collision;
+    if (p.collision == LBM_SMRT) {
+      const bool hi = p.max_order == 6;
+      if (p.force_order == 4) d.coll = 5;
+      else if (p.force_order == 3) d.coll = hi ? 6 : 4;
+      else if (hi) d.coll = 3;
+    }
     d.storage = p.storage;
     d.gk = gk;
     d.fin = buf[cur];
@@ -323,10 +329,15 @@ int validate(const lbm_params *p) {
     if (p->tau[4] != 1.0)
       return fail(LBM_EINVAL, "SMRT trims order 4: tau[4] must be 1 (got %g)", p->tau[4]);
   }
-  if (p->force_order != 0 && p->force_order != 1 && p->force_order != 3)
-    return fail(LBM_EINVAL, "force_order must be 1 or 3 (got %d)", p->force_order);
-  if (p->force_order == 3 && p->collision != LBM_SMRT)
-    return fail(LBM_EINVAL, "force_order 3 needs the SMRT collision");
+  if (p->force_order != 0 && p->force_order != 1 && p->force_order != 3 && p->force_order != 4)
+    return fail(LBM_EINVAL, "force_order must be 1, 3 or 4 (got %d)", p->force_order);
+  if (p->force_order >= 3 && p->collision != LBM_SMRT)
+    return fail(LBM_EINVAL, "force_order %d needs the SMRT collision", p->force_order);
+  if (p->force_order == 4 && p->lattice == LBM_D3Q39)
+    return fail(LBM_EINVAL,
+                "force_order 4 needs independent fourth-order moments, which D3Q39 lacks");
+  if (p->force_order == 4 && p->max_order == 6)
+    return fail(LBM_EINVAL, "force_order 4 is not combined with max_order 6");
   if (p->tau_bulk != 0) {
     if (p->collision != LBM_SMRT)
       return fail(LBM_EINVAL, "tau_bulk needs the SMRT collision");
@@ -346,8 +357,8 @@ int validate(const lbm_params *p) {
       return fail(LBM_EINVAL, "tau_31: D2Q9 carries no traceless third-order component");
     if (p->lattice == LBM_D3Q39)
       return fail(LBM_EINVAL, "tau_31 is defined on D3Q19/D3Q27 (D3Q39 carries D_aaa)");
-    if (p->force_order == 3)
-      return fail(LBM_EINVAL, "tau_31 is not combined with force_order 3");
+    if (p->force_order >= 3)
+      return fail(LBM_EINVAL, "tau_31 is not combined with force_order %d", p->force_order);
     if (!(p->tau_31 > 0.5) || !std::isfinite(p->tau_31))
       return fail(LBM_EINVAL, "tau_31 = %g must exceed 1/2 (or be 0)", p->tau_31);
   }
@@ -714,7 +725,7 @@ int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init, 
       c->c2 = 1.0 - 0.5 / p->tau[2];
       c->c3 = 1.0 - 0.5 / p->tau[3];
     } else {
-      if (p->force_order == 3) c->c2 = (1.0 - 0.5 / p->tau[3]) * (1.0 - 0.5 / p->tau[2]);
+      if (p->force_order >= 3) c->c2 = 1.0 - 0.5 / p->tau[3];
       if (p->tau_bulk != 0 && p->tau_bulk != p->tau[2])
         c->c3 = ((1.0 - 1.0 / p->tau_bulk) - (1.0 - 1.0 / p->tau[2])) / c->D;
       if (p->tau_31 != 0 && p->tau_31 != p->tau[3])
@@ -1234,7 +1245,7 @@ uint64_t params_hash(const lbm_ctx *c) {
   uint64_t h = kFnvBasis;
   const int32_t ints[] = {p.lattice, p.collision, p.storage, p.nx,     p.ny,     p.nz,
                           p.bc[0],   p.bc[1],     p.bc[2],   p.g_kind, p.g_axis,
-                          p.force_order == 3 ? 3 : 1, p.max_order == 6 ? 6 : 4};
+                          p.force_order >= 3 ? p.force_order : 1, p.max_order == 6 ? 6 : 4};
   h = fnv1a(h, ints, sizeof(ints));
   const double reals[] = {p.tau[2], p.tau[3], p.tau[4], p.rho0,
                           p.tau_bulk == 0 ? p.tau[2] : p.tau_bulk,

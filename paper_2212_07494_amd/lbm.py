@@ -178,7 +178,7 @@ def make_params(lattice="D2Q9", collision="bgk", storage="f64", shape=(1, 1, 1),
                 monitor_every=0, allocator=None, force_order=1, solid=None, tau_bulk=0.0,
                 tau_31=0.0, max_order=4, mach_limit=0.0, debug_poison=False):
     """Fill an lbm_params.  g: uniform (3,) acceleration; g_profile: (axis, (3, n) table);
-    g_field: (3, N) array; force_order 1 or 3 (SMRT third-order force content); solid: N
+    g_field: (3, N) array; force_order 1, 3 or 4 (SMRT force content to that order); solid: N
     flags (nonzero = solid node) or None; mach_limit: warn (MachWarning) when a monitor
     record has max |u| above mach_limit c_s (0 = off); debug_poison: fill the buffer each
     step writes with NaN first.  Returned together with the arrays it points to (keep

@@ -45,6 +45,15 @@ def test_version_and_strerror():
     (dict(lattice="D3Q19", shape=(2048, 2048, 1024)), "2^31"),
     (dict(force_order=2), "force_order"),
     (dict(force_order=3), "SMRT"),
+    (dict(force_order=4), "SMRT"),
+    (dict(collision="rmrt", force_order=4), "SMRT"),
+    (dict(force_order=5), "1, 3 or 4"),
+    (dict(lattice="D3Q39", shape=(8, 8, 8), collision="smrt", force_order=4),
+     "fourth-order moments"),
+    (dict(lattice="D3Q27", shape=(8, 8, 8), collision="smrt", force_order=4, max_order=6),
+     "not combined with max_order 6"),
+    (dict(lattice="D3Q19", shape=(8, 8, 8), collision="smrt", tau_31=0.7, force_order=4),
+     "not combined with force_order 4"),
     (dict(tau_bulk=1.2), "tau_bulk needs the SMRT"),
     (dict(collision="rmrt", tau_bulk=1.2), "tau_bulk needs the SMRT"),
     (dict(collision="smrt", tau_bulk=0.5), "must exceed 1/2"),

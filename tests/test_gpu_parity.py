@@ -81,31 +81,35 @@ def test_step_parity_random_state(lat, coll, storage):
 
 @pytest.mark.parametrize("storage", STORES)
 @pytest.mark.parametrize("lat", LATS)
-def test_third_order_force_parity(lat, storage):
-    """SMRT with the third-order force content (force_order 3): random state and force
-    field, three steps with force scales (1, 0.5, -2), bit-identical to the oracle; and it
-    does change the state against force_order 1."""
+@pytest.mark.parametrize("order,tau_bulk", [(3, 0.0), (3, 1.4), (4, 0.0), (4, 1.4)])
+def test_force_content_parity(lat, storage, order, tau_bulk):
+    """SMRT with the non-equilibrium force content to third (force_order 3) or fourth
+    order (force_order 4), alone and with a separate bulk rate: random state and force
+    field, three steps with force scales (1, 0.5, -2), bit-identical to the oracle; and
+    the content does change the state against the order below."""
     L = lbm()
     shape = SHAPES[lat]
     N = int(np.prod(shape))
     walls = WALLS[lat][-1]
     kw, g = _force(lat, shape, "field", seed=8)
     f0 = _state(lat, storage, N, seed=12)
-    o = oracle_for(lat, "smrt", storage, shape, walls, TAU["smrt"], force_order=3)
+    o = oracle_for(lat, "smrt", storage, shape, walls, TAU["smrt"], force_order=order,
+                   tau_bulk=tau_bulk)
     scales = [1.0, 0.5, -2.0]
     fo = f0.astype(o.dtype)
     for s in scales:
         fo = o.step(fo, g, s)
+    below = 1 if order == 3 else 3
     got = {}
-    for order in (1, 3):
-        with L.Lattice(lat, "smrt", storage, shape, walls, TAU["smrt"], force_order=order,
-                       **kw) as gpu:
+    for fo_ in (below, order):
+        with L.Lattice(lat, "smrt", storage, shape, walls, TAU["smrt"], force_order=fo_,
+                       tau_bulk=tau_bulk, **kw) as gpu:
             gpu.set_populations(f0)
             gpu.step(3, g_scale=scales)
-            got[order] = gpu.populations()
-    assert exact_mismatch(got[3], fo.astype(np.float64)) == 0
+            got[fo_] = gpu.populations()
+    assert exact_mismatch(got[order], fo.astype(np.float64)) == 0
     if storage != "f16s":  # binary16 may round the small change away
-        assert exact_mismatch(got[3], got[1]) > 0
+        assert exact_mismatch(got[order], got[below]) > 0
 
 
 @pytest.mark.parametrize("storage", STORES)
@@ -165,9 +169,11 @@ def test_split_rates_parity(lat, storage):
 
 
 @pytest.mark.parametrize("storage", STORES)
-def test_high_orders_parity(storage):
-    """D3Q27 SMRT carrying orders 5 and 6 (max_order 6): random state, force field and
-    walls, three steps, bit-identical to the oracle; and it changes the state."""
+@pytest.mark.parametrize("force_order", [1, 3])
+def test_high_orders_parity(storage, force_order):
+    """D3Q27 SMRT carrying orders 5 and 6 (max_order 6), without and with the third-order
+    force content: random state, force field and walls, three steps, bit-identical to
+    the oracle; and it changes the state."""
     L = lbm()
     lat = "D3Q27"
     shape = SHAPES[lat]
@@ -175,7 +181,8 @@ def test_high_orders_parity(storage):
     walls = WALLS[lat][-1]
     kw, g = _force(lat, shape, "field", seed=11)
     f0 = _state(lat, storage, N, seed=15)
-    o = oracle_for(lat, "smrt", storage, shape, walls, TAU["smrt"], max_order=6)
+    o = oracle_for(lat, "smrt", storage, shape, walls, TAU["smrt"], max_order=6,
+                   force_order=force_order)
     scales = [1.0, 0.5, -2.0]
     fo = f0.astype(o.dtype)
     for s in scales:
@@ -183,7 +190,7 @@ def test_high_orders_parity(storage):
     got = {}
     for mo in (4, 6):
         with L.Lattice(lat, "smrt", storage, shape, walls, TAU["smrt"], max_order=mo,
-                       **kw) as gpu:
+                       force_order=force_order, **kw) as gpu:
             gpu.set_populations(f0)
             gpu.step(3, g_scale=scales)
             got[mo] = gpu.populations()

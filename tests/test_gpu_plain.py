@@ -89,9 +89,11 @@ def test_fp64_kernel_matches_plain_definition(lat, coll):
 
 @pytest.mark.parametrize("lat,opts", [
     ("D2Q9", dict(force_order=3)), ("D3Q19", dict(force_order=3)),
-    ("D3Q27", dict(force_order=3)), ("D2Q9", dict(tau_bulk=1.3)),
+    ("D3Q27", dict(force_order=3)), ("D2Q9", dict(force_order=4)),
+    ("D3Q19", dict(force_order=4, tau_bulk=1.3)), ("D3Q27", dict(force_order=4)),
+    ("D2Q9", dict(tau_bulk=1.3)),
     ("D3Q19", dict(tau_bulk=1.3)), ("D3Q19", dict(tau_31=1.6)), ("D3Q27", dict(tau_31=0.7)),
-    ("D3Q27", dict(max_order=6)),
+    ("D3Q27", dict(max_order=6)), ("D3Q27", dict(max_order=6, force_order=3)),
 ])
 def test_fp64_kernel_options_match_plain_definition(lat, opts):
     L = lbm()

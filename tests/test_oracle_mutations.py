@@ -90,7 +90,19 @@ MUTATIONS = {
         (C_SRC, "R = fmar((real)S->cup[k][t] * U[S->kl[k][t]], Pc[km], R);",
          "R = fmar((real)S->cup[k][t] * U[S->kl[k][t]], N[km], R);"),
     "SMRT third-order force content without m_a":
-        (C_SRC, "s = s + ((real)m[a] * g[a]) * D2[j];", "s = s + g[a] * D2[j];"),
+        (C_SRC, "s = s + ((real)m[a] * g[a]) * ((real)0.5 * (D2[j] + Pc[j]));",
+         "s = s + g[a] * ((real)0.5 * (D2[j] + Pc[j]));"),
+    "third-order force content from the pre-collision second moment":
+        (C_SRC, "((real)0.5 * (D2[j] + Pc[j]))", "D2[j]"),
+    "third-order force content blind to the bulk rate":
+        (C_SRC, "((real)0.5 * (D2[j] + Pc[j]))", "((real)0.5 * (D2[j] + P->q2 * D2[j]))"),
+    "fourth-order force content without 1 - omega_4/2":
+        (C_SRC, "Pc[k] = (real)0.5 * s;", "Pc[k] = s;"),
+    "fourth-order force content from the pre-collision third moment":
+        (C_SRC, "((real)0.5 * (D3[j] + Pc[j]))", "D3[j]"),
+    "fourth-order force content left out of the back-shift":
+        (C_SRC, "real R = (n <= 3 || (n == 4 && P->fo4)) ? Pc[k] : (real)-0.0;",
+         "real R = (n <= 3) ? Pc[k] : (real)-0.0;"),
     "SMRT bulk rate over every second-order moment":
         (C_SRC, "if (mabs(m) == 2 && (m[0] == 2 || m[1] == 2 || m[2] == 2)) tr = tr + D2[k];",
          "if (mabs(m) == 2) tr = tr + D2[k];"),
@@ -130,12 +142,12 @@ MUTATIONS = {
     "bounce-back without reversing the direction":
         (C_SRC, "fnew[(int64_t)L->opp[i] * N + n] = v;", "fnew[(int64_t)i * N + n] = v;"),
     # host-side rates and factors
-    "third-order force factor without 1 - omega_2/2":
-        (PY_SRC, "fq3 = (1.0 - 0.5 / tau3) * (1.0 - 0.5 / tau2) if force_order == 3 else 0.0",
-         "fq3 = (1.0 - 0.5 / tau3) if force_order == 3 else 0.0"),
     "third-order force factor at the order-2 rate":
-        (PY_SRC, "fq3 = (1.0 - 0.5 / tau3) * (1.0 - 0.5 / tau2) if force_order == 3 else 0.0",
-         "fq3 = (1.0 - 0.5 / tau2) * (1.0 - 0.5 / tau2) if force_order == 3 else 0.0"),
+        (PY_SRC, "fq3 = (1.0 - 0.5 / tau3) if force_order >= 3 else 0.0",
+         "fq3 = (1.0 - 0.5 / tau2) if force_order >= 3 else 0.0"),
+    "third-order force factor 1 - omega_3":
+        (PY_SRC, "fq3 = (1.0 - 0.5 / tau3) if force_order >= 3 else 0.0",
+         "fq3 = (1.0 - 1.0 / tau3) if force_order >= 3 else 0.0"),
     "bulk rate not divided by D":
         (PY_SRC, "dqb = (((1.0 - 1.0 / tau_bulk) - (1.0 - 1.0 / tau2)) / dim",
          "dqb = (((1.0 - 1.0 / tau_bulk) - (1.0 - 1.0 / tau2))"),
