@@ -76,10 +76,11 @@ int main(int argc, char **argv) {
   for (int coll = 0; coll < 3; ++coll)
     for (int wi = 0; wi < 3; ++wi)
       for (int so = 0; so < 2; ++so)
-        for (int opt = 0; opt < 5; ++opt) {
+        for (int opt = 0; opt < 6; ++opt) {
           if (opt && coll != 1) continue;            /* options are the SMRT's */
           if (opt == 3 && D == 2) continue;          /* no traceless third order on D2Q9 */
           if (opt == 4 && Q != 27) continue;         /* orders 5-6 live on D3Q27 only */
+          if (opt == 5 && L.NM < Q) continue;        /* order-4 force content: NM == Q */
           for (int s16 = 0; s16 < (sizeof(real) == 4 ? 2 : 1); ++s16) {
             oracle_params P;
             memset(&P, 0, sizeof(P));
@@ -96,7 +97,8 @@ int main(int argc, char **argv) {
             P.q3 = (real)(1.0 - 1.0 / 0.9);
             P.h2 = (real)(1.0 - 0.5 / 0.7);
             P.h3 = (real)(1.0 - 0.5 / 0.9);
-            P.fq3 = opt == 1 ? (real)((1.0 - 0.5 / 0.9) * (1.0 - 0.5 / 0.7)) : (real)0;
+            P.fq3 = (opt == 1 || opt == 5) ? (real)(1.0 - 0.5 / 0.9) : (real)0;
+            P.fo4 = opt == 5;
             P.dqb = opt == 2 ? (real)(((1.0 - 1.0 / 1.3) - (1.0 - 1.0 / 0.7)) / D) : (real)0;
             P.dq31 = opt == 3 ? (real)(((1.0 - 1.0 / 1.4) - (1.0 - 1.0 / 0.9)) / 2) : (real)0;
             P.max_order = opt == 4 ? 6 : 4;

@@ -79,6 +79,10 @@ int main(void) {
   EXPECT(lbm_init(&p, NULL, NULL, NULL, &c) == LBM_EINVAL);
   p = base_params(); p.lattice = LBM_D3Q39; p.bc[1] = LBM_WALLS;
   EXPECT(lbm_init(&p, NULL, NULL, NULL, &c) == LBM_EINVAL);
+  p = base_params(); p.lattice = LBM_D3Q39; p.collision = LBM_SMRT; p.force_order = 4;
+  EXPECT(lbm_init(&p, NULL, NULL, NULL, &c) == LBM_EINVAL);
+  p = base_params(); p.collision = LBM_BGK; p.force_order = 4;
+  EXPECT(lbm_init(&p, NULL, NULL, NULL, &c) == LBM_EINVAL);
   EXPECT(lbm_init(NULL, NULL, NULL, NULL, &c) == LBM_EINVAL);
   EXPECT(lbm_init(&p, NULL, NULL, NULL, NULL) == LBM_EINVAL);
   /* a valid context where there is no device: a device error, nothing leaked */
