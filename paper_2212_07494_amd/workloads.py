@@ -138,8 +138,9 @@ def main():
                     help="collision of the single-lattice workloads")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--force-order", type=int, default=None, choices=[1, 3],
-                    help="SMRT force content (3: with the third-order term)")
+    ap.add_argument("--force-order", type=int, default=None, choices=[1, 3, 4],
+                    help="SMRT force content (3: with the third-order term; 4: and the "
+                         "fourth-order term)")
     ap.add_argument("--max-order", type=int, default=None, choices=[4, 6],
                     help="SMRT on D3Q27: carry orders 5-6 (6)")
     ap.add_argument("--tau-bulk", type=float, default=None, help="SMRT bulk rate (tau-hat)")
