@@ -31,9 +31,10 @@ struct GeomDesc {
 // One launch of a lattice kernel.  Coefficients are binary64 on the host and are
 // rounded once to the arithmetic type of the storage mode.
 struct LaunchDesc {
-  int coll;      // 0 BGK, 1 SMRT, 2 RMRT, 3 SMRT carrying orders 5-6 (D3Q27); SMRT with the
-                 // non-equilibrium force content: 4 to order 3, 5 to order 4, 6 to order 3
-                 // carrying orders 5-6
+  int coll;      // 0 BGK, 1 SMRT with one rate per order, 2 RMRT; SMRT whose traces may
+                 // relax at rates of their own: 7, 3 carrying orders 5-6 (D3Q27), and with
+                 // the non-equilibrium force content 4 to order 3, 5 to order 4, 6 to
+                 // order 3 carrying orders 5-6
   int storage;   // lbm_storage
   int gk;        // 0 profile/uniform table, 1 full field
   const void *fin;

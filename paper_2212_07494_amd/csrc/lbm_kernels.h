@@ -228,6 +228,8 @@ __device__ __forceinline__ void step_node(const S *__restrict__ fin, S *__restri
   } else {
     const SMRTCoef<T> sc{c0, c1, c2, c3, c4};
     if constexpr (COLL == 1)
+      collide_smrt<L, false, T, 0, false>(d, shift, g, sc);
+    else if constexpr (COLL == 7)
       collide_smrt<L, false, T, 0>(d, shift, g, sc);
     else if constexpr (COLL == 3)
       collide_smrt<L, true, T, 0>(d, shift, g, sc);

@@ -97,6 +97,8 @@ struct Ops {
       }
       if (d.coll == 4)
         return d.gk ? step_t<4, S, T, GK_FIELD>(d, s) : step_t<4, S, T, GK_PROFILE>(d, s);
+      if (d.coll == 7)
+        return d.gk ? step_t<7, S, T, GK_FIELD>(d, s) : step_t<7, S, T, GK_PROFILE>(d, s);
       if constexpr (L::NM == L::Q) {
         if (d.coll == 5)
           return d.gk ? step_t<5, S, T, GK_FIELD>(d, s) : step_t<5, S, T, GK_PROFILE>(d, s);

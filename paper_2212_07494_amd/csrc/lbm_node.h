@@ -439,9 +439,11 @@ __device__ __forceinline__ void reconstruct(const T (&a)[L::NM], T (&out)[L::Q])
 // by reconstruct_full_folded, and the order-4 moments are not projected (a* of order 4
 // does not depend on them).
 // FC: the non-equilibrium force content carried, 0 (none: d_F^(n) = 0 for n >= 2, the
-// paper's runs), 3 (d_F^(3)) or 4 (d_F^(3) and d_F^(4)); a compile-time choice, so the
-// step without it carries none of its code.
-template <class L, bool HI56, class T, int FC = 0>
+// paper's runs), 3 (d_F^(3)) or 4 (d_F^(3) and d_F^(4)).  SPLIT: whether the traces at
+// orders 2 and 3 may relax at rates of their own (dqb, dq31); without it one rate per
+// order.  Both are compile-time choices, so the step without them carries none of their
+// code.
+template <class L, bool HI56, class T, int FC = 0, bool SPLIT = true>
 __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)[3],
                                              const SMRTCoef<T> &c) {
   constexpr int NM = L::NM;
@@ -482,23 +484,27 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
   // at its own rate, P_aa += (q_bulk - q2)/D tr(D), the traceless part keeps q2 (a zero
   // coefficient leaves every P unchanged).
   T tb = T(-0.0);
-  static_for<NM>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    if constexpr (is_diag2<L>(k)) tb = tb + central<L, k>(U, N);
-  });
-  tb = c.dqb * tb;
+  if constexpr (SPLIT) {
+    static_for<NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      if constexpr (is_diag2<L>(k)) tb = tb + central<L, k>(U, N);
+    });
+    tb = c.dqb * tb;
+  }
   // The same at order 3: the trace S^(3,1), carried per axis a by D_abb + D_acc, may relax
   // at its own rate, P_abb += (q_31 - q3)/2 (D_abb + D_acc) and likewise P_acc; the
   // differences D_abb - D_acc and D_xyz keep q3.
   T t3[NM];
-  static_for<NM>([&](auto K) {
-    constexpr int k = decltype(K)::value;
-    constexpr int p = trace_partner3<L>(k);
-    if constexpr (p > k) {
-      t3[k] = c.dq31 * (central<L, k>(U, N) + central<L, p>(U, N));
-      t3[p] = t3[k];
-    }
-  });
+  if constexpr (SPLIT) {
+    static_for<NM>([&](auto K) {
+      constexpr int k = decltype(K)::value;
+      constexpr int p = trace_partner3<L>(k);
+      if constexpr (p > k) {
+        t3[k] = c.dq31 * (central<L, k>(U, N) + central<L, p>(U, N));
+        t3[p] = t3[k];
+      }
+    });
+  }
   static_for<NM>([&](auto K) {
     constexpr int k = decltype(K)::value;
     constexpr int n = L::ORD[k];
@@ -510,8 +516,8 @@ __device__ __forceinline__ void collide_smrt(T (&d)[L::Q], T shift, const T (&g)
       if constexpr (n == 2) C2[k] = Dm;
       if constexpr (n == 3 && FO4) C3[k] = Dm;
       P[k] = (n == 2 ? c.q2 : c.q3) * Dm;
-      if constexpr (is_diag2<L>(k)) P[k] = P[k] + tb;
-      if constexpr (trace_partner3<L>(k) >= 0) P[k] = P[k] + t3[k];
+      if constexpr (SPLIT && is_diag2<L>(k)) P[k] = P[k] + tb;
+      if constexpr (SPLIT && trace_partner3<L>(k) >= 0) P[k] = P[k] + t3[k];
       if constexpr (n == 3) {
         // Third-order force content (eq:Frc at theta = 1, d_F^(3) = 3 g d^(2)): the
         // symmetric product sum_a m_a g_a d_{m - e_a} of the acceleration with the central

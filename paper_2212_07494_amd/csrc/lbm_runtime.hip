@@ -255,6 +255,7 @@ struct lbm_ctx {
       if (p.force_order == 4) d.coll = 5;
       else if (p.force_order == 3) d.coll = hi ? 6 : 4;
       else if (hi) d.coll = 3;
+      else if (c3 != 0 || c4 != 0) d.coll = 7;  // split trace rates
     }
     d.storage = p.storage;
     d.gk = gk;
