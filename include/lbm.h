@@ -188,7 +188,8 @@ typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
  *   hip_stream: a hipStream_t (NULL = the default stream).
  * Errors: LBM_EINVAL (tau <= 1/2, SMRT with tau[4] != 1, nz != 1 on D2Q9, unknown
  * enum, non-positive size, node count >= 2^31, missing g_data, rho0 <= 0, D3Q39 with
- * walls, solid nodes, tau_31 or an extent below 3),
+ * walls, solid nodes, tau_31 or an extent below 3, force_order 3 or 4 without SMRT,
+ * force_order 4 on D3Q39 or with max_order 6, tau_31 with force_order 3 or 4),
  * LBM_ENOMEM, LBM_EDEVICE.  On error *out is NULL. */
 int lbm_init(const lbm_params *p, const double *rho_init, const double *u_init,
              void *hip_stream, lbm_ctx **out);
