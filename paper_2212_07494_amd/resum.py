@@ -56,6 +56,31 @@ ORDER = 4
 LEARNED = (2, 3)
 SIGMA_MIN = 1e-3   # problems below this series ratio start steady: no data from them
 TRAIN_SEED, VAL_SEED, TEST_SEED = 40_000, 60_000, 80_000
+# Seeds of the three splits: validation problems come from [VAL_SEED, VAL_SEED + VAL_SPAN),
+# held-out test problems from TEST_SEED on; training problems from anywhere else at or
+# above TRAIN_SEED (cmd_data refuses a set that reaches either range, cmd_train a set
+# whose seeds meet the validation problems').
+VAL_SPAN = 10_000
+
+
+def _split_of_seed(s):
+    if s >= TEST_SEED:
+        return "test"
+    if VAL_SEED <= s < VAL_SEED + VAL_SPAN:
+        return "val"
+    return "train" if s >= TRAIN_SEED else None
+
+
+def check_splits(rows):
+    """Refuses data rows whose seeds lie outside their split's range or that share a seed
+    between the training and validation splits (rows written before seeds were recorded
+    carry none and pass)."""
+    tr = {r["seed"] for r in rows if r["split"] == "train" and "seed" in r}
+    va = {r["seed"] for r in rows if r["split"] == "val" and "seed" in r}
+    stray = sorted(r["seed"] for r in rows if "seed" in r and _split_of_seed(r["seed"]) != r["split"])
+    if tr & va or stray:
+        raise SystemExit(f"training and validation problems overlap or leave their seed "
+                         f"ranges (shared seeds: {sorted(tr & va)[:5]}, out of range: {stray[:5]})")
 
 
 def order_fields(k, ph, amp, ends, box):
@@ -253,6 +278,7 @@ def problems(seed0, n, box=128, sigma_min=SIGMA_MIN, max_draws=None):
     limit = max_draws or 50 * n
     while len(out) < n and s - seed0 < limit:
         p = inputs.warmstart_problem(s, box=box, family="wide")
+        p["seed"] = s
         s += 1
         ex = expansion(p, box)
         if ex[5] >= sigma_min:
@@ -292,13 +318,16 @@ def cmd_data(args):
     for split, seed0, n in (("train", TRAIN_SEED + args.seed_offset, args.n),
                             ("val", VAL_SEED + args.seed_offset, args.val)):
         for i, (p, ex) in enumerate(problems(seed0, n, args.box)):
+            if _split_of_seed(p["seed"]) != split:
+                raise SystemExit(f"seed {p['seed']} of a {split} problem lies in the "
+                                 f"{_split_of_seed(p['seed'])} range: choose another offset")
             rho, u, steps, resid = converge(p, ex, args.box)
             if not resid < DATA_TOL:
                 print(f"{split} {i}: not converged (resid {resid:.2e}), skipped", flush=True)
                 continue
             k, ph, amp, ends, feat, sigma = ex
             c, fit, plain = fit_factors(p, args.box, k, ph, amp, ends, rho, u)
-            rows.append(dict(split=split, tau2=p["tau2"], modes=[
+            rows.append(dict(split=split, seed=int(p["seed"]), tau2=p["tau2"], modes=[
                 dict(k=[int(v) for v in m["k"]], p=[float(v) for v in m["p"]],
                      phase=float(m["phase"]), amp=float(m["amp"])) for m in p["modes"]],
                 feat=feat.tolist(), sigma=sigma, c=c.tolist(), fit_resid=fit,
@@ -323,6 +352,7 @@ def cmd_train(args):
             rows += json.load(open(os.path.join(args.data, name)))
     tr = [r for r in rows if r["split"] == "train"]
     va = [r for r in rows if r["split"] == "val"]
+    check_splits(rows)
     X = np.array([r["feat"] for r in tr], np.float64)
     Y = np.array([(np.array(r["c"]) - 1.0) / r["sigma"] for r in tr], np.float64)
     mean, std = X.mean(0), X.std(0) + 1e-6
