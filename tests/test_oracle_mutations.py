@@ -220,14 +220,27 @@ def _case(name):
         shutil.rmtree(root, ignore_errors=True)
 
 
+class _Outcomes(dict):
+    """Outcome of each case, run on first use when not computed up front."""
+
+    def __missing__(self, name):
+        self[name] = out = _case(name)
+        return out
+
+
 @pytest.fixture(scope="module")
 def outcomes():
     from oracle import build
     build.build(force=False)  # the copies start from built, current libraries
-    names = [None, *MUTATIONS]
-    workers = max(1, min(8, os.cpu_count() or 1))
-    with cf.ThreadPoolExecutor(workers) as ex:
-        return dict(zip(names, ex.map(_case, names)))
+    out = _Outcomes()
+    # Serially, every case runs up front on a thread pool.  Under pytest-xdist each worker
+    # would repeat that for itself, so there each test runs its own case only.
+    if not os.environ.get("PYTEST_XDIST_WORKER"):
+        names = [None, *MUTATIONS]
+        workers = max(1, min(8, os.cpu_count() or 1))
+        with cf.ThreadPoolExecutor(workers) as ex:
+            out.update(zip(names, ex.map(_case, names)))
+    return out
 
 
 def test_harness_imports_the_copy_and_passes_unplanted(outcomes):
