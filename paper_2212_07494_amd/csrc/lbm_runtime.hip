@@ -499,7 +499,7 @@ int poll_checks(lbm_ctx *c, bool wait) {
   return judge_record(c, m);
 }
 
-// The state was replaced: no record, residual or non-finite verdict carries over.
+// The state was replaced: no record, residual or non-finite flag carries over.
 void state_replaced(lbm_ctx *c) {
   c->uprev_time = -2;
   c->dev_step = -1;
